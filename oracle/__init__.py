@@ -1,0 +1,201 @@
+"""The oracle: plain FP64 CPU block relaxation, written from the paper.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The product
+path (``paper_1208_1975_amd``) never imports it, and the two share no code.
+
+The arithmetic lives in ``bso.c`` (plain C, ``-O2 -ffp-contract=off``,
+OpenMP only over independent blocks).  This module builds it with ``gcc`` and
+wraps it with ctypes; it adds no arithmetic of its own.
+
+Layout (section 2.1, index spaces): ``u`` is padded with one ghost layer,
+shape ``(nz+2, ny+2, nx+2)``; ``f`` is unpadded, shape ``(nz, ny, nx)``;
+x is the fastest axis.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bso.c")
+_LIB = os.path.join(_HERE, "libbso.so")
+
+JACOBI, LEX_GS, COLORED_GS = 0, 1, 2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile bso.c into libbso.so next to it (plain gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    D, I, P = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
+    lib.bso_residual.argtypes = [I, I, I, P, D, P, P, P]
+    lib.bso_residual.restype = D
+    lib.bso_tridiag_solve.argtypes = [I, D, D, P, P]
+    lib.bso_tridiag_solve.restype = None
+    lib.bso_line_sweeps.argtypes = [I, I, I, P, D, I, I, D, I, I, P, P]
+    lib.bso_line_sweeps.restype = I
+    lib.bso_plane_sweeps.argtypes = [I, I, I, P, D, I, I, D, I, P, P]
+    lib.bso_plane_sweeps.restype = I
+    lib.bso_plane_update_some.argtypes = [I, I, I, P, D, I, D, I, P, P, P, P]
+    lib.bso_plane_update_some.restype = I
+    lib.bso_line_update_some.argtypes = [I, I, I, P, D, I, D, I, P, P, P, P]
+    lib.bso_line_update_some.restype = I
+    lib.bso_line_jacobi_adjoint.argtypes = [I, I, I, P, D, I, D, I, P, P, P, P, P, P]
+    lib.bso_line_jacobi_adjoint.restype = I
+    lib.bso_line_jacobi_eps_tangent.argtypes = [I, I, I, P, D, I, D, I, P, P, P, P]
+    lib.bso_line_jacobi_eps_tangent.restype = I
+    lib.bso_set_threads.argtypes = [I]
+    lib.bso_set_threads.restype = None
+    lib.bso_get_threads.argtypes = []
+    lib.bso_get_threads.restype = I
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _dims_of(u):
+    nz, ny, nx = (s - 2 for s in u.shape)
+    return nx, ny, nz
+
+
+def _check(u, f=None):
+    assert u.dtype == np.float64 and u.flags.c_contiguous and u.ndim == 3
+    nx, ny, nz = _dims_of(u)
+    if f is not None:
+        assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (nz, ny, nx)
+    return nx, ny, nz
+
+
+def _eps(eps):
+    return np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(3))
+
+
+def set_threads(n: int) -> None:
+    _load().bso_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().bso_get_threads())
+
+
+def residual(u, f, eps, h, want_r=True):
+    """(r, sum r^2): r = h^2 f - A_eps u over interior cells (eq. stencil3d7)."""
+    lib = _load()
+    nx, ny, nz = _check(u, f)
+    e = _eps(eps)
+    r = np.empty((nz, ny, nx)) if want_r else None
+    s = lib.bso_residual(nx, ny, nz, _p(e), float(h), _p(u), _p(f), _p(r))
+    return r, s
+
+
+def tridiag_solve(off, diag, rhs):
+    """Textbook Thomas solve of tridiag(off, diag, off) x = rhs."""
+    lib = _load()
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+    x = np.empty_like(rhs)
+    lib.bso_tridiag_solve(rhs.size, float(off), float(diag), _p(rhs), _p(x))
+    return x
+
+
+def line_sweeps(u, f, eps, h, axis, scheme, omega, nsweeps, lex_form=0):
+    """Return u after nsweeps line-block sweeps (u is not modified)."""
+    lib = _load()
+    nx, ny, nz = _check(u, f)
+    out = u.copy()
+    rc = lib.bso_line_sweeps(nx, ny, nz, _p(_eps(eps)), float(h), int(axis), int(scheme),
+                             float(omega), int(nsweeps), int(lex_form), _p(out), _p(f))
+    if rc:
+        raise ValueError("bso_line_sweeps failed (%d)" % rc)
+    return out
+
+
+def plane_sweeps(u, f, eps, h, normal, scheme, omega, nsweeps):
+    """Return u after nsweeps plane-block sweeps (u is not modified)."""
+    lib = _load()
+    nx, ny, nz = _check(u, f)
+    out = u.copy()
+    rc = lib.bso_plane_sweeps(nx, ny, nz, _p(_eps(eps)), float(h), int(normal), int(scheme),
+                              float(omega), int(nsweeps), _p(out), _p(f))
+    if rc:
+        raise ValueError("bso_plane_sweeps failed (%d)" % rc)
+    return out
+
+
+def plane_update_some(usrc, f, eps, h, normal, omega, planes, udst=None):
+    """One Jacobi update of the listed planes from usrc; other cells copied from usrc."""
+    lib = _load()
+    nx, ny, nz = _check(usrc, f)
+    out = usrc.copy() if udst is None else udst
+    pl = np.ascontiguousarray(np.asarray(planes, dtype=np.int32))
+    rc = lib.bso_plane_update_some(nx, ny, nz, _p(_eps(eps)), float(h), int(normal), float(omega),
+                                   pl.size, _p(pl), _p(usrc), _p(out), _p(f))
+    if rc:
+        raise ValueError("bso_plane_update_some failed")
+    return out
+
+
+def line_update_some(usrc, f, eps, h, axis, omega, lines, udst=None):
+    """One update of the listed lines (p, q) from usrc; other cells copied from usrc."""
+    lib = _load()
+    nx, ny, nz = _check(usrc, f)
+    out = usrc.copy() if udst is None else udst
+    pq = np.ascontiguousarray(np.asarray(lines, dtype=np.int32).reshape(-1, 2))
+    rc = lib.bso_line_update_some(nx, ny, nz, _p(_eps(eps)), float(h), int(axis), float(omega),
+                                  pq.shape[0], _p(pq), _p(usrc), _p(out), _p(f))
+    if rc:
+        raise ValueError("bso_line_update_some failed")
+    return out
+
+
+def line_jacobi_adjoint(u0, f, eps, h, axis, omega, K, gK):
+    """Reverse-mode gradients of K damped Jacobi line sweeps for dL/du_K = gK.
+
+    Returns (g_u0 padded incl. face-ghost gradients, g_f unpadded, g_eps[3])."""
+    lib = _load()
+    nx, ny, nz = _check(u0, f)
+    gK = np.ascontiguousarray(gK, dtype=np.float64)
+    assert gK.shape == u0.shape
+    g_u0 = np.zeros_like(u0)
+    g_f = np.zeros_like(f)
+    g_eps = np.zeros(3)
+    rc = lib.bso_line_jacobi_adjoint(nx, ny, nz, _p(_eps(eps)), float(h), int(axis), float(omega),
+                                     int(K), _p(u0), _p(f), _p(gK), _p(g_u0), _p(g_f), _p(g_eps))
+    if rc:
+        raise ValueError("bso_line_jacobi_adjoint failed")
+    return g_u0, g_f, g_eps
+
+
+def line_jacobi_eps_tangent(u0, f, eps, h, axis, omega, K, gK):
+    """Forward-mode dL/deps (3 values) for dL/du_K = gK."""
+    lib = _load()
+    nx, ny, nz = _check(u0, f)
+    gK = np.ascontiguousarray(gK, dtype=np.float64)
+    out = np.zeros(3)
+    rc = lib.bso_line_jacobi_eps_tangent(nx, ny, nz, _p(_eps(eps)), float(h), int(axis),
+                                         float(omega), int(K), _p(u0), _p(f), _p(gK), _p(out))
+    if rc:
+        raise ValueError("bso_line_jacobi_eps_tangent failed")
+    return out

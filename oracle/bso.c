@@ -1,0 +1,773 @@
+/*
+ * bso.c -- the oracle: a plain, slow, FP64 CPU implementation of block
+ * relaxation for the constant-coefficient 7-point stencil, written from the
+ * paper (Birke, Philip, Wang, Berrill, "Block-Relaxation Methods for 3D
+ * Constant-Coefficient Stencils on GPUs and Multicore CPUs").
+ *
+ * THIS IS TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  The product path (the HIP
+ * library) shares no code, header, table or helper with this file.
+ *
+ * Conventions (section 1.1 and the index-space discussion of section 2.1):
+ *   - a patch has nx*ny*nz interior cells, x fastest;
+ *   - u is stored WITH one ghost layer: (nz+2)(ny+2)(nx+2) doubles, interior
+ *     cell (i,j,k) at ((k+1)(ny+2)+(j+1))(nx+2)+(i+1);
+ *   - f is stored WITHOUT ghosts: nz*ny*nx doubles, cell (i,j,k) at
+ *     (k*ny+j)*nx+i.
+ *   - Ghosts are caller data and never change during a sweep; boundary cells
+ *     use the same stencil as interior cells (section 1.1).  Zero Dirichlet
+ *     means a zero ghost layer.
+ *
+ * Operator (eq. stencil3d7, with one weight per axis; at eps = (1,1,1) it is
+ * exactly the paper's stencil):
+ *   (A u)_c = sum_a eps_a (2 u_c - u_{c-e_a} - u_{c+e_a}),  b = h^2 f,
+ *   r = b - A u  over interior cells.
+ *
+ * Iteration (eq. blockiteration2, residual-correction form):
+ *   u_b <- u_b + omega * M_b^{-1} r_b
+ * where M_b is the diagonal block of A for block b:
+ *   - a line along axis a: tridiag(-eps_a, d, -eps_a), d = 2(eps_x+eps_y+eps_z);
+ *   - a plane with normal c (in-plane axes a<b): d I - eps_a(shifts in a)
+ *     - eps_b(shifts in b), truncated at the plane edge.
+ * Schemes (section 2, Algorithm 1 and eq. sm:blockm):
+ *   - Jacobi: every block from the same old u, written to a second vector;
+ *   - lexicographic block Gauss-Seidel: blocks visited in lexicographic order
+ *     of their free indices (lower axis fastest), each using the current u;
+ *   - coloured block Gauss-Seidel: colour = (sum of the free indices) mod 2
+ *     for lines, plane index mod 2 for planes; colour 0 first, then colour 1.
+ *
+ * Numerical choices:
+ *   - line solves: the textbook Thomas algorithm, factorised on every call;
+ *   - plane solves: partial diagonalisation -- an explicit sine transform
+ *     along the lower in-plane axis (DST-I basis, integer-reduced argument),
+ *     one Thomas solve per sine mode along the other axis, inverse transform;
+ *   - sums of squares accumulate in long double in a fixed order.
+ * Compile with -ffp-contract=off so no FMA contraction changes the rounding.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdint.h>
+#include <stddef.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { BSO_JACOBI = 0, BSO_LEX_GS = 1, BSO_COLORED_GS = 2 };
+
+typedef struct {
+    int nx, ny, nz;
+    double ex, ey, ez, h2;
+    ptrdiff_t sx, sy;   /* u strides in y and z (padded) */
+} grid_t;
+
+static grid_t mkgrid(int nx, int ny, int nz, const double eps[3], double h)
+{
+    grid_t g;
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.ex = eps[0]; g.ey = eps[1]; g.ez = eps[2];
+    g.h2 = h * h;
+    g.sx = nx + 2;
+    g.sy = (ptrdiff_t)(nx + 2) * (ny + 2);
+    return g;
+}
+
+static inline ptrdiff_t uidx(const grid_t *g, int i, int j, int k)
+{
+    return (ptrdiff_t)(k + 1) * g->sy + (ptrdiff_t)(j + 1) * g->sx + (i + 1);
+}
+
+static inline ptrdiff_t fidx(const grid_t *g, int i, int j, int k)
+{
+    return ((ptrdiff_t)k * g->ny + j) * g->nx + i;
+}
+
+static int dim_of(const grid_t *g, int a) { return a == 0 ? g->nx : (a == 1 ? g->ny : g->nz); }
+static double eps_of(const grid_t *g, int a) { return a == 0 ? g->ex : (a == 1 ? g->ey : g->ez); }
+static ptrdiff_t ustride_of(const grid_t *g, int a) { return a == 0 ? 1 : (a == 1 ? g->sx : g->sy); }
+
+/* Residual of one interior cell: h^2 f - (A u) (eq. stencil3d7 with axis weights). */
+static inline double cell_res(const grid_t *g, const double *u, const double *f, int i, int j, int k)
+{
+    ptrdiff_t c = uidx(g, i, j, k);
+    double ax = g->ex * (2.0 * u[c] - u[c - 1] - u[c + 1]);
+    double ay = g->ey * (2.0 * u[c] - u[c - g->sx] - u[c + g->sx]);
+    double az = g->ez * (2.0 * u[c] - u[c - g->sy] - u[c + g->sy]);
+    return g->h2 * f[fidx(g, i, j, k)] - (ax + ay + az);
+}
+
+static int g_threads = 0;
+void bso_set_threads(int n) { g_threads = n; }
+int bso_get_threads(void)
+{
+#ifdef _OPENMP
+    return g_threads > 0 ? g_threads : omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+#ifdef _OPENMP
+#define NT bso_get_threads()
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* Residual and its norm (the quantity monitored in section 3).               */
+/* ------------------------------------------------------------------------- */
+
+/* r (unpadded, may be NULL) = h^2 f - A u; returns sum of r^2 over interior
+ * cells, accumulated in long double in k,j,i order. */
+double bso_residual(int nx, int ny, int nz, const double eps[3], double h,
+                    const double *u, const double *f, double *r)
+{
+    grid_t g = mkgrid(nx, ny, nz, eps, h);
+    long double *part = (long double *)calloc((size_t)nz, sizeof(long double));
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(NT) schedule(static)
+#endif
+    for (int k = 0; k < nz; ++k) {
+        long double s = 0.0L;
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double v = cell_res(&g, u, f, i, j, k);
+                if (r) r[fidx(&g, i, j, k)] = v;
+                s += (long double)v * (long double)v;
+            }
+        part[k] = s;
+    }
+    long double tot = 0.0L;
+    for (int k = 0; k < nz; ++k) tot += part[k];
+    free(part);
+    return (double)tot;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tridiagonal solve (textbook Thomas algorithm, Conte & de Boor form).       */
+/* Solves tridiag(off, diag, off) x = rhs for a symmetric Toeplitz system,    */
+/* factorising on every call.  cp is scratch of length n.  x may alias rhs.   */
+/* ------------------------------------------------------------------------- */
+static void thomas(int n, double off, double diag, const double *rhs, double *x, double *cp)
+{
+    /* forward elimination */
+    double denom = diag;
+    cp[0] = off / denom;
+    x[0] = rhs[0] / denom;
+    for (int i = 1; i < n; ++i) {
+        denom = diag - off * cp[i - 1];
+        cp[i] = off / denom;
+        x[i] = (rhs[i] - off * x[i - 1]) / denom;
+    }
+    /* back substitution */
+    for (int i = n - 2; i >= 0; --i)
+        x[i] = x[i] - cp[i] * x[i + 1];
+}
+
+/* Exposed for the test that pins the line solver against a banded LAPACK solve. */
+void bso_tridiag_solve(int n, double off, double diag, const double *rhs, double *x)
+{
+    double *cp = (double *)malloc(sizeof(double) * (size_t)n);
+    thomas(n, off, diag, rhs, x, cp);
+    free(cp);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Line blocks.                                                               */
+/* A line along axis a is named by its two free indices (p, q): p is the      */
+/* lower remaining axis, q the higher one.                                    */
+/* ------------------------------------------------------------------------- */
+static void line_cell(int axis, int p, int q, int t, int *i, int *j, int *k)
+{
+    if (axis == 0) { *i = t; *j = p; *k = q; }
+    else if (axis == 1) { *i = p; *j = t; *k = q; }
+    else { *i = p; *j = q; *k = t; }
+}
+
+static void free_dims(const grid_t *g, int axis, int *np, int *nq)
+{
+    if (axis == 0) { *np = g->ny; *nq = g->nz; }
+    else if (axis == 1) { *np = g->nx; *nq = g->nz; }
+    else { *np = g->nx; *nq = g->ny; }
+}
+
+/* One block update of line (p,q): residual from usrc, exact tridiagonal
+ * solve, udst = usrc + omega*du on the line's cells.  All residuals are formed
+ * before any value is written, so usrc == udst (in place) is allowed.
+ * buf must hold 2n doubles. */
+static void line_update(const grid_t *g, int axis, int p, int q, const double *usrc,
+                        double *udst, const double *f, double omega, double *buf)
+{
+    int n = dim_of(g, axis);
+    double ea = eps_of(g, axis);
+    double d = 2.0 * (g->ex + g->ey + g->ez);
+    double *r = buf, *cp = buf + n;
+    int i, j, k;
+    for (int t = 0; t < n; ++t) {
+        line_cell(axis, p, q, t, &i, &j, &k);
+        r[t] = cell_res(g, usrc, f, i, j, k);
+    }
+    thomas(n, -ea, d, r, r, cp);
+    for (int t = 0; t < n; ++t) {
+        line_cell(axis, p, q, t, &i, &j, &k);
+        ptrdiff_t c = uidx(g, i, j, k);
+        udst[c] = usrc[c] + omega * r[t];
+    }
+}
+
+static void copy_padded(const grid_t *g, const double *src, double *dst)
+{
+    size_t n = (size_t)(g->nz + 2) * (size_t)g->sy;
+    memcpy(dst, src, n * sizeof(double));
+}
+
+/* Line sweeps.  scheme: 0 Jacobi, 1 lexicographic GS, 2 coloured GS.
+ * lex_form: 0 = the serial lexicographic loop (the definition);
+ *           1 = the anti-diagonal form: lines (p,q) with equal p+q are
+ *               mutually uncoupled and all their already-updated neighbours
+ *               lie on the previous anti-diagonal, so processing diagonals in
+ *               order gives bit-identical results, in parallel.
+ * Returns 0 on success, nonzero on bad arguments. */
+int bso_line_sweeps(int nx, int ny, int nz, const double eps[3], double h, int axis,
+                    int scheme, double omega, int nsweeps, int lex_form,
+                    double *u, const double *f)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || axis < 0 || axis > 2 || nsweeps < 0) return 1;
+    grid_t g = mkgrid(nx, ny, nz, eps, h);
+    int n = dim_of(&g, axis), np, nq;
+    free_dims(&g, axis, &np, &nq);
+    size_t tot = (size_t)(nz + 2) * (size_t)g.sy;
+    double *v = NULL;
+    if (scheme == BSO_JACOBI) {
+        v = (double *)malloc(tot * sizeof(double));
+        copy_padded(&g, u, v);   /* ghosts of the second vector = ghosts of u */
+    }
+    for (int s = 0; s < nsweeps; ++s) {
+        if (scheme == BSO_JACOBI) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(NT)
+#endif
+            {
+                double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+#ifdef _OPENMP
+#pragma omp for collapse(2) schedule(static)
+#endif
+                for (int q = 0; q < nq; ++q)
+                    for (int p = 0; p < np; ++p)
+                        line_update(&g, axis, p, q, u, v, f, omega, buf);
+                free(buf);
+            }
+            double *t = u; /* copy back (the oracle keeps the result in u) */
+            copy_padded(&g, v, t);
+        } else if (scheme == BSO_LEX_GS) {
+            if (lex_form == 0) {
+                double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+                for (int q = 0; q < nq; ++q)
+                    for (int p = 0; p < np; ++p)
+                        line_update(&g, axis, p, q, u, u, f, omega, buf);
+                free(buf);
+            } else {
+                for (int dg = 0; dg <= (np - 1) + (nq - 1); ++dg) {
+                    int qlo = dg - (np - 1) > 0 ? dg - (np - 1) : 0;
+                    int qhi = dg < nq - 1 ? dg : nq - 1;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(NT)
+#endif
+                    {
+                        double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+                        for (int q = qlo; q <= qhi; ++q)
+                            line_update(&g, axis, dg - q, q, u, u, f, omega, buf);
+                        free(buf);
+                    }
+                }
+            }
+        } else if (scheme == BSO_COLORED_GS) {
+            for (int colour = 0; colour < 2; ++colour) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(NT)
+#endif
+                {
+                    double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+#ifdef _OPENMP
+#pragma omp for collapse(2) schedule(static)
+#endif
+                    for (int q = 0; q < nq; ++q)
+                        for (int p = 0; p < np; ++p)
+                            if (((p + q) & 1) == colour)
+                                line_update(&g, axis, p, q, u, u, f, omega, buf);
+                    free(buf);
+                }
+            }
+        } else {
+            free(v);
+            return 2;
+        }
+    }
+    free(v);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Plane blocks, solved by partial diagonalisation.                           */
+/* Plane with normal c at index s; in-plane axes a < b.  The plane block is   */
+/*   M = T_a (x) I + I (x) T'_b,  T_a = tridiag(-eps_a, 2eps_a, -eps_a),      */
+/*   T'_b = tridiag(-eps_b, 2eps_b + 2eps_c, -eps_b).                          */
+/* T_a = S diag(sigma) S with the orthonormal DST-I basis                      */
+/*   S[i][p] = sqrt(2/(n+1)) sin(pi (i+1)(p+1)/(n+1)),                         */
+/*   sigma_p = 4 eps_a sin^2((p+1) pi / (2(n+1))).                             */
+/* Transforming along a leaves one tridiagonal system in b per mode p.         */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int na, nb;
+    double *S;      /* na*na, S[i*na + p] */
+    double *sigma;  /* na */
+} sine_basis_t;
+
+static sine_basis_t make_basis(int na, double ea)
+{
+    sine_basis_t B;
+    B.na = na; B.nb = 0;
+    B.S = (double *)malloc(sizeof(double) * (size_t)na * na);
+    B.sigma = (double *)malloc(sizeof(double) * (size_t)na);
+    const double scale = sqrt(2.0 / (double)(na + 1));
+    const long period = 2L * (na + 1);
+    for (int i = 0; i < na; ++i)
+        for (int p = 0; p < na; ++p) {
+            long m = ((long)(i + 1) * (long)(p + 1)) % period;   /* exact reduction */
+            B.S[(size_t)i * na + p] = scale * sin(M_PI * (double)m / (double)(na + 1));
+        }
+    for (int p = 0; p < na; ++p) {
+        double s = sin(M_PI * (double)(p + 1) / (2.0 * (double)(na + 1)));
+        B.sigma[p] = 4.0 * ea * s * s;
+    }
+    return B;
+}
+
+static void free_basis(sine_basis_t *B) { free(B->S); free(B->sigma); }
+
+static void plane_axes(int normal, int *a, int *b)
+{
+    if (normal == 0) { *a = 1; *b = 2; }
+    else if (normal == 1) { *a = 0; *b = 2; }
+    else { *a = 0; *b = 1; }
+}
+
+static void plane_cell(int normal, int s, int ia, int ib, int *i, int *j, int *k)
+{
+    if (normal == 0) { *i = s; *j = ia; *k = ib; }
+    else if (normal == 1) { *i = ia; *j = s; *k = ib; }
+    else { *i = ia; *j = ib; *k = s; }
+}
+
+/* buf must hold 3*na*nb + nb doubles. */
+static void plane_update(const grid_t *g, int normal, int s, const sine_basis_t *B,
+                         const double *usrc, double *udst, const double *f, double omega,
+                         double *buf)
+{
+    int a, b;
+    plane_axes(normal, &a, &b);
+    int na = dim_of(g, a), nb = dim_of(g, b);
+    double eb = eps_of(g, b), ec = eps_of(g, normal);
+    double *r = buf;                          /* r[ia*nb + ib] */
+    double *rh = buf + (size_t)na * nb;       /* rh[p*nb + ib] */
+    double *w = buf + 2 * (size_t)na * nb;    /* w[ia*nb + ib] */
+    double *cp = buf + 3 * (size_t)na * nb;   /* nb */
+    int i, j, k;
+    for (int ia = 0; ia < na; ++ia)
+        for (int ib = 0; ib < nb; ++ib) {
+            plane_cell(normal, s, ia, ib, &i, &j, &k);
+            r[(size_t)ia * nb + ib] = cell_res(g, usrc, f, i, j, k);
+        }
+    /* forward sine transform along a: rh[p][ib] = sum_ia S[ia][p] r[ia][ib] */
+    for (int p = 0; p < na; ++p)
+        for (int ib = 0; ib < nb; ++ib) {
+            double acc = 0.0;
+            for (int ia = 0; ia < na; ++ia)
+                acc += B->S[(size_t)ia * na + p] * r[(size_t)ia * nb + ib];
+            rh[(size_t)p * nb + ib] = acc;
+        }
+    /* one tridiagonal solve along b per mode */
+    for (int p = 0; p < na; ++p)
+        thomas(nb, -eb, B->sigma[p] + 2.0 * eb + 2.0 * ec, rh + (size_t)p * nb,
+               rh + (size_t)p * nb, cp);
+    /* inverse transform: w[ia][ib] = sum_p S[ia][p] rh[p][ib] */
+    for (int ia = 0; ia < na; ++ia)
+        for (int ib = 0; ib < nb; ++ib) {
+            double acc = 0.0;
+            for (int p = 0; p < na; ++p)
+                acc += B->S[(size_t)ia * na + p] * rh[(size_t)p * nb + ib];
+            w[(size_t)ia * nb + ib] = acc;
+        }
+    for (int ia = 0; ia < na; ++ia)
+        for (int ib = 0; ib < nb; ++ib) {
+            plane_cell(normal, s, ia, ib, &i, &j, &k);
+            ptrdiff_t c = uidx(g, i, j, k);
+            udst[c] = usrc[c] + omega * w[(size_t)ia * nb + ib];
+        }
+}
+
+/* Plane sweeps (normal axis 0/1/2).  scheme as for lines; lexicographic GS
+ * visits planes s = 0..n_c-1 in order. */
+int bso_plane_sweeps(int nx, int ny, int nz, const double eps[3], double h, int normal,
+                     int scheme, double omega, int nsweeps, double *u, const double *f)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || normal < 0 || normal > 2 || nsweeps < 0) return 1;
+    grid_t g = mkgrid(nx, ny, nz, eps, h);
+    int a, b;
+    plane_axes(normal, &a, &b);
+    int na = dim_of(&g, a), nb = dim_of(&g, b), nc = dim_of(&g, normal);
+    sine_basis_t B = make_basis(na, eps_of(&g, a));
+    size_t tot = (size_t)(nz + 2) * (size_t)g.sy;
+    size_t bufn = 3 * (size_t)na * nb + (size_t)nb;
+    double *v = NULL;
+    if (scheme == BSO_JACOBI) {
+        v = (double *)malloc(tot * sizeof(double));
+        copy_padded(&g, u, v);
+    }
+    for (int sw = 0; sw < nsweeps; ++sw) {
+        if (scheme == BSO_JACOBI) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(NT)
+#endif
+            {
+                double *buf = (double *)malloc(sizeof(double) * bufn);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+                for (int s = 0; s < nc; ++s)
+                    plane_update(&g, normal, s, &B, u, v, f, omega, buf);
+                free(buf);
+            }
+            copy_padded(&g, v, u);
+        } else if (scheme == BSO_LEX_GS) {
+            double *buf = (double *)malloc(sizeof(double) * bufn);
+            for (int s = 0; s < nc; ++s)
+                plane_update(&g, normal, s, &B, u, u, f, omega, buf);
+            free(buf);
+        } else if (scheme == BSO_COLORED_GS) {
+            for (int colour = 0; colour < 2; ++colour) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(NT)
+#endif
+                {
+                    double *buf = (double *)malloc(sizeof(double) * bufn);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+                    for (int s = 0; s < nc; ++s)
+                        if ((s & 1) == colour)
+                            plane_update(&g, normal, s, &B, u, u, f, omega, buf);
+                    free(buf);
+                }
+            }
+        } else {
+            free(v);
+            free_basis(&B);
+            return 2;
+        }
+    }
+    free(v);
+    free_basis(&B);
+    return 0;
+}
+
+/* One Jacobi plane update restricted to a list of planes, reading usrc and
+ * writing udst (padded).  Used to check single planes of a large sweep. */
+int bso_plane_update_some(int nx, int ny, int nz, const double eps[3], double h, int normal,
+                          double omega, int nplanes, const int *planes,
+                          const double *usrc, double *udst, const double *f)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || normal < 0 || normal > 2) return 1;
+    grid_t g = mkgrid(nx, ny, nz, eps, h);
+    int a, b;
+    plane_axes(normal, &a, &b);
+    int na = dim_of(&g, a), nb = dim_of(&g, b), nc = dim_of(&g, normal);
+    sine_basis_t B = make_basis(na, eps_of(&g, a));
+    size_t bufn = 3 * (size_t)na * nb + (size_t)nb;
+    int bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(NT)
+#endif
+    {
+        double *buf = (double *)malloc(sizeof(double) * bufn);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int t = 0; t < nplanes; ++t) {
+            if (planes[t] < 0 || planes[t] >= nc) { bad = 1; continue; }
+            plane_update(&g, normal, planes[t], &B, usrc, udst, f, omega, buf);
+        }
+        free(buf);
+    }
+    free_basis(&B);
+    return bad;
+}
+
+/* One line update for a list of lines (p,q), reading usrc, writing udst. */
+int bso_line_update_some(int nx, int ny, int nz, const double eps[3], double h, int axis,
+                         double omega, int nlines, const int *pq,
+                         const double *usrc, double *udst, const double *f)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || axis < 0 || axis > 2) return 1;
+    grid_t g = mkgrid(nx, ny, nz, eps, h);
+    int n = dim_of(&g, axis), np, nq, bad = 0;
+    free_dims(&g, axis, &np, &nq);
+    double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    for (int t = 0; t < nlines; ++t) {
+        int p = pq[2 * t], q = pq[2 * t + 1];
+        if (p < 0 || p >= np || q < 0 || q >= nq) { bad = 1; continue; }
+        line_update(&g, axis, p, q, usrc, udst, f, omega, buf);
+    }
+    free(buf);
+    return bad;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adjoint of K damped Jacobi line sweeps (reverse mode, every state stored). */
+/*                                                                            */
+/* Forward: x^{k+1} = x^k + omega M^{-1} r(x^k), r = h^2 F + B g - A_int x,   */
+/* with interior unknowns x, fixed ghosts g (B g = ghost terms of the         */
+/* stencil) and A_int the interior operator with zero ghosts.  M and A are    */
+/* symmetric, so for a loss L with dL/dx^K = gbar:                            */
+/*   lambda   = M^{-1} gbar                                                   */
+/*   dL/dF   += omega h^2 lambda                                              */
+/*   dL/dg   += omega B^T lambda          (face ghosts only)                  */
+/*   dL/deps_a += -omega <lambda, D_a U^k + (dM/deps_a) w^k>,                 */
+/*                 w^k = M^{-1} r(x^k),  D_a U = 2U - U_{-a} - U_{+a}         */
+/*   gbar    <- gbar - omega A_int lambda                                     */
+/* and finally dL/dx^0 = gbar.  For lines along a, dM/deps_a =                */
+/* tridiag(-1,2,-1) on each line and dM/deps_other = 2 I.                     */
+/* All gradient arrays are padded like u; gK's ghost entries are ignored.     */
+/* g_u0 receives interior gradients and face-ghost gradients (edges and       */
+/* corners are never read and get 0).                                         */
+/* ------------------------------------------------------------------------- */
+
+/* M^{-1} applied to every line of a padded field (interior), out may alias in. */
+static void apply_minv_lines(const grid_t *g, int axis, const double *in, double *out)
+{
+    int n = dim_of(g, axis), np, nq;
+    free_dims(g, axis, &np, &nq);
+    double ea = eps_of(g, axis), d = 2.0 * (g->ex + g->ey + g->ez);
+#ifdef _OPENMP
+#pragma omp parallel num_threads(NT)
+#endif
+    {
+        double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+        int i, j, k;
+#ifdef _OPENMP
+#pragma omp for collapse(2) schedule(static)
+#endif
+        for (int q = 0; q < nq; ++q)
+            for (int p = 0; p < np; ++p) {
+                for (int t = 0; t < n; ++t) {
+                    line_cell(axis, p, q, t, &i, &j, &k);
+                    buf[t] = in[uidx(g, i, j, k)];
+                }
+                thomas(n, -ea, d, buf, buf, buf + n);
+                for (int t = 0; t < n; ++t) {
+                    line_cell(axis, p, q, t, &i, &j, &k);
+                    out[uidx(g, i, j, k)] = buf[t];
+                }
+            }
+        free(buf);
+    }
+}
+
+/* out = A_int x (x padded, its ghosts treated as zero), interior written. */
+static void apply_a_int(const grid_t *g, const double *x, double *out)
+{
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(NT) schedule(static)
+#endif
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                ptrdiff_t c = uidx(g, i, j, k);
+                double xm = i > 0 ? x[c - 1] : 0.0, xp = i < g->nx - 1 ? x[c + 1] : 0.0;
+                double ym = j > 0 ? x[c - g->sx] : 0.0, yp = j < g->ny - 1 ? x[c + g->sx] : 0.0;
+                double zm = k > 0 ? x[c - g->sy] : 0.0, zp = k < g->nz - 1 ? x[c + g->sy] : 0.0;
+                out[c] = g->ex * (2.0 * x[c] - xm - xp) + g->ey * (2.0 * x[c] - ym - yp)
+                       + g->ez * (2.0 * x[c] - zm - zp);
+            }
+}
+
+/* D_a U (ghosts included) at interior cell c. */
+static inline double d_axis(const grid_t *g, const double *u, ptrdiff_t c, int a)
+{
+    ptrdiff_t s = ustride_of(g, a);
+    return 2.0 * u[c] - u[c - s] - u[c + s];
+}
+
+/* (dM/deps_b) w at interior cell for lines along `axis`. */
+static inline double dm_apply(const grid_t *g, int axis, int b, const double *w, int i, int j, int k)
+{
+    ptrdiff_t c = uidx(g, i, j, k);
+    if (b != axis) return 2.0 * w[c];
+    int t = axis == 0 ? i : (axis == 1 ? j : k);
+    int n = dim_of(g, axis);
+    ptrdiff_t s = ustride_of(g, axis);
+    double lo = t > 0 ? w[c - s] : 0.0, hi = t < n - 1 ? w[c + s] : 0.0;
+    return 2.0 * w[c] - lo - hi;
+}
+
+static void jacobi_line_step(const grid_t *g, int axis, double omega, const double *x,
+                             double *xn, const double *f, double *w)
+{
+    /* w = M^{-1} r(x); xn = x + omega w (ghosts of xn = ghosts of x) */
+    size_t tot = (size_t)(g->nz + 2) * (size_t)g->sy;
+    memcpy(xn, x, tot * sizeof(double));
+    memset(w, 0, tot * sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(NT) schedule(static)
+#endif
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i)
+                w[uidx(g, i, j, k)] = cell_res(g, x, f, i, j, k);
+    apply_minv_lines(g, axis, w, w);
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(NT) schedule(static)
+#endif
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                ptrdiff_t c = uidx(g, i, j, k);
+                xn[c] = x[c] + omega * w[c];
+            }
+}
+
+/* Forward K Jacobi line sweeps that keep every state: states[(k)*tot ...]. */
+int bso_line_jacobi_adjoint(int nx, int ny, int nz, const double eps[3], double h, int axis,
+                            double omega, int K, const double *u0, const double *f,
+                            const double *gK, double *g_u0, double *g_f, double g_eps[3])
+{
+    if (nx < 1 || ny < 1 || nz < 1 || axis < 0 || axis > 2 || K < 0) return 1;
+    grid_t g = mkgrid(nx, ny, nz, eps, h);
+    size_t tot = (size_t)(nz + 2) * (size_t)g.sy;
+    double *states = (double *)malloc(sizeof(double) * tot * (size_t)(K + 1));
+    double *ws = (double *)malloc(sizeof(double) * tot * (size_t)(K > 0 ? K : 1));
+    memcpy(states, u0, tot * sizeof(double));
+    for (int k = 0; k < K; ++k)
+        jacobi_line_step(&g, axis, omega, states + (size_t)k * tot, states + (size_t)(k + 1) * tot,
+                         f, ws + (size_t)k * tot);
+
+    double *gb = (double *)calloc(tot, sizeof(double));
+    double *lam = (double *)calloc(tot, sizeof(double));
+    double *alam = (double *)calloc(tot, sizeof(double));
+    double *gghost = (double *)calloc(tot, sizeof(double));
+    long double geps[3] = {0.0L, 0.0L, 0.0L};
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                ptrdiff_t c = uidx(&g, i, j, k);
+                gb[c] = gK[c];
+            }
+    if (g_f) memset(g_f, 0, sizeof(double) * (size_t)nx * ny * nz);
+    double ev[3] = {g.ex, g.ey, g.ez};
+    for (int k = K - 1; k >= 0; --k) {
+        const double *U = states + (size_t)k * tot;
+        const double *W = ws + (size_t)k * tot;
+        apply_minv_lines(&g, axis, gb, lam);                 /* lambda = M^{-1} gbar */
+        for (int b = 0; b < 3; ++b) {                          /* eps partials, fixed order */
+            long double s = 0.0L;
+            for (int kk = 0; kk < nz; ++kk)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        ptrdiff_t c = uidx(&g, i, j, kk);
+                        double t = d_axis(&g, U, c, b) + dm_apply(&g, axis, b, W, i, j, kk);
+                        s += (long double)lam[c] * (long double)t;
+                    }
+            geps[b] += -(long double)omega * s;
+        }
+        if (g_f)
+            for (int kk = 0; kk < nz; ++kk)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i)
+                        g_f[fidx(&g, i, j, kk)] += omega * g.h2 * lam[uidx(&g, i, j, kk)];
+        /* ghost gradient: B^T lambda -- face ghost next to interior cell c gets eps_a lambda_c */
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    ptrdiff_t c = uidx(&g, i, j, kk);
+                    double l = omega * lam[c];
+                    if (i == 0) gghost[c - 1] += ev[0] * l;
+                    if (i == nx - 1) gghost[c + 1] += ev[0] * l;
+                    if (j == 0) gghost[c - g.sx] += ev[1] * l;
+                    if (j == ny - 1) gghost[c + g.sx] += ev[1] * l;
+                    if (kk == 0) gghost[c - g.sy] += ev[2] * l;
+                    if (kk == nz - 1) gghost[c + g.sy] += ev[2] * l;
+                }
+        apply_a_int(&g, lam, alam);
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    ptrdiff_t c = uidx(&g, i, j, kk);
+                    gb[c] = gb[c] - omega * alam[c];
+                }
+    }
+    if (g_u0) {
+        for (size_t t = 0; t < tot; ++t) g_u0[t] = gghost[t];
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    ptrdiff_t c = uidx(&g, i, j, kk);
+                    g_u0[c] = gb[c];
+                }
+    }
+    if (g_eps)
+        for (int b = 0; b < 3; ++b) g_eps[b] = (double)geps[b];
+    free(states); free(ws); free(gb); free(lam); free(alam); free(gghost);
+    return 0;
+}
+
+/* Forward-mode check of the eps gradient: the tangent t_b = dx/deps_b obeys
+ *   t^{k+1} = t^k + omega M^{-1}(-D_b U^k - A_int t^k - (dM/deps_b) w^k),
+ * t^0 = 0, and dL/deps_b = <gK, t^K>. */
+int bso_line_jacobi_eps_tangent(int nx, int ny, int nz, const double eps[3], double h, int axis,
+                                double omega, int K, const double *u0, const double *f,
+                                const double *gK, double out[3])
+{
+    if (nx < 1 || ny < 1 || nz < 1 || axis < 0 || axis > 2 || K < 0) return 1;
+    grid_t g = mkgrid(nx, ny, nz, eps, h);
+    size_t tot = (size_t)(nz + 2) * (size_t)g.sy;
+    double *x = (double *)malloc(sizeof(double) * tot);
+    double *xn = (double *)malloc(sizeof(double) * tot);
+    double *w = (double *)malloc(sizeof(double) * tot);
+    double *t[3], *at = (double *)calloc(tot, sizeof(double)), *rhs = (double *)calloc(tot, sizeof(double));
+    for (int b = 0; b < 3; ++b) t[b] = (double *)calloc(tot, sizeof(double));
+    memcpy(x, u0, tot * sizeof(double));
+    for (int k = 0; k < K; ++k) {
+        /* w^k = M^{-1} r(x^k) and x^{k+1} */
+        jacobi_line_step(&g, axis, omega, x, xn, f, w);
+        for (int b = 0; b < 3; ++b) {
+            apply_a_int(&g, t[b], at);
+            for (int kk = 0; kk < nz; ++kk)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        ptrdiff_t c = uidx(&g, i, j, kk);
+                        rhs[c] = -d_axis(&g, x, c, b) - at[c] - dm_apply(&g, axis, b, w, i, j, kk);
+                    }
+            apply_minv_lines(&g, axis, rhs, rhs);
+            for (int kk = 0; kk < nz; ++kk)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        ptrdiff_t c = uidx(&g, i, j, kk);
+                        t[b][c] = t[b][c] + omega * rhs[c];
+                    }
+        }
+        double *sw = x; x = xn; xn = sw;
+    }
+    for (int b = 0; b < 3; ++b) {
+        long double s = 0.0L;
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    ptrdiff_t c = uidx(&g, i, j, kk);
+                    s += (long double)gK[c] * (long double)t[b][c];
+                }
+        out[b] = (double)s;
+    }
+    free(x); free(xn); free(w); free(at); free(rhs);
+    for (int b = 0; b < 3; ++b) free(t[b]);
+    return 0;
+}

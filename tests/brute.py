@@ -1,0 +1,116 @@
+"""Dense brute force for tiny grids: assemble the interior matrix A and the
+block splitting M as dense matrices and run sweeps with numpy.linalg.solve.
+
+This pins the oracle to the paper's definitions without sharing any of its
+code: the splitting A = M - N and the residual-correction form
+u <- u + M^{-1} r (eq. blockiteration1 / blockiteration2), with M block
+diagonal (Jacobi, scaled by 1/omega for damping) or block lower triangular in
+the visiting order (block Gauss-Seidel / SOR, eq. sm:blockm).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def interior_index(nx, ny, nz):
+    idx = np.arange(nx * ny * nz).reshape(nz, ny, nx)
+    return idx
+
+
+def assemble(nx, ny, nz, eps):
+    """Dense A_int (m x m) for interior cells, C order [k][j][i]."""
+    m = nx * ny * nz
+    A = np.zeros((m, m))
+    idx = interior_index(nx, ny, nz)
+    ex, ey, ez = eps
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                c = idx[k, j, i]
+                A[c, c] = 2 * (ex + ey + ez)
+                for (di, dj, dk, e) in ((1, 0, 0, ex), (-1, 0, 0, ex), (0, 1, 0, ey), (0, -1, 0, ey),
+                                        (0, 0, 1, ez), (0, 0, -1, ez)):
+                    ii, jj, kk = i + di, j + dj, k + dk
+                    if 0 <= ii < nx and 0 <= jj < ny and 0 <= kk < nz:
+                        A[c, idx[kk, jj, ii]] = -e
+    return A
+
+
+def ghost_rhs(upad, eps):
+    """B g: the ghost terms of the stencil moved to the right-hand side."""
+    nz, ny, nx = (s - 2 for s in upad.shape)
+    ex, ey, ez = eps
+    g = np.zeros((nz, ny, nx))
+    g[:, :, 0] += ex * upad[1:-1, 1:-1, 0]
+    g[:, :, -1] += ex * upad[1:-1, 1:-1, -1]
+    g[:, 0, :] += ey * upad[1:-1, 0, 1:-1]
+    g[:, -1, :] += ey * upad[1:-1, -1, 1:-1]
+    g[0, :, :] += ez * upad[0, 1:-1, 1:-1]
+    g[-1, :, :] += ez * upad[-1, 1:-1, 1:-1]
+    return g.reshape(-1)
+
+
+def block_ids(nx, ny, nz, kind, axis):
+    """(block id per cell, visiting order key per block id, colour per block id).
+
+    Lines along `axis` are named by their free indices (p, q), p the lower
+    remaining axis; lexicographic order is p fastest.  Planes with normal
+    `axis` are named by their index s."""
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    coords = {0: i, 1: j, 2: k}
+    dims = {0: nx, 1: ny, 2: nz}
+    if kind == "line":
+        others = [a for a in (0, 1, 2) if a != axis]
+        p, q = coords[others[0]], coords[others[1]]
+        bid = (q * dims[others[0]] + p).reshape(-1)
+        nb = dims[others[0]] * dims[others[1]]
+        pp = np.arange(nb) % dims[others[0]]
+        qq = np.arange(nb) // dims[others[0]]
+        order = np.arange(nb)
+        colour = (pp + qq) % 2
+    else:
+        s = coords[axis]
+        bid = s.reshape(-1)
+        nb = dims[axis]
+        order = np.arange(nb)
+        colour = np.arange(nb) % 2
+    return bid, order, colour
+
+
+def splitting(A, bid, order, colour, scheme, omega):
+    """M for the scheme: 'jacobi' -> D/omega, 'lex' -> D/omega + L(order),
+    'colored' -> D/omega + L(colour 0 before colour 1)."""
+    same = bid[:, None] == bid[None, :]
+    D = np.where(same, A, 0.0)
+    if scheme == "jacobi":
+        return D / omega
+    if scheme == "lex":
+        key = order[bid]
+    elif scheme == "colored":
+        key = colour[bid]
+    else:
+        raise ValueError(scheme)
+    L = np.where(key[:, None] > key[None, :], A, 0.0)
+    return D / omega + L
+
+
+def sweeps(upad, f, eps, h, kind, axis, scheme, omega, nsweeps):
+    nz, ny, nx = f.shape
+    A = assemble(nx, ny, nz, eps)
+    bid, order, colour = block_ids(nx, ny, nz, kind, axis)
+    M = splitting(A, bid, order, colour, scheme, omega)
+    b = h * h * f.reshape(-1) + ghost_rhs(upad, eps)
+    x = upad[1:-1, 1:-1, 1:-1].reshape(-1).copy()
+    for _ in range(nsweeps):
+        r = b - A @ x
+        x = x + np.linalg.solve(M, r)
+    out = upad.copy()
+    out[1:-1, 1:-1, 1:-1] = x.reshape(nz, ny, nx)
+    return out
+
+
+def iteration_matrix(nx, ny, nz, eps, kind, axis, scheme, omega):
+    A = assemble(nx, ny, nz, eps)
+    bid, order, colour = block_ids(nx, ny, nz, kind, axis)
+    M = splitting(A, bid, order, colour, scheme, omega)
+    return np.eye(A.shape[0]) - np.linalg.solve(M, A), A, M

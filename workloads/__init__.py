@@ -1,0 +1,141 @@
+"""Seeded synthetic inputs for block relaxation, shared by the tests, the
+benchmark and the smoke check.
+
+This module holds NO arithmetic of the smoother: it only draws random numbers
+and places them in the storage layout (u padded with one ghost layer, f
+unpadded, x fastest; section 2.1, index spaces).  Everything is NumPy
+``Generator(PCG64(seed))`` and the draw order is fixed:
+
+  single patch:  f (interior, C order [k][j][i]), then u0 interior, then the
+                 ghost shell (every ghost position of the padded array, in C
+                 order), each only when that field is random;
+  patch set:     dims = choice({16,24,32,48,64}, (P,3)) (columns nx,ny,nz),
+                 eps = 10**uniform(0, 2, (P,3)), then per patch f, u, ghosts.
+
+The paper's workloads are synthetic (random initial guess, section 3); no
+dataset exists or is needed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+EDGE_CHOICES = (16, 24, 32, 48, 64)
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def ghost_mask(nx: int, ny: int, nz: int) -> np.ndarray:
+    m = np.ones((nz + 2, ny + 2, nx + 2), dtype=bool)
+    m[1:-1, 1:-1, 1:-1] = False
+    return m
+
+
+@dataclass
+class Patch:
+    """One patch: padded u0 (nz+2, ny+2, nx+2), unpadded f (nz, ny, nx)."""
+    u0: np.ndarray
+    f: np.ndarray
+    eps: tuple
+    h: float
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def dims(self):
+        nz, ny, nx = self.f.shape
+        return nx, ny, nz
+
+
+def make_patch(nx, ny, nz, eps, h, seed, f="uniform", u0="uniform", ghosts="zero") -> Patch:
+    """Draw one patch.  Each of f/u0/ghosts is 'uniform' (U[-1,1]) or 'zero'."""
+    rng = rng_for(seed)
+    ff = rng.uniform(-1.0, 1.0, size=(nz, ny, nx)) if f == "uniform" else np.zeros((nz, ny, nx))
+    u = np.zeros((nz + 2, ny + 2, nx + 2))
+    if u0 == "uniform":
+        u[1:-1, 1:-1, 1:-1] = rng.uniform(-1.0, 1.0, size=(nz, ny, nx))
+    if ghosts == "uniform":
+        gm = ghost_mask(nx, ny, nz)
+        u[gm] = rng.uniform(-1.0, 1.0, size=int(gm.sum()))
+    return Patch(u0=u, f=np.ascontiguousarray(ff), eps=tuple(float(e) for e in eps), h=float(h))
+
+
+# --- the five workloads -------------------------------------------------------
+
+def c1_patch() -> Patch:
+    """32^3, eps (1,1,1), h 1/32, zero ghosts, f ~ U[-1,1], u0 = 0 (seed 1)."""
+    return make_patch(32, 32, 32, (1.0, 1.0, 1.0), 1.0 / 32, seed=1, f="uniform", u0="zero")
+
+
+def c2_patch(n: int = 256) -> Patch:
+    """256^3, eps (1,1,100), h 1/256, zero ghosts, f, u0 ~ U[-1,1] (seed 2)."""
+    return make_patch(n, n, n, (1.0, 1.0, 100.0), 1.0 / n, seed=2, f="uniform", u0="uniform")
+
+
+def c3_patch(n: int = 512) -> Patch:
+    """512^3, eps (1,100,100), h 1/512, zero ghosts, f, u0 ~ U[-1,1] (seed 3)."""
+    return make_patch(n, n, n, (1.0, 100.0, 100.0), 1.0 / n, seed=3, f="uniform", u0="uniform")
+
+
+def c5_patch(n: int = 128):
+    """128^3, eps init (1,1,10), h 1/128, zero ghosts, f ~ U[-1,1], u0 = 0 (seed 5),
+    and a smooth target: sum of 8 products of sines with integer frequencies in
+    {1..4} and amplitudes U[-1,1], sampled at cell centres (i+1/2)h."""
+    rng = rng_for(5)
+    f = rng.uniform(-1.0, 1.0, size=(n, n, n))
+    u0 = np.zeros((n + 2, n + 2, n + 2))
+    freqs = rng.integers(1, 5, size=(8, 3))
+    amps = rng.uniform(-1.0, 1.0, size=8)
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    tgt = np.zeros((n, n, n))
+    for m in range(8):
+        p, q, s = (int(v) for v in freqs[m])
+        tgt += amps[m] * (np.sin(np.pi * s * x)[:, None, None] * np.sin(np.pi * q * x)[None, :, None]
+                          * np.sin(np.pi * p * x)[None, None, :])
+    return Patch(u0=u0, f=f, eps=(1.0, 1.0, 10.0), h=h, extra={"target": tgt})
+
+
+@dataclass
+class PatchSet:
+    dims: np.ndarray     # (P,3) int32: nx, ny, nz
+    eps: np.ndarray      # (P,3) float64
+    h: np.ndarray        # (P,) float64
+    u0: list             # P padded arrays
+    f: list              # P unpadded arrays
+
+    @property
+    def npatch(self):
+        return int(self.dims.shape[0])
+
+    def cells(self) -> int:
+        return int(np.prod(self.dims.astype(np.int64), axis=1).sum())
+
+
+def c4_patchset(npatch: int = 3000, seed: int = 4, edges=EDGE_CHOICES) -> PatchSet:
+    """Uneven patches: edges from `edges` per axis, eps = 10^U[0,2] per axis,
+    h = 1/max(n), u, f and ghosts ~ U[-1,1]."""
+    rng = rng_for(seed)
+    dims = rng.choice(np.asarray(edges, dtype=np.int64), size=(npatch, 3)).astype(np.int32)
+    eps = 10.0 ** rng.uniform(0.0, 2.0, size=(npatch, 3))
+    h = 1.0 / dims.max(axis=1).astype(np.float64)
+    us, fs = [], []
+    for p in range(npatch):
+        nx, ny, nz = (int(v) for v in dims[p])
+        f = rng.uniform(-1.0, 1.0, size=(nz, ny, nx))
+        u = np.empty((nz + 2, ny + 2, nx + 2))
+        u[1:-1, 1:-1, 1:-1] = rng.uniform(-1.0, 1.0, size=(nz, ny, nx))
+        gm = ghost_mask(nx, ny, nz)
+        u[gm] = rng.uniform(-1.0, 1.0, size=int(gm.sum()))
+        us.append(u)
+        fs.append(f)
+    return PatchSet(dims=dims, eps=eps, h=h, u0=us, f=fs)
+
+
+def small_patch(nx, ny, nz, seed, eps=None, ghosts="uniform", u0="uniform", f="uniform") -> Patch:
+    """A small random test patch; eps defaults to distinct per-axis weights."""
+    if eps is None:
+        eps = (1.0, 3.0, 7.0)
+    return make_patch(nx, ny, nz, eps, 1.0 / max(nx, ny, nz), seed, f=f, u0=u0, ghosts=ghosts)
