@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the line-block smoother on one MI355X.
+
+Workload (one step): a 256^3 patch, eps = (1,1,100), h = 1/256, zero ghosts,
+f, u0 ~ U[-1,1] (seed 2); 100 z-line block Jacobi sweeps (omega 0.8) and 100
+chaotic z-line block Gauss-Seidel sweeps (omega 1), with the residual norm
+taken every 10 sweeps.  value = interior cells x sweeps / wall time (GLUP/s).
+
+Also reported: the roofline of the dominant kernel (a z-line sweep; bytes per
+launch = 24 B/cell algorithmic: read u, read f, write u) from HIP events on
+the launch stream, and the oracle timed on the host cores on a bounded sample.
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per sweep (GLUP/s) + % HBM roofline; mixed/batched vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+N = 256
+EPS = (1.0, 1.0, 100.0)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="for rocprofv3 counter runs: a 1 GiB device copy (reference for FETCH_SIZE / "
+                         "WRITE_SIZE scaling), then 10 z-line Jacobi and 10 chaotic GS sweep launches; no JSON")
+    return ap.parse_args()
+
+
+def profile_run():
+    """Fixed kernel sequence for counter collection: copy of known size, then sweeps."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import c2_patch
+
+    torch.cuda.set_device(0)
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    patch = c2_patch(N)
+    ps = bs.PatchSet([patch.dims], [patch.eps], [patch.h])
+    u = ps.pack_u([patch.u0])
+    f = ps.pack_f([patch.f])
+    work = ps.empty_u()
+    uc = u.clone()
+    torch.cuda.synchronize()
+    ps.line_relax(2, "jacobi", 0.8, 10, u, f, work)
+    ps.line_relax(2, "chaotic", 1.0, 10, uc, f)
+    n2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ps.residual(u, f, None, n2)
+    torch.cuda.synchronize()
+    print("profile run done", flush=True)
+
+
+def timed_sweeps(fn, nsweeps_list, reps=5):
+    """Median event time of fn(n) for each n (ms); events on the launch stream."""
+    import torch
+    out = {}
+    for n in nsweeps_list:
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn(n)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        ts.sort()
+        out[n] = ts[len(ts) // 2]
+    return out
+
+
+def cpu_baseline(patch, target_s):
+    import oracle
+    oracle.set_threads(0)
+    threads = oracle.get_threads()
+    cells = patch.f.size
+    # probe one sweep of each scheme, then size the sample to about target_s seconds
+    t0 = time.perf_counter()
+    u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.JACOBI, 0.8, 1)
+    tj = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.LEX_GS, 1.0, 1, lex_form=1)
+    tg = time.perf_counter() - t0
+    per_pair = tj + tg
+    k = max(1, int(target_s / per_pair))
+    t0 = time.perf_counter()
+    u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.JACOBI, 0.8, k)
+    u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.LEX_GS, 1.0, k, lex_form=1)
+    dt = time.perf_counter() - t0
+    del u
+    return {"value": round(cells * 2 * k / dt / 1e9, 5), "unit": "GLUP/s", "cores": threads, "kind": "oracle",
+            "sample": "%d^3 z-lines, eps (1,1,100): %d Jacobi + %d lexicographic GS sweeps (anti-diagonal form) "
+                      "on the full grid, %.1f s" % (N, k, k, dt)}
+
+
+def main():
+    args = parse()
+    if args.profile:
+        profile_run()
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only; --gpus %d is not supported by this build" % args.gpus)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import c2_patch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU")
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    patch = c2_patch(N)
+    ps = bs.PatchSet([patch.dims], [patch.eps], [patch.h])
+    u0 = ps.pack_u([patch.u0])
+    f = ps.pack_f([patch.f])
+    uj = u0.clone()
+    uc = u0.clone()
+    work = ps.empty_u()
+    norms = torch.zeros(20, dtype=torch.float64, device="cuda")
+    cells = N ** 3
+    sweeps_per_step = 200
+
+    def step():
+        for blk in range(10):
+            ps.line_relax(2, "jacobi", 0.8, 10, uj, f, work)
+            ps.residual(uj, f, None, norms[blk:blk + 1])
+        for blk in range(10):
+            ps.line_relax(2, "chaotic", 1.0, 10, uc, f)
+            ps.residual(uc, f, None, norms[10 + blk:11 + blk])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    value = cells * sweeps_per_step * args.steps / dt / 1e9
+
+    # per-launch kernel time from the difference of two sweep counts (removes fixed costs)
+    tj = timed_sweeps(lambda n: ps.line_relax(2, "jacobi", 0.8, n, uj, f, work), (10, 40))
+    tc = timed_sweeps(lambda n: ps.line_relax(2, "chaotic", 1.0, n, uc, f), (10, 40))
+    jac_us = (tj[40] - tj[10]) / 30 * 1e3
+    cha_us = (tc[40] - tc[10]) / 30 * 1e3
+    bytes_per_launch = 24.0 * cells
+    dom_name, dom_us = ("z-line Jacobi sweep", jac_us) if jac_us >= cha_us else ("z-line chaotic GS sweep", cha_us)
+    achieved = bytes_per_launch / (dom_us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": dom_name, "us_per_launch": round(dom_us, 2),
+            "bytes_per_launch": bytes_per_launch,
+            "other": {"jacobi_us": round(jac_us, 2), "chaotic_us": round(cha_us, 2),
+                      "jacobi_frac": round(bytes_per_launch / (jac_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                      "chaotic_frac": round(bytes_per_launch / (cha_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
+    rn = norms.cpu().numpy()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(patch, args.cpu_seconds)
+
+    line = {"metric": METRIC, "value": round(value, 3), "unit": "GLUP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "256^3 patch, eps (1,1,100): 100 z-line block Jacobi sweeps (omega 0.8) + "
+                                   "100 chaotic z-line block GS sweeps (omega 1), residual norm every 10 sweeps",
+                       "cells": cells, "sweeps_per_step": sweeps_per_step, "parallelism": "single GPU"},
+            "roofline": roof, "cpu_baseline": cpu,
+            "residual_last": {"jacobi": float(math.sqrt(rn[9])), "chaotic": float(math.sqrt(rn[19]))}}
+    print(json.dumps(line), flush=True)
+    ps.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * bs.h -- C ABI of the block-smoothing library (libblocksmooth.so): line- and
+ * plane-block relaxation of the constant-coefficient 7-point stencil on
+ * structured patches, for AMD MI355X (gfx950).
+ *
+ * Method: Birke, Philip, Wang, Berrill, "Block-Relaxation Methods for 3D
+ * Constant-Coefficient Stencils on GPUs and Multicore CPUs".
+ *   - operator: eq. (stencil3d7), generalised to one weight per axis:
+ *       (A u)_c = sum_a eps_a (2u_c - u_{c-e_a} - u_{c+e_a}) = h^2 f_c;
+ *   - iteration: eq. (blockiteration2), u <- u + omega M^{-1} r, r = h^2 f - A u,
+ *     with M the block diagonal (Jacobi) or the block triangle in the visiting
+ *     order (block Gauss-Seidel, eq. sm:blockm);
+ *   - schemes: damped block Jacobi and chaotic block Gauss-Seidel (section 2,
+ *     Algorithm 1), plus a deterministic two-colour block Gauss-Seidel;
+ *   - blocks: whole x/y/z lines (tridiagonal, solved exactly) and whole planes
+ *     (solved exactly by fast diagonalisation); the paper's partition admits
+ *     any block split of A (section 2, discussion of eq. sm:blocka).
+ *
+ * Storage (section 2.1, index spaces): a patch of nx*ny*nz cells stores u WITH
+ * one ghost layer -- (nz+2)(ny+2)(nx+2) doubles, x fastest, interior cell
+ * (i,j,k) at ((k+1)(ny+2)+(j+1))(nx+2)+(i+1) -- and f WITHOUT ghosts --
+ * nz*ny*nx doubles, cell (i,j,k) at (k*ny+j)*nx+i.  A patch set concatenates
+ * its patches; element offsets come from bs_layout (the library may leave
+ * alignment gaps between patches; gap contents are never read or written).
+ *
+ * Ghosts are inputs that the caller owns and updates between calls (section
+ * 2: ghost cells are refreshed after a full smoothing step); every call leaves
+ * u's ghost cells bit-unchanged.  Edge and corner ghosts are never read.
+ *
+ * Pointers named *_host are host memory; every other buffer pointer is device
+ * memory on the device that was current at bs_create_patchset.  The caller
+ * owns u, f, work, r and gradient buffers; the library owns the patch set and
+ * everything it allocates (factor tables, sine bases, work lists, graphs).
+ *
+ * Asynchrony: every call taking a hipStream_t enqueues work on that stream and
+ * returns without synchronising.  bs_create_patchset, bs_set_eps and
+ * bs_destroy_patchset are synchronous.  Calls on one patch set must not run
+ * concurrently from several host threads.
+ *
+ * Errors: arguments are validated before anything is enqueued; on a non-OK
+ * status nothing has been launched, except BS_ERR_HIP, which reports a failed
+ * HIP call (its message is in bs_last_error()).  No C++ exception crosses
+ * this interface.
+ */
+#ifndef BS_H
+#define BS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bs_patchset bs_patchset;   /* opaque, library-owned */
+
+typedef enum {
+    BS_OK = 0,
+    BS_ERR_INVALID = 1,      /* bad argument: null pointer, range, size */
+    BS_ERR_UNSUPPORTED = 2,  /* valid but not provided (see each call) */
+    BS_ERR_OOM = 3,          /* device or host allocation failed */
+    BS_ERR_HIP = 4           /* a HIP runtime call failed */
+} bs_status;
+
+typedef enum {
+    BS_JACOBI = 0,       /* every block from the old u, result via a second vector */
+    BS_CHAOTIC_GS = 1,   /* every block updated once, in place, no ordering between
+                            blocks (Algorithm 1); blocks are dispatched colour-major
+                            in one launch; results are not bit-reproducible */
+    BS_COLORED_GS = 2    /* two-colour block GS: colour = (sum of a line's two free
+                            indices) mod 2, or plane index mod 2; colour 0 first;
+                            deterministic */
+} bs_scheme;
+
+typedef enum {
+    BS_FP64 = 0,         /* everything in FP64 */
+    BS_MIXED_FP32 = 1,   /* FP64 residual and update, FP32 block solve */
+    BS_MIXED_BF16 = 2    /* FP64 residual and update, BF16 transforms with FP32
+                            accumulation (planes only) */
+} bs_precision;
+
+/* Layout of a patch set, computed on the host with no device work.
+ * dims_host: [3*npatch] = nx,ny,nz per patch (each >= 1).
+ * Outputs: total doubles of u (padded) and f (unpadded); optional per-patch
+ * element offsets ([npatch] each, may be NULL).  Patches start on 256-byte
+ * boundaries.  BS_ERR_INVALID on npatch < 1, a null dims/numel pointer, or
+ * dims < 1. */
+bs_status bs_layout_plan(int32_t npatch, const int32_t *dims_host, int64_t *u_numel,
+                         int64_t *f_numel, int64_t *u_off_host, int64_t *f_off_host);
+
+/* Create a patch set: per patch dims (nx,ny,nz), axis weights eps (eps_x,
+ * eps_y, eps_z > 0) and cell width h > 0.  Builds every precomputed table on
+ * the current device (section 2: the block inverse is formed once before the
+ * smoothing iterations): the LU factors and interface-coupling tables of the
+ * exact line solves, and the sine eigenbases and eigenvalues of the exact
+ * plane solves.  Synchronous.  BS_ERR_INVALID on bad sizes or non-positive
+ * eps/h; BS_ERR_OOM / BS_ERR_HIP on allocation or copy failures. */
+bs_status bs_create_patchset(int32_t npatch, const int32_t *dims_host, const double *eps_host,
+                             const double *h_host, bs_patchset **out);
+
+/* Free a patch set and everything it owns.  Waits for the device.  NULL ok. */
+void bs_destroy_patchset(bs_patchset *ps);
+
+/* Replace every patch's eps ([3*npatch], > 0) and rebuild the tables that
+ * depend on it.  Synchronous. */
+bs_status bs_set_eps(bs_patchset *ps, const double *eps_host);
+
+/* Layout of an existing patch set (same meaning as bs_layout_plan). */
+bs_status bs_layout(const bs_patchset *ps, int64_t *u_numel, int64_t *f_numel,
+                    int64_t *u_off_host, int64_t *f_off_host);
+
+/* Residual r = h^2 f - A u over interior cells (eq. stencil3d7 with axis
+ * weights; section 3 monitors its 2-norm).  r: f-layout output, or NULL for
+ * norms only.  rnorm2: [npatch] device doubles receiving sum(r^2) per patch,
+ * or NULL.  The sums are reduced in a fixed order, so they are bit-identical
+ * from run to run.  At least one of r, rnorm2 must be non-NULL. */
+bs_status bs_residual(const bs_patchset *ps, const double *u, const double *f, double *r,
+                      double *rnorm2, hipStream_t stream);
+
+/* nsweeps sweeps of line-block relaxation along `axis` (0=x, 1=y, 2=z) on every
+ * patch of the set: each line's residual is formed from the current u
+ * (off-line neighbours and ghosts included), the line's tridiagonal block
+ * tridiag(-eps_a, 2(eps_x+eps_y+eps_z), -eps_a) is solved exactly, and the
+ * line is updated by omega times the correction (Algorithm 1; Algorithm 2's
+ * residual / block solve / update structure).
+ *   u     in/out, u-layout; on return it holds the result (also for Jacobi
+ *         with an odd sweep count).
+ *   f     f-layout.
+ *   work  u-layout scratch for BS_JACOBI (the paper's second vector v); may
+ *         be NULL for the Gauss-Seidel schemes.  Its ghosts are overwritten.
+ *   omega in (0, 2).  nsweeps >= 0 (0 enqueues nothing).
+ * BS_ERR_UNSUPPORTED for BS_MIXED_BF16 (BF16 is offered for planes only). */
+bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double omega,
+                        int32_t nsweeps, bs_precision prec, double *u, const double *f,
+                        double *work, hipStream_t stream);
+
+/* nsweeps sweeps of plane-block relaxation with planes normal to normal_axis.
+ * Each plane block M_P = d I - eps_a(S_a + S_a^T) - eps_b(S_b + S_b^T) is
+ * solved exactly by fast diagonalisation with the orthonormal DST-I bases of
+ * the two in-plane axes.  refine >= 0 inner defect-correction steps are
+ * applied to the block solve for the mixed precisions (ignored for FP64).
+ * Other arguments as bs_line_relax.  BS_ERR_UNSUPPORTED if an in-plane edge
+ * exceeds 1024. */
+bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme, double omega,
+                         int32_t nsweeps, bs_precision prec, int32_t refine, double *u,
+                         const double *f, double *work, hipStream_t stream);
+
+/* Device workspace needed by bs_relax_backward for these arguments, or 0 on
+ * invalid arguments. */
+size_t bs_backward_workspace_bytes(const bs_patchset *ps, int32_t axis, int32_t nsweeps,
+                                   int32_t ckpt_every);
+
+/* Adjoint of nsweeps damped Jacobi line sweeps along `axis` (FP64), for a
+ * loss L with dL/du_K = grad_uK (u-layout; ghost entries ignored).  States
+ * are recomputed from checkpoints taken every ckpt_every sweeps.  Outputs
+ * (each may be NULL):
+ *   grad_u0  u-layout: interior entries dL/du0; face-ghost entries dL/dghost
+ *            (edges and corners 0);
+ *   grad_f   f-layout: dL/df;
+ *   grad_eps [3*npatch] device doubles: dL/d(eps_x, eps_y, eps_z) per patch.
+ * workspace: device memory of at least bs_backward_workspace_bytes bytes.
+ * BS_ERR_UNSUPPORTED for a scheme other than Jacobi (only Jacobi has a
+ * backward here). */
+bs_status bs_relax_backward(bs_patchset *ps, int32_t axis, double omega, int32_t nsweeps,
+                            int32_t ckpt_every, const double *u0, const double *f,
+                            const double *grad_uK, double *grad_u0, double *grad_f,
+                            double *grad_eps, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream);
+
+/* Message for the last non-OK status returned on this host thread ("" if none). */
+const char *bs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BS_H */

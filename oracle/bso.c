@@ -264,21 +264,22 @@ int bso_line_sweeps(int nx, int ny, int nz, const double eps[3], double h, int a
                         line_update(&g, axis, p, q, u, u, f, omega, buf);
                 free(buf);
             } else {
-                for (int dg = 0; dg <= (np - 1) + (nq - 1); ++dg) {
-                    int qlo = dg - (np - 1) > 0 ? dg - (np - 1) : 0;
-                    int qhi = dg < nq - 1 ? dg : nq - 1;
 #ifdef _OPENMP
 #pragma omp parallel num_threads(NT)
 #endif
-                    {
-                        double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+                {
+                    double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+                    for (int dg = 0; dg <= (np - 1) + (nq - 1); ++dg) {
+                        int qlo = dg - (np - 1) > 0 ? dg - (np - 1) : 0;
+                        int qhi = dg < nq - 1 ? dg : nq - 1;
+                        /* the loop's implicit barrier ends each anti-diagonal */
 #ifdef _OPENMP
 #pragma omp for schedule(static)
 #endif
                         for (int q = qlo; q <= qhi; ++q)
                             line_update(&g, axis, dg - q, q, u, u, f, omega, buf);
-                        free(buf);
                     }
+                    free(buf);
                 }
             }
         } else if (scheme == BSO_COLORED_GS) {

@@ -1,0 +1,266 @@
+"""Python binding of libblocksmooth.so (line- and plane-block relaxation of the
+constant-coefficient 7-point stencil on MI355X).
+
+Argument marshalling only: every step of every sweep runs in the library's
+HIP kernels.  PyTorch supplies device memory (float64 CUDA tensors) and the
+current stream.  The functions carry the C names (``bs_line_relax`` ...) and
+raise ``BSError`` on a non-OK status.  If the library has not been built the
+first call raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must be loaded first: the library binds to torch's HIP runtime)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libblocksmooth.so")
+
+BS_OK, BS_ERR_INVALID, BS_ERR_UNSUPPORTED, BS_ERR_OOM, BS_ERR_HIP = range(5)
+BS_JACOBI, BS_CHAOTIC_GS, BS_COLORED_GS = range(3)
+BS_FP64, BS_MIXED_FP32, BS_MIXED_BF16 = range(3)
+
+SCHEMES = {"jacobi": BS_JACOBI, "chaotic": BS_CHAOTIC_GS, "chaotic_gs": BS_CHAOTIC_GS,
+           "colored": BS_COLORED_GS, "colored_gs": BS_COLORED_GS}
+PRECISIONS = {"fp64": BS_FP64, "fp32": BS_MIXED_FP32, "bf16": BS_MIXED_BF16}
+
+_STATUS = {1: "BS_ERR_INVALID", 2: "BS_ERR_UNSUPPORTED", 3: "BS_ERR_OOM", 4: "BS_ERR_HIP"}
+
+# Every symbol the public header declares.
+EXPORTS = ("bs_layout_plan", "bs_create_patchset", "bs_destroy_patchset", "bs_set_eps", "bs_layout",
+           "bs_residual", "bs_line_relax", "bs_plane_relax", "bs_backward_workspace_bytes",
+           "bs_relax_backward", "bs_last_error")
+
+
+class BSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libblocksmooth.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, dbl, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+    P = ctypes.POINTER
+    L.bs_layout_plan.argtypes = [i32, vp, P(i64), P(i64), vp, vp]
+    L.bs_create_patchset.argtypes = [i32, vp, vp, vp, P(vp)]
+    L.bs_destroy_patchset.argtypes = [vp]
+    L.bs_destroy_patchset.restype = None
+    L.bs_set_eps.argtypes = [vp, vp]
+    L.bs_layout.argtypes = [vp, P(i64), P(i64), vp, vp]
+    L.bs_residual.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.bs_line_relax.argtypes = [vp, i32, ctypes.c_int, dbl, i32, ctypes.c_int, vp, vp, vp, vp]
+    L.bs_plane_relax.argtypes = [vp, i32, ctypes.c_int, dbl, i32, ctypes.c_int, i32, vp, vp, vp, vp]
+    L.bs_backward_workspace_bytes.argtypes = [vp, i32, i32, i32]
+    L.bs_backward_workspace_bytes.restype = sz
+    L.bs_relax_backward.argtypes = [vp, i32, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.bs_last_error.argtypes = []
+    L.bs_last_error.restype = ctypes.c_char_p
+    for name in ("bs_layout_plan", "bs_create_patchset", "bs_set_eps", "bs_layout", "bs_residual",
+                 "bs_line_relax", "bs_plane_relax", "bs_relax_backward"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != BS_OK:
+        raise BSError(st, lib().bs_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError("buffers must be device (cuda) tensors")
+    if not t.is_contiguous():
+        raise ValueError("buffers must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(t, numel, name):
+    if t is None:
+        return None
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64" % name)
+    if t.numel() < numel:
+        raise ValueError("%s has %d elements, needs %d" % (name, t.numel(), numel))
+    return _ptr(t)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _host_array(ctype, values):
+    values = list(values)
+    return (ctype * len(values))(*values)
+
+
+def _scheme(s):
+    return SCHEMES[s] if isinstance(s, str) else int(s)
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+# --- the C names -------------------------------------------------------------
+
+def bs_layout_plan(dims):
+    """(u_numel, f_numel, u_offsets, f_offsets) for patches dims = [(nx,ny,nz), ...]."""
+    n = len(dims)
+    d = _host_array(ctypes.c_int32, [int(v) for t in dims for v in t])
+    un, fn = ctypes.c_int64(), ctypes.c_int64()
+    uo = (ctypes.c_int64 * max(n, 1))()
+    fo = (ctypes.c_int64 * max(n, 1))()
+    _check(lib().bs_layout_plan(n, d, ctypes.byref(un), ctypes.byref(fn), uo, fo))
+    return un.value, fn.value, list(uo)[:n], list(fo)[:n]
+
+
+def bs_create_patchset(dims, eps, h):
+    """Opaque handle for patches dims [(nx,ny,nz)], eps [(ex,ey,ez)], h [h]."""
+    n = len(dims)
+    d = _host_array(ctypes.c_int32, [int(v) for t in dims for v in t])
+    e = _host_array(ctypes.c_double, [float(v) for t in eps for v in t])
+    hh = _host_array(ctypes.c_double, [float(v) for v in h])
+    out = ctypes.c_void_p()
+    _check(lib().bs_create_patchset(n, d, e, hh, ctypes.byref(out)))
+    return out
+
+
+def bs_destroy_patchset(ps):
+    lib().bs_destroy_patchset(ps)
+
+
+def bs_set_eps(ps, eps):
+    e = _host_array(ctypes.c_double, [float(v) for t in eps for v in t])
+    _check(lib().bs_set_eps(ps, e))
+
+
+def bs_layout(ps, npatch):
+    un, fn = ctypes.c_int64(), ctypes.c_int64()
+    uo = (ctypes.c_int64 * npatch)()
+    fo = (ctypes.c_int64 * npatch)()
+    _check(lib().bs_layout(ps, ctypes.byref(un), ctypes.byref(fn), uo, fo))
+    return un.value, fn.value, list(uo), list(fo)
+
+
+def bs_residual(ps, u, f, r=None, rnorm2=None, stream=None):
+    _check(lib().bs_residual(ps, _ptr(u), _ptr(f), _ptr(r), _ptr(rnorm2), _stream(stream)))
+
+
+def bs_line_relax(ps, axis, scheme, omega, nsweeps, prec, u, f, work=None, stream=None):
+    _check(lib().bs_line_relax(ps, int(axis), _scheme(scheme), float(omega), int(nsweeps), _prec(prec),
+                               _ptr(u), _ptr(f), _ptr(work), _stream(stream)))
+
+
+def bs_plane_relax(ps, normal_axis, scheme, omega, nsweeps, prec, refine, u, f, work=None, stream=None):
+    _check(lib().bs_plane_relax(ps, int(normal_axis), _scheme(scheme), float(omega), int(nsweeps),
+                                _prec(prec), int(refine), _ptr(u), _ptr(f), _ptr(work), _stream(stream)))
+
+
+def bs_backward_workspace_bytes(ps, axis, nsweeps, ckpt_every):
+    return int(lib().bs_backward_workspace_bytes(ps, int(axis), int(nsweeps), int(ckpt_every)))
+
+
+def bs_relax_backward(ps, axis, omega, nsweeps, ckpt_every, u0, f, grad_uK, grad_u0=None, grad_f=None,
+                      grad_eps=None, workspace=None, stream=None):
+    wb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().bs_relax_backward(ps, int(axis), float(omega), int(nsweeps), int(ckpt_every), _ptr(u0),
+                                   _ptr(f), _ptr(grad_uK), _ptr(grad_u0), _ptr(grad_f), _ptr(grad_eps),
+                                   _ptr(workspace), wb, _stream(stream)))
+
+
+def bs_last_error():
+    return lib().bs_last_error().decode(errors="replace")
+
+
+# --- a small owner of a patch set and its device buffers ---------------------
+
+class PatchSet:
+    """Owns a patch set handle; packs / unpacks per-patch arrays into the
+    library's concatenated layout (u padded, f unpadded)."""
+
+    def __init__(self, dims, eps, h, device="cuda"):
+        self.dims = [tuple(int(v) for v in t) for t in dims]
+        self.eps = [tuple(float(v) for v in t) for t in eps]
+        self.h = [float(v) for v in h]
+        self.device = torch.device(device)
+        self.handle = bs_create_patchset(self.dims, self.eps, self.h)
+        self.u_numel, self.f_numel, self.u_off, self.f_off = bs_layout(self.handle, len(self.dims))
+
+    @property
+    def npatch(self):
+        return len(self.dims)
+
+    def close(self):
+        if self.handle is not None:
+            bs_destroy_patchset(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_eps(self, eps):
+        self.eps = [tuple(float(v) for v in t) for t in eps]
+        bs_set_eps(self.handle, self.eps)
+
+    def empty_u(self):
+        return torch.zeros(self.u_numel, dtype=torch.float64, device=self.device)
+
+    def empty_f(self):
+        return torch.zeros(self.f_numel, dtype=torch.float64, device=self.device)
+
+    def pack_u(self, arrays, out=None):
+        out = self.empty_u() if out is None else out
+        for p, a in enumerate(arrays):
+            nx, ny, nz = self.dims[p]
+            n = (nx + 2) * (ny + 2) * (nz + 2)
+            out[self.u_off[p]:self.u_off[p] + n].copy_(torch.as_tensor(a).reshape(-1))
+        return out
+
+    def pack_f(self, arrays, out=None):
+        out = self.empty_f() if out is None else out
+        for p, a in enumerate(arrays):
+            nx, ny, nz = self.dims[p]
+            n = nx * ny * nz
+            out[self.f_off[p]:self.f_off[p] + n].copy_(torch.as_tensor(a).reshape(-1))
+        return out
+
+    def view_u(self, t, p):
+        nx, ny, nz = self.dims[p]
+        n = (nx + 2) * (ny + 2) * (nz + 2)
+        return t[self.u_off[p]:self.u_off[p] + n].view(nz + 2, ny + 2, nx + 2)
+
+    def view_f(self, t, p):
+        nx, ny, nz = self.dims[p]
+        return t[self.f_off[p]:self.f_off[p] + nx * ny * nz].view(nz, ny, nx)
+
+    # thin method forms of the C calls
+    def residual(self, u, f, r=None, rnorm2=None, stream=None):
+        bs_residual(self.handle, u, f, r, rnorm2, stream)
+
+    def line_relax(self, axis, scheme, omega, nsweeps, u, f, work=None, prec="fp64", stream=None):
+        bs_line_relax(self.handle, axis, scheme, omega, nsweeps, prec, u, f, work, stream)
+
+    def plane_relax(self, normal_axis, scheme, omega, nsweeps, u, f, work=None, prec="fp64", refine=0,
+                    stream=None):
+        bs_plane_relax(self.handle, normal_axis, scheme, omega, nsweeps, prec, refine, u, f, work, stream)

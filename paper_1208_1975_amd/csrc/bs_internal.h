@@ -1,0 +1,93 @@
+// Internal definitions shared by the library's host code and HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bs {
+
+// Chunk counts a line may be split into (one wavefront per chunk).  A line of
+// n cells split for P_req chunks uses chunks of Lr = ceil(n / P_req) cells,
+// P = ceil(n / Lr) <= P_req chunks, the last one Llast = n - (P-1) Lr long.
+constexpr int kNumPOpt = 5;
+constexpr int kPOpts[kNumPOpt] = {1, 2, 4, 8, 16};
+constexpr int kMaxChunkLen = 64;   // largest Lr a kernel instantiation holds in registers
+
+struct LineTabRef {
+    int64_t off;   // offset in doubles into the table buffer, -1 if not built
+    int32_t Lr, P, Llast, pad;
+};
+
+// Line table layout (doubles), chunk length Lr, P chunks:
+//   g[Lr]   forward-elimination multipliers  eps_a / m_{t-1}   (g[0] = 0)
+//   q[Lr]   reciprocal pivots                1 / m_t
+//   evF[Lr], ewF[Lr]  eps_a * T^{-1} e_0 and eps_a * T^{-1} e_{Lr-1}, full chunks
+//   evT[Lr], ewT[Lr]  the same for the last chunk (length Llast), zero padded
+//   Kb[P][2P]  row of the inverse interface system giving the previous
+//              chunk's last correction (zero row for chunk 0)
+//   Ka[P][2P]  row giving the next chunk's first correction (zero for the last)
+__host__ __device__ inline int line_table_size(int Lr, int P) { return 6 * Lr + 4 * P * P; }
+
+// Plane table (per patch, per normal axis): orthonormal DST-I bases of the two
+// in-plane axes (a < b) and the eigenvalue grid of the plane block.
+struct PlaneTabRef {
+    int64_t off;       // offset in doubles, -1 if not built
+    int32_t na, nb;    // in-plane sizes, na = lower axis
+};
+
+struct PatchDesc {
+    int32_t n[3];          // nx, ny, nz
+    int32_t pad0;
+    int64_t uoff, foff;    // element offsets of this patch in u and f
+    double eps[3];
+    double h2;
+    LineTabRef line[3][kNumPOpt];
+    PlaneTabRef plane[3];
+};
+
+// One unit of work for a launch: (patch, tile, colour).
+struct WorkItem {
+    int32_t patch, tile, colour, pad;
+};
+
+// Arguments of the line-relaxation kernels.
+struct LineArgs {
+    const double *src;      // u read (old iterate)
+    double *dst;            // written (== src for the Gauss-Seidel schemes)
+    const double *f;
+    const PatchDesc *pd;
+    const double *tab;
+    const WorkItem *items;
+    int32_t axis;
+    int32_t popt;           // index into kPOpts of the table set in use
+    int32_t tx;             // lanes per row along the fast free axis (strided kernel)
+    int32_t colour_mode;    // 0: every line; 1: only lines of the item's colour
+    double omega;
+};
+
+struct ResidArgs {
+    const double *u;
+    const double *f;
+    double *r;              // may be null
+    double *partial;        // per-block partial sums (may be null)
+    const PatchDesc *pd;
+    const int32_t *block_patch;   // block -> patch
+    const int32_t *block_first;   // block -> first cell (within its patch)
+};
+
+// Host launchers (defined in the .hip files).
+hipError_t launch_line_strided(const LineArgs &a, int nitems, int Lmax, int nwaves, size_t lds,
+                               hipStream_t s);
+hipError_t launch_line_x(const LineArgs &a, int nitems, int Lmax, int nwaves, size_t lds,
+                         hipStream_t s);
+hipError_t launch_residual(const ResidArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_residual_final(const double *partial, const int32_t *patch_first_block,
+                                 int npatch, double *out, hipStream_t s);
+hipError_t launch_ghost_copy(const double *src, double *dst, const PatchDesc *pd, int npatch,
+                             hipStream_t s);
+hipError_t launch_interior_copy(const double *src, double *dst, const PatchDesc *pd, int npatch,
+                                hipStream_t s);
+
+constexpr int kResidCellsPerBlock = 2048;   // cells per residual block (256 threads x 8)
+
+}  // namespace bs

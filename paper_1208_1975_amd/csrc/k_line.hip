@@ -1,0 +1,419 @@
+// Line-block relaxation kernels (FP64): one sweep of every line along an axis.
+//
+// Per line (section 2, Algorithm 1; Algorithm 2's three steps):
+//   1. block residual r = h^2 f - A u on the line's cells, from the current u
+//      (off-line neighbours and ghosts included);
+//   2. exact solve of the line block tridiag(-eps_a, d, -eps_a) du = r;
+//   3. update dst = src + omega du.
+//
+// The exact solve is split across wavefronts: the line is cut into P chunks of
+// Lr cells, each wavefront solves its chunk's tridiagonal block with
+// precomputed LU factors (registers only), and the chunks are coupled exactly
+// through the interface values: with y = T_chunk^{-1} r_chunk and the
+// precomputed spikes v = T^{-1} e_0, w = T^{-1} e_last,
+//   du_chunk = y + beta_prev * eps_a v + alpha_next * eps_a w,
+// where beta_prev / alpha_next (the neighbouring chunks' end corrections) come
+// from one row each of the precomputed inverse of the 2P x 2P interface
+// system.  This is an exact reformulation of the tridiagonal solve (partition
+// method), not an approximation.
+#include "bs_internal.h"
+
+namespace bs {
+
+__device__ __forceinline__ int uniform_wave()
+{
+    return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+}
+
+// Chunk solve in registers: r (length Lp <= L; entries t >= Lp are ignored)
+// -> y = T^{-1} r with the LU factors g (multipliers) and q (reciprocal
+// pivots), both Lr long, held in LDS.  Branch-free: entries past Lp are forced
+// to zero, which keeps the back substitution exact for t < Lp.
+template <int L>
+__device__ __forceinline__ void chunk_solve(double (&r)[L], int Lp, int Lr, const double *g, const double *q,
+                                            double ea, double &y0, double &yl)
+{
+    double zprev = 0.0;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const double z = fma(g[t < Lr ? t : Lr - 1], zprev, r[t]);
+        r[t] = (t < Lp) ? z : 0.0;
+        zprev = r[t];
+    }
+    double ynext = 0.0;
+    yl = 0.0;
+#pragma unroll
+    for (int t = L - 1; t >= 0; --t) {
+        const double y = fma(ea, ynext, r[t]) * q[t < Lr ? t : Lr - 1];
+        r[t] = y;
+        ynext = y;
+        yl = (t == Lp - 1) ? y : yl;
+    }
+    y0 = r[0];
+}
+
+// Neighbour of a lane's value along the wavefront (DPP wave shift by one lane):
+// dir < 0 gives lane l the value of lane l-1, dir > 0 that of lane l+1.
+template <int DIR>
+__device__ __forceinline__ double lane_shift(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    constexpr int ctrl = DIR < 0 ? 0x138 : 0x130;   // wave_shr:1 / wave_shl:1
+    const int lo2 = __builtin_amdgcn_update_dpp(0, lo, ctrl, 0xf, 0xf, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(0, hi, ctrl, 0xf, 0xf, false);
+    return __hiloint2double(hi2, lo2);
+}
+
+// Interface coupling: every chunk's wavefront reads the ends of all chunks of
+// its line from LDS and forms the two corrections it needs.
+__device__ __forceinline__ void interface_terms(const double *tab, const double *ends, int Lr, int P,
+                                                int p, int lane, double &bprev, double &anext)
+{
+    const double *Kb = tab + 6 * Lr + p * 2 * P;
+    const double *Ka = tab + 6 * Lr + 2 * P * P + p * 2 * P;
+    bprev = 0.0;
+    anext = 0.0;
+    for (int jj = 0; jj < 2 * P; ++jj) {
+        const double Y = ends[((jj >> 1) * 64 + lane) * 2 + (jj & 1)];
+        bprev = fma(Kb[jj], Y, bprev);
+        anext = fma(Ka[jj], Y, anext);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y- and z-lines.  Lanes run along x (coalesced), a tile is tx lanes along x
+// by 64/tx along the other free axis; wavefront p of the workgroup holds
+// chunk p of all 64 lines.  With colour_mode, a tile holds lines of one
+// colour only ((i + o) parity), which makes x stride 2.
+// ---------------------------------------------------------------------------
+template <int L, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a)
+{
+    extern __shared__ double smem[];
+    const WorkItem it = a.items[blockIdx.x];
+    const PatchDesc *pd = a.pd + it.patch;
+    const int axis = a.axis;          // 1 or 2
+    const int oaxis = 3 - axis;       // the other free axis
+    const int nx = pd->n[0], ny = pd->n[1];
+    const int no = pd->n[oaxis];
+    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2);
+    const int64_t Sa = axis == 2 ? sy : sx;
+    const int64_t So = axis == 2 ? sx : sy;
+    const int64_t Fa = axis == 2 ? (int64_t)nx * ny : (int64_t)nx;
+    const int64_t Fo = axis == 2 ? (int64_t)nx : (int64_t)nx * ny;
+    const double ex = pd->eps[0], ea = pd->eps[axis], eo = pd->eps[oaxis];
+    const double d = 2.0 * (pd->eps[0] + pd->eps[1] + pd->eps[2]);
+    const double h2 = pd->h2;
+    const LineTabRef tr = pd->line[axis][a.popt];
+    const int Lr = tr.Lr, P = tr.P, Llast = tr.Llast;
+    const int tsz = line_table_size(Lr, P);
+
+    double *tab = smem;
+    double *ends = smem + ((tsz + 1) & ~1);
+    for (int t = threadIdx.x; t < tsz; t += blockDim.x) tab[t] = a.tab[tr.off + t];
+
+    const int lane = threadIdx.x & 63;
+    const int p = uniform_wave();
+    const int tx = a.tx, tyo = 64 / tx;
+    const int li = lane % tx, lo = lane / tx;
+    int i, o;
+    if (a.colour_mode) {
+        const int half = (nx + 1) >> 1;
+        const int nti = (half + tx - 1) / tx;
+        o = (it.tile / nti) * tyo + lo;
+        i = 2 * ((it.tile % nti) * tx + li) + ((o + it.colour) & 1);
+    } else {
+        const int nti = (nx + tx - 1) / tx;
+        o = (it.tile / nti) * tyo + lo;
+        i = (it.tile % nti) * tx + li;
+    }
+    const bool valid = (i < nx) && (o < no) && (p < P);
+    // Inactive lanes and chunks read clamped, in-patch addresses so that every
+    // load can be issued without a branch; their results are never stored.
+    const int ic = i < nx ? i : nx - 1;
+    const int oc = o < no ? o : no - 1;
+    const int pc = p < P ? p : P - 1;
+    const int Lp = (pc == P - 1) ? Llast : Lr;
+    const int t0 = pc * Lr;
+    // x-neighbours come from the adjacent lanes unless the lane is at a row
+    // edge of the tile (or of the patch), or lanes are colour-strided.
+    const bool load_l = a.colour_mode || li == 0;
+    const bool load_r = a.colour_mode || li == tx - 1 || i >= nx - 1;
+
+    const double *s = a.src;
+    const int64_t cu = pd->uoff + (ic + 1) + (int64_t)(t0 + 1) * Sa + (int64_t)(oc + 1) * So;
+    const int64_t cf = pd->foff + ic + (int64_t)t0 * Fa + (int64_t)oc * Fo;
+    // Loads are issued in batches of B cells, each batch before any of its
+    // values is used (the scheduling barriers keep the compiler from sinking
+    // loads next to their uses), so a wavefront makes a few memory round trips
+    // per chunk instead of one per cell.
+    constexpr int B = L < 4 ? L : (L <= 16 ? 4 : 8);
+    double uc[L], r[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int tt = t < Lp ? t : Lp - 1;
+        uc[t] = s[cu + tt * Sa];
+    }
+    const double ulo = s[cu - Sa];
+    const double uhi = s[cu + (int64_t)Lp * Sa];
+#pragma unroll
+    for (int tb = 0; tb < L; tb += B) {
+        double fb[B], om[B], op[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int t = tb + k;
+            const int tt = t < Lp ? t : Lp - 1;
+            const int64_t c = cu + tt * Sa;
+            fb[k] = a.f[cf + tt * Fa];
+            om[k] = s[c - So];
+            op[k] = s[c + So];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < B; ++k) r[tb + k] = fma(h2, fb[k], eo * (om[k] + op[k]));
+    }
+    // x-neighbours that are not in an adjacent lane are read from memory
+    if (load_l || load_r) {
+#pragma unroll
+        for (int tb = 0; tb < L; tb += B) {
+            double xl[B], xr[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int t = tb + k;
+                const int64_t c = cu + (t < Lp ? t : Lp - 1) * Sa;
+                xl[k] = s[c - 1];      // both are in-patch (ghost at worst)
+                xr[k] = s[c + 1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                r[tb + k] = fma(ex, (load_l ? xl[k] : 0.0) + (load_r ? xr[k] : 0.0), r[tb + k]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const double left = lane_shift<-1>(uc[t]);
+        const double right = lane_shift<+1>(uc[t]);
+        const double um = (t == 0) ? ulo : uc[t > 0 ? t - 1 : 0];
+        double up = uhi;
+        if (t + 1 < L) up = (t + 1 < Lp) ? uc[t + 1 < L ? t + 1 : 0] : uhi;
+        const double xs = (load_l ? 0.0 : left) + (load_r ? 0.0 : right);
+        r[t] = fma(-d, uc[t], fma(ex, xs, fma(ea, um + up, r[t])));
+    }
+    double y0, yl;
+    __syncthreads();   // table in LDS
+    chunk_solve<L>(r, Lp, Lr, tab, tab + Lr, ea, y0, yl);
+    ends[(p * 64 + lane) * 2 + 0] = y0;
+    ends[(p * 64 + lane) * 2 + 1] = yl;
+    __syncthreads();   // all reads of this tile's lines precede any write
+    if (valid) {
+        double bprev, anext;
+        interface_terms(tab, ends, Lr, P, p, lane, bprev, anext);
+        const double *ev = tab + (p == P - 1 ? 4 * Lr : 2 * Lr);
+        const double *ew = ev + Lr;
+        const double om = a.omega;
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            if (t < Lp) {
+                const double du = fma(anext, ew[t], fma(bprev, ev[t], r[t]));
+                a.dst[cu + t * Sa] = fma(om, du, uc[t]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x-lines (contiguous).  A workgroup owns 64 rows (lines); the residual of the
+// tile is formed cooperatively with x-coalesced loads into LDS, each lane then
+// solves its row's chunk from LDS in registers, and the update is written back
+// coalesced.  With colour_mode the tile holds rows of one colour ((j+k) parity).
+// ---------------------------------------------------------------------------
+template <int L, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_line_x(LineArgs a)
+{
+    extern __shared__ double smem[];
+    const WorkItem it = a.items[blockIdx.x];
+    const PatchDesc *pd = a.pd + it.patch;
+    const int nx = pd->n[0], ny = pd->n[1], nz = pd->n[2];
+    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2);
+    const double ex = pd->eps[0], ey = pd->eps[1], ez = pd->eps[2];
+    const double d = 2.0 * (ex + ey + ez);
+    const double h2 = pd->h2;
+    const LineTabRef tr = pd->line[0][a.popt];
+    const int Lr = tr.Lr, P = tr.P, Llast = tr.Llast;
+    const int tsz = line_table_size(Lr, P);
+    const int sd = nx | 1;                 // odd row stride in LDS (bank spread)
+    const int nw = blockDim.x >> 6;
+
+    double *tab = smem;
+    double *ends = tab + ((tsz + 1) & ~1);
+    double *rb = ends + 2 * 64 * nw;
+    int64_t *rowu = reinterpret_cast<int64_t *>(rb + 64 * sd);   // per row: u offset of cell (0,j,k), -1 if outside
+    int64_t *rowf = rowu + 64;
+    for (int t = threadIdx.x; t < tsz; t += blockDim.x) tab[t] = a.tab[tr.off + t];
+    if (threadIdx.x < 64) {
+        const int rho = it.tile * 64 + (int)threadIdx.x;
+        int j, k;
+        if (a.colour_mode) {
+            const int M = (ny + 1) >> 1;
+            k = rho / M;
+            j = 2 * (rho % M) + ((k + it.colour) & 1);
+        } else {
+            k = rho / ny;
+            j = rho % ny;
+        }
+        const bool in = j < ny && k < nz;
+        rowu[threadIdx.x] = in ? pd->uoff + (int64_t)(k + 1) * sy + (int64_t)(j + 1) * sx + 1 : -1;
+        rowf[threadIdx.x] = in ? pd->foff + ((int64_t)k * ny + j) * nx : -1;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int w = uniform_wave();
+    const double *s = a.src;
+    const int ncell = 64 * nx;
+
+    // phase 1: residuals of the tile into LDS (x-coalesced); four cells per
+    // thread per round, rows outside the patch read a clamped in-patch row
+    const int64_t safe_u = pd->uoff + sy + sx + 1;
+    const int64_t safe_f = pd->foff;
+    for (int i0 = threadIdx.x; i0 < ncell; i0 += 4 * (int)blockDim.x) {
+        double res[4];
+        int at[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int idx = i0 + m * (int)blockDim.x;
+            const int idc = idx < ncell ? idx : ncell - 1;
+            const int row = idc / nx, i = idc - row * nx;
+            const int64_t bu = rowu[row];
+            at[m] = (idx < ncell && bu >= 0) ? row * sd + i : -1;
+            const int64_t c = (bu >= 0 ? bu : safe_u) + i;
+            const int64_t fc = (bu >= 0 ? rowf[row] : safe_f) + i;
+            const double nb = ex * (s[c - 1] + s[c + 1]) + ey * (s[c - sx] + s[c + sx]) + ez * (s[c - sy] + s[c + sy]);
+            res[m] = fma(-d, s[c], fma(h2, a.f[fc], nb));
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (at[m] >= 0) rb[at[m]] = res[m];
+    }
+    __syncthreads();
+
+    // phase 2: lane = row, wavefront = chunk
+    const int p = w;
+    const bool valid = (rowu[lane] >= 0) && (p < P);
+    const int Lp = (p == P - 1) ? Llast : Lr;
+    const int t0 = p * Lr;
+    double r[L];
+    double y0 = 0.0, yl = 0.0;
+    if (valid) {
+#pragma unroll
+        for (int t = 0; t < L; ++t)
+            if (t < Lp) r[t] = rb[lane * sd + t0 + t];
+        chunk_solve<L>(r, Lp, Lr, tab, tab + Lr, ex, y0, yl);
+    }
+    ends[(p * 64 + lane) * 2 + 0] = y0;
+    ends[(p * 64 + lane) * 2 + 1] = yl;
+    __syncthreads();
+    if (valid) {
+        double bprev, anext;
+        interface_terms(tab, ends, Lr, P, p, lane, bprev, anext);
+        const double *ev = tab + (p == P - 1 ? 4 * Lr : 2 * Lr);
+        const double *ew = ev + Lr;
+#pragma unroll
+        for (int t = 0; t < L; ++t)
+            if (t < Lp) rb[lane * sd + t0 + t] = fma(anext, ew[t], fma(bprev, ev[t], r[t]));
+    }
+    __syncthreads();
+
+    // phase 3: coalesced update (all reads of the tile happened before the barriers)
+    const double om = a.omega;
+    for (int i0 = threadIdx.x; i0 < ncell; i0 += 4 * (int)blockDim.x) {
+        double val[4];
+        int64_t dst[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int idx = i0 + m * (int)blockDim.x;
+            const int idc = idx < ncell ? idx : ncell - 1;
+            const int row = idc / nx, i = idc - row * nx;
+            const int64_t bu = rowu[row];
+            dst[m] = (idx < ncell && bu >= 0) ? bu + i : -1;
+            val[m] = fma(om, rb[row * sd + i], s[(bu >= 0 ? bu : safe_u) + i]);
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (dst[m] >= 0) a.dst[dst[m]] = val[m];
+    }
+}
+
+// Opt a kernel into more than the default 64 KiB of dynamic LDS (once).
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t lds, bool &done)
+{
+    if (lds <= 65536 || done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
+template <int L, int MAXT>
+static hipError_t launch_strided_t(const LineArgs &a, int nitems, int nwaves, size_t lds, hipStream_t s)
+{
+    static bool big_lds = false;
+    hipError_t e = allow_lds(k_line_strided<L, MAXT>, lds, big_lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_line_strided<L, MAXT>), dim3(nitems), dim3(64 * nwaves), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int L, int MAXT>
+static hipError_t launch_x_t(const LineArgs &a, int nitems, int nwaves, size_t lds, hipStream_t s)
+{
+    static bool big_lds = false;
+    hipError_t e = allow_lds(k_line_x<L, MAXT>, lds, big_lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_line_x<L, MAXT>), dim3(nitems), dim3(64 * nwaves), lds, s, a);
+    return hipGetLastError();
+}
+
+// The thread bound of an instantiation is the smallest of 256/512/1024 that
+// holds the workgroup, so a small workgroup may use more registers per lane.
+#define BS_DISPATCH(FN)                                                                  \
+    template <int L>                                                                     \
+    static hipError_t FN##_b(const LineArgs &a, int nitems, int nwaves, size_t lds,     \
+                             hipStream_t s)                                              \
+    {                                                                                    \
+        const int t = 64 * nwaves;                                                       \
+        if (t <= 256) return FN<L, 256>(a, nitems, nwaves, lds, s);                      \
+        if (t <= 512) return FN<L, 512>(a, nitems, nwaves, lds, s);                      \
+        if (t <= 1024) return FN<L, 1024>(a, nitems, nwaves, lds, s);                    \
+        return hipErrorInvalidValue;                                                     \
+    }
+BS_DISPATCH(launch_strided_t)
+BS_DISPATCH(launch_x_t)
+#undef BS_DISPATCH
+
+hipError_t launch_line_strided(const LineArgs &a, int nitems, int Lmax, int nwaves, size_t lds,
+                               hipStream_t s)
+{
+    switch (Lmax) {
+    case 8: return launch_strided_t_b<8>(a, nitems, nwaves, lds, s);
+    case 16: return launch_strided_t_b<16>(a, nitems, nwaves, lds, s);
+    case 32: return launch_strided_t_b<32>(a, nitems, nwaves, lds, s);
+    case 64: return launch_strided_t_b<64>(a, nitems, nwaves, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_line_x(const LineArgs &a, int nitems, int Lmax, int nwaves, size_t lds, hipStream_t s)
+{
+    switch (Lmax) {
+    case 8: return launch_x_t_b<8>(a, nitems, nwaves, lds, s);
+    case 16: return launch_x_t_b<16>(a, nitems, nwaves, lds, s);
+    case 32: return launch_x_t_b<32>(a, nitems, nwaves, lds, s);
+    case 64: return launch_x_t_b<64>(a, nitems, nwaves, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace bs

@@ -1,0 +1,72 @@
+// The patch set owned by the library, and helpers shared by its host files.
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "bs.h"
+#include "bs_internal.h"
+
+namespace bs {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { reset(); }
+    void reset()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+// A device work list: items of colour 0 first, then colour 1 (colour-split
+// lists), or a single run (all lines).
+struct WorkList {
+    DevBuf buf;
+    int count[2] = {0, 0};
+};
+
+// Key: kernel kind (0 strided y/z, 1 x), axis, chunk option, tile width, colour mode.
+using WorkKey = std::tuple<int, int, int, int, int>;
+
+// A tuned launch configuration for one (axis, scheme class) of a patch set.
+struct LineCfg {
+    int popt = -1;    // index into kPOpts
+    int Lmax = 0;     // register chunk template (>= every patch's Lr)
+    int nwaves = 0;   // wavefronts per workgroup (= P_req)
+    int tx = 64;      // strided kernel: lanes along x per row
+};
+
+bs_status fail(bs_status st, const char *fmt, ...);
+bs_status hip_fail(hipError_t e, const char *what);
+bs_status upload(DevBuf &b, const void *src, size_t bytes, const char *what);
+bs_status dev_alloc(DevBuf &b, size_t bytes, const char *what);
+
+}  // namespace bs
+
+struct bs_patchset {
+    int32_t npatch = 0;
+    int device = 0;
+    std::vector<int32_t> dims;
+    std::vector<double> eps, h;
+    std::vector<int64_t> uoff, foff;
+    int64_t u_numel = 0, f_numel = 0;
+    int32_t max_n[3] = {0, 0, 0};
+    std::vector<bs::PatchDesc> desc;
+    bs::DevBuf desc_d, tab_d;
+    // residual reduction plan
+    int32_t nrblocks = 0;
+    bs::DevBuf rblock_patch_d, rblock_first_d, rpatch_first_d, rpartial_d;
+    // cached work lists and tuned configurations
+    std::map<bs::WorkKey, std::unique_ptr<bs::WorkList>> lists;
+    std::map<std::pair<int, int>, bs::LineCfg> line_cfg;   // (axis, colour_mode) -> cfg
+};

@@ -1,0 +1,16 @@
+// Sweep-driver internals shared by the host files.
+#pragma once
+
+#include "patchset.h"
+
+namespace bs {
+
+bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, int colour_mode, WorkList **out);
+LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode);
+bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c);
+size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c);
+bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
+                    double *dst, const double *f, double omega, hipStream_t stream);
+const LineCfg &line_cfg(bs_patchset *ps, int axis, int colour_mode);
+
+}  // namespace bs

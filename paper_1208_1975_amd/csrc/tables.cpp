@@ -1,0 +1,148 @@
+// Host precompute of the exact block solves (section 2: the block inverse is
+// formed once, before the smoothing iterations; section 4.3: for constant
+// coefficients one set per block shape suffices).  Everything is computed in
+// long double and rounded once to double.
+#include "tables.h"
+
+#include <cmath>
+#include <stdexcept>
+#include <vector>
+
+namespace bs {
+
+namespace {
+
+using ld = long double;
+
+// LU of the Toeplitz tridiagonal T = tridiag(-e, d, -e) of order len:
+// pivots m_t (m_0 = d, m_t = d - e^2 / m_{t-1}).
+std::vector<ld> pivots(int len, ld e, ld d)
+{
+    std::vector<ld> m(len);
+    m[0] = d;
+    for (int t = 1; t < len; ++t) m[t] = d - e * e / m[t - 1];
+    return m;
+}
+
+// x = T^{-1} rhs for T of order len, with its pivots m.
+std::vector<ld> tsolve(const std::vector<ld> &m, int len, ld e, std::vector<ld> rhs)
+{
+    for (int t = 1; t < len; ++t) rhs[t] += e / m[t - 1] * rhs[t - 1];
+    rhs[len - 1] /= m[len - 1];
+    for (int t = len - 2; t >= 0; --t) rhs[t] = (rhs[t] + e * rhs[t + 1]) / m[t];
+    return rhs;
+}
+
+// In-place inverse of a dense n x n matrix (row-major) by Gauss-Jordan with
+// partial pivoting.
+void invert(std::vector<ld> &a, int n)
+{
+    std::vector<ld> inv(static_cast<size_t>(n) * n, 0.0L);
+    for (int i = 0; i < n; ++i) inv[static_cast<size_t>(i) * n + i] = 1.0L;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[static_cast<size_t>(r) * n + c]) > std::fabs(a[static_cast<size_t>(piv) * n + c])) piv = r;
+        if (a[static_cast<size_t>(piv) * n + c] == 0.0L) throw std::runtime_error("singular interface system");
+        if (piv != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(a[static_cast<size_t>(piv) * n + k], a[static_cast<size_t>(c) * n + k]);
+                std::swap(inv[static_cast<size_t>(piv) * n + k], inv[static_cast<size_t>(c) * n + k]);
+            }
+        const ld s = 1.0L / a[static_cast<size_t>(c) * n + c];
+        for (int k = 0; k < n; ++k) {
+            a[static_cast<size_t>(c) * n + k] *= s;
+            inv[static_cast<size_t>(c) * n + k] *= s;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const ld fct = a[static_cast<size_t>(r) * n + c];
+            if (fct == 0.0L) continue;
+            for (int k = 0; k < n; ++k) {
+                a[static_cast<size_t>(r) * n + k] -= fct * a[static_cast<size_t>(c) * n + k];
+                inv[static_cast<size_t>(r) * n + k] -= fct * inv[static_cast<size_t>(c) * n + k];
+            }
+        }
+    }
+    a.swap(inv);
+}
+
+}  // namespace
+
+bool line_split(int n, int preq, int &Lr, int &P, int &Llast)
+{
+    if (n < 1 || preq < 1) return false;
+    Lr = (n + preq - 1) / preq;
+    if (Lr > kMaxChunkLen) return false;
+    P = (n + Lr - 1) / Lr;
+    Llast = n - (P - 1) * Lr;
+    return true;
+}
+
+std::vector<double> build_line_table(int n, double eps_a, double d, int preq)
+{
+    int Lr, P, Llast;
+    if (!line_split(n, preq, Lr, P, Llast)) throw std::runtime_error("line split");
+    const ld e = eps_a, dd = d;
+    std::vector<double> out(static_cast<size_t>(line_table_size(Lr, P)), 0.0);
+    const std::vector<ld> m = pivots(Lr, e, dd);
+    out[0] = 0.0;
+    for (int t = 1; t < Lr; ++t) out[t] = static_cast<double>(e / m[t - 1]);
+    for (int t = 0; t < Lr; ++t) out[Lr + t] = static_cast<double>(1.0L / m[t]);
+
+    // spikes of a chunk of length len: eps_a T^{-1} e_0 and eps_a T^{-1} e_{len-1}
+    auto spikes = [&](int len, std::vector<ld> &ev, std::vector<ld> &ew) {
+        std::vector<ld> e0(len, 0.0L), el(len, 0.0L);
+        e0[0] = 1.0L;
+        el[len - 1] = 1.0L;
+        ev = tsolve(m, len, e, e0);
+        ew = tsolve(m, len, e, el);
+        for (auto &v : ev) v *= e;
+        for (auto &v : ew) v *= e;
+    };
+    std::vector<ld> evF, ewF, evT, ewT;
+    spikes(Lr, evF, ewF);
+    spikes(Llast, evT, ewT);
+    for (int t = 0; t < Lr; ++t) {
+        out[2 * Lr + t] = static_cast<double>(evF[t]);
+        out[3 * Lr + t] = static_cast<double>(ewF[t]);
+    }
+    for (int t = 0; t < Llast; ++t) {
+        out[4 * Lr + t] = static_cast<double>(evT[t]);
+        out[5 * Lr + t] = static_cast<double>(ewT[t]);
+    }
+
+    // Interface system over z = (alpha_0, beta_0, ..., alpha_{P-1}, beta_{P-1}),
+    // alpha_p / beta_p = correction at the first / last cell of chunk p:
+    //   alpha_p - beta_{p-1} ev_p[0]      - alpha_{p+1} ew_p[0]      = y_p[0]
+    //   beta_p  - beta_{p-1} ev_p[last]   - alpha_{p+1} ew_p[last]   = y_p[last]
+    const int N = 2 * P;
+    std::vector<ld> S(static_cast<size_t>(N) * N, 0.0L);
+    for (int p = 0; p < P; ++p) {
+        const bool lastc = (p == P - 1);
+        const std::vector<ld> &ev = lastc ? evT : evF;
+        const std::vector<ld> &ew = lastc ? ewT : ewF;
+        const int len = lastc ? Llast : Lr;
+        const int ra = 2 * p, rb = 2 * p + 1;
+        S[static_cast<size_t>(ra) * N + ra] = 1.0L;
+        S[static_cast<size_t>(rb) * N + rb] = 1.0L;
+        if (p > 0) {
+            S[static_cast<size_t>(ra) * N + (2 * p - 1)] -= ev[0];
+            S[static_cast<size_t>(rb) * N + (2 * p - 1)] -= ev[len - 1];
+        }
+        if (p < P - 1) {
+            S[static_cast<size_t>(ra) * N + (2 * p + 2)] -= ew[0];
+            S[static_cast<size_t>(rb) * N + (2 * p + 2)] -= ew[len - 1];
+        }
+    }
+    invert(S, N);
+    const size_t kb = 6 * static_cast<size_t>(Lr), ka = kb + 2 * static_cast<size_t>(P) * P;
+    for (int p = 0; p < P; ++p)
+        for (int jj = 0; jj < N; ++jj) {
+            if (p > 0) out[kb + static_cast<size_t>(p) * N + jj] = static_cast<double>(S[static_cast<size_t>(2 * p - 1) * N + jj]);
+            if (p < P - 1) out[ka + static_cast<size_t>(p) * N + jj] = static_cast<double>(S[static_cast<size_t>(2 * p + 2) * N + jj]);
+        }
+    return out;
+}
+
+}  // namespace bs

@@ -1,0 +1,190 @@
+"""CPU-only checks of the library boundary: it loads, exports every symbol the
+header declares, validates arguments before touching the device, lays out
+patches as the paper stores them, and builds line tables that solve the
+tridiagonal blocks exactly (checked with a NumPy model of the partitioned
+solve against a banded LAPACK solve)."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bs.h")
+
+bsmod = pytest.importorskip("paper_1208_1975_amd")
+
+
+def _lib():
+    if not os.path.exists(bsmod.LIB_PATH):
+        pytest.skip("libblocksmooth.so not built")
+    return bsmod.lib()
+
+
+def header_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(bs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_header_symbol():
+    lib = _lib()
+    syms = header_symbols()
+    assert set(syms) == set(bsmod.EXPORTS)
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def _status(rc):
+    return rc, bsmod.lib().bs_last_error().decode()
+
+
+def test_validation_before_any_launch():
+    L = _lib()
+    vp = ctypes.c_void_p
+    # scalar arguments are checked first, then pointers; none needs a device
+    rc, msg = _status(L.bs_line_relax(None, 3, 0, 0.8, 1, 0, None, None, None, None))
+    assert rc == bsmod.BS_ERR_INVALID and "axis" in msg
+    rc, msg = _status(L.bs_line_relax(None, 2, 7, 0.8, 1, 0, None, None, None, None))
+    assert rc == bsmod.BS_ERR_INVALID and "scheme" in msg
+    for om in (0.0, 2.0, -1.0, float("nan")):
+        rc, msg = _status(L.bs_line_relax(None, 2, 0, om, 1, 0, None, None, None, None))
+        assert rc == bsmod.BS_ERR_INVALID and "omega" in msg
+    rc, msg = _status(L.bs_line_relax(None, 2, 0, 0.8, -1, 0, None, None, None, None))
+    assert rc == bsmod.BS_ERR_INVALID and "nsweeps" in msg
+    rc, msg = _status(L.bs_line_relax(None, 2, 0, 0.8, 1, 2, None, None, None, None))
+    assert rc == bsmod.BS_ERR_UNSUPPORTED and "BF16" in msg
+    rc, msg = _status(L.bs_line_relax(None, 2, 0, 0.8, 1, 0, None, None, None, None))
+    assert rc == bsmod.BS_ERR_INVALID and "null" in msg
+    rc, msg = _status(L.bs_plane_relax(None, -1, 0, 1.0, 1, 0, 0, None, None, None, None))
+    assert rc == bsmod.BS_ERR_INVALID and "axis" in msg
+    rc, msg = _status(L.bs_plane_relax(None, 2, 0, 1.0, 1, 0, -1, None, None, None, None))
+    assert rc == bsmod.BS_ERR_INVALID and "refine" in msg
+    rc, msg = _status(L.bs_relax_backward(None, 2, 0.8, 4, 0, None, None, None, None, None, None, None, 0, None))
+    assert rc == bsmod.BS_ERR_INVALID and "ckpt" in msg
+    rc, msg = _status(L.bs_residual(None, None, None, None, None, None))
+    assert rc == bsmod.BS_ERR_INVALID
+    # patch-set creation: dims, eps, h
+    out = vp()
+    dims = (ctypes.c_int32 * 3)(4, 0, 4)
+    eps = (ctypes.c_double * 3)(1, 1, 1)
+    h = (ctypes.c_double * 1)(0.25)
+    rc, msg = _status(L.bs_create_patchset(1, dims, eps, h, ctypes.byref(out)))
+    assert rc == bsmod.BS_ERR_INVALID and out.value is None
+    dims = (ctypes.c_int32 * 3)(4, 4, 4)
+    for bad in ((0.0, 1, 1), (1, -2, 1), (1, 1, float("inf"))):
+        e = (ctypes.c_double * 3)(*bad)
+        rc, msg = _status(L.bs_create_patchset(1, dims, e, h, ctypes.byref(out)))
+        assert rc == bsmod.BS_ERR_INVALID and "eps" in msg
+    rc, msg = _status(L.bs_create_patchset(1, dims, eps, (ctypes.c_double * 1)(0.0), ctypes.byref(out)))
+    assert rc == bsmod.BS_ERR_INVALID and "h[" in msg
+    rc, msg = _status(L.bs_create_patchset(0, dims, eps, h, ctypes.byref(out)))
+    assert rc == bsmod.BS_ERR_INVALID
+
+
+def test_layout_plan_matches_paper_storage():
+    """Padded u, unpadded f (section 2.1 index spaces) reproduce the paper's
+    printed ghost overheads and storage sizes (section 3)."""
+    _lib()
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_storage.json")))
+    def cells(n):
+        # u_numel / f_numel include at most 31 doubles of alignment after the patch
+        un, fn, _, _ = bsmod.bs_layout_plan([(n, n, n)])
+        u_cells, f_cells = (n + 2) ** 3, n ** 3
+        assert 0 <= un - u_cells < 32 and 0 <= fn - f_cells < 32
+        return u_cells, f_cells
+
+    u, f = cells(32)
+    assert u - f == g["ghost_overhead"]["extra_cells_32"]
+    for n, frac in g["ghost_overhead"]["fraction_approx"].items():
+        u, f = cells(int(n))
+        assert (u - f) / f == pytest.approx(frac, abs=0.005)
+    u, f = cells(96)
+    mib = 1024.0 * 1024.0
+    assert (u + f) * 8 / mib == pytest.approx(g["storage_96_megabytes"]["gauss_seidel"], abs=0.5)
+    assert (2 * u + f) * 8 / mib == pytest.approx(g["storage_96_megabytes"]["jacobi"], abs=0.5)
+    t2 = g["table2_cells"]
+    for n in ("64", "80", "96"):
+        _, fn, _, _ = bsmod.bs_layout_plan([(int(n),) * 3] * 80)
+        assert 3 * sum(int(n) ** 3 for _ in range(80)) == t2[n]
+        assert fn >= 80 * int(n) ** 3
+    mixed = [(s, s, s) for s in t2["mixed_sizes"] for _ in range(16)]
+    assert 3 * sum(s[0] ** 3 for s in mixed) == t2["mixed"]
+
+
+def test_layout_plan_offsets():
+    _lib()
+    dims = [(5, 4, 3), (16, 24, 32), (1, 1, 1)]
+    un, fn, uo, fo = bsmod.bs_layout_plan(dims)
+    pos_u = pos_f = 0
+    for (nx, ny, nz), a, b in zip(dims, uo, fo):
+        assert a >= pos_u and a % 32 == 0 and b >= pos_f and b % 32 == 0
+        pos_u = a + (nx + 2) * (ny + 2) * (nz + 2)
+        pos_f = b + nx * ny * nz
+    assert un >= pos_u and fn >= pos_f
+    with pytest.raises(bsmod.BSError):
+        bsmod.bs_layout_plan([(3, 0, 3)])
+
+
+def line_table(n, e, d, preq):
+    L = _lib()
+    f = L.bsi_line_table
+    f.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                  ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    info = (ctypes.c_int * 3)()
+    size = f(n, e, d, preq, None, 0, info)
+    assert size > 0
+    out = np.zeros(size)
+    assert f(n, e, d, preq, out.ctypes.data_as(ctypes.c_void_p), size, info) == size
+    return out, tuple(info)
+
+
+def partitioned_solve(tab, info, e, r):
+    """NumPy model of the chunked solve the line kernels perform."""
+    Lr, P, Ll = info
+    g, q = tab[:Lr], tab[Lr:2 * Lr]
+    y = []
+    for p in range(P):
+        Lp = Ll if p == P - 1 else Lr
+        z = r[p * Lr:p * Lr + Lp].copy()
+        for t in range(1, Lp):
+            z[t] += g[t] * z[t - 1]
+        yy = np.zeros(Lp)
+        nxt = 0.0
+        for t in range(Lp - 1, -1, -1):
+            yy[t] = (z[t] + e * nxt) * q[t]
+            nxt = yy[t]
+        y.append(yy)
+    Y = np.array([v for yy in y for v in (yy[0], yy[-1])])
+    Kb = tab[6 * Lr:6 * Lr + 2 * P * P].reshape(P, 2 * P)
+    Ka = tab[6 * Lr + 2 * P * P:].reshape(P, 2 * P)
+    out = []
+    for p in range(P):
+        Lp = Ll if p == P - 1 else Lr
+        ev = tab[(4 if p == P - 1 else 2) * Lr:][:Lp]
+        ew = tab[(5 if p == P - 1 else 3) * Lr:][:Lp]
+        out.append(y[p] + (Kb[p] @ Y) * ev + (Ka[p] @ Y) * ew)
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("n,preq", [(1, 1), (2, 2), (7, 4), (32, 1), (33, 4), (64, 16), (100, 8), (256, 8),
+                                    (256, 16), (255, 16), (512, 16), (17, 16)])
+@pytest.mark.parametrize("eps", [(1.0, 1.0, 100.0), (3.0, 1.0, 1.0), (1.0, 100.0, 100.0)])
+def test_line_table_solves_exactly(n, preq, eps):
+    d = 2 * sum(eps)
+    e = eps[2]
+    tab, info = line_table(n, e, d, preq)
+    Lr, P, Ll = info
+    assert Lr <= 64 and (P - 1) * Lr + Ll == n and 1 <= Ll <= Lr and P <= preq
+    rng = np.random.default_rng(n + preq)
+    r = rng.uniform(-1, 1, n)
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -e
+    ab[1, :] = d
+    ab[2, :-1] = -e
+    ref = scipy.linalg.solve_banded((1, 1), ab, r)
+    got = partitioned_solve(tab, info, e, r)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
