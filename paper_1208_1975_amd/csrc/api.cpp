@@ -134,6 +134,7 @@ bs_status build_tables(bs_patchset *ps)
     bs_status st = upload(ps->tab_d, tab.data(), tab.size() * sizeof(double), "tables");
     if (st != BS_OK) return st;
     ps->lists.clear();
+    ps->plane_ready = false;   // plane tables depend on eps; rebuilt on next use
     return upload(ps->desc_d, ps->desc.data(), ps->desc.size() * sizeof(PatchDesc), "patch descriptors");
 }
 

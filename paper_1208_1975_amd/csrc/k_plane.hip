@@ -1,0 +1,119 @@
+// Plane-block solves by fast diagonalisation: every plane block
+//   M_P = d I - eps_a (shifts along a) - eps_b (shifts along b)
+// equals (S_a (x) S_b) (Lambda) (S_a (x) S_b) with the orthonormal DST-I bases
+// S_a, S_b of the two in-plane axes and Lambda_pq = sigma_a,p + sigma_b,q +
+// 2 eps_c, so M_P^{-1} R = S_b [ (S_b R S_a) ./ Lambda ] S_a.  The four
+// transforms are batched dense products -- the one dense contraction of the
+// method -- and run on the FP64 matrix cores (v_mfma_f64_16x16x4).
+//
+// One strided batched kernel C_b = A_b B_b (row-major, either operand may be
+// shared across the batch with a zero batch stride) serves every plane
+// orientation; its epilogue either stores C, stores C scaled elementwise by a
+// table (the inverse eigenvalue grid), or writes dst = src + omega C straight
+// into the padded u layout (the block update).
+#include "bs_internal.h"
+#include "plane.h"
+
+namespace bs {
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+}  // namespace
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
+{
+    __shared__ double As[BK][BM + 1];
+    __shared__ double Bs[BK][BN + 1];
+    const int b = blockIdx.z;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const double *A = g.A + (int64_t)b * g.sA;
+    const double *B = g.B + (int64_t)b * g.sB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int l16 = lane & 15, lk = lane >> 4;
+
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        // A tile BM x BK (rows coalesced along k), stored k-major
+#pragma unroll
+        for (int q = 0; q < (BM * BK) / 256; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e / BK, c = e % BK;
+            const int gr = m0 + r, gc = k0 + c;
+            As[c][r] = (gr < g.M && gc < g.K) ? A[(int64_t)gr * g.lda + gc] : 0.0;
+        }
+        // B tile BK x BN
+#pragma unroll
+        for (int q = 0; q < (BK * BN) / 256; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e / BN, c = e % BN;
+            const int gr = k0 + r, gc = n0 + c;
+            Bs[r][c] = (gr < g.K && gc < g.N) ? B[(int64_t)gr * g.ldb + gc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double af[2], bf[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = As[kk + lk][wm * 32 + i * 16 + l16];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bf[j] = Bs[kk + lk][wn * 32 + j * 16 + l16];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // D layout of the FP64 16x16 block: register r of a lane holds row
+    // 4*r + lane/16, column lane%16 (checked by the layout test)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 32 + i * 16 + r * 4 + lk;
+                const int col = n0 + wn * 32 + j * 16 + l16;
+                if (row >= g.M || col >= g.N) continue;
+                const double v = acc[i][j][r];
+                if (EPI == kEpiStore) {
+                    g.C[(int64_t)b * g.sC + (int64_t)row * g.ldc + col] = v;
+                } else if (EPI == kEpiScale) {
+                    const double s = g.scale[(int64_t)b * g.sc_b + (int64_t)row * g.sc_m + (int64_t)col * g.sc_n];
+                    g.C[(int64_t)b * g.sC + (int64_t)row * g.ldc + col] = v * s;
+                } else {
+                    if (g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour) continue;
+                    const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
+                    g.udst[u] = fma(g.omega, v, g.usrc[u]);
+                }
+            }
+}
+
+hipError_t launch_gemm_f64(const GemmArgs &g, int epi, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
+    const dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
+    switch (epi) {
+    case kEpiStore: hipLaunchKernelGGL(k_gemm_f64<kEpiStore>, grid, dim3(256), 0, s, g); break;
+    case kEpiScale: hipLaunchKernelGGL(k_gemm_f64<kEpiScale>, grid, dim3(256), 0, s, g); break;
+    case kEpiUpdate: hipLaunchKernelGGL(k_gemm_f64<kEpiUpdate>, grid, dim3(256), 0, s, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bs

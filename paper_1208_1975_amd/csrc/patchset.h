@@ -66,6 +66,11 @@ struct bs_patchset {
     // residual reduction plan
     int32_t nrblocks = 0;
     bs::DevBuf rblock_patch_d, rblock_first_d, rpatch_first_d, rpartial_d;
+    // plane solves: sine bases per patch and axis, inverse eigenvalue grids per
+    // patch and normal axis (built on first use), and two f-layout scratch fields
+    bool plane_ready = false;
+    bs::DevBuf plane_tab_d, plane_r_d, plane_t_d;
+    std::vector<int64_t> basis_off, lam_off;   // [3 * npatch] each, offsets in doubles
     // cached work lists and tuned configurations
     std::map<bs::WorkKey, std::unique_ptr<bs::WorkList>> lists;
     std::map<std::pair<int, int>, bs::LineCfg> line_cfg;   // (axis, colour_mode) -> cfg

@@ -1,0 +1,36 @@
+// Plane-block solves: batched dense products for fast diagonalisation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bs {
+
+enum { kEpiStore = 0, kEpiScale = 1, kEpiUpdate = 2 };
+
+// C_b = A_b B_b, row-major, b in [0, batch); a zero batch stride shares an
+// operand across the batch.  Epilogues:
+//   kEpiStore:  C = A B
+//   kEpiScale:  C = (A B) .* scale[b*sc_b + m*sc_m + n*sc_n]
+//   kEpiUpdate: udst[u] = usrc[u] + omega (A B), u = u0 + b*u_b + m*u_m + n*u_n,
+//               for columns n with (n + colour_shift) % 2 == ncolour (all if ncolour < 0)
+struct GemmArgs {
+    const double *A;
+    int64_t lda, sA;
+    const double *B;
+    int64_t ldb, sB;
+    double *C;
+    int64_t ldc, sC;
+    int M, N, K, batch;
+    const double *scale;
+    int64_t sc_b, sc_m, sc_n;
+    const double *usrc;
+    double *udst;
+    int64_t u0, u_b, u_m, u_n;
+    double omega;
+    int ncolour, colour_shift;
+};
+
+hipError_t launch_gemm_f64(const GemmArgs &g, int epi, hipStream_t s);
+
+}  // namespace bs

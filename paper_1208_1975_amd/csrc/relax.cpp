@@ -254,24 +254,6 @@ bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double 
     return BS_OK;
 }
 
-bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme, double omega, int32_t nsweeps,
-                         bs_precision prec, int32_t refine, double *u, const double *f, double *work,
-                         hipStream_t stream)
-{
-    (void)stream;
-    if (normal_axis < 0 || normal_axis > 2) return fail(BS_ERR_INVALID, "bs_plane_relax: axis must be 0, 1 or 2");
-    if (scheme != BS_JACOBI && scheme != BS_CHAOTIC_GS && scheme != BS_COLORED_GS)
-        return fail(BS_ERR_INVALID, "bs_plane_relax: unknown scheme");
-    if (!(omega > 0.0 && omega < 2.0)) return fail(BS_ERR_INVALID, "bs_plane_relax: omega must be in (0, 2)");
-    if (nsweeps < 0) return fail(BS_ERR_INVALID, "bs_plane_relax: nsweeps < 0");
-    if (refine < 0) return fail(BS_ERR_INVALID, "bs_plane_relax: refine < 0");
-    if (prec != BS_FP64 && prec != BS_MIXED_FP32 && prec != BS_MIXED_BF16)
-        return fail(BS_ERR_INVALID, "bs_plane_relax: unknown precision");
-    if (!ps || !u || !f) return fail(BS_ERR_INVALID, "bs_plane_relax: null patch set, u or f");
-    if (scheme == BS_JACOBI && !work) return fail(BS_ERR_INVALID, "bs_plane_relax: Jacobi needs a work buffer");
-    return fail(BS_ERR_UNSUPPORTED, "bs_plane_relax: plane solves are not built yet");
-}
-
 size_t bs_backward_workspace_bytes(const bs_patchset *ps, int32_t axis, int32_t nsweeps, int32_t ckpt_every)
 {
     (void)ps;

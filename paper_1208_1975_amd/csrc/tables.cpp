@@ -145,4 +145,30 @@ std::vector<double> build_line_table(int n, double eps_a, double d, int preq)
     return out;
 }
 
+std::vector<double> sine_basis(int n)
+{
+    std::vector<double> S(static_cast<size_t>(n) * n);
+    const ld scale = std::sqrt(2.0L / static_cast<ld>(n + 1));
+    const ld pi = 3.141592653589793238462643383279502884L;
+    const long period = 2L * (n + 1);
+    for (int i = 0; i < n; ++i)
+        for (int p = 0; p < n; ++p) {
+            // reduce the argument in integers before the library sine
+            const long m = (static_cast<long>(i + 1) * (p + 1)) % period;
+            S[static_cast<size_t>(i) * n + p] = static_cast<double>(scale * std::sin(pi * m / (n + 1)));
+        }
+    return S;
+}
+
+std::vector<long double> sine_eigenvalues(int n, double eps)
+{
+    std::vector<long double> sg(n);
+    const ld pi = 3.141592653589793238462643383279502884L;
+    for (int p = 0; p < n; ++p) {
+        const ld s = std::sin(pi * (p + 1) / (2.0L * (n + 1)));
+        sg[p] = 4.0L * eps * s * s;
+    }
+    return sg;
+}
+
 }  // namespace bs

@@ -14,4 +14,12 @@ bool line_split(int n, int preq, int &Lr, int &P, int &Llast);
 // Line table (layout in bs_internal.h) for tridiag(-eps_a, d, -eps_a) of order n.
 std::vector<double> build_line_table(int n, double eps_a, double d, int preq);
 
+// Orthonormal DST-I basis of order n, row-major n x n (symmetric, its own
+// inverse): S[i][p] = sqrt(2/(n+1)) sin(pi (i+1)(p+1) / (n+1)).
+std::vector<double> sine_basis(int n);
+
+// Eigenvalues of tridiag(-eps, 2 eps, -eps) of order n, in the basis order:
+// sigma_p = 4 eps sin^2((p+1) pi / (2(n+1))).
+std::vector<long double> sine_eigenvalues(int n, double eps);
+
 }  // namespace bs
