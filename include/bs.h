@@ -130,6 +130,10 @@ bs_status bs_residual(const bs_patchset *ps, const double *u, const double *f, d
  *   work  u-layout scratch for BS_JACOBI (the paper's second vector v); may
  *         be NULL for the Gauss-Seidel schemes.  Its ghosts are overwritten.
  *   omega in (0, 2).  nsweeps >= 0 (0 enqueues nothing).
+ * Every patch of the set is relaxed by the same launches (one per sweep, or
+ * per colour for BS_COLORED_GS), larger patches first.  A sequence of two or
+ * more sweeps is captured into a HIP graph on its first call and replayed by
+ * later calls with the same arguments and buffers.
  * BS_ERR_UNSUPPORTED for BS_MIXED_BF16 (BF16 is offered for planes only). */
 bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double omega,
                         int32_t nsweeps, bs_precision prec, double *u, const double *f,
@@ -145,6 +149,20 @@ bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double 
 bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme, double omega,
                          int32_t nsweeps, bs_precision prec, int32_t refine, double *u,
                          const double *f, double *work, hipStream_t stream);
+
+/* Autotuner: time the candidate launch configurations of line sweeps along
+ * `axis` for `scheme` (chunk count per line, tile width, one workgroup per
+ * tile or a persistent grid) on copies of u -- the caller's buffers are not
+ * modified -- and keep the fastest for later bs_line_relax calls on this patch
+ * set.  Synchronous; allocates two u-sized scratch buffers for its duration. */
+bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, const double *u, const double *f,
+                           hipStream_t stream);
+
+/* The launch configuration bs_line_relax uses for (axis, scheme):
+ * cfg_host[0] chunks per line, [1] register chunk length, [2] tile width in
+ * lanes, [3] persistent grid size (0: one workgroup per tile), [4] 1 if it
+ * was set by the autotuner. */
+bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, int32_t cfg_host[5]);
 
 /* Device workspace needed by bs_relax_backward for these arguments, or 0 on
  * invalid arguments. */

@@ -29,8 +29,8 @@ _STATUS = {1: "BS_ERR_INVALID", 2: "BS_ERR_UNSUPPORTED", 3: "BS_ERR_OOM", 4: "BS
 
 # Every symbol the public header declares.
 EXPORTS = ("bs_layout_plan", "bs_create_patchset", "bs_destroy_patchset", "bs_set_eps", "bs_layout",
-           "bs_residual", "bs_line_relax", "bs_plane_relax", "bs_backward_workspace_bytes",
-           "bs_relax_backward", "bs_last_error")
+           "bs_residual", "bs_line_relax", "bs_plane_relax", "bs_autotune_line", "bs_line_config",
+           "bs_backward_workspace_bytes", "bs_relax_backward", "bs_last_error")
 
 
 class BSError(RuntimeError):
@@ -61,13 +61,21 @@ def lib():
     L.bs_residual.argtypes = [vp, vp, vp, vp, vp, vp]
     L.bs_line_relax.argtypes = [vp, i32, ctypes.c_int, dbl, i32, ctypes.c_int, vp, vp, vp, vp]
     L.bs_plane_relax.argtypes = [vp, i32, ctypes.c_int, dbl, i32, ctypes.c_int, i32, vp, vp, vp, vp]
+    L.bs_autotune_line.argtypes = [vp, i32, ctypes.c_int, vp, vp, vp]
+    L.bs_line_config.argtypes = [vp, i32, ctypes.c_int, vp]
+    L.bsi_set_line_cfg.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.bsi_set_line_cfg.restype = ctypes.c_int
+    L.bsi_set_graphs.argtypes = [vp, ctypes.c_int]
+    L.bsi_set_graphs.restype = ctypes.c_int
+    L.bsi_line_relax_per_patch.argtypes = [vp, i32, ctypes.c_int, dbl, i32, vp, vp, vp, vp]
+    L.bsi_line_relax_per_patch.restype = ctypes.c_int
     L.bs_backward_workspace_bytes.argtypes = [vp, i32, i32, i32]
     L.bs_backward_workspace_bytes.restype = sz
     L.bs_relax_backward.argtypes = [vp, i32, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.bs_last_error.argtypes = []
     L.bs_last_error.restype = ctypes.c_char_p
     for name in ("bs_layout_plan", "bs_create_patchset", "bs_set_eps", "bs_layout", "bs_residual",
-                 "bs_line_relax", "bs_plane_relax", "bs_relax_backward"):
+                 "bs_line_relax", "bs_plane_relax", "bs_autotune_line", "bs_line_config", "bs_relax_backward"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -174,6 +182,17 @@ def bs_plane_relax(ps, normal_axis, scheme, omega, nsweeps, prec, refine, u, f, 
                                 _prec(prec), int(refine), _ptr(u), _ptr(f), _ptr(work), _stream(stream)))
 
 
+def bs_autotune_line(ps, axis, scheme, u, f, stream=None):
+    _check(lib().bs_autotune_line(ps, int(axis), _scheme(scheme), _ptr(u), _ptr(f), _stream(stream)))
+
+
+def bs_line_config(ps, axis, scheme):
+    """dict(chunks, chunk_len, tile, grid, tuned) of the launch configuration in use."""
+    out = (ctypes.c_int32 * 5)()
+    _check(lib().bs_line_config(ps, int(axis), _scheme(scheme), out))
+    return dict(zip(("chunks", "chunk_len", "tile", "grid", "tuned"), list(out)))
+
+
 def bs_backward_workspace_bytes(ps, axis, nsweeps, ckpt_every):
     return int(lib().bs_backward_workspace_bytes(ps, int(axis), int(nsweeps), int(ckpt_every)))
 
@@ -264,3 +283,22 @@ class PatchSet:
     def plane_relax(self, normal_axis, scheme, omega, nsweeps, u, f, work=None, prec="fp64", refine=0,
                     stream=None):
         bs_plane_relax(self.handle, normal_axis, scheme, omega, nsweeps, prec, refine, u, f, work, stream)
+
+    def autotune_line(self, axis, scheme, u, f, stream=None):
+        bs_autotune_line(self.handle, axis, scheme, u, f, stream)
+
+    def line_config(self, axis, scheme):
+        return bs_line_config(self.handle, axis, scheme)
+
+    # tuning and comparison hooks of the library (not part of the C header)
+    def set_line_config(self, axis, scheme, chunks, tile=64, grid=0):
+        popt = (1, 2, 4, 8, 16).index(int(chunks))
+        cm = 0 if _scheme(scheme) == BS_JACOBI else 1
+        _check(lib().bsi_set_line_cfg(self.handle, int(axis), cm, popt, int(tile), int(grid)))
+
+    def set_graphs(self, enable):
+        _check(lib().bsi_set_graphs(self.handle, 1 if enable else 0))
+
+    def line_relax_per_patch(self, axis, scheme, omega, nsweeps, u, f, work=None, stream=None):
+        _check(lib().bsi_line_relax_per_patch(self.handle, int(axis), _scheme(scheme), float(omega), int(nsweeps),
+                                             _ptr(u), _ptr(f), _ptr(work), _stream(stream)))

@@ -9,6 +9,7 @@
 #include <new>
 
 #include "patchset.h"
+#include "relax.h"
 #include "tables.h"
 
 namespace bs {
@@ -134,6 +135,7 @@ bs_status build_tables(bs_patchset *ps)
     bs_status st = upload(ps->tab_d, tab.data(), tab.size() * sizeof(double), "tables");
     if (st != BS_OK) return st;
     ps->lists.clear();
+    clear_graphs(ps);
     ps->plane_ready = false;   // plane tables depend on eps; rebuilt on next use
     return upload(ps->desc_d, ps->desc.data(), ps->desc.size() * sizeof(PatchDesc), "patch descriptors");
 }

@@ -62,6 +62,7 @@ struct LineArgs {
     int32_t popt;           // index into kPOpts of the table set in use
     int32_t tx;             // lanes per row along the fast free axis (strided kernel)
     int32_t colour_mode;    // 0: every line; 1: only lines of the item's colour
+    int32_t nitems;         // work items; a workgroup takes items blockIdx.x, +gridDim.x, ...
     double omega;
 };
 
@@ -76,10 +77,10 @@ struct ResidArgs {
 };
 
 // Host launchers (defined in the .hip files).
-hipError_t launch_line_strided(const LineArgs &a, int nitems, int Lmax, int nwaves, size_t lds,
-                               hipStream_t s);
-hipError_t launch_line_x(const LineArgs &a, int nitems, int Lmax, int nwaves, size_t lds,
-                         hipStream_t s);
+// grid: workgroups launched (each drains items blockIdx.x, +grid, ... < a.nitems)
+hipError_t launch_line_strided(const LineArgs &a, int grid, int Lmax, int nwaves, size_t lds, hipStream_t s);
+hipError_t launch_line_x(const LineArgs &a, int grid, int Lmax, int nwaves, size_t lds, hipStream_t s);
+hipError_t prepare_line_kernels();
 hipError_t launch_residual(const ResidArgs &a, int nblocks, hipStream_t s);
 hipError_t launch_residual_final(const double *partial, const int32_t *patch_first_block,
                                  int npatch, double *out, hipStream_t s);

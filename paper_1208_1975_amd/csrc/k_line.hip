@@ -87,10 +87,23 @@ __device__ __forceinline__ void interface_terms(const double *tab, const double 
 // colour only ((i + o) parity), which makes x stride 2.
 // ---------------------------------------------------------------------------
 template <int L, int MAXT>
+__device__ __forceinline__ void line_strided_item(const LineArgs &a, const WorkItem it, double *smem);
+
+// A workgroup drains work items blockIdx.x, blockIdx.x + gridDim.x, ...: one
+// item per workgroup when the grid covers the list, a persistent grid otherwise.
+template <int L, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a)
 {
     extern __shared__ double smem[];
-    const WorkItem it = a.items[blockIdx.x];
+    for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
+        line_strided_item<L, MAXT>(a, a.items[i], smem);
+        __syncthreads();   // LDS is reused by the next item
+    }
+}
+
+template <int L, int MAXT>
+__device__ __forceinline__ void line_strided_item(const LineArgs &a, const WorkItem it, double *smem)
+{
     const PatchDesc *pd = a.pd + it.patch;
     const int axis = a.axis;          // 1 or 2
     const int oaxis = 3 - axis;       // the other free axis
@@ -229,10 +242,21 @@ __global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a)
 // coalesced.  With colour_mode the tile holds rows of one colour ((j+k) parity).
 // ---------------------------------------------------------------------------
 template <int L, int MAXT>
+__device__ __forceinline__ void line_x_item(const LineArgs &a, const WorkItem it, double *smem);
+
+template <int L, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_line_x(LineArgs a)
 {
     extern __shared__ double smem[];
-    const WorkItem it = a.items[blockIdx.x];
+    for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
+        line_x_item<L, MAXT>(a, a.items[i], smem);
+        __syncthreads();
+    }
+}
+
+template <int L, int MAXT>
+__device__ __forceinline__ void line_x_item(const LineArgs &a, const WorkItem it, double *smem)
+{
     const PatchDesc *pd = a.pd + it.patch;
     const int nx = pd->n[0], ny = pd->n[1], nz = pd->n[2];
     const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2);
@@ -345,34 +369,17 @@ __global__ void __launch_bounds__(MAXT) k_line_x(LineArgs a)
     }
 }
 
-// Opt a kernel into more than the default 64 KiB of dynamic LDS (once).
-template <typename K>
-static hipError_t allow_lds(K kernel, size_t lds, bool &done)
-{
-    if (lds <= 65536 || done) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e == hipSuccess) done = true;
-    return e;
-}
-
 template <int L, int MAXT>
-static hipError_t launch_strided_t(const LineArgs &a, int nitems, int nwaves, size_t lds, hipStream_t s)
+static hipError_t launch_strided_t(const LineArgs &a, int grid, int nwaves, size_t lds, hipStream_t s)
 {
-    static bool big_lds = false;
-    hipError_t e = allow_lds(k_line_strided<L, MAXT>, lds, big_lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_line_strided<L, MAXT>), dim3(nitems), dim3(64 * nwaves), lds, s, a);
+    hipLaunchKernelGGL((k_line_strided<L, MAXT>), dim3(grid), dim3(64 * nwaves), lds, s, a);
     return hipGetLastError();
 }
 
 template <int L, int MAXT>
-static hipError_t launch_x_t(const LineArgs &a, int nitems, int nwaves, size_t lds, hipStream_t s)
+static hipError_t launch_x_t(const LineArgs &a, int grid, int nwaves, size_t lds, hipStream_t s)
 {
-    static bool big_lds = false;
-    hipError_t e = allow_lds(k_line_x<L, MAXT>, lds, big_lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_line_x<L, MAXT>), dim3(nitems), dim3(64 * nwaves), lds, s, a);
+    hipLaunchKernelGGL((k_line_x<L, MAXT>), dim3(grid), dim3(64 * nwaves), lds, s, a);
     return hipGetLastError();
 }
 
@@ -392,6 +399,36 @@ static hipError_t launch_x_t(const LineArgs &a, int nitems, int nwaves, size_t l
 BS_DISPATCH(launch_strided_t)
 BS_DISPATCH(launch_x_t)
 #undef BS_DISPATCH
+
+// Allow the large-LDS line kernels (x-lines of up to 256 cells) once per
+// process, so that no attribute call ever happens inside a graph capture.
+template <int L>
+static hipError_t allow_all_t()
+{
+    hipError_t e = hipSuccess;
+    const void *ks[] = {reinterpret_cast<const void *>(k_line_x<L, 256>), reinterpret_cast<const void *>(k_line_x<L, 512>),
+                        reinterpret_cast<const void *>(k_line_x<L, 1024>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 256>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 512>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 1024>)};
+    for (const void *k : ks) {
+        hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (r != hipSuccess) e = r;
+    }
+    return e;
+}
+
+hipError_t prepare_line_kernels()
+{
+    static hipError_t done = hipErrorNotInitialized;
+    if (done == hipSuccess) return done;
+    hipError_t e = allow_all_t<8>();
+    if (e == hipSuccess) e = allow_all_t<16>();
+    if (e == hipSuccess) e = allow_all_t<32>();
+    if (e == hipSuccess) e = allow_all_t<64>();
+    done = e;
+    return e;
+}
 
 hipError_t launch_line_strided(const LineArgs &a, int nitems, int Lmax, int nwaves, size_t lds,
                                hipStream_t s)

@@ -33,6 +33,9 @@ struct DevBuf {
 struct WorkList {
     DevBuf buf;
     int count[2] = {0, 0};
+    // per colour run, per patch: first item (relative to the run) and count;
+    // a patch's items are contiguous within each run
+    std::vector<int> pfirst[2], pcount[2];
 };
 
 // Key: kernel kind (0 strided y/z, 1 x), axis, chunk option, tile width, colour mode.
@@ -44,6 +47,7 @@ struct LineCfg {
     int Lmax = 0;     // register chunk template (>= every patch's Lr)
     int nwaves = 0;   // wavefronts per workgroup (= P_req)
     int tx = 64;      // strided kernel: lanes along x per row
+    int grid = 0;     // persistent grid size (0: one workgroup per work item)
 };
 
 bs_status fail(bs_status st, const char *fmt, ...);
@@ -74,4 +78,9 @@ struct bs_patchset {
     // cached work lists and tuned configurations
     std::map<bs::WorkKey, std::unique_ptr<bs::WorkList>> lists;
     std::map<std::pair<int, int>, bs::LineCfg> line_cfg;   // (axis, colour_mode) -> cfg
+    // captured sweep sequences, replayed with one graph launch
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    hipStream_t capture_stream = nullptr;
+    bool use_graphs = true;
+    ~bs_patchset();
 };

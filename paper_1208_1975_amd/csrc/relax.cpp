@@ -1,8 +1,11 @@
-// Sweep drivers: launch configuration, work lists and the sweep sequences of
-// the three schemes (section 2: Jacobi with a second vector and pointer swap;
-// chaotic block Gauss-Seidel in place, Algorithm 1; plus two-colour GS).
+// Line sweep drivers: launch configurations, work lists, the sweep sequences
+// of the three schemes (section 2: Jacobi through a second vector with a
+// pointer swap; chaotic block Gauss-Seidel in place, Algorithm 1; plus
+// two-colour GS), graph capture of whole sequences, the autotuner and the
+// backward entry points' argument checks.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 #include "patchset.h"
@@ -56,7 +59,25 @@ void xcd_order(std::vector<WorkItem> &run)
     run.swap(out);
 }
 
+int device_cus()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
 }  // namespace
+
+void clear_graphs(bs_patchset *ps)
+{
+    for (auto &kv : ps->graphs) (void)hipGraphExecDestroy(kv.second);
+    ps->graphs.clear();
+}
 
 bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, int colour_mode, WorkList **out)
 {
@@ -79,8 +100,12 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
     const int ncol = colour_mode ? 2 : 1;
     for (int c = 0; c < ncol; ++c) {
         std::vector<WorkItem> run;
+        wl->pfirst[c].assign(ps->npatch, 0);
+        wl->pcount[c].assign(ps->npatch, 0);
         for (int p : order) {
             const int nt = tiles_of(ps, p, kind, axis, tx, colour_mode);
+            wl->pfirst[c][p] = static_cast<int>(run.size());
+            wl->pcount[c][p] = nt;
             for (int t = 0; t < nt; ++t) run.push_back(WorkItem{p, t, c, 0});
         }
         if (ps->npatch == 1) xcd_order(run);
@@ -98,8 +123,8 @@ LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode)
 {
     LineCfg c;
     const int nmax = ps->max_n[axis];
-    // the fewest chunks whose length stays <= 16 (registers: about 122 VGPRs
-    // at 1024 threads); longer lines take 32-cell chunks
+    // the fewest chunks whose length stays <= 16 (about 126 VGPRs at 1024
+    // threads); longer lines take 32-cell chunks
     for (int o = 0; o < kNumPOpt; ++o) {
         const int Lr = (nmax + kPOpts[o] - 1) / kPOpts[o];
         if (Lr <= 16 || o == kNumPOpt - 1) {
@@ -117,23 +142,8 @@ LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode)
     } else {
         c.tx = 64;
     }
+    c.grid = 0;
     return c;
-}
-
-bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c)
-{
-    if (c.popt < 0 || c.popt >= kNumPOpt) return fail(BS_ERR_INVALID, "line config: bad chunk option");
-    if (c.nwaves != kPOpts[c.popt]) return fail(BS_ERR_INVALID, "line config: waves != chunk count");
-    if (c.tx < 1 || c.tx > 64 || (c.tx & (c.tx - 1))) return fail(BS_ERR_INVALID, "line config: bad tile width");
-    if (c.Lmax != 8 && c.Lmax != 16 && c.Lmax != 32 && c.Lmax != 64)
-        return fail(BS_ERR_INVALID, "line config: bad register chunk");
-    for (int p = 0; p < ps->npatch; ++p) {
-        const LineTabRef &r = ps->desc[p].line[axis][c.popt];
-        if (r.off < 0 || r.Lr > c.Lmax)
-            return fail(BS_ERR_UNSUPPORTED, "line config: patch %d axis %d has no chunk table for %d chunks", p, axis,
-                        kPOpts[c.popt]);
-    }
-    return BS_OK;
 }
 
 size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c)
@@ -149,44 +159,70 @@ size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c)
     return n * sizeof(double);
 }
 
+bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c)
+{
+    if (c.popt < 0 || c.popt >= kNumPOpt) return fail(BS_ERR_INVALID, "line config: bad chunk option");
+    if (c.nwaves != kPOpts[c.popt]) return fail(BS_ERR_INVALID, "line config: waves != chunk count");
+    if (c.tx < 1 || c.tx > 64 || (c.tx & (c.tx - 1))) return fail(BS_ERR_INVALID, "line config: bad tile width");
+    if (c.Lmax != 8 && c.Lmax != 16 && c.Lmax != 32 && c.Lmax != 64)
+        return fail(BS_ERR_INVALID, "line config: bad register chunk");
+    if (c.grid < 0) return fail(BS_ERR_INVALID, "line config: negative grid");
+    for (int p = 0; p < ps->npatch; ++p) {
+        const LineTabRef &r = ps->desc[p].line[axis][c.popt];
+        if (r.off < 0 || r.Lr > c.Lmax)
+            return fail(BS_ERR_UNSUPPORTED, "line config: patch %d axis %d has no chunk table for %d chunks", p, axis,
+                        kPOpts[c.popt]);
+    }
+    if (line_lds_bytes(ps, axis, c) > 160 * 1024) return fail(BS_ERR_UNSUPPORTED, "line config: LDS exceeds 160 KiB");
+    return BS_OK;
+}
+
 // One pass over the lines of `axis`: colour_mode 0 = all lines (one run);
 // colour_mode 1 with run = 0 / 1 = that colour only, run = 2 = both colours in
-// one launch, colour 0 dispatched first (chaotic).
+// one launch, colour 0 dispatched first (chaotic).  patch >= 0 restricts the
+// pass to one patch's items (one launch per patch and run).
 bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
-                    double *dst, const double *f, double omega, hipStream_t stream)
+                    double *dst, const double *f, double omega, hipStream_t stream, int patch)
 {
     const int kind = axis == 0 ? 1 : 0;
     WorkList *wl = nullptr;
     bs_status st = get_worklist(ps, kind, axis, c.popt, c.tx, colour_mode, &wl);
     if (st != BS_OK) return st;
-    int first = 0, count = wl->count[0];
-    if (colour_mode) {
-        if (run == 1) {
-            first = wl->count[0];
-            count = wl->count[1];
-        } else if (run == 2) {
-            count = wl->count[0] + wl->count[1];
-        }
-    }
-    if (count == 0) return BS_OK;
     LineArgs a{};
     a.src = src;
     a.dst = dst;
     a.f = f;
     a.pd = static_cast<const PatchDesc *>(ps->desc_d.p);
     a.tab = static_cast<const double *>(ps->tab_d.p);
-    a.items = static_cast<const WorkItem *>(wl->buf.p) + first;
     a.axis = axis;
     a.popt = c.popt;
     a.tx = c.tx;
     a.colour_mode = colour_mode;
     a.omega = omega;
     const size_t lds = line_lds_bytes(ps, axis, c);
-    if (lds > 160 * 1024) return fail(BS_ERR_UNSUPPORTED, "line sweep needs %zu bytes of LDS", lds);
-    hipError_t e = axis == 0 ? launch_line_x(a, count, c.Lmax, c.nwaves, lds, stream)
-                             : launch_line_strided(a, count, c.Lmax, c.nwaves, lds, stream);
-    if (e != hipSuccess) return hip_fail(e, "line sweep kernel");
-    return BS_OK;
+    const WorkItem *base = static_cast<const WorkItem *>(wl->buf.p);
+    auto launch = [&](int first, int count) -> bs_status {
+        if (count <= 0) return BS_OK;
+        a.items = base + first;
+        a.nitems = count;
+        const int grid = c.grid > 0 ? std::min(count, c.grid) : count;
+        hipError_t e = axis == 0 ? launch_line_x(a, grid, c.Lmax, c.nwaves, lds, stream)
+                                 : launch_line_strided(a, grid, c.Lmax, c.nwaves, lds, stream);
+        return e == hipSuccess ? BS_OK : hip_fail(e, "line sweep kernel");
+    };
+    if (patch >= 0) {
+        const int runs = colour_mode ? (run == 2 ? 2 : 1) : 1;
+        for (int k = 0; k < runs; ++k) {
+            const int cr = colour_mode ? (run == 2 ? k : run) : 0;
+            const int off = cr == 1 ? wl->count[0] : 0;
+            if ((st = launch(off + wl->pfirst[cr][patch], wl->pcount[cr][patch])) != BS_OK) return st;
+        }
+        return BS_OK;
+    }
+    if (!colour_mode) return launch(0, wl->count[0]);
+    if (run == 0) return launch(0, wl->count[0]);
+    if (run == 1) return launch(wl->count[0], wl->count[1]);
+    return launch(0, wl->count[0] + wl->count[1]);
 }
 
 const LineCfg &line_cfg(bs_patchset *ps, int axis, int colour_mode)
@@ -197,45 +233,29 @@ const LineCfg &line_cfg(bs_patchset *ps, int axis, int colour_mode)
     return itr->second;
 }
 
-}  // namespace bs
-
-using namespace bs;
-
-extern "C" {
-
-bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double omega, int32_t nsweeps,
-                        bs_precision prec, double *u, const double *f, double *work, hipStream_t stream)
+// The launch sequence of nsweeps line sweeps.  per_patch: one launch per
+// patch and colour run instead of one per run (the comparison baseline).
+bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const LineCfg &c, double omega,
+                              int nsweeps, double *u, const double *f, double *work, hipStream_t stream,
+                              bool per_patch)
 {
-    if (axis < 0 || axis > 2) return fail(BS_ERR_INVALID, "bs_line_relax: axis must be 0, 1 or 2");
-    if (scheme != BS_JACOBI && scheme != BS_CHAOTIC_GS && scheme != BS_COLORED_GS)
-        return fail(BS_ERR_INVALID, "bs_line_relax: unknown scheme");
-    if (!(omega > 0.0 && omega < 2.0)) return fail(BS_ERR_INVALID, "bs_line_relax: omega must be in (0, 2)");
-    if (nsweeps < 0) return fail(BS_ERR_INVALID, "bs_line_relax: nsweeps < 0");
-    if (prec != BS_FP64 && prec != BS_MIXED_FP32 && prec != BS_MIXED_BF16)
-        return fail(BS_ERR_INVALID, "bs_line_relax: unknown precision");
-    if (prec == BS_MIXED_BF16) return fail(BS_ERR_UNSUPPORTED, "bs_line_relax: BF16 is offered for planes only");
-    if (prec == BS_MIXED_FP32) return fail(BS_ERR_UNSUPPORTED, "bs_line_relax: FP32 line solves are not provided");
-    if (!ps || !u || !f) return fail(BS_ERR_INVALID, "bs_line_relax: null patch set, u or f");
-    if (scheme == BS_JACOBI && !work) return fail(BS_ERR_INVALID, "bs_line_relax: Jacobi needs a work buffer");
-    if (ps->max_n[axis] > 16 * kMaxChunkLen)
-        return fail(BS_ERR_UNSUPPORTED, "bs_line_relax: lines longer than %d cells", 16 * kMaxChunkLen);
-    if (axis == 0 && ps->max_n[0] > 256)
-        return fail(BS_ERR_UNSUPPORTED, "bs_line_relax: x-lines longer than 256 cells");
-    if (nsweeps == 0) return BS_OK;
-
-    const int cm = scheme == BS_JACOBI ? 0 : 1;
-    const LineCfg &c = line_cfg(ps, axis, cm);
-    bs_status st = check_line_cfg(ps, axis, c);
-    if (st != BS_OK) return st;
     const PatchDesc *pdd = static_cast<const PatchDesc *>(ps->desc_d.p);
-
+    bs_status st;
+    auto pass = [&](int cm, int run, const double *src, double *dst) -> bs_status {
+        if (!per_patch) return line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, -1);
+        for (int p = 0; p < ps->npatch; ++p) {
+            bs_status s2 = line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, p);
+            if (s2 != BS_OK) return s2;
+        }
+        return BS_OK;
+    };
     if (scheme == BS_JACOBI) {
         hipError_t e = launch_ghost_copy(u, work, pdd, ps->npatch, stream);
         if (e != hipSuccess) return hip_fail(e, "ghost copy");
         for (int s = 0; s < nsweeps; ++s) {
             const double *src = (s & 1) ? work : u;
             double *dst = (s & 1) ? u : work;
-            if ((st = line_pass(ps, axis, c, 0, 0, src, dst, f, omega, stream)) != BS_OK) return st;
+            if ((st = pass(0, 0, src, dst)) != BS_OK) return st;
         }
         if (nsweeps & 1) {
             e = launch_interior_copy(work, u, pdd, ps->npatch, stream);
@@ -245,13 +265,262 @@ bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double 
     }
     for (int s = 0; s < nsweeps; ++s) {
         if (scheme == BS_COLORED_GS) {
-            if ((st = line_pass(ps, axis, c, 1, 0, u, u, f, omega, stream)) != BS_OK) return st;
-            if ((st = line_pass(ps, axis, c, 1, 1, u, u, f, omega, stream)) != BS_OK) return st;
+            if ((st = pass(1, 0, u, u)) != BS_OK) return st;
+            if ((st = pass(1, 1, u, u)) != BS_OK) return st;
         } else {
-            if ((st = line_pass(ps, axis, c, 1, 2, u, u, f, omega, stream)) != BS_OK) return st;
+            if ((st = pass(1, 2, u, u)) != BS_OK) return st;
         }
     }
     return BS_OK;
+}
+
+// Build every work list a sequence needs before any capture begins.
+bs_status prepare_lists(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode)
+{
+    WorkList *wl;
+    return get_worklist(ps, axis == 0 ? 1 : 0, axis, c.popt, c.tx, colour_mode, &wl);
+}
+
+}  // namespace bs
+
+bs_patchset::~bs_patchset()
+{
+    bs::clear_graphs(this);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+}
+
+using namespace bs;
+
+namespace {
+
+bs_status check_line_args(int32_t axis, bs_scheme scheme, double omega, int32_t nsweeps, bs_precision prec,
+                          const char *fn)
+{
+    if (axis < 0 || axis > 2) return fail(BS_ERR_INVALID, "%s: axis must be 0, 1 or 2", fn);
+    if (scheme != BS_JACOBI && scheme != BS_CHAOTIC_GS && scheme != BS_COLORED_GS)
+        return fail(BS_ERR_INVALID, "%s: unknown scheme", fn);
+    if (!(omega > 0.0 && omega < 2.0)) return fail(BS_ERR_INVALID, "%s: omega must be in (0, 2)", fn);
+    if (nsweeps < 0) return fail(BS_ERR_INVALID, "%s: nsweeps < 0", fn);
+    if (prec != BS_FP64 && prec != BS_MIXED_FP32 && prec != BS_MIXED_BF16)
+        return fail(BS_ERR_INVALID, "%s: unknown precision", fn);
+    if (prec == BS_MIXED_BF16) return fail(BS_ERR_UNSUPPORTED, "%s: BF16 is offered for planes only", fn);
+    if (prec == BS_MIXED_FP32) return fail(BS_ERR_UNSUPPORTED, "%s: FP32 line solves are not provided", fn);
+    return BS_OK;
+}
+
+bs_status check_line_ps(const bs_patchset *ps, int32_t axis, const char *fn)
+{
+    if (ps->max_n[axis] > 16 * kMaxChunkLen)
+        return fail(BS_ERR_UNSUPPORTED, "%s: lines longer than %d cells", fn, 16 * kMaxChunkLen);
+    if (axis == 0 && ps->max_n[0] > 256) return fail(BS_ERR_UNSUPPORTED, "%s: x-lines longer than 256 cells", fn);
+    return BS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double omega, int32_t nsweeps,
+                        bs_precision prec, double *u, const double *f, double *work, hipStream_t stream)
+{
+    bs_status st = check_line_args(axis, scheme, omega, nsweeps, prec, "bs_line_relax");
+    if (st != BS_OK) return st;
+    if (!ps || !u || !f) return fail(BS_ERR_INVALID, "bs_line_relax: null patch set, u or f");
+    if (scheme == BS_JACOBI && !work) return fail(BS_ERR_INVALID, "bs_line_relax: Jacobi needs a work buffer");
+    if ((st = check_line_ps(ps, axis, "bs_line_relax")) != BS_OK) return st;
+    if (nsweeps == 0) return BS_OK;
+    const int cm = scheme == BS_JACOBI ? 0 : 1;
+    const LineCfg c = line_cfg(ps, axis, cm);
+    if ((st = check_line_cfg(ps, axis, c)) != BS_OK) return st;
+    if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;
+    hipError_t e = prepare_line_kernels();
+    if (e != hipSuccess) return hip_fail(e, "line kernel attributes");
+    if (!ps->use_graphs || nsweeps < 2)
+        return enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, stream, false);
+
+    // replay a captured graph of the whole sequence (captured on first use)
+    int64_t obits;
+    std::memcpy(&obits, &omega, sizeof obits);
+    const std::vector<int64_t> key{0, axis, scheme, obits, nsweeps, reinterpret_cast<int64_t>(u),
+                                   reinterpret_cast<int64_t>(f), reinterpret_cast<int64_t>(work), c.popt, c.tx,
+                                   c.grid, c.Lmax};
+    auto itr = ps->graphs.find(key);
+    if (itr == ps->graphs.end()) {
+        if (ps->graphs.size() >= 64) clear_graphs(ps);
+        if (!ps->capture_stream &&
+            (e = hipStreamCreateWithFlags(&ps->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "capture stream");
+        hipGraph_t graph = nullptr;
+        if ((e = hipStreamBeginCapture(ps->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        st = enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, ps->capture_stream, false);
+        e = hipStreamEndCapture(ps->capture_stream, &graph);
+        if (st != BS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        itr = ps->graphs.emplace(key, exec).first;
+    }
+    if ((e = hipGraphLaunch(itr->second, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return BS_OK;
+}
+
+bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, const double *u, const double *f,
+                           hipStream_t stream)
+{
+    bs_status st = check_line_args(axis, scheme, 1.0, 1, BS_FP64, "bs_autotune_line");
+    if (st != BS_OK) return st;
+    if (!ps || !u || !f) return fail(BS_ERR_INVALID, "bs_autotune_line: null patch set, u or f");
+    if ((st = check_line_ps(ps, axis, "bs_autotune_line")) != BS_OK) return st;
+    hipError_t e = prepare_line_kernels();
+    if (e != hipSuccess) return hip_fail(e, "line kernel attributes");
+    const int cm = scheme == BS_JACOBI ? 0 : 1;
+    DevBuf su, sw;
+    const size_t bytes = static_cast<size_t>(ps->u_numel) * sizeof(double);
+    if ((st = dev_alloc(su, bytes, "autotune scratch")) != BS_OK) return st;
+    if ((st = dev_alloc(sw, bytes, "autotune scratch")) != BS_OK) return st;
+    if ((e = hipMemcpyAsync(su.p, u, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess) return hip_fail(e, "copy");
+    if ((e = hipMemcpyAsync(sw.p, u, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess) return hip_fail(e, "copy");
+    std::vector<LineCfg> cands;
+    const int cus = device_cus();
+    for (int o = 0; o < kNumPOpt; ++o) {
+        int lr_max = 0;
+        bool ok = true;
+        for (int p = 0; p < ps->npatch; ++p) {
+            const LineTabRef &r = ps->desc[p].line[axis][o];
+            if (r.off < 0) ok = false;
+            lr_max = std::max(lr_max, r.Lr);
+        }
+        if (!ok) continue;
+        const int Lmax = lmax_for(lr_max);
+        // shapes that would spill registers on gfx950 are not candidates
+        if ((Lmax == 32 && kPOpts[o] > 8) || (Lmax == 64 && kPOpts[o] > 4)) continue;
+        for (int tx : {64, 32, 16, 8}) {
+            if (axis == 0 && tx != 64) continue;
+            for (int grid : {0, 4 * cus, 8 * cus}) {
+                LineCfg c;
+                c.popt = o;
+                c.nwaves = kPOpts[o];
+                c.Lmax = Lmax;
+                c.tx = tx;
+                c.grid = grid;
+                if (check_line_cfg(ps, axis, c) == BS_OK) cands.push_back(c);
+            }
+        }
+    }
+    if (cands.empty()) return fail(BS_ERR_UNSUPPORTED, "bs_autotune_line: no valid configuration");
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "event");
+    }
+    double best_ms = 1e30;
+    LineCfg best = cands[0];
+    double *pu = static_cast<double *>(su.p), *pw = static_cast<double *>(sw.p);
+    for (const LineCfg &c : cands) {
+        if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) break;
+        double tmin = 1e30;
+        for (int rep = 0; rep < 4 && st == BS_OK; ++rep) {
+            (void)hipEventRecord(e0, stream);
+            st = enqueue_line_sweeps(ps, axis, scheme, c, scheme == BS_JACOBI ? 0.8 : 1.0, 2, pu, f, pw, stream,
+                                     false);
+            (void)hipEventRecord(e1, stream);
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+                st = hip_fail(e, "autotune timing");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) tmin = std::min(tmin, static_cast<double>(ms));
+        }
+        if (st != BS_OK) break;
+        if (tmin < best_ms) {
+            best_ms = tmin;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != BS_OK) return st;
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "autotune");
+    ps->line_cfg[std::make_pair(static_cast<int>(axis), cm)] = best;
+    clear_graphs(ps);
+    return BS_OK;
+}
+
+bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, int32_t cfg_host[5])
+{
+    if (!ps || !cfg_host) return fail(BS_ERR_INVALID, "bs_line_config: null argument");
+    if (axis < 0 || axis > 2) return fail(BS_ERR_INVALID, "bs_line_config: axis must be 0, 1 or 2");
+    const int cm = scheme == BS_JACOBI ? 0 : 1;
+    auto itr = ps->line_cfg.find(std::make_pair(static_cast<int>(axis), cm));
+    const bool set = itr != ps->line_cfg.end();
+    const LineCfg c = set ? itr->second : default_line_cfg(ps, axis, cm);
+    cfg_host[0] = kPOpts[c.popt];
+    cfg_host[1] = c.Lmax;
+    cfg_host[2] = c.tx;
+    cfg_host[3] = c.grid;
+    cfg_host[4] = set ? 1 : 0;
+    return BS_OK;
+}
+
+// Host-side hooks (not part of the public header).
+
+// Set the launch configuration of line sweeps along `axis` for the Jacobi
+// (colour_mode 0) or Gauss-Seidel (colour_mode 1) kernels: popt indexes the
+// chunk counts {1,2,4,8,16}; tx is the strided kernel's lanes per row; grid is
+// the persistent grid size (0: one workgroup per work item).
+int bsi_set_line_cfg(bs_patchset *ps, int axis, int colour_mode, int popt, int tx, int grid)
+{
+    if (!ps || axis < 0 || axis > 2 || colour_mode < 0 || colour_mode > 1) return BS_ERR_INVALID;
+    if (popt < 0 || popt >= kNumPOpt) return BS_ERR_INVALID;
+    LineCfg c;
+    c.popt = popt;
+    c.nwaves = kPOpts[popt];
+    c.tx = tx;
+    c.grid = grid;
+    int lr_max = 0;
+    for (int p = 0; p < ps->npatch; ++p) {
+        if (ps->desc[p].line[axis][popt].off < 0) return BS_ERR_UNSUPPORTED;
+        lr_max = std::max(lr_max, ps->desc[p].line[axis][popt].Lr);
+    }
+    c.Lmax = lmax_for(lr_max);
+    bs_status st = check_line_cfg(ps, axis, c);
+    if (st != BS_OK) return st;
+    ps->line_cfg[std::make_pair(axis, colour_mode)] = c;
+    clear_graphs(ps);
+    return BS_OK;
+}
+
+// Enable (1) or disable (0) graph capture of sweep sequences.
+int bsi_set_graphs(bs_patchset *ps, int enable)
+{
+    if (!ps) return BS_ERR_INVALID;
+    ps->use_graphs = enable != 0;
+    return BS_OK;
+}
+
+// The same sweeps as bs_line_relax with one launch per patch and colour run
+// (no graph): the per-patch baseline that one batched launch replaces.
+int bsi_line_relax_per_patch(bs_patchset *ps, int32_t axis, bs_scheme scheme, double omega, int32_t nsweeps,
+                             double *u, const double *f, double *work, hipStream_t stream)
+{
+    bs_status st = check_line_args(axis, scheme, omega, nsweeps, BS_FP64, "bsi_line_relax_per_patch");
+    if (st != BS_OK) return st;
+    if (!ps || !u || !f || (scheme == BS_JACOBI && !work)) return BS_ERR_INVALID;
+    if ((st = check_line_ps(ps, axis, "bsi_line_relax_per_patch")) != BS_OK) return st;
+    const int cm = scheme == BS_JACOBI ? 0 : 1;
+    const LineCfg c = line_cfg(ps, axis, cm);
+    if ((st = check_line_cfg(ps, axis, c)) != BS_OK) return st;
+    if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;
+    if (prepare_line_kernels() != hipSuccess) return BS_ERR_HIP;
+    return enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, stream, true);
 }
 
 size_t bs_backward_workspace_bytes(const bs_patchset *ps, int32_t axis, int32_t nsweeps, int32_t ckpt_every)
@@ -279,30 +548,6 @@ bs_status bs_relax_backward(bs_patchset *ps, int32_t axis, double omega, int32_t
     if (nsweeps < 0 || ckpt_every < 1) return fail(BS_ERR_INVALID, "bs_relax_backward: bad nsweeps or ckpt_every");
     if (!ps || !u0 || !f || !grad_uK) return fail(BS_ERR_INVALID, "bs_relax_backward: null argument");
     return fail(BS_ERR_UNSUPPORTED, "bs_relax_backward: not built yet");
-}
-
-// Host-side tuning hook (not part of the public header): set the launch
-// configuration of line sweeps along `axis` for the Jacobi (colour_mode 0) or
-// Gauss-Seidel (colour_mode 1) kernels.  popt indexes the chunk counts
-// {1,2,4,8,16}; tx is the strided kernel's lanes per row (power of two <= 64).
-int bsi_set_line_cfg(bs_patchset *ps, int axis, int colour_mode, int popt, int tx)
-{
-    if (!ps || axis < 0 || axis > 2 || colour_mode < 0 || colour_mode > 1) return BS_ERR_INVALID;
-    if (popt < 0 || popt >= kNumPOpt) return BS_ERR_INVALID;
-    LineCfg c;
-    c.popt = popt;
-    c.nwaves = kPOpts[popt];
-    c.tx = tx;
-    int lr_max = 0;
-    for (int p = 0; p < ps->npatch; ++p) {
-        if (ps->desc[p].line[axis][popt].off < 0) return BS_ERR_UNSUPPORTED;
-        lr_max = std::max(lr_max, ps->desc[p].line[axis][popt].Lr);
-    }
-    c.Lmax = lr_max <= 8 ? 8 : lr_max <= 16 ? 16 : lr_max <= 32 ? 32 : 64;
-    bs_status st = check_line_cfg(ps, axis, c);
-    if (st != BS_OK) return st;
-    ps->line_cfg[std::make_pair(axis, colour_mode)] = c;
-    return BS_OK;
 }
 
 }  // extern "C"

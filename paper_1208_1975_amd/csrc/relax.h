@@ -10,7 +10,12 @@ LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode);
 bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c);
 size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c);
 bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
-                    double *dst, const double *f, double omega, hipStream_t stream);
+                    double *dst, const double *f, double omega, hipStream_t stream, int patch);
 const LineCfg &line_cfg(bs_patchset *ps, int axis, int colour_mode);
+bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const LineCfg &c, double omega,
+                              int nsweeps, double *u, const double *f, double *work, hipStream_t stream,
+                              bool per_patch);
+bs_status prepare_lists(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode);
+void clear_graphs(bs_patchset *ps);
 
 }  // namespace bs
