@@ -302,3 +302,51 @@ class PatchSet:
     def line_relax_per_patch(self, axis, scheme, omega, nsweeps, u, f, work=None, stream=None):
         _check(lib().bsi_line_relax_per_patch(self.handle, int(axis), _scheme(scheme), float(omega), int(nsweeps),
                                              _ptr(u), _ptr(f), _ptr(work), _stream(stream)))
+
+
+# --- differentiable smoother ---------------------------------------------------
+
+class LineJacobiFn(torch.autograd.Function):
+    """u_K = K damped Jacobi line sweeps along `axis` from (f, u0) with axis
+    weights eps, differentiable in f, u0 (incl. face ghosts) and eps through
+    the library's adjoint kernels, recomputing states from checkpoints taken
+    every `ckpt` sweeps.
+
+    apply(f, u0, eps, ps, axis, omega, K, ckpt): f and u0 in the patch set's
+    f / u layouts (float64, on the device), eps a (npatch, 3) float64 tensor,
+    ps a PatchSet whose eps is reset to `eps` when it differs."""
+
+    @staticmethod
+    def forward(ctx, f, u0, eps, ps, axis, omega, K, ckpt):
+        _sync_eps(ps, eps)
+        u = u0.detach().clone()
+        work = torch.empty_like(u)
+        ps.line_relax(axis, "jacobi", omega, K, u, f.detach(), work)
+        ctx.save_for_backward(f, u0, eps)
+        ctx.cfg = (ps, int(axis), float(omega), int(K), int(ckpt))
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_uK):
+        f, u0, eps = ctx.saved_tensors
+        ps, axis, omega, K, ckpt = ctx.cfg
+        _sync_eps(ps, eps)
+        nbytes = bs_backward_workspace_bytes(ps.handle, axis, K, ckpt)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=u0.device)
+        g_u0 = torch.zeros_like(u0)     # alignment gaps between patches stay 0
+        g_f = torch.zeros_like(f)
+        g_eps = torch.empty(ps.npatch * 3, dtype=torch.float64, device=u0.device)
+        bs_relax_backward(ps.handle, axis, omega, K, ckpt, u0.detach(), f.detach(), grad_uK.contiguous(),
+                          g_u0, g_f, g_eps, ws)
+        return g_f, g_u0, g_eps.view(eps.shape).to(eps.device), None, None, None, None, None
+
+
+def _sync_eps(ps, eps):
+    e = [tuple(float(v) for v in row) for row in eps.detach().cpu().reshape(-1, 3).tolist()]
+    if e != ps.eps:
+        ps.set_eps(e)
+
+
+def line_jacobi(f, u0, eps, ps, axis=2, omega=0.8, K=20, ckpt=5):
+    """Differentiable K-sweep damped Jacobi line smoother (see LineJacobiFn)."""
+    return LineJacobiFn.apply(f, u0, eps, ps, axis, omega, K, ckpt)

@@ -63,6 +63,8 @@ struct LineArgs {
     int32_t tx;             // lanes per row along the fast free axis (strided kernel)
     int32_t colour_mode;    // 0: every line; 1: only lines of the item's colour
     int32_t nitems;         // work items; a workgroup takes items blockIdx.x, +gridDim.x, ...
+    int32_t rhs_mode;       // 0: right-hand side = residual h^2 f - A src; 1: = src itself (f unused)
+    int32_t out_mode;       // 0: dst = src + omega du; 1: dst = du (the block solve alone)
     double omega;
 };
 
@@ -90,5 +92,14 @@ hipError_t launch_interior_copy(const double *src, double *dst, const PatchDesc 
                                 hipStream_t s);
 
 constexpr int kResidCellsPerBlock = 2048;   // cells per residual block (256 threads x 8)
+
+// Adjoint of damped Jacobi line sweeps (k_adjoint.hip).
+hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);
+hipError_t launch_adj_init(const double *gK, double *gbar, const PatchDesc *pd, int npatch, hipStream_t s);
+hipError_t launch_adj_step(const double *lam, const double *U, const double *w, double *gbar, double *gf,
+                           double *acc, const PatchDesc *pd, const int32_t *block_patch,
+                           const int32_t *block_first, int nblocks, int axis, double omega, hipStream_t s);
+hipError_t launch_eps_final(const double *acc, const int32_t *first_block, int npatch, double omega, double *out,
+                            hipStream_t s);
 
 }  // namespace bs

@@ -169,6 +169,10 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const WorkI
     }
     const double ulo = s[cu - Sa];
     const double uhi = s[cu + (int64_t)Lp * Sa];
+    if (a.rhs_mode) {
+#pragma unroll
+        for (int t = 0; t < L; ++t) r[t] = uc[t];
+    } else {
 #pragma unroll
     for (int tb = 0; tb < L; tb += B) {
         double fb[B], om[B], op[B];
@@ -213,6 +217,7 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const WorkI
         const double xs = (load_l ? 0.0 : left) + (load_r ? 0.0 : right);
         r[t] = fma(-d, uc[t], fma(ex, xs, fma(ea, um + up, r[t])));
     }
+    }
     double y0, yl;
     __syncthreads();   // table in LDS
     chunk_solve<L>(r, Lp, Lr, tab, tab + Lr, ea, y0, yl);
@@ -229,7 +234,7 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const WorkI
         for (int t = 0; t < L; ++t) {
             if (t < Lp) {
                 const double du = fma(anext, ew[t], fma(bprev, ev[t], r[t]));
-                a.dst[cu + t * Sa] = fma(om, du, uc[t]);
+                a.dst[cu + t * Sa] = a.out_mode ? du : fma(om, du, uc[t]);
             }
         }
     }
@@ -313,8 +318,12 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const WorkItem it
             at[m] = (idx < ncell && bu >= 0) ? row * sd + i : -1;
             const int64_t c = (bu >= 0 ? bu : safe_u) + i;
             const int64_t fc = (bu >= 0 ? rowf[row] : safe_f) + i;
-            const double nb = ex * (s[c - 1] + s[c + 1]) + ey * (s[c - sx] + s[c + sx]) + ez * (s[c - sy] + s[c + sy]);
-            res[m] = fma(-d, s[c], fma(h2, a.f[fc], nb));
+            if (a.rhs_mode) {
+                res[m] = s[c];
+            } else {
+                const double nb = ex * (s[c - 1] + s[c + 1]) + ey * (s[c - sx] + s[c + sx]) + ez * (s[c - sy] + s[c + sy]);
+                res[m] = fma(-d, s[c], fma(h2, a.f[fc], nb));
+            }
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -361,7 +370,7 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const WorkItem it
             const int row = idc / nx, i = idc - row * nx;
             const int64_t bu = rowu[row];
             dst[m] = (idx < ncell && bu >= 0) ? bu + i : -1;
-            val[m] = fma(om, rb[row * sd + i], s[(bu >= 0 ? bu : safe_u) + i]);
+            val[m] = a.out_mode ? rb[row * sd + i] : fma(om, rb[row * sd + i], s[(bu >= 0 ? bu : safe_u) + i]);
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m)

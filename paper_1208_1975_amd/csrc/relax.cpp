@@ -182,7 +182,8 @@ bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c)
 // one launch, colour 0 dispatched first (chaotic).  patch >= 0 restricts the
 // pass to one patch's items (one launch per patch and run).
 bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
-                    double *dst, const double *f, double omega, hipStream_t stream, int patch)
+                    double *dst, const double *f, double omega, hipStream_t stream, int patch, int rhs_mode,
+                    int out_mode)
 {
     const int kind = axis == 0 ? 1 : 0;
     WorkList *wl = nullptr;
@@ -198,6 +199,8 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
     a.popt = c.popt;
     a.tx = c.tx;
     a.colour_mode = colour_mode;
+    a.rhs_mode = rhs_mode;
+    a.out_mode = out_mode;
     a.omega = omega;
     const size_t lds = line_lds_bytes(ps, axis, c);
     const WorkItem *base = static_cast<const WorkItem *>(wl->buf.p);
@@ -242,9 +245,9 @@ bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const
     const PatchDesc *pdd = static_cast<const PatchDesc *>(ps->desc_d.p);
     bs_status st;
     auto pass = [&](int cm, int run, const double *src, double *dst) -> bs_status {
-        if (!per_patch) return line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, -1);
+        if (!per_patch) return line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, -1, 0, 0);
         for (int p = 0; p < ps->npatch; ++p) {
-            bs_status s2 = line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, p);
+            bs_status s2 = line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, p, 0, 0);
             if (s2 != BS_OK) return s2;
         }
         return BS_OK;
@@ -317,6 +320,10 @@ bs_status check_line_ps(const bs_patchset *ps, int32_t axis, const char *fn)
 }
 
 }  // namespace
+
+namespace bs {
+bs_status check_line_ps_ext(const bs_patchset *ps, int32_t axis, const char *fn) { return check_line_ps(ps, axis, fn); }
+}  // namespace bs
 
 extern "C" {
 
@@ -521,33 +528,6 @@ int bsi_line_relax_per_patch(bs_patchset *ps, int32_t axis, bs_scheme scheme, do
     if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;
     if (prepare_line_kernels() != hipSuccess) return BS_ERR_HIP;
     return enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, stream, true);
-}
-
-size_t bs_backward_workspace_bytes(const bs_patchset *ps, int32_t axis, int32_t nsweeps, int32_t ckpt_every)
-{
-    (void)ps;
-    (void)axis;
-    (void)nsweeps;
-    (void)ckpt_every;
-    return 0;
-}
-
-bs_status bs_relax_backward(bs_patchset *ps, int32_t axis, double omega, int32_t nsweeps, int32_t ckpt_every,
-                            const double *u0, const double *f, const double *grad_uK, double *grad_u0,
-                            double *grad_f, double *grad_eps, void *workspace, size_t workspace_bytes,
-                            hipStream_t stream)
-{
-    (void)grad_u0;
-    (void)grad_f;
-    (void)grad_eps;
-    (void)workspace;
-    (void)workspace_bytes;
-    (void)stream;
-    if (axis < 0 || axis > 2) return fail(BS_ERR_INVALID, "bs_relax_backward: axis must be 0, 1 or 2");
-    if (!(omega > 0.0 && omega < 2.0)) return fail(BS_ERR_INVALID, "bs_relax_backward: omega must be in (0, 2)");
-    if (nsweeps < 0 || ckpt_every < 1) return fail(BS_ERR_INVALID, "bs_relax_backward: bad nsweeps or ckpt_every");
-    if (!ps || !u0 || !f || !grad_uK) return fail(BS_ERR_INVALID, "bs_relax_backward: null argument");
-    return fail(BS_ERR_UNSUPPORTED, "bs_relax_backward: not built yet");
 }
 
 }  // extern "C"

@@ -9,13 +9,17 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
 LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode);
 bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c);
 size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c);
+// rhs_mode 0: right-hand side = residual of src; 1: = src itself.
+// out_mode 0: dst = src + omega du; 1: dst = du.
 bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
-                    double *dst, const double *f, double omega, hipStream_t stream, int patch);
+                    double *dst, const double *f, double omega, hipStream_t stream, int patch, int rhs_mode,
+                    int out_mode);
 const LineCfg &line_cfg(bs_patchset *ps, int axis, int colour_mode);
 bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const LineCfg &c, double omega,
                               int nsweeps, double *u, const double *f, double *work, hipStream_t stream,
                               bool per_patch);
 bs_status prepare_lists(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode);
 void clear_graphs(bs_patchset *ps);
+bs_status check_line_ps_ext(const bs_patchset *ps, int32_t axis, const char *fn);
 
 }  // namespace bs
