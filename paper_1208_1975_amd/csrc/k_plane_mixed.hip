@@ -1,0 +1,220 @@
+// Mixed-precision plane solves: the four fast-diagonalisation products in FP32
+// or BF16 on the matrix cores with FP32 accumulation, while the residual, the
+// defect of the refinement and the update stay in FP64.  For the plane block
+// M_P and residual R (FP64), the correction D solves M_P D = R by
+//   D_0 = M~^{-1} R,  D_{j+1} = D_j + M~^{-1}(R - M_P D_j)   (j < refine)
+// with M~^{-1} the low-precision transform chain, M_P D_j applied in FP64,
+// and finally u += omega D in FP64.
+#include "bs_internal.h"
+#include "plane.h"
+
+namespace bs {
+
+namespace {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 64, BN = 64, BK = 32;
+
+}  // namespace
+
+// C_b = A_b B_b with float operands in memory.  PREC 1: FP32 products
+// (v_mfma_f32_16x16x4_f32); PREC 2: operands rounded to BF16
+// (v_mfma_f32_16x16x32_bf16).  FP32 accumulation in both.
+template <int PREC, int EPI>
+__global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
+{
+    // A tile row-major [m][k]; B tile stored [n][k] (k contiguous) for BF16,
+    // [k][n] for FP32
+    __shared__ float As[BM][BK + 1];
+    __shared__ float Bs[BK > BN ? BK : BN][(BK > BN ? BK : BN) + 1];
+    const int b = blockIdx.z;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const float *A = g.A + (int64_t)b * g.sA;
+    const float *B = g.B + (int64_t)b * g.sB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int l16 = lane & 15, lk = lane >> 4;
+
+    flt4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+        for (int q = 0; q < (BM * BK) / 256; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e / BK, c = e % BK;
+            const int gr = m0 + r, gc = k0 + c;
+            As[r][c] = (gr < g.M && gc < g.K) ? A[(int64_t)gr * g.lda + gc] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < (BK * BN) / 256; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e / BN, c = e % BN;
+            const int gr = k0 + r, gc = n0 + c;
+            const float v = (gr < g.K && gc < g.N) ? B[(int64_t)gr * g.ldb + gc] : 0.f;
+            if (PREC == 2)
+                Bs[c][r] = v;
+            else
+                Bs[r][c] = v;
+        }
+        __syncthreads();
+        if (PREC == 1) {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                float af[2], bfr[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) af[i] = As[wm * 32 + i * 16 + l16][kk + lk];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) bfr[j] = Bs[kk + lk][wn * 32 + j * 16 + l16];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
+            }
+        } else {
+            // one K=32 step: lane supplies k = 8*(lane/16) .. +7 of its row / column
+            bf8 af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) af[i][t] = (__bf16)As[wm * 32 + i * 16 + l16][8 * lk + t];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) bfr[j][t] = (__bf16)Bs[wn * 32 + j * 16 + l16][8 * lk + t];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // D layout of the FP32 16x16 block: register r of a lane holds row
+    // 4*(lane/16) + r, column lane%16 (checked by the layout test)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 32 + i * 16 + (g.dlayout ? r * 4 + lk : lk * 4 + r);
+                const int col = n0 + wn * 32 + j * 16 + l16;
+                if (row >= g.M || col >= g.N) continue;
+                const float v = acc[i][j][r];
+                const int64_t ci = (int64_t)b * g.sC + (int64_t)row * g.ldc + col;
+                if (EPI == kEpiStore) {
+                    g.C[ci] = v;
+                } else if (EPI == kEpiScale) {
+                    g.C[ci] = v * g.scale[(int64_t)b * g.sc_b + (int64_t)row * g.sc_m + (int64_t)col * g.sc_n];
+                } else if (EPI == kEpiD64) {
+                    g.D[ci] = g.accumulate ? g.D[ci] + (double)v : (double)v;
+                } else {
+                    if (g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour) continue;
+                    const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
+                    g.udst[u] = fma(g.omega, (double)v, g.usrc[u]);
+                }
+            }
+}
+
+// E = (float)(R - M_P D) on every cell of one patch (D may be null: E = R),
+// M_P the plane block with normal c: d D - eps_a (in-plane neighbours along a)
+// - eps_b (along b), zero beyond the plane's edges.  blockIdx.y: unused.
+__global__ void __launch_bounds__(256) k_plane_defect(const double *R, const double *D, float *E, int nx, int ny,
+                                                      int nz, int normal, double ex, double ey, double ez)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const double d = 2.0 * (ex + ey + ez);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        double v = R[c];
+        if (D) {
+            const int i = (int)(c % nx);
+            const int j = (int)((c / nx) % ny);
+            const int k = (int)(c / ((int64_t)nx * ny));
+            double md = d * D[c];
+            if (normal != 0) {
+                if (i > 0) md -= ex * D[c - 1];
+                if (i < nx - 1) md -= ex * D[c + 1];
+            }
+            if (normal != 1) {
+                if (j > 0) md -= ey * D[c - nx];
+                if (j < ny - 1) md -= ey * D[c + nx];
+            }
+            if (normal != 2) {
+                const int64_t pl = (int64_t)nx * ny;
+                if (k > 0) md -= ez * D[c - pl];
+                if (k < nz - 1) md -= ez * D[c + pl];
+            }
+            v -= md;
+        }
+        E[c] = (float)v;
+    }
+}
+
+// dst = src + omega D on the interior cells of one patch whose plane index
+// (along `normal`) has parity `colour` (all cells if colour < 0).
+__global__ void __launch_bounds__(256) k_plane_update(const double *D, const double *src, double *dst, int64_t uoff,
+                                                      int nx, int ny, int nz, int normal, int colour, double omega)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx);
+        const int j = (int)((c / nx) % ny);
+        const int k = (int)(c / ((int64_t)nx * ny));
+        const int s = normal == 0 ? i : (normal == 1 ? j : k);
+        if (colour >= 0 && (s & 1) != colour) continue;
+        const int64_t u = uoff + (int64_t)(k + 1) * sy + (int64_t)(j + 1) * sx + (i + 1);
+        dst[u] = fma(omega, D[c], src[u]);
+    }
+}
+
+template <int PREC>
+static hipError_t launch_mixed_t(const GemmMixedArgs &g, int epi, hipStream_t s)
+{
+    const dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
+    switch (epi) {
+    case kEpiStore: hipLaunchKernelGGL((k_gemm_mixed<PREC, kEpiStore>), grid, dim3(256), 0, s, g); break;
+    case kEpiScale: hipLaunchKernelGGL((k_gemm_mixed<PREC, kEpiScale>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_mixed<PREC, kEpiUpdate>), grid, dim3(256), 0, s, g); break;
+    case kEpiD64: hipLaunchKernelGGL((k_gemm_mixed<PREC, kEpiD64>), grid, dim3(256), 0, s, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
+    return prec == 2 ? launch_mixed_t<2>(g, epi, s) : launch_mixed_t<1>(g, epi, s);
+}
+
+hipError_t launch_plane_defect(const double *R, const double *D, float *E, int nx, int ny, int nz, int normal,
+                               const double eps[3], hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_plane_defect, dim3(blocks), dim3(256), 0, s, R, D, E, nx, ny, nz, normal, eps[0], eps[1],
+                       eps[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_update(const double *D, const double *src, double *dst, int64_t uoff, int nx, int ny, int nz,
+                               int normal, int colour, double omega, hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_plane_update, dim3(blocks), dim3(256), 0, s, D, src, dst, uoff, nx, ny, nz, normal, colour,
+                       omega);
+    return hipGetLastError();
+}
+
+}  // namespace bs

@@ -74,6 +74,8 @@ struct bs_patchset {
     // patch and normal axis (built on first use), and two f-layout scratch fields
     bool plane_ready = false;
     bs::DevBuf plane_tab_d, plane_r_d, plane_t_d;
+    bs::DevBuf plane_tab32_d, plane_f1_d, plane_f2_d;   // FP32 copies and float scratch (mixed precision)
+    int mixed_dlayout = 0;
     std::vector<int64_t> basis_off, lam_off;   // [3 * npatch] each, offsets in doubles
     // cached work lists and tuned configurations
     std::map<bs::WorkKey, std::unique_ptr<bs::WorkList>> lists;

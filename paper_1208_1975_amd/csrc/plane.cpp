@@ -1,5 +1,6 @@
 // Plane-block relaxation driver: tables, scratch and the four-product chain
-// of fast diagonalisation for each plane orientation.
+// of fast diagonalisation for each plane orientation, in FP64 or mixed
+// precision (FP32 / BF16 products, FP64 residual, defect and update).
 #include <algorithm>
 #include <cmath>
 
@@ -16,7 +17,7 @@ constexpr int kMaxPlaneEdge = 1024;
 
 // Bases S_x, S_y, S_z of every patch and the inverse eigenvalue grid of every
 // (patch, normal):  normal z: [q_y][p_x] = 1/(sigma_y,q + sigma_x,p + 2 eps_z);
-// normal y: [q_z][p_x]; normal x: [q_z][q_y].
+// normal y: [q_z][p_x]; normal x: [q_z][q_y].  FP32 copies share the offsets.
 bs_status build_plane_tables(bs_patchset *ps)
 {
     std::vector<double> tab;
@@ -34,9 +35,8 @@ bs_status build_plane_tables(bs_patchset *ps)
             sg[a] = sine_eigenvalues(n[a], e[a]);
         }
         for (int c = 0; c < 3; ++c) {
-            // rows (slow index) and columns (fast index) of the grid
-            const int ar = c == 0 ? 2 : (c == 1 ? 2 : 1);
-            const int ac = c == 0 ? 1 : 0;
+            const int ar = c == 0 ? 2 : (c == 1 ? 2 : 1);   // grid rows (slow index)
+            const int ac = c == 0 ? 1 : 0;                   // grid columns
             ps->lam_off[3 * p + c] = static_cast<int64_t>(tab.size());
             for (int q = 0; q < n[ar]; ++q)
                 for (int r = 0; r < n[ac]; ++r)
@@ -46,6 +46,8 @@ bs_status build_plane_tables(bs_patchset *ps)
     }
     bs_status st = upload(ps->plane_tab_d, tab.data(), tab.size() * sizeof(double), "plane tables");
     if (st != BS_OK) return st;
+    std::vector<float> tab32(tab.begin(), tab.end());
+    if ((st = upload(ps->plane_tab32_d, tab32.data(), tab32.size() * sizeof(float), "plane tables")) != BS_OK) return st;
     if (!ps->plane_r_d.p) {
         if ((st = dev_alloc(ps->plane_r_d, static_cast<size_t>(ps->f_numel) * 8, "plane scratch")) != BS_OK) return st;
         if ((st = dev_alloc(ps->plane_t_d, static_cast<size_t>(ps->f_numel) * 8, "plane scratch")) != BS_OK) return st;
@@ -54,75 +56,213 @@ bs_status build_plane_tables(bs_patchset *ps)
     return BS_OK;
 }
 
-GemmArgs gemm(const double *A, int64_t lda, int64_t sA, const double *B, int64_t ldb, int64_t sB, double *C,
-              int64_t ldc, int64_t sC, int M, int N, int K, int batch)
+bs_status ensure_mixed_scratch(bs_patchset *ps)
 {
-    GemmArgs g{};
-    g.A = A; g.lda = lda; g.sA = sA;
-    g.B = B; g.ldb = ldb; g.sB = sB;
-    g.C = C; g.ldc = ldc; g.sC = sC;
-    g.M = M; g.N = N; g.K = K; g.batch = batch;
-    g.ncolour = -1;
-    return g;
+    bs_status st = BS_OK;
+    if (!ps->plane_f1_d.p) {
+        if ((st = dev_alloc(ps->plane_f1_d, static_cast<size_t>(ps->f_numel) * 4, "plane scratch")) != BS_OK) return st;
+        if ((st = dev_alloc(ps->plane_f2_d, static_cast<size_t>(ps->f_numel) * 4, "plane scratch")) != BS_OK) return st;
+    }
+    return st;
 }
 
-// One pass of plane solves with normal c over the planes of `colour` (-1: all)
-// of every patch: R = residual(src) must already be in plane_r; writes dst.
-bs_status plane_chain(bs_patchset *ps, int c, int colour, const double *src, double *dst, double omega,
-                      hipStream_t s)
+// Geometry of one product of the chain: C_b = A_b B_b, with A, B, C given as
+// (buffer id, offset, leading dimension, batch stride).  Buffer ids:
+// kX = input field, kY = the other scratch field, bases/grid from the tables.
+enum Buf { kIn = 0, kOut = 1, kSx = 2, kSy = 3, kSz = 4, kLam = 5 };
+struct Operand {
+    int buf;
+    int64_t off, ld, sb;
+};
+struct Product {
+    Operand A, B, C;
+    int M, N, K, batch;
+    int64_t sc_b = 0, sc_m = 0, sc_n = 0;   // grid strides (second product)
+};
+struct Chain {
+    Product g[4];
+    int64_t u0, u_b, u_m, u_n;   // update mapping of the last product
+    int filter_n = 0;            // last product filters columns by colour (normal x)
+    bool empty = false;
+};
+
+// The four products M_P^{-1} R = S_b[(S_b R S_a)./Lambda]S_a for every plane
+// of one patch with normal c and the given colour (-1: all).  Fields live in
+// the patch's f layout; the chain alternates between the input field (kIn)
+// and the scratch field (kOut), ending with the update.
+Chain plane_chain_geometry(const bs_patchset *ps, int p, int c, int colour)
 {
+    Chain ch;
+    const int nx = ps->dims[3 * p], ny = ps->dims[3 * p + 1], nz = ps->dims[3 * p + 2];
+    const int64_t sx = nx + 2, sy = sx * (ny + 2), pl = static_cast<int64_t>(nx) * ny;
+    const int64_t uo = ps->uoff[p];
+    const int first = colour < 0 ? 0 : colour, step = colour < 0 ? 1 : 2;
+    auto prod = [](Operand A, Operand B, Operand C, int M, int N, int K, int batch) {
+        Product q;
+        q.A = A; q.B = B; q.C = C; q.M = M; q.N = N; q.K = K; q.batch = batch;
+        return q;
+    };
+    if (c == 2) {   // planes k: (ny x nx); x by right product, y by left product
+        const int nb = (nz - first + step - 1) / step;
+        if (nb <= 0) { ch.empty = true; return ch; }
+        const int64_t o = first * pl, sb = step * pl;
+        ch.g[0] = prod({kIn, o, nx, sb}, {kSx, 0, nx, 0}, {kOut, o, nx, sb}, ny, nx, nx, nb);
+        ch.g[1] = prod({kSy, 0, ny, 0}, {kOut, o, nx, sb}, {kIn, o, nx, sb}, ny, nx, ny, nb);
+        ch.g[1].sc_m = nx; ch.g[1].sc_n = 1;
+        ch.g[2] = prod({kSy, 0, ny, 0}, {kIn, o, nx, sb}, {kOut, o, nx, sb}, ny, nx, ny, nb);
+        ch.g[3] = prod({kOut, o, nx, sb}, {kSx, 0, nx, 0}, {kIn, o, nx, sb}, ny, nx, nx, nb);
+        ch.u0 = uo + (first + 1) * sy + sx + 1; ch.u_b = step * sy; ch.u_m = sx; ch.u_n = 1;
+    } else if (c == 1) {   // planes j: (nz x nx) with row stride nx*ny
+        const int nb = (ny - first + step - 1) / step;
+        if (nb <= 0) { ch.empty = true; return ch; }
+        const int64_t o = static_cast<int64_t>(first) * nx, sb = static_cast<int64_t>(step) * nx;
+        ch.g[0] = prod({kIn, o, pl, sb}, {kSx, 0, nx, 0}, {kOut, o, pl, sb}, nz, nx, nx, nb);
+        ch.g[1] = prod({kSz, 0, nz, 0}, {kOut, o, pl, sb}, {kIn, o, pl, sb}, nz, nx, nz, nb);
+        ch.g[1].sc_m = nx; ch.g[1].sc_n = 1;
+        ch.g[2] = prod({kSz, 0, nz, 0}, {kIn, o, pl, sb}, {kOut, o, pl, sb}, nz, nx, nz, nb);
+        ch.g[3] = prod({kOut, o, pl, sb}, {kSx, 0, nx, 0}, {kIn, o, pl, sb}, nz, nx, nx, nb);
+        ch.u0 = uo + sy + (first + 1) * sx + 1; ch.u_b = step * sx; ch.u_m = sy; ch.u_n = 1;
+    } else {   // planes i: z by left product per j, y by left product per k; colour filters columns
+        ch.g[0] = prod({kSz, 0, nz, 0}, {kIn, 0, pl, nx}, {kOut, 0, pl, nx}, nz, nx, nz, ny);
+        ch.g[1] = prod({kSy, 0, ny, 0}, {kOut, 0, nx, pl}, {kIn, 0, nx, pl}, ny, nx, ny, nz);
+        ch.g[1].sc_b = ny; ch.g[1].sc_m = 1; ch.g[1].sc_n = 0;
+        ch.g[2] = prod({kSy, 0, ny, 0}, {kIn, 0, nx, pl}, {kOut, 0, nx, pl}, ny, nx, ny, nz);
+        ch.g[3] = prod({kSz, 0, nz, 0}, {kOut, 0, pl, nx}, {kIn, 0, pl, nx}, nz, nx, nz, ny);
+        ch.u0 = uo + sy + sx + 1; ch.u_b = sx; ch.u_m = sy; ch.u_n = 1;
+        ch.filter_n = 1;
+    }
+    return ch;
+}
+
+template <typename T>
+const T *operand_ptr(const bs_patchset *ps, int p, int c, const Operand &o, const T *in, const T *out, const T *tab)
+{
+    switch (o.buf) {
+    case kIn: return in + o.off;
+    case kOut: return out + o.off;
+    case kSx: return tab + ps->basis_off[3 * p + 0];
+    case kSy: return tab + ps->basis_off[3 * p + 1];
+    case kSz: return tab + ps->basis_off[3 * p + 2];
+    default: return tab + ps->lam_off[3 * p + c];
+    }
+}
+
+// FP64 chain for one patch: R (residual, f layout) is consumed as scratch.
+bs_status chain_f64(bs_patchset *ps, int p, int c, int colour, const double *src, double *dst, double omega,
+                    hipStream_t s)
+{
+    const Chain ch = plane_chain_geometry(ps, p, c, colour);
+    if (ch.empty) return BS_OK;
     const double *tab = static_cast<const double *>(ps->plane_tab_d.p);
-    double *Rall = static_cast<double *>(ps->plane_r_d.p);
-    double *Tall = static_cast<double *>(ps->plane_t_d.p);
-    for (int p = 0; p < ps->npatch; ++p) {
-        const int nx = ps->dims[3 * p], ny = ps->dims[3 * p + 1], nz = ps->dims[3 * p + 2];
-        const int64_t sx = nx + 2, sy = sx * (ny + 2), pl = static_cast<int64_t>(nx) * ny;
-        const int64_t uo = ps->uoff[p];
-        double *R = Rall + ps->foff[p];
-        double *T = Tall + ps->foff[p];
-        const double *Sx = tab + ps->basis_off[3 * p + 0];
-        const double *Sy = tab + ps->basis_off[3 * p + 1];
-        const double *Sz = tab + ps->basis_off[3 * p + 2];
-        const double *lam = tab + ps->lam_off[3 * p + c];
-        const int first = colour < 0 ? 0 : colour, step = colour < 0 ? 1 : 2;
-        GemmArgs g1, g2, g3, g4;
-        if (c == 2) {          // planes k: (ny x nx); x by right product, y by left product
-            const int nb = (nz - first + step - 1) / step;
-            if (nb <= 0) continue;
-            const int64_t o = first * pl, sb = step * pl;
-            g1 = gemm(R + o, nx, sb, Sx, nx, 0, T + o, nx, sb, ny, nx, nx, nb);
-            g2 = gemm(Sy, ny, 0, T + o, nx, sb, R + o, nx, sb, ny, nx, ny, nb);
-            g2.scale = lam; g2.sc_b = 0; g2.sc_m = nx; g2.sc_n = 1;
-            g3 = gemm(Sy, ny, 0, R + o, nx, sb, T + o, nx, sb, ny, nx, ny, nb);
-            g4 = gemm(T + o, nx, sb, Sx, nx, 0, nullptr, 0, 0, ny, nx, nx, nb);
-            g4.u0 = uo + (first + 1) * sy + sx + 1; g4.u_b = step * sy; g4.u_m = sx; g4.u_n = 1;
-        } else if (c == 1) {   // planes j: (nz x nx) with row stride nx*ny
-            const int nb = (ny - first + step - 1) / step;
-            if (nb <= 0) continue;
-            const int64_t o = static_cast<int64_t>(first) * nx, sb = static_cast<int64_t>(step) * nx;
-            g1 = gemm(R + o, pl, sb, Sx, nx, 0, T + o, pl, sb, nz, nx, nx, nb);
-            g2 = gemm(Sz, nz, 0, T + o, pl, sb, R + o, pl, sb, nz, nx, nz, nb);
-            g2.scale = lam; g2.sc_b = 0; g2.sc_m = nx; g2.sc_n = 1;
-            g3 = gemm(Sz, nz, 0, R + o, pl, sb, T + o, pl, sb, nz, nx, nz, nb);
-            g4 = gemm(T + o, pl, sb, Sx, nx, 0, nullptr, 0, 0, nz, nx, nx, nb);
-            g4.u0 = uo + sy + (first + 1) * sx + 1; g4.u_b = step * sx; g4.u_m = sy; g4.u_n = 1;
-        } else {               // planes i: z by left product per j, y by left product per k
-            g1 = gemm(Sz, nz, 0, R, pl, nx, T, pl, nx, nz, nx, nz, ny);
-            g2 = gemm(Sy, ny, 0, T, nx, pl, R, nx, pl, ny, nx, ny, nz);
-            g2.scale = lam; g2.sc_b = ny; g2.sc_m = 1; g2.sc_n = 0;
-            g3 = gemm(Sy, ny, 0, R, nx, pl, T, nx, pl, ny, nx, ny, nz);
-            g4 = gemm(Sz, nz, 0, T, pl, nx, nullptr, 0, 0, nz, nx, nz, ny);
-            g4.u0 = uo + sy + sx + 1; g4.u_b = sx; g4.u_m = sy; g4.u_n = 1;
-            g4.ncolour = colour; g4.colour_shift = 0;
+    double *R = static_cast<double *>(ps->plane_r_d.p) + ps->foff[p];
+    double *T = static_cast<double *>(ps->plane_t_d.p) + ps->foff[p];
+    for (int q = 0; q < 4; ++q) {
+        const Product &pr = ch.g[q];
+        GemmArgs g{};
+        g.A = operand_ptr<double>(ps, p, c, pr.A, R, T, tab);
+        g.lda = pr.A.ld; g.sA = pr.A.sb;
+        g.B = operand_ptr<double>(ps, p, c, pr.B, R, T, tab);
+        g.ldb = pr.B.ld; g.sB = pr.B.sb;
+        g.C = const_cast<double *>(operand_ptr<double>(ps, p, c, pr.C, R, T, tab));
+        g.ldc = pr.C.ld; g.sC = pr.C.sb;
+        g.M = pr.M; g.N = pr.N; g.K = pr.K; g.batch = pr.batch;
+        g.ncolour = -1;
+        int epi = kEpiStore;
+        if (q == 1) {
+            epi = kEpiScale;
+            g.scale = tab + ps->lam_off[3 * p + c];
+            g.sc_b = pr.sc_b; g.sc_m = pr.sc_m; g.sc_n = pr.sc_n;
+        } else if (q == 3) {
+            epi = kEpiUpdate;
+            g.usrc = src; g.udst = dst; g.omega = omega;
+            g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
+            if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
         }
-        g4.usrc = src;
-        g4.udst = dst;
-        g4.omega = omega;
-        hipError_t e;
-        if ((e = launch_gemm_f64(g1, kEpiStore, s)) != hipSuccess) return hip_fail(e, "plane transform 1");
-        if ((e = launch_gemm_f64(g2, kEpiScale, s)) != hipSuccess) return hip_fail(e, "plane transform 2");
-        if ((e = launch_gemm_f64(g3, kEpiStore, s)) != hipSuccess) return hip_fail(e, "plane transform 3");
-        if ((e = launch_gemm_f64(g4, kEpiUpdate, s)) != hipSuccess) return hip_fail(e, "plane transform 4");
+        hipError_t e = launch_gemm_f64(g, epi, s);
+        if (e != hipSuccess) return hip_fail(e, "plane transform");
+    }
+    return BS_OK;
+}
+
+// Low-precision chain M~^{-1} E for one patch: E (float, f layout) in F1,
+// scratch F2; the last product either updates u (final) or stores / adds
+// into D (FP64).
+bs_status chain_lowp(bs_patchset *ps, int p, int c, int colour, int prec, int last_epi, int accumulate,
+                     const double *src, double *dst, double omega, hipStream_t s)
+{
+    const Chain ch = plane_chain_geometry(ps, p, c, colour);
+    if (ch.empty) return BS_OK;
+    const float *tab = static_cast<const float *>(ps->plane_tab32_d.p);
+    float *F1 = static_cast<float *>(ps->plane_f1_d.p) + ps->foff[p];
+    float *F2 = static_cast<float *>(ps->plane_f2_d.p) + ps->foff[p];
+    double *D = static_cast<double *>(ps->plane_t_d.p) + ps->foff[p];
+    for (int q = 0; q < 4; ++q) {
+        const Product &pr = ch.g[q];
+        GemmMixedArgs g{};
+        g.A = operand_ptr<float>(ps, p, c, pr.A, F1, F2, tab);
+        g.lda = pr.A.ld; g.sA = pr.A.sb;
+        g.B = operand_ptr<float>(ps, p, c, pr.B, F1, F2, tab);
+        g.ldb = pr.B.ld; g.sB = pr.B.sb;
+        g.C = const_cast<float *>(operand_ptr<float>(ps, p, c, pr.C, F1, F2, tab));
+        g.ldc = pr.C.ld; g.sC = pr.C.sb;
+        g.M = pr.M; g.N = pr.N; g.K = pr.K; g.batch = pr.batch;
+        g.ncolour = -1;
+        g.dlayout = ps->mixed_dlayout;
+        int epi = kEpiStore;
+        if (q == 1) {
+            epi = kEpiScale;
+            g.scale = tab + ps->lam_off[3 * p + c];
+            g.sc_b = pr.sc_b; g.sc_m = pr.sc_m; g.sc_n = pr.sc_n;
+        } else if (q == 3) {
+            epi = last_epi;
+            if (epi == kEpiUpdate) {
+                g.usrc = src; g.udst = dst; g.omega = omega;
+                g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
+                if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
+            } else {
+                // D shares the f-layout indexing of the chain's final field (kIn = F1)
+                g.D = D + (g.C - F1);
+                g.accumulate = accumulate;
+            }
+        }
+        hipError_t e = launch_gemm_mixed(g, prec, epi, s);
+        if (e != hipSuccess) return hip_fail(e, "plane transform (mixed)");
+    }
+    return BS_OK;
+}
+
+// One plane pass (normal c, colour or -1) on every patch.  R = residual of
+// src must be in plane_r.  Mixed: D_0 = M~^{-1} R, refine defect corrections,
+// then dst = src + omega D.
+bs_status plane_pass(bs_patchset *ps, int c, int colour, int prec, int refine, const double *src, double *dst,
+                     double omega, hipStream_t s)
+{
+    for (int p = 0; p < ps->npatch; ++p) {
+        if (prec == BS_FP64) {
+            bs_status st = chain_f64(ps, p, c, colour, src, dst, omega, s);
+            if (st != BS_OK) return st;
+            continue;
+        }
+        const int nx = ps->dims[3 * p], ny = ps->dims[3 * p + 1], nz = ps->dims[3 * p + 2];
+        const double *R = static_cast<const double *>(ps->plane_r_d.p) + ps->foff[p];
+        double *D = static_cast<double *>(ps->plane_t_d.p) + ps->foff[p];
+        float *F1 = static_cast<float *>(ps->plane_f1_d.p) + ps->foff[p];
+        const double *eps = &ps->eps[3 * static_cast<size_t>(p)];
+        const int lp = prec == BS_MIXED_BF16 ? 2 : 1;
+        hipError_t e = launch_plane_defect(R, nullptr, F1, nx, ny, nz, c, eps, s);
+        if (e != hipSuccess) return hip_fail(e, "plane defect");
+        bs_status st;
+        if (refine == 0) {
+            if ((st = chain_lowp(ps, p, c, colour, lp, kEpiUpdate, 0, src, dst, omega, s)) != BS_OK) return st;
+            continue;
+        }
+        if ((st = chain_lowp(ps, p, c, colour, lp, kEpiD64, 0, src, dst, omega, s)) != BS_OK) return st;
+        for (int j = 0; j < refine; ++j) {
+            if ((e = launch_plane_defect(R, D, F1, nx, ny, nz, c, eps, s)) != hipSuccess) return hip_fail(e, "plane defect");
+            if ((st = chain_lowp(ps, p, c, colour, lp, kEpiD64, 1, src, dst, omega, s)) != BS_OK) return st;
+        }
+        if ((e = launch_plane_update(D, src, dst, ps->uoff[p], nx, ny, nz, c, colour, omega, s)) != hipSuccess)
+            return hip_fail(e, "plane update");
     }
     return BS_OK;
 }
@@ -148,9 +288,11 @@ bs_status residual_into_scratch(bs_patchset *ps, const double *u, const double *
 
 using namespace bs;
 
-extern "C" bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme, double omega,
-                                    int32_t nsweeps, bs_precision prec, int32_t refine, double *u,
-                                    const double *f, double *work, hipStream_t stream)
+extern "C" {
+
+bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme, double omega, int32_t nsweeps,
+                         bs_precision prec, int32_t refine, double *u, const double *f, double *work,
+                         hipStream_t stream)
 {
     if (normal_axis < 0 || normal_axis > 2) return fail(BS_ERR_INVALID, "bs_plane_relax: axis must be 0, 1 or 2");
     if (scheme != BS_JACOBI && scheme != BS_CHAOTIC_GS && scheme != BS_COLORED_GS)
@@ -165,10 +307,11 @@ extern "C" bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_sch
     for (int a = 0; a < 3; ++a)
         if (a != normal_axis && ps->max_n[a] > kMaxPlaneEdge)
             return fail(BS_ERR_UNSUPPORTED, "bs_plane_relax: an in-plane edge exceeds %d", kMaxPlaneEdge);
-    if (prec != BS_FP64) return fail(BS_ERR_UNSUPPORTED, "bs_plane_relax: mixed precision is not built yet");
     if (nsweeps == 0) return BS_OK;
     bs_status st;
     if (!ps->plane_ready && (st = build_plane_tables(ps)) != BS_OK) return st;
+    if (prec != BS_FP64 && (st = ensure_mixed_scratch(ps)) != BS_OK) return st;
+    const int rf = prec == BS_FP64 ? 0 : refine;
     const PatchDesc *pdd = static_cast<const PatchDesc *>(ps->desc_d.p);
     if (scheme == BS_JACOBI) {
         hipError_t e = launch_ghost_copy(u, work, pdd, ps->npatch, stream);
@@ -177,7 +320,7 @@ extern "C" bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_sch
             const double *src = (sw & 1) ? work : u;
             double *dst = (sw & 1) ? u : work;
             if ((st = residual_into_scratch(ps, src, f, stream)) != BS_OK) return st;
-            if ((st = plane_chain(ps, normal_axis, -1, src, dst, omega, stream)) != BS_OK) return st;
+            if ((st = plane_pass(ps, normal_axis, -1, prec, rf, src, dst, omega, stream)) != BS_OK) return st;
         }
         if (nsweeps & 1) {
             e = launch_interior_copy(work, u, pdd, ps->npatch, stream);
@@ -190,23 +333,52 @@ extern "C" bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_sch
     for (int sw = 0; sw < nsweeps; ++sw)
         for (int colour = 0; colour < 2; ++colour) {
             if ((st = residual_into_scratch(ps, u, f, stream)) != BS_OK) return st;
-            if ((st = plane_chain(ps, normal_axis, colour, u, u, omega, stream)) != BS_OK) return st;
+            if ((st = plane_pass(ps, normal_axis, colour, prec, rf, u, u, omega, stream)) != BS_OK) return st;
         }
     return BS_OK;
 }
 
-// Host-side test hook (not part of the public header): one batched product
-// C_b = A_b B_b with the plane kernel's store epilogue (epi 0) or scale
-// epilogue (epi 1, scale indexed [b*sc_b + m*sc_m + n*sc_n]).  Device pointers.
-extern "C" int bsi_gemm_f64(const double *A, int64_t lda, int64_t sA, const double *B, int64_t ldb, int64_t sB,
-                            double *C, int64_t ldc, int64_t sC, int M, int N, int K, int batch, int epi,
-                            const double *scale, int64_t sc_b, int64_t sc_m, int64_t sc_n, hipStream_t s)
+// Host-side test hooks (not part of the public header).
+
+// One batched product C_b = A_b B_b with the FP64 kernel's store (epi 0) or
+// scale (epi 1, scale indexed [b*sc_b + m*sc_m + n*sc_n]) epilogue.
+int bsi_gemm_f64(const double *A, int64_t lda, int64_t sA, const double *B, int64_t ldb, int64_t sB, double *C,
+                 int64_t ldc, int64_t sC, int M, int N, int K, int batch, int epi, const double *scale, int64_t sc_b,
+                 int64_t sc_m, int64_t sc_n, hipStream_t s)
 {
-    if (epi != bs::kEpiStore && epi != bs::kEpiScale) return BS_ERR_INVALID;
-    bs::GemmArgs g = bs::gemm(A, lda, sA, B, ldb, sB, C, ldc, sC, M, N, K, batch);
-    g.scale = scale;
-    g.sc_b = sc_b;
-    g.sc_m = sc_m;
-    g.sc_n = sc_n;
-    return bs::launch_gemm_f64(g, epi, s) == hipSuccess ? BS_OK : BS_ERR_HIP;
+    if (epi != kEpiStore && epi != kEpiScale) return BS_ERR_INVALID;
+    GemmArgs g{};
+    g.A = A; g.lda = lda; g.sA = sA;
+    g.B = B; g.ldb = ldb; g.sB = sB;
+    g.C = C; g.ldc = ldc; g.sC = sC;
+    g.M = M; g.N = N; g.K = K; g.batch = batch;
+    g.scale = scale; g.sc_b = sc_b; g.sc_m = sc_m; g.sc_n = sc_n;
+    g.ncolour = -1;
+    return launch_gemm_f64(g, epi, s) == hipSuccess ? BS_OK : BS_ERR_HIP;
 }
+
+// The same with float operands: prec 1 (FP32) or 2 (BF16), store epilogue,
+// dlayout as in GemmMixedArgs.
+int bsi_gemm_mixed(const float *A, int64_t lda, int64_t sA, const float *B, int64_t ldb, int64_t sB, float *C,
+                   int64_t ldc, int64_t sC, int M, int N, int K, int batch, int prec, int dlayout, hipStream_t s)
+{
+    if (prec != 1 && prec != 2) return BS_ERR_INVALID;
+    GemmMixedArgs g{};
+    g.A = A; g.lda = lda; g.sA = sA;
+    g.B = B; g.ldb = ldb; g.sB = sB;
+    g.C = C; g.ldc = ldc; g.sC = sC;
+    g.M = M; g.N = N; g.K = K; g.batch = batch;
+    g.ncolour = -1;
+    g.dlayout = dlayout;
+    return launch_gemm_mixed(g, prec, kEpiStore, s) == hipSuccess ? BS_OK : BS_ERR_HIP;
+}
+
+// Register-to-row mapping used by the mixed products of this patch set.
+int bsi_set_mixed_dlayout(bs_patchset *ps, int dlayout)
+{
+    if (!ps || (dlayout != 0 && dlayout != 1)) return BS_ERR_INVALID;
+    ps->mixed_dlayout = dlayout;
+    return BS_OK;
+}
+
+}  // extern "C"

@@ -6,7 +6,7 @@
 
 namespace bs {
 
-enum { kEpiStore = 0, kEpiScale = 1, kEpiUpdate = 2 };
+enum { kEpiStore = 0, kEpiScale = 1, kEpiUpdate = 2, kEpiD64 = 3 };
 
 // C_b = A_b B_b, row-major, b in [0, batch); a zero batch stride shares an
 // operand across the batch.  Epilogues:
@@ -32,5 +32,35 @@ struct GemmArgs {
 };
 
 hipError_t launch_gemm_f64(const GemmArgs &g, int epi, hipStream_t s);
+
+// The same product with float operands and FP32 accumulation (prec 1: FP32
+// products, prec 2: BF16 products); kEpiD64 stores (or adds, accumulate != 0)
+// the result into the FP64 array D with C's indexing.  dlayout selects the
+// register-to-row mapping of the 16x16 result block (0: 4*(lane/16)+r).
+struct GemmMixedArgs {
+    const float *A;
+    int64_t lda, sA;
+    const float *B;
+    int64_t ldb, sB;
+    float *C;
+    int64_t ldc, sC;
+    int M, N, K, batch;
+    const float *scale;
+    int64_t sc_b, sc_m, sc_n;
+    double *D;
+    int accumulate;
+    const double *usrc;
+    double *udst;
+    int64_t u0, u_b, u_m, u_n;
+    double omega;
+    int ncolour, colour_shift;
+    int dlayout;
+};
+
+hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStream_t s);
+hipError_t launch_plane_defect(const double *R, const double *D, float *E, int nx, int ny, int nz, int normal,
+                               const double eps[3], hipStream_t s);
+hipError_t launch_plane_update(const double *D, const double *src, double *dst, int64_t uoff, int nx, int ny, int nz,
+                               int normal, int colour, double omega, hipStream_t s);
 
 }  // namespace bs

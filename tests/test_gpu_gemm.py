@@ -71,3 +71,50 @@ def test_gemm_output_layout_probe():
     bad = np.argwhere(got != A)
     print("mismatches", len(bad), bad[:8].tolist(), [got[tuple(b)] for b in bad[:8]])
     assert len(bad) == 0
+
+
+def gemm_mixed(A, lda, sA, B, ldb, sB, C, ldc, sC, M, N, K, batch, prec, dlayout):
+    L = bs.lib()
+    f = L.bsi_gemm_mixed
+    i64, vp = ctypes.c_int64, ctypes.c_void_p
+    f.argtypes = [vp, i64, i64, vp, i64, i64, vp, i64, i64] + [ctypes.c_int] * 6 + [vp]
+    f.restype = ctypes.c_int
+    rc = f(A.data_ptr(), lda, sA, B.data_ptr(), ldb, sB, C.data_ptr(), ldc, sC, M, N, K, batch, prec, dlayout,
+           torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 2e-2)])
+@pytest.mark.parametrize("M,N,K,batch", [(64, 64, 32, 1), (100, 130, 70, 3), (512, 64, 512, 2), (5, 7, 3, 2)])
+def test_mixed_gemm_matches_numpy(prec, tol, M, N, K, batch):
+    """FP32 / BF16 products with FP32 accumulation: relative to the FP64 product
+    of the same float inputs, within the precision's rounding (BF16: 8 bits)."""
+    need_gpu()
+    rng = np.random.default_rng(M + 7 * N + prec)
+    A = rng.standard_normal((batch, M, K)).astype(np.float32)
+    B = rng.standard_normal((batch, K, N)).astype(np.float32)
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    tA, tB = torch.tensor(A, device="cuda"), torch.tensor(B, device="cuda")
+    tC = torch.zeros((batch, M, N), dtype=torch.float32, device="cuda")
+    gemm_mixed(tA, K, M * K, tB, N, K * N, tC, N, M * N, M, N, K, batch, prec, 0)
+    err = np.max(np.abs(tC.cpu().numpy() - ref)) / (np.sqrt(K) * np.max(np.abs(A)) * np.max(np.abs(B)))
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixed_output_layout_probe(prec):
+    """A = small integers (exact in BF16), B = identity: C must equal A."""
+    need_gpu()
+    M = N = K = 64
+    A = (np.arange(M * K) % 97).astype(np.float32).reshape(M, K)
+    B = np.eye(K, dtype=np.float32)
+    tA, tB = torch.tensor(A, device="cuda"), torch.tensor(B, device="cuda")
+    good = []
+    for dl in (0, 1):
+        tC = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+        gemm_mixed(tA, K, 0, tB, N, 0, tC, N, 0, M, N, K, 1, prec, dl)
+        if np.array_equal(tC.cpu().numpy(), A):
+            good.append(dl)
+    print("prec %d: matching result layouts %s" % (prec, good))
+    assert good == [0]

@@ -77,3 +77,70 @@ def test_c3_xy_plane_jacobi_sampled():
             log("  plane %d relerr %.3e" % (k, e))
             assert e < TOL
         prev = got
+
+
+# Stated bound for the mixed forms: each low-precision solve returns the
+# correction with relative error at most eta (FP32 transforms: 1e-6, BF16
+# transforms with FP32 accumulation: 1.5e-2), each defect-correction step
+# multiplies it by eta, and the iteration contracts, so after k sweeps the
+# deviation from the FP64 iterate is at most about k * omega * eta^(refine+1)
+# relative to max|u| (the first correction is of the size of u).
+ETA = {"fp32": 1e-6, "bf16": 1.5e-2}
+
+
+def mixed_bound(prec, refine, k, omega=1.0):
+    return k * omega * ETA[prec] ** (refine + 1)
+
+
+MIXED = [("fp32", 0), ("fp32", 1), ("bf16", 0), ("bf16", 1), ("bf16", 2)]
+
+
+@pytest.mark.parametrize("prec,refine", MIXED)
+@pytest.mark.parametrize("normal", [0, 1, 2])
+def test_mixed_plane_error_vs_fp64(prec, refine, normal):
+    """Mixed plane Jacobi (FP64 residual and update): the error against the FP64
+    oracle after three sweeps stays within the stated bound."""
+    p = small_patch(40, 36, 33, seed=81 + normal, eps=(1.0, 100.0, 100.0))
+    bound = mixed_bound(prec, refine, 3)
+    s = Single(p)
+    s.plane(normal, "jacobi", 1.0, 3, prec=prec, refine=refine)
+    got = s.u_np()
+    ref = oracle.plane_sweeps(p.u0, p.f, p.eps, p.h, normal, oracle.JACOBI, 1.0, 3)
+    e = relerr(got, ref)
+    log("mixed %s refine %d normal %d: relerr vs FP64 %.3e (bound %.0e)" % (prec, refine, normal, e, bound))
+    assert e < bound
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_plane_fixed_point(prec):
+    """With the exact solution the FP64 residual is at rounding level, so the
+    low-precision correction cannot move u beyond it."""
+    p = small_patch(24, 20, 18, seed=9, eps=(2.0, 1.0, 5.0))
+    r, _ = oracle.residual(p.u0, np.zeros_like(p.f), p.eps, p.h)
+    f_exact = -r / (p.h * p.h)
+    for normal in (0, 2):
+        s = Single(p)
+        s.f = s.ps.pack_f([f_exact])
+        s.plane(normal, "colored", 1.0, 2, prec=prec, refine=1)
+        assert relerr(s.u_np(), p.u0) < 1e-13
+
+
+@pytest.mark.timeout(900)
+def test_c3_mixed_forms_error_statement():
+    """512^3, eps (1,100,100), xy-plane Jacobi omega 1: five sweeps per form;
+    error of each mixed form against the FP64 GPU result (itself checked
+    against the oracle plane by plane above)."""
+    p = c3_patch()
+    ref = Single(p)
+    ref.plane(2, "jacobi", 1.0, 5)
+    u64 = ref.u_np()
+    r64 = ref.rnorm()
+    for prec, refine in (("fp32", 0), ("fp32", 1), ("bf16", 1), ("bf16", 2)):
+        bound = mixed_bound(prec, refine, 5)
+        s = Single(p)
+        s.plane(2, "jacobi", 1.0, 5, prec=prec, refine=refine)
+        e = relerr(s.u_np(), u64)
+        rr = s.rnorm() / r64
+        log("C3 %s refine %d: relerr vs FP64 %.3e (bound %.1e), residual ratio %.6f" % (prec, refine, e, bound, rr))
+        assert e < bound
+        assert abs(rr - 1.0) < 1e-3
