@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the other configurations")
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3 counter runs: a 1 GiB device copy (reference for FETCH_SIZE / "
                          "WRITE_SIZE scaling), then 10 z-line Jacobi and 10 chaotic GS sweep launches; no JSON")
@@ -86,6 +87,114 @@ def timed_sweeps(fn, nsweeps_list, reps=5):
             ts.append(a.elapsed_time(b))
         ts.sort()
         out[n] = ts[len(ts) // 2]
+    return out
+
+
+def ev_ms(fn, reps=3):
+    """Median HIP-event time (ms) of fn() on the current stream."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def forms():
+    """The other configurations on the same GPU: timings, rates and errors."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import c1_patch, c3_patch, c4_patchset, c5_patch
+
+    out = {}
+    # 32^3 x-line Jacobi, 10 sweeps (cache resident, launch bound)
+    p = c1_patch()
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    u, f, w = ps.pack_u([p.u0]), ps.pack_f([p.f]), ps.empty_u()
+    ps.line_relax(0, "jacobi", 1.0, 10, u, f, w)
+    ms = ev_ms(lambda: ps.line_relax(0, "jacobi", 1.0, 10, u, f, w), reps=7)
+    out["c1_xline_jacobi_32"] = {"ms_10_sweeps": round(ms, 4), "glups": round(32 ** 3 * 10 / (ms * 1e-3) / 1e9, 3)}
+    ps.close()
+    del u, f, w
+
+    # 512^3 xy-plane Jacobi: FP64 fast diagonalisation vs mixed forms, 5 sweeps
+    p = c3_patch()
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    f = ps.pack_f([p.f])
+    u0 = ps.pack_u([p.u0])
+    w = ps.empty_u()
+    cells = 512 ** 3
+    flops = 4 * 2.0 * 512 ** 3 * 512          # four 512^3 products per plane, 512 planes
+    res = {}
+    u64 = None
+    for name, prec, refine in (("fp64", "fp64", 0), ("fp32", "fp32", 0), ("fp32_r1", "fp32", 1),
+                               ("bf16_r1", "bf16", 1), ("bf16_r2", "bf16", 2)):
+        u = u0.clone()
+        ps.plane_relax(2, "jacobi", 1.0, 1, u, f, w, prec=prec, refine=refine)   # warm (tables, scratch)
+        u.copy_(u0)
+        ms = ev_ms(lambda: ps.plane_relax(2, "jacobi", 1.0, 5, u, f, w, prec=prec, refine=refine), reps=1)
+        entry = {"ms_per_sweep": round(ms / 5, 3), "glups": round(cells * 5 / (ms * 1e-3) / 1e9, 3)}
+        if name == "fp64":
+            u64 = u.clone()
+            entry["mfma_tflops"] = round(flops * 5 / (ms * 1e-3) / 1e12, 2)
+            entry["mfma_frac_fp64"] = round(flops * 5 / (ms * 1e-3) / 78.6e12, 4)
+        else:
+            entry["relerr_vs_fp64_5_sweeps"] = float((u - u64).abs().max() / u64.abs().max())
+        res[name] = entry
+        del u
+    out["c3_xyplane_jacobi_512"] = res
+    ps.close()
+    del f, u0, w, u64
+    torch.cuda.empty_cache()
+
+    # 3000 uneven AMR patches, x-line chaotic GS, 20 sweeps
+    s = c4_patchset()
+    ps = bs.PatchSet([tuple(d) for d in s.dims], [tuple(e) for e in s.eps], list(s.h))
+    u = ps.pack_u(s.u0)
+    f = ps.pack_f(s.f)
+    cells = s.cells()
+    ps.autotune_line(0, "chaotic", u, f)
+    ps.line_relax(0, "chaotic", 1.0, 20, u, f)                        # capture the graph
+    ms_one = ev_ms(lambda: ps.line_relax(0, "chaotic", 1.0, 20, u, f), reps=3)
+    ms_pp = ev_ms(lambda: ps.line_relax_per_patch(0, "chaotic", 1.0, 20, u, f), reps=1)
+    out["c4_amr3000_xline_chaotic"] = {
+        "cells": cells, "config": ps.line_config(0, "chaotic"),
+        "one_graph_launch_ms": round(ms_one, 3), "glups": round(cells * 20 / (ms_one * 1e-3) / 1e9, 3),
+        "hbm_frac": round((24.0 * cells * 20) / (ms_one * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "per_patch_launches_ms": round(ms_pp, 3), "launches_per_patch_path": 20 * 2 * s.npatch,
+        "speedup_vs_per_patch": round(ms_pp / ms_one, 2)}
+    ps.close()
+    del u, f
+    torch.cuda.empty_cache()
+
+    # 128^3 differentiable smoother: K = 20 z-line Jacobi, checkpoint every 5
+    p = c5_patch()
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    u0, f, w = ps.pack_u([p.u0]), ps.pack_f([p.f]), ps.empty_u()
+    u = u0.clone()
+    ps.line_relax(2, "jacobi", 0.8, 20, u, f, w)                       # capture the graph
+    ms_f = ev_ms(lambda: (u.copy_(u0), ps.line_relax(2, "jacobi", 0.8, 20, u, f, w)), reps=5)
+    g = torch.randn_like(u0)
+    nbytes = bs.bs_backward_workspace_bytes(ps.handle, 2, 20, 5)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    gu0, gf = torch.zeros_like(u0), torch.zeros_like(f)
+    geps = torch.zeros(3, dtype=torch.float64, device="cuda")
+    bwd = lambda: bs.bs_relax_backward(ps.handle, 2, 0.8, 20, 5, u0, f, g, gu0, gf, geps, ws)
+    bwd()
+    ms_b = ev_ms(bwd, reps=5)
+    cells = 128 ** 3
+    out["c5_adjoint_128_K20"] = {"forward_ms": round(ms_f, 3), "backward_ms": round(ms_b, 3),
+                                 "backward_over_forward": round(ms_b / ms_f, 2),
+                                 "forward_glups": round(cells * 20 / (ms_f * 1e-3) / 1e9, 3),
+                                 "workspace_MiB": round(nbytes / 2 ** 20, 1)}
+    ps.close()
     return out
 
 
@@ -178,6 +287,11 @@ def main():
                       "chaotic_frac": round(bytes_per_launch / (cha_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
     rn = norms.cpu().numpy()
 
+    ps.close()
+    del uj, uc, u0, f, work
+    torch.cuda.empty_cache()
+    other = None if args.no_forms else forms()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(patch, args.cpu_seconds)
@@ -189,9 +303,9 @@ def main():
                                    "100 chaotic z-line block GS sweeps (omega 1), residual norm every 10 sweeps",
                        "cells": cells, "sweeps_per_step": sweeps_per_step, "parallelism": "single GPU"},
             "roofline": roof, "cpu_baseline": cpu,
-            "residual_last": {"jacobi": float(math.sqrt(rn[9])), "chaotic": float(math.sqrt(rn[19]))}}
+            "residual_last": {"jacobi": float(math.sqrt(rn[9])), "chaotic": float(math.sqrt(rn[19]))},
+            "forms": other}
     print(json.dumps(line), flush=True)
-    ps.close()
 
 
 if __name__ == "__main__":
