@@ -95,7 +95,10 @@ bs_status bs_layout_plan(int32_t npatch, const int32_t *dims_host, int64_t *u_nu
  * smoothing iterations): the LU factors and interface-coupling tables of the
  * exact line solves, and the sine eigenbases and eigenvalues of the exact
  * plane solves.  Synchronous.  BS_ERR_INVALID on bad sizes or non-positive
- * eps/h; BS_ERR_OOM / BS_ERR_HIP on allocation or copy failures. */
+ * eps/h; BS_ERR_UNSUPPORTED for an edge above 4096 or a patch whose padded u
+ * reaches 4 GiB ((nx+2)(ny+2)(nz+2) >= 2^29, about 810^3 cells: split such a
+ * domain into patches); BS_ERR_OOM / BS_ERR_HIP on allocation or copy
+ * failures. */
 bs_status bs_create_patchset(int32_t npatch, const int32_t *dims_host, const double *eps_host,
                              const double *h_host, bs_patchset **out);
 

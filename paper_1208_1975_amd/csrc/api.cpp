@@ -174,6 +174,13 @@ bs_status bs_create_patchset(int32_t npatch, const int32_t *dims_host, const dou
         if (!finite_pos(h_host[p])) return fail(BS_ERR_INVALID, "bs_create_patchset: h[%d] must be finite and > 0", p);
     for (int64_t t = 0; t < 3 * static_cast<int64_t>(npatch); ++t)
         if (dims_host[t] > 4096) return fail(BS_ERR_UNSUPPORTED, "bs_create_patchset: an edge exceeds 4096");
+    // the line kernels address a patch with 32-bit byte offsets
+    for (int p = 0; p < npatch; ++p) {
+        const int64_t padded = static_cast<int64_t>(dims_host[3 * p] + 2) * (dims_host[3 * p + 1] + 2) *
+                               (dims_host[3 * p + 2] + 2);
+        if (padded >= (int64_t(1) << 29))
+            return fail(BS_ERR_UNSUPPORTED, "bs_create_patchset: patch %d's padded u reaches 4 GiB; split it", p);
+    }
 
     std::unique_ptr<bs_patchset> ps(new (std::nothrow) bs_patchset);
     if (!ps) return fail(BS_ERR_OOM, "bs_create_patchset: host allocation");

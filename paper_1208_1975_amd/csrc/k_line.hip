@@ -52,6 +52,35 @@ __device__ __forceinline__ void chunk_solve(double (&r)[L], int Lp, int Lr, cons
     y0 = r[0];
 }
 
+// The same solve with the factors read at constant indices from a
+// wave-uniform table (scalar loads, fetched in bulk).  Entries g[t], q[t] for
+// t >= Lr read the following table entries, which are finite; their results
+// are discarded exactly as above (the table holds at least 3 Lr > Lr + L - 1
+// entries because L < 2 Lr).
+template <int L>
+__device__ __forceinline__ void chunk_solve_u(double (&r)[L], int Lp, const double *__restrict__ g,
+                                              const double *__restrict__ q, double ea, double &y0, double &yl)
+{
+    double zprev = 0.0;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const double z = fma(g[t], zprev, r[t]);
+        r[t] = (t < Lp) ? z : 0.0;
+        zprev = r[t];
+    }
+    asm volatile("" ::: "memory");   // q is fetched after g is consumed
+    double ynext = 0.0;
+    yl = 0.0;
+#pragma unroll
+    for (int t = L - 1; t >= 0; --t) {
+        const double y = fma(ea, ynext, r[t]) * q[t];
+        r[t] = y;
+        ynext = y;
+        yl = (t == Lp - 1) ? y : yl;
+    }
+    y0 = r[0];
+}
+
 // Neighbour of a lane's value along the wavefront (DPP wave shift by one lane):
 // dir < 0 gives lane l the value of lane l-1, dir > 0 that of lane l+1.
 template <int DIR>
@@ -85,45 +114,57 @@ __device__ __forceinline__ void interface_terms(const double *tab, const double 
 // by 64/tx along the other free axis; wavefront p of the workgroup holds
 // chunk p of all 64 lines.  With colour_mode, a tile holds lines of one
 // colour only ((i + o) parity), which makes x stride 2.
+//
+// Register economy decides the speed of this kernel: a patch is addressed
+// with wave-uniform base pointers and 32-bit byte offsets (one VGPR per
+// address), the chunk factors and interface rows are wave-uniform and come
+// through the scalar cache, and u is read again for the update instead of
+// being held through the solve.  LDS holds only the chunk ends (two buffers,
+// so consecutive items need no trailing barrier).
 // ---------------------------------------------------------------------------
-template <int L, int MAXT>
-__device__ __forceinline__ void line_strided_item(const LineArgs &a, const WorkItem it, double *smem);
+__device__ __forceinline__ double ldb(const char *base, uint32_t off)
+{
+    return *reinterpret_cast<const double *>(base + off);
+}
+
+template <int L>
+__device__ __forceinline__ void line_strided_item(const LineArgs &a, const double *__restrict__ tabs,
+                                                  const WorkItem it, double *ends);
 
 // A workgroup drains work items blockIdx.x, blockIdx.x + gridDim.x, ...: one
 // item per workgroup when the grid covers the list, a persistent grid otherwise.
 template <int L, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a)
+__global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a, const double *__restrict__ tabs)
 {
     extern __shared__ double smem[];
+    const int nw = blockDim.x >> 6;
+    int buf = 0;
     for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
-        line_strided_item<L, MAXT>(a, a.items[i], smem);
-        __syncthreads();   // LDS is reused by the next item
+        line_strided_item<L>(a, tabs, a.items[i], smem + buf * (2 * 64 * nw));
+        buf ^= 1;
     }
 }
 
-template <int L, int MAXT>
-__device__ __forceinline__ void line_strided_item(const LineArgs &a, const WorkItem it, double *smem)
+template <int L>
+__device__ __forceinline__ void line_strided_item(const LineArgs &a, const double *__restrict__ tabs,
+                                                  const WorkItem it, double *ends)
 {
     const PatchDesc *pd = a.pd + it.patch;
     const int axis = a.axis;          // 1 or 2
     const int oaxis = 3 - axis;       // the other free axis
     const int nx = pd->n[0], ny = pd->n[1];
     const int no = pd->n[oaxis];
-    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2);
-    const int64_t Sa = axis == 2 ? sy : sx;
-    const int64_t So = axis == 2 ? sx : sy;
-    const int64_t Fa = axis == 2 ? (int64_t)nx * ny : (int64_t)nx;
-    const int64_t Fo = axis == 2 ? (int64_t)nx : (int64_t)nx * ny;
+    const uint32_t sx = nx + 2, sy = sx * (uint32_t)(ny + 2);
+    const uint32_t Sa = axis == 2 ? sy : sx;           // u strides (elements)
+    const uint32_t So = axis == 2 ? sx : sy;
+    const uint32_t Fa = axis == 2 ? (uint32_t)nx * ny : (uint32_t)nx;   // f strides
+    const uint32_t Fo = axis == 2 ? (uint32_t)nx : (uint32_t)nx * ny;
     const double ex = pd->eps[0], ea = pd->eps[axis], eo = pd->eps[oaxis];
     const double d = 2.0 * (pd->eps[0] + pd->eps[1] + pd->eps[2]);
     const double h2 = pd->h2;
     const LineTabRef tr = pd->line[axis][a.popt];
     const int Lr = tr.Lr, P = tr.P, Llast = tr.Llast;
-    const int tsz = line_table_size(Lr, P);
-
-    double *tab = smem;
-    double *ends = smem + ((tsz + 1) & ~1);
-    for (int t = threadIdx.x; t < tsz; t += blockDim.x) tab[t] = a.tab[tr.off + t];
+    const double *tab = tabs + tr.off;
 
     const int lane = threadIdx.x & 63;
     const int p = uniform_wave();
@@ -148,93 +189,108 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const WorkI
     const int pc = p < P ? p : P - 1;
     const int Lp = (pc == P - 1) ? Llast : Lr;
     const int t0 = pc * Lr;
-    // x-neighbours come from the adjacent lanes unless the lane is at a row
-    // edge of the tile (or of the patch), or lanes are colour-strided.
-    const bool load_l = a.colour_mode || li == 0;
-    const bool load_r = a.colour_mode || li == tx - 1 || i >= nx - 1;
+    // x-neighbours come from the adjacent lanes (DPP) unless the lane is at a
+    // row edge of the tile or the patch, or lanes are colour-strided.  A lane
+    // that needs one side from memory gets it with the batched loads; a lane
+    // that needs both (colour-strided, or a one-lane row) takes one more load.
+    const bool need_l = a.colour_mode || li == 0;
+    const bool need_r = a.colour_mode || li == tx - 1 || i >= nx - 1;
+    const bool both = need_l && need_r;
 
-    const double *s = a.src;
-    const int64_t cu = pd->uoff + (ic + 1) + (int64_t)(t0 + 1) * Sa + (int64_t)(oc + 1) * So;
-    const int64_t cf = pd->foff + ic + (int64_t)t0 * Fa + (int64_t)oc * Fo;
+    const char *ub = reinterpret_cast<const char *>(a.src + pd->uoff);
+    const char *fbase = reinterpret_cast<const char *>(a.f + pd->foff);
+    const char *ubm = ub - 8u * So, *ubp = ub + 8u * So;   // the o-neighbours share u's offsets
+    // byte offsets of this lane's first chunk cell in u and f
+    const uint32_t cu = 8u * ((uint32_t)(ic + 1) + (uint32_t)(t0 + 1) * Sa + (uint32_t)(oc + 1) * So);
+    const uint32_t cf = 8u * ((uint32_t)ic + (uint32_t)t0 * Fa + (uint32_t)oc * Fo);
+    const uint32_t Sa8 = 8u * Sa, So8 = 8u * So, Fa8 = 8u * Fa;
+    const uint32_t xo = need_l ? 0u - 8u : 8u;
     // Loads are issued in batches of B cells, each batch before any of its
     // values is used (the scheduling barriers keep the compiler from sinking
-    // loads next to their uses), so a wavefront makes a few memory round trips
-    // per chunk instead of one per cell.
-    constexpr int B = L < 4 ? L : (L <= 16 ? 4 : 8);
-    double uc[L], r[L];
-#pragma unroll
-    for (int t = 0; t < L; ++t) {
-        const int tt = t < Lp ? t : Lp - 1;
-        uc[t] = s[cu + tt * Sa];
-    }
-    const double ulo = s[cu - Sa];
-    const double uhi = s[cu + (int64_t)Lp * Sa];
+    // loads next to their uses).
+    constexpr int B = L < 4 ? L : 4;
+    double r[L];
+    const double ulo = ldb(ub, cu - Sa8);
+    const double uhi = ldb(ub, cu + (uint32_t)Lp * Sa8);
     if (a.rhs_mode) {
 #pragma unroll
-        for (int t = 0; t < L; ++t) r[t] = uc[t];
+        for (int t = 0; t < L; ++t) r[t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
     } else {
-#pragma unroll
-    for (int tb = 0; tb < L; tb += B) {
-        double fb[B], om[B], op[B];
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const int t = tb + k;
-            const int tt = t < Lp ? t : Lp - 1;
-            const int64_t c = cu + tt * Sa;
-            fb[k] = a.f[cf + tt * Fa];
-            om[k] = s[c - So];
-            op[k] = s[c + So];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int k = 0; k < B; ++k) r[tb + k] = fma(h2, fb[k], eo * (om[k] + op[k]));
-    }
-    // x-neighbours that are not in an adjacent lane are read from memory
-    if (load_l || load_r) {
+        // r = h^2 f + eps_o (o-neighbours) + eps_x (x-neighbours) + eps_a
+        // (line neighbours) - d u, finished cell by cell as soon as the next
+        // centre value has arrived, so only B + 1 centre values stay live
+        double uprev = ulo, ucur = 0.0, rpend = 0.0;
 #pragma unroll
         for (int tb = 0; tb < L; tb += B) {
-            double xl[B], xr[B];
+            double ub4[B], fb[B], om[B], op[B], xa[B];
 #pragma unroll
             for (int k = 0; k < B; ++k) {
                 const int t = tb + k;
-                const int64_t c = cu + (t < Lp ? t : Lp - 1) * Sa;
-                xl[k] = s[c - 1];      // both are in-patch (ghost at worst)
-                xr[k] = s[c + 1];
+                const uint32_t tt = (uint32_t)(t < Lp ? t : Lp - 1);
+                const uint32_t c = cu + tt * Sa8;
+                ub4[k] = ldb(ub, c);
+                fb[k] = ldb(fbase, cf + tt * Fa8);
+                om[k] = ldb(ubm, c);
+                op[k] = ldb(ubp, c);
+                xa[k] = ldb(ub, c + xo);
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int k = 0; k < B; ++k)
-                r[tb + k] = fma(ex, (load_l ? xl[k] : 0.0) + (load_r ? xr[k] : 0.0), r[tb + k]);
+            for (int k = 0; k < B; ++k) {
+                const int t = tb + k;
+                const double left = lane_shift<-1>(ub4[k]);
+                const double right = lane_shift<+1>(ub4[k]);
+                const double xs = (need_l ? xa[k] : left) + (need_r ? (need_l ? 0.0 : xa[k]) : right);
+                const double rt = fma(-d, ub4[k], fma(ex, xs, fma(h2, fb[k], eo * (om[k] + op[k]))));
+                // cell t-1 is complete now that u_t is known (beyond Lp the
+                // upper neighbour is the chunk's far neighbour uhi)
+                if (t > 0) r[t - 1] = fma(ea, uprev + (t < Lp ? ub4[k] : uhi), rpend);
+                uprev = ucur;
+                ucur = ub4[k];
+                rpend = rt;
+                if (t == 0) uprev = ulo;
+            }
+            // keep the next batch's loads below this point (bounded registers)
+            asm volatile("" ::: "memory");
+        }
+        r[L - 1] = fma(ea, uprev + uhi, rpend);
+        if (__builtin_amdgcn_ballot_w64(both) != 0) {
+#pragma unroll
+            for (int tb = 0; tb < L; tb += B) {
+                double xb[B];
+#pragma unroll
+                for (int k = 0; k < B; ++k)
+                    xb[k] = ldb(ub, cu + (uint32_t)((tb + k) < Lp ? (tb + k) : Lp - 1) * Sa8 + 8u);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < B; ++k) r[tb + k] = fma(ex, both ? xb[k] : 0.0, r[tb + k]);
+            }
         }
     }
-#pragma unroll
-    for (int t = 0; t < L; ++t) {
-        const double left = lane_shift<-1>(uc[t]);
-        const double right = lane_shift<+1>(uc[t]);
-        const double um = (t == 0) ? ulo : uc[t > 0 ? t - 1 : 0];
-        double up = uhi;
-        if (t + 1 < L) up = (t + 1 < Lp) ? uc[t + 1 < L ? t + 1 : 0] : uhi;
-        const double xs = (load_l ? 0.0 : left) + (load_r ? 0.0 : right);
-        r[t] = fma(-d, uc[t], fma(ex, xs, fma(ea, um + up, r[t])));
-    }
-    }
     double y0, yl;
-    __syncthreads();   // table in LDS
-    chunk_solve<L>(r, Lp, Lr, tab, tab + Lr, ea, y0, yl);
+    chunk_solve_u<L>(r, Lp, tab, tab + Lr, ea, y0, yl);
     ends[(p * 64 + lane) * 2 + 0] = y0;
     ends[(p * 64 + lane) * 2 + 1] = yl;
-    __syncthreads();   // all reads of this tile's lines precede any write
+    __syncthreads();   // every chunk's ends are in LDS; all reads of the tile's lines precede any write
+    // the update reads u again (holding it through the solve would double the
+    // register footprint)
+    double uo[L];
+    if (!a.out_mode) {
+#pragma unroll
+        for (int t = 0; t < L; ++t) uo[t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
+    }
+    double bprev, anext;
+    interface_terms(tab, ends, Lr, P, pc, lane, bprev, anext);
+    const double *ev = tab + (pc == P - 1 ? 4 * Lr : 2 * Lr);
+    const double *ew = ev + Lr;
+    const double om = a.omega;
+    char *db = reinterpret_cast<char *>(a.dst + pd->uoff);
     if (valid) {
-        double bprev, anext;
-        interface_terms(tab, ends, Lr, P, p, lane, bprev, anext);
-        const double *ev = tab + (p == P - 1 ? 4 * Lr : 2 * Lr);
-        const double *ew = ev + Lr;
-        const double om = a.omega;
 #pragma unroll
         for (int t = 0; t < L; ++t) {
             if (t < Lp) {
                 const double du = fma(anext, ew[t], fma(bprev, ev[t], r[t]));
-                a.dst[cu + t * Sa] = a.out_mode ? du : fma(om, du, uc[t]);
+                *reinterpret_cast<double *>(db + (cu + (uint32_t)t * Sa8)) = a.out_mode ? du : fma(om, du, uo[t]);
             }
         }
     }
@@ -381,7 +437,7 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const WorkItem it
 template <int L, int MAXT>
 static hipError_t launch_strided_t(const LineArgs &a, int grid, int nwaves, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_line_strided<L, MAXT>), dim3(grid), dim3(64 * nwaves), lds, s, a);
+    hipLaunchKernelGGL((k_line_strided<L, MAXT>), dim3(grid), dim3(64 * nwaves), lds, s, a, a.tab);
     return hipGetLastError();
 }
 

@@ -154,8 +154,11 @@ size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c)
         tsz = std::max(tsz, line_table_size(r.Lr, r.P));
         sd = std::max(sd, ps->dims[3 * p] | 1);
     }
+    // y/z lines: two buffers of chunk ends (the table is read through the
+    // scalar cache); x lines: table, chunk ends, the tile's rows, row offsets
+    if (axis != 0) return 2 * 2 * 64 * static_cast<size_t>(c.nwaves) * sizeof(double);
     size_t n = static_cast<size_t>((tsz + 1) & ~1) + 2 * 64 * static_cast<size_t>(c.nwaves);
-    if (axis == 0) n += 64 * static_cast<size_t>(sd) + 128;
+    n += 64 * static_cast<size_t>(sd) + 128;
     return n * sizeof(double);
 }
 
