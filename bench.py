@@ -71,6 +71,25 @@ def profile_run():
     print("profile run done", flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the z-line sweep kernel from the committed
+    counter summary (FETCH_SIZE / WRITE_SIZE, scaled by a copy of known size),
+    used only while the kernel source is the one the counters were taken on."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "paper_1208_1975_amd", "csrc", "k_line.hip")
+    prof = os.path.join(here, "profiles", "zline_256cube_hbm_counters.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        for ln in open(prof):
+            if ln.startswith("traffic-json: "):
+                t = json.loads(ln[len("traffic-json: "):])
+                return t if t.get("source_sha256") == sha else None
+    except OSError:
+        return None
+    return None
+
+
 def timed_sweeps(fn, nsweeps_list, reps=5):
     """Median event time of fn(n) for each n (ms); events on the launch stream."""
     import torch
@@ -111,9 +130,32 @@ def forms():
     import torch
 
     import paper_1208_1975_amd as bs
-    from workloads import c1_patch, c3_patch, c4_patchset, c5_patch
+    from workloads import c1_patch, c2_patch, c3_patch, c4_patchset, c5_patch
 
     out = {}
+    # 256^3 z-line Jacobi with the line solve in FP32 (FP64 residual and update)
+    # against the FP64 form: 20 sweeps from the same state
+    p = c2_patch(256)
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    u0, f, w = ps.pack_u([p.u0]), ps.pack_f([p.f]), ps.empty_u()
+    res = {}
+    u64 = None
+    for prec in ("fp64", "fp32"):
+        u = u0.clone()
+        ps.line_relax(2, "jacobi", 0.8, 20, u, f, w, prec=prec)   # warm (graph capture)
+        u.copy_(u0)
+        ms = ev_ms(lambda: ps.line_relax(2, "jacobi", 0.8, 20, u, f, w, prec=prec), reps=1)
+        entry = {"ms_per_sweep": round(ms / 20, 4), "glups": round(256 ** 3 * 20 / (ms * 1e-3) / 1e9, 3)}
+        if prec == "fp64":
+            u64 = u.clone()
+        else:
+            entry["relerr_vs_fp64_20_sweeps"] = float((u - u64).abs().max() / u64.abs().max())
+        res[prec] = entry
+        del u
+    out["c2_zline_jacobi_line_solve_precision"] = res
+    ps.close()
+    del u0, f, w, u64
+
     # 32^3 x-line Jacobi, 10 sweeps (cache resident, launch bound)
     p = c1_patch()
     ps = bs.PatchSet([p.dims], [p.eps], [p.h])
@@ -278,8 +320,13 @@ def main():
     bytes_per_launch = 24.0 * cells
     dom_name, dom_us = ("z-line Jacobi sweep", jac_us) if jac_us >= cha_us else ("z-line chaotic GS sweep", cha_us)
     achieved = bytes_per_launch / (dom_us * 1e-6) / 1e9
+    mt = measured_traffic()
+    traffic = None
+    if mt is not None:
+        k = "jacobi" if dom_name.startswith("z-line Jacobi") else "chaotic"
+        traffic = mt[k + "_read_bytes"] + mt[k + "_write_bytes"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": dom_name, "us_per_launch": round(dom_us, 2),
             "bytes_per_launch": bytes_per_launch,
             "other": {"jacobi_us": round(jac_us, 2), "chaotic_us": round(cha_us, 2),

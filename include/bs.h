@@ -133,10 +133,17 @@ bs_status bs_residual(const bs_patchset *ps, const double *u, const double *f, d
  *   work  u-layout scratch for BS_JACOBI (the paper's second vector v); may
  *         be NULL for the Gauss-Seidel schemes.  Its ghosts are overwritten.
  *   omega in (0, 2).  nsweeps >= 0 (0 enqueues nothing).
+ *   prec  BS_FP64, or BS_MIXED_FP32: the line solve (chunk factors and
+ *         interface coupling) in FP32 while the residual and the update
+ *         u += omega du stay in FP64; every sweep recomputes the FP64
+ *         residual, so the sweeps themselves act as the defect correction and
+ *         the exact discrete solution stays a fixed point.
  * Every patch of the set is relaxed by the same launches (one per sweep, or
- * per colour for BS_COLORED_GS), larger patches first.  A sequence of two or
- * more sweeps is captured into a HIP graph on its first call and replayed by
- * later calls with the same arguments and buffers.
+ * per colour for BS_COLORED_GS), larger patches first.  BS_CHAOTIC_GS on y/z
+ * lines updates each tile's colour-0 lines, then its colour-1 lines from the
+ * new in-tile values, in place, tiles of even tile rows dispatched first.  A
+ * sequence of two or more sweeps is captured into a HIP graph on its first
+ * call and replayed by later calls with the same arguments and buffers.
  * BS_ERR_UNSUPPORTED for BS_MIXED_BF16 (BF16 is offered for planes only). */
 bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double omega,
                         int32_t nsweeps, bs_precision prec, double *u, const double *f,

@@ -293,8 +293,7 @@ class PatchSet:
     # tuning and comparison hooks of the library (not part of the C header)
     def set_line_config(self, axis, scheme, chunks, tile=64, grid=0):
         popt = (1, 2, 4, 8, 16).index(int(chunks))
-        cm = 0 if _scheme(scheme) == BS_JACOBI else 1
-        _check(lib().bsi_set_line_cfg(self.handle, int(axis), cm, popt, int(tile), int(grid)))
+        _check(lib().bsi_set_line_cfg(self.handle, int(axis), _scheme(scheme), popt, int(tile), int(grid)))
 
     def set_graphs(self, enable):
         _check(lib().bsi_set_graphs(self.handle, 1 if enable else 0))

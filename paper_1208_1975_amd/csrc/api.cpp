@@ -134,6 +134,8 @@ bs_status build_tables(bs_patchset *ps)
     }
     bs_status st = upload(ps->tab_d, tab.data(), tab.size() * sizeof(double), "tables");
     if (st != BS_OK) return st;
+    const std::vector<float> tab32(tab.begin(), tab.end());   // for FP32 block solves
+    if ((st = upload(ps->tab32_d, tab32.data(), tab32.size() * sizeof(float), "tables")) != BS_OK) return st;
     ps->lists.clear();
     clear_graphs(ps);
     ps->plane_ready = false;   // plane tables depend on eps; rebuilt on next use

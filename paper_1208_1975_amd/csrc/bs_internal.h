@@ -66,6 +66,8 @@ struct LineArgs {
     int32_t rhs_mode;       // 0: right-hand side = residual h^2 f - A src; 1: = src itself (f unused)
     int32_t out_mode;       // 0: dst = src + omega du; 1: dst = du (the block solve alone)
     double omega;
+    const float *tab32;     // FP32 copy of tab (same offsets)
+    int32_t f32;            // 1: block solve in FP32 (residual and update stay FP64)
 };
 
 struct ResidArgs {

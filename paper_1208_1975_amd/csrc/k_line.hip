@@ -16,6 +16,8 @@
 // from one row each of the precomputed inverse of the 2P x 2P interface
 // system.  This is an exact reformulation of the tridiagonal solve (partition
 // method), not an approximation.
+#include <type_traits>
+
 #include "bs_internal.h"
 
 namespace bs {
@@ -57,23 +59,23 @@ __device__ __forceinline__ void chunk_solve(double (&r)[L], int Lp, int Lr, cons
 // t >= Lr read the following table entries, which are finite; their results
 // are discarded exactly as above (the table holds at least 3 Lr > Lr + L - 1
 // entries because L < 2 Lr).
-template <int L>
-__device__ __forceinline__ void chunk_solve_u(double (&r)[L], int Lp, const double *__restrict__ g,
-                                              const double *__restrict__ q, double ea, double &y0, double &yl)
+template <int L, typename T>
+__device__ __forceinline__ void chunk_solve_u(T (&r)[L], int Lp, const T *__restrict__ g, const T *__restrict__ q,
+                                              T ea, T &y0, T &yl)
 {
-    double zprev = 0.0;
+    T zprev = 0;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
-        const double z = fma(g[t], zprev, r[t]);
-        r[t] = (t < Lp) ? z : 0.0;
+        const T z = fma(g[t], zprev, r[t]);
+        r[t] = (t < Lp) ? z : T(0);
         zprev = r[t];
     }
     asm volatile("" ::: "memory");   // q is fetched after g is consumed
-    double ynext = 0.0;
-    yl = 0.0;
+    T ynext = 0;
+    yl = 0;
 #pragma unroll
     for (int t = L - 1; t >= 0; --t) {
-        const double y = fma(ea, ynext, r[t]) * q[t];
+        const T y = fma(ea, ynext, r[t]) * q[t];
         r[t] = y;
         ynext = y;
         yl = (t == Lp - 1) ? y : yl;
@@ -93,17 +95,26 @@ __device__ __forceinline__ double lane_shift(double v)
     return __hiloint2double(hi2, lo2);
 }
 
+// Value of lane `src` (any lane of the wavefront, through the LDS crossbar).
+__device__ __forceinline__ double lane_get(double v, int src)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 // Interface coupling: every chunk's wavefront reads the ends of all chunks of
 // its line from LDS and forms the two corrections it needs.
-__device__ __forceinline__ void interface_terms(const double *tab, const double *ends, int Lr, int P,
-                                                int p, int lane, double &bprev, double &anext)
+template <typename T>
+__device__ __forceinline__ void interface_terms(const T *tab, const double *ends, int Lr, int P, int p, int lane,
+                                                T &bprev, T &anext)
 {
-    const double *Kb = tab + 6 * Lr + p * 2 * P;
-    const double *Ka = tab + 6 * Lr + 2 * P * P + p * 2 * P;
-    bprev = 0.0;
-    anext = 0.0;
+    const T *Kb = tab + 6 * Lr + p * 2 * P;
+    const T *Ka = tab + 6 * Lr + 2 * P * P + p * 2 * P;
+    bprev = 0;
+    anext = 0;
     for (int jj = 0; jj < 2 * P; ++jj) {
-        const double Y = ends[((jj >> 1) * 64 + lane) * 2 + (jj & 1)];
+        const T Y = static_cast<T>(ends[((jj >> 1) * 64 + lane) * 2 + (jj & 1)]);
         bprev = fma(Kb[jj], Y, bprev);
         anext = fma(Ka[jj], Y, anext);
     }
@@ -127,28 +138,45 @@ __device__ __forceinline__ double ldb(const char *base, uint32_t off)
     return *reinterpret_cast<const double *>(base + off);
 }
 
-template <int L>
+template <int L, int CM, bool F32>
 __device__ __forceinline__ void line_strided_item(const LineArgs &a, const double *__restrict__ tabs,
-                                                  const WorkItem it, double *ends);
+                                                  const float *__restrict__ tabs32, const WorkItem it, double *ends,
+                                                  double *ends2, double *ucs);
 
 // A workgroup drains work items blockIdx.x, blockIdx.x + gridDim.x, ...: one
 // item per workgroup when the grid covers the list, a persistent grid otherwise.
-template <int L, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a, const double *__restrict__ tabs)
+// LDS: the chunk values of u (L per lane, each lane reads back only its own)
+// followed by two buffers of chunk ends.  CM: the kernel mode (0 all lines,
+// 1 one colour per launch, 2 in-tile two-colour), a.colour_mode == CM.  F32:
+// the block solve in FP32 (residual and update stay FP64).
+template <int L, int MAXT, int CM, bool F32>
+__global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a, const double *__restrict__ tabs,
+                                                      const float *__restrict__ tabs32)
 {
     extern __shared__ double smem[];
     const int nw = blockDim.x >> 6;
+    double *ucs = smem;
+    double *endb = smem + L * 64 * nw;
     int buf = 0;
     for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
-        line_strided_item<L>(a, tabs, a.items[i], smem + buf * (2 * 64 * nw));
-        buf ^= 1;
+        line_strided_item<L, CM, F32>(a, tabs, tabs32, a.items[i], endb + buf * (2 * 64 * nw),
+                                      endb + (buf ^ 1) * (2 * 64 * nw), ucs);
+        // one barrier per item alternates the buffers; the in-tile two-colour
+        // mode uses both in every item behind two barriers
+        if (CM != 2) buf ^= 1;
     }
 }
 
-template <int L>
+template <int L, int CM, bool F32>
 __device__ __forceinline__ void line_strided_item(const LineArgs &a, const double *__restrict__ tabs,
-                                                  const WorkItem it, double *ends)
+                                                  const float *__restrict__ tabs32, const WorkItem it, double *ends,
+                                                  double *ends2, double *ucs)
 {
+    using T = typename std::conditional<F32, float, double>::type;
+    const int nthr = blockDim.x;
+    // chunks of up to 16 cells keep u in LDS for the update (16 waves x 64
+    // lanes x 16 doubles = 128 KiB); longer chunks read it again from memory
+    constexpr bool kUcLds = L <= 16;
     const PatchDesc *pd = a.pd + it.patch;
     const int axis = a.axis;          // 1 or 2
     const int oaxis = 3 - axis;       // the other free axis
@@ -164,14 +192,18 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
     const double h2 = pd->h2;
     const LineTabRef tr = pd->line[axis][a.popt];
     const int Lr = tr.Lr, P = tr.P, Llast = tr.Llast;
-    const double *tab = tabs + tr.off;
+    const T *tab;
+    if constexpr (F32)
+        tab = tabs32 + tr.off;
+    else
+        tab = tabs + tr.off;
 
     const int lane = threadIdx.x & 63;
     const int p = uniform_wave();
     const int tx = a.tx, tyo = 64 / tx;
     const int li = lane % tx, lo = lane / tx;
     int i, o;
-    if (a.colour_mode) {
+    if (CM == 1) {
         const int half = (nx + 1) >> 1;
         const int nti = (half + tx - 1) / tx;
         o = (it.tile / nti) * tyo + lo;
@@ -193,8 +225,8 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
     // row edge of the tile or the patch, or lanes are colour-strided.  A lane
     // that needs one side from memory gets it with the batched loads; a lane
     // that needs both (colour-strided, or a one-lane row) takes one more load.
-    const bool need_l = a.colour_mode || li == 0;
-    const bool need_r = a.colour_mode || li == tx - 1 || i >= nx - 1;
+    const bool need_l = CM == 1 || li == 0;
+    const bool need_r = CM == 1 || li == tx - 1 || i >= nx - 1;
     const bool both = need_l && need_r;
 
     const char *ub = reinterpret_cast<const char *>(a.src + pd->uoff);
@@ -214,7 +246,10 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
     const double uhi = ldb(ub, cu + (uint32_t)Lp * Sa8);
     if (a.rhs_mode) {
 #pragma unroll
-        for (int t = 0; t < L; ++t) r[t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
+        for (int t = 0; t < L; ++t) {
+            r[t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
+            if (kUcLds) ucs[t * nthr + threadIdx.x] = r[t];
+        }
     } else {
         // r = h^2 f + eps_o (o-neighbours) + eps_x (x-neighbours) + eps_a
         // (line neighbours) - d u, finished cell by cell as soon as the next
@@ -238,6 +273,7 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
 #pragma unroll
             for (int k = 0; k < B; ++k) {
                 const int t = tb + k;
+                if (kUcLds) ucs[t * nthr + threadIdx.x] = ub4[k];
                 const double left = lane_shift<-1>(ub4[k]);
                 const double right = lane_shift<+1>(ub4[k]);
                 const double xs = (need_l ? xa[k] : left) + (need_r ? (need_l ? 0.0 : xa[k]) : right);
@@ -267,30 +303,84 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
             }
         }
     }
-    double y0, yl;
-    chunk_solve_u<L>(r, Lp, tab, tab + Lr, ea, y0, yl);
+    T rs[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) rs[t] = static_cast<T>(r[t]);
+    T y0, yl;
+    chunk_solve_u<L, T>(rs, Lp, tab, tab + Lr, static_cast<T>(ea), y0, yl);
     ends[(p * 64 + lane) * 2 + 0] = y0;
     ends[(p * 64 + lane) * 2 + 1] = yl;
     __syncthreads();   // every chunk's ends are in LDS; all reads of the tile's lines precede any write
-    // the update reads u again (holding it through the solve would double the
-    // register footprint)
-    double uo[L];
-    if (!a.out_mode) {
+    double uo[kUcLds ? 1 : L];
+    if (!kUcLds && !a.out_mode) {
 #pragma unroll
-        for (int t = 0; t < L; ++t) uo[t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
+        for (int t = 0; t < L; ++t) uo[kUcLds ? 0 : t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
     }
-    double bprev, anext;
-    interface_terms(tab, ends, Lr, P, pc, lane, bprev, anext);
-    const double *ev = tab + (pc == P - 1 ? 4 * Lr : 2 * Lr);
-    const double *ew = ev + Lr;
+    T bprev, anext;
+    interface_terms<T>(tab, ends, Lr, P, pc, lane, bprev, anext);
+    const T *ev = tab + (pc == P - 1 ? 4 * Lr : 2 * Lr);
+    const T *ew = ev + Lr;
     const double om = a.omega;
     char *db = reinterpret_cast<char *>(a.dst + pd->uoff);
+    if (CM == 2) {
+        // In-tile two-colour (chaotic GS): the solve above is exact for the
+        // colour-0 lines ((i + o) even).  Every lane takes u + omega du (for
+        // colour-1 lines that is the part of their solve due to the residual
+        // as loaded; the line solve is linear), and the colour-1 lines then
+        // solve for the residual change caused by their updated colour-0
+        // neighbours inside the tile.  Neighbours in other tiles are read as
+        // they were (the asynchronous part of the scheme).
+        const bool red = ((i + o) & 1) == 0;
+        const bool in_dn = lo > 0, in_up = lo < tyo - 1 && o + 1 < no;
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            const double du = static_cast<double>(fma(anext, ew[t], fma(bprev, ev[t], rs[t])));
+            if (kUcLds) {
+                double *us = ucs + t * nthr + threadIdx.x;
+                *us = fma(om, du, *us);
+            } else {
+                uo[kUcLds ? 0 : t] = fma(om, du, uo[kUcLds ? 0 : t]);
+            }
+            const double dl = (red && valid) ? om * du : 0.0;
+            const double cl = lane_shift<-1>(dl), cr = lane_shift<+1>(dl);
+            double c = ex * ((need_l ? 0.0 : cl) + (need_r ? 0.0 : cr));
+            if (tyo > 1) {
+                const double cd = lane_get(dl, lane - tx < 0 ? lane : lane - tx);
+                const double cu2 = lane_get(dl, lane + tx > 63 ? lane : lane + tx);
+                c = fma(eo, (in_dn ? cd : 0.0) + (in_up ? cu2 : 0.0), c);
+            }
+            rs[t] = static_cast<T>((!red && t < Lp) ? c : 0.0);
+        }
+        // reload the factors rather than holding them in scalar registers
+        // across both solves
+        const T *tab2 = tab;
+        asm volatile("" : "+s"(tab2));
+        chunk_solve_u<L, T>(rs, Lp, tab2, tab2 + Lr, static_cast<T>(ea), y0, yl);
+        ends2[(p * 64 + lane) * 2 + 0] = y0;
+        ends2[(p * 64 + lane) * 2 + 1] = yl;
+        __syncthreads();
+        interface_terms<T>(tab2, ends2, Lr, P, pc, lane, bprev, anext);
+        const T *ev2 = tab2 + (pc == P - 1 ? 4 * Lr : 2 * Lr);
+        const T *ew2 = ev2 + Lr;
+        if (valid) {
+#pragma unroll
+            for (int t = 0; t < L; ++t) {
+                if (t < Lp) {
+                    const double du = static_cast<double>(fma(anext, ew2[t], fma(bprev, ev2[t], rs[t])));
+                    *reinterpret_cast<double *>(db + (cu + (uint32_t)t * Sa8)) =
+                        fma(om, du, kUcLds ? ucs[t * nthr + threadIdx.x] : uo[kUcLds ? 0 : t]);
+                }
+            }
+        }
+        return;
+    }
     if (valid) {
 #pragma unroll
         for (int t = 0; t < L; ++t) {
             if (t < Lp) {
-                const double du = fma(anext, ew[t], fma(bprev, ev[t], r[t]));
-                *reinterpret_cast<double *>(db + (cu + (uint32_t)t * Sa8)) = a.out_mode ? du : fma(om, du, uo[t]);
+                const double du = static_cast<double>(fma(anext, ew[t], fma(bprev, ev[t], rs[t])));
+                *reinterpret_cast<double *>(db + (cu + (uint32_t)t * Sa8)) =
+                    a.out_mode ? du : fma(om, du, kUcLds ? ucs[t * nthr + threadIdx.x] : uo[kUcLds ? 0 : t]);
             }
         }
     }
@@ -302,21 +392,25 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
 // solves its row's chunk from LDS in registers, and the update is written back
 // coalesced.  With colour_mode the tile holds rows of one colour ((j+k) parity).
 // ---------------------------------------------------------------------------
-template <int L, int MAXT>
-__device__ __forceinline__ void line_x_item(const LineArgs &a, const WorkItem it, double *smem);
+template <int L, int MAXT, bool F32>
+__device__ __forceinline__ void line_x_item(const LineArgs &a, const float *__restrict__ tabs32, const WorkItem it,
+                                            double *smem);
 
-template <int L, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_line_x(LineArgs a)
+// F32: the block solve in FP32 (factors from the FP32 table copy, read
+// through the scalar cache); residual and update stay FP64.
+template <int L, int MAXT, bool F32>
+__global__ void __launch_bounds__(MAXT) k_line_x(LineArgs a, const float *__restrict__ tabs32)
 {
     extern __shared__ double smem[];
     for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
-        line_x_item<L, MAXT>(a, a.items[i], smem);
+        line_x_item<L, MAXT, F32>(a, tabs32, a.items[i], smem);
         __syncthreads();
     }
 }
 
-template <int L, int MAXT>
-__device__ __forceinline__ void line_x_item(const LineArgs &a, const WorkItem it, double *smem)
+template <int L, int MAXT, bool F32>
+__device__ __forceinline__ void line_x_item(const LineArgs &a, const float *__restrict__ tabs32, const WorkItem it,
+                                            double *smem)
 {
     const PatchDesc *pd = a.pd + it.patch;
     const int nx = pd->n[0], ny = pd->n[1], nz = pd->n[2];
@@ -392,25 +486,34 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const WorkItem it
     const bool valid = (rowu[lane] >= 0) && (p < P);
     const int Lp = (p == P - 1) ? Llast : Lr;
     const int t0 = p * Lr;
-    double r[L];
-    double y0 = 0.0, yl = 0.0;
+    using T = typename std::conditional<F32, float, double>::type;
+    const T *tabT;
+    if constexpr (F32)
+        tabT = tabs32 + tr.off;
+    else
+        tabT = tab;
+    T r[L];
+    T y0 = 0, yl = 0;
     if (valid) {
 #pragma unroll
         for (int t = 0; t < L; ++t)
-            if (t < Lp) r[t] = rb[lane * sd + t0 + t];
-        chunk_solve<L>(r, Lp, Lr, tab, tab + Lr, ex, y0, yl);
+            if (t < Lp) r[t] = static_cast<T>(rb[lane * sd + t0 + t]);
+        if constexpr (F32)
+            chunk_solve_u<L, T>(r, Lp, tabT, tabT + Lr, static_cast<T>(ex), y0, yl);
+        else
+            chunk_solve<L>(r, Lp, Lr, tab, tab + Lr, ex, y0, yl);
     }
     ends[(p * 64 + lane) * 2 + 0] = y0;
     ends[(p * 64 + lane) * 2 + 1] = yl;
     __syncthreads();
     if (valid) {
-        double bprev, anext;
-        interface_terms(tab, ends, Lr, P, p, lane, bprev, anext);
-        const double *ev = tab + (p == P - 1 ? 4 * Lr : 2 * Lr);
-        const double *ew = ev + Lr;
+        T bprev, anext;
+        interface_terms<T>(tabT, ends, Lr, P, p, lane, bprev, anext);
+        const T *ev = tabT + (p == P - 1 ? 4 * Lr : 2 * Lr);
+        const T *ew = ev + Lr;
 #pragma unroll
         for (int t = 0; t < L; ++t)
-            if (t < Lp) rb[lane * sd + t0 + t] = fma(anext, ew[t], fma(bprev, ev[t], r[t]));
+            if (t < Lp) rb[lane * sd + t0 + t] = static_cast<double>(fma(anext, ew[t], fma(bprev, ev[t], r[t])));
     }
     __syncthreads();
 
@@ -434,17 +537,35 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const WorkItem it
     }
 }
 
+template <int L, int MAXT, bool F32>
+static void launch_strided_p(const LineArgs &a, int grid, int nwaves, size_t lds, hipStream_t s)
+{
+    const dim3 g(grid), b(64 * nwaves);
+    switch (a.colour_mode) {
+    case 0: hipLaunchKernelGGL((k_line_strided<L, MAXT, 0, F32>), g, b, lds, s, a, a.tab, a.tab32); break;
+    case 1: hipLaunchKernelGGL((k_line_strided<L, MAXT, 1, F32>), g, b, lds, s, a, a.tab, a.tab32); break;
+    default: hipLaunchKernelGGL((k_line_strided<L, MAXT, 2, F32>), g, b, lds, s, a, a.tab, a.tab32); break;
+    }
+}
+
 template <int L, int MAXT>
 static hipError_t launch_strided_t(const LineArgs &a, int grid, int nwaves, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_line_strided<L, MAXT>), dim3(grid), dim3(64 * nwaves), lds, s, a, a.tab);
+    if (a.colour_mode < 0 || a.colour_mode > 2) return hipErrorInvalidValue;
+    if (a.f32)
+        launch_strided_p<L, MAXT, true>(a, grid, nwaves, lds, s);
+    else
+        launch_strided_p<L, MAXT, false>(a, grid, nwaves, lds, s);
     return hipGetLastError();
 }
 
 template <int L, int MAXT>
 static hipError_t launch_x_t(const LineArgs &a, int grid, int nwaves, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_line_x<L, MAXT>), dim3(grid), dim3(64 * nwaves), lds, s, a);
+    if (a.f32)
+        hipLaunchKernelGGL((k_line_x<L, MAXT, true>), dim3(grid), dim3(64 * nwaves), lds, s, a, a.tab32);
+    else
+        hipLaunchKernelGGL((k_line_x<L, MAXT, false>), dim3(grid), dim3(64 * nwaves), lds, s, a, a.tab32);
     return hipGetLastError();
 }
 
@@ -467,20 +588,34 @@ BS_DISPATCH(launch_x_t)
 
 // Allow the large-LDS line kernels (x-lines of up to 256 cells) once per
 // process, so that no attribute call ever happens inside a graph capture.
-template <int L>
-static hipError_t allow_all_t()
+template <int L, bool F32>
+static hipError_t allow_all_p()
 {
     hipError_t e = hipSuccess;
-    const void *ks[] = {reinterpret_cast<const void *>(k_line_x<L, 256>), reinterpret_cast<const void *>(k_line_x<L, 512>),
-                        reinterpret_cast<const void *>(k_line_x<L, 1024>),
-                        reinterpret_cast<const void *>(k_line_strided<L, 256>),
-                        reinterpret_cast<const void *>(k_line_strided<L, 512>),
-                        reinterpret_cast<const void *>(k_line_strided<L, 1024>)};
+    const void *ks[] = {reinterpret_cast<const void *>(k_line_x<L, 256, F32>),
+                        reinterpret_cast<const void *>(k_line_x<L, 512, F32>),
+                        reinterpret_cast<const void *>(k_line_x<L, 1024, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 256, 0, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 512, 0, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 1024, 0, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 256, 1, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 512, 1, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 1024, 1, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 256, 2, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 512, 2, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 1024, 2, F32>)};
     for (const void *k : ks) {
         hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (r != hipSuccess) e = r;
     }
     return e;
+}
+
+template <int L>
+static hipError_t allow_all_t()
+{
+    hipError_t e = allow_all_p<L, false>();
+    return e == hipSuccess ? allow_all_p<L, true>() : e;
 }
 
 hipError_t prepare_line_kernels()

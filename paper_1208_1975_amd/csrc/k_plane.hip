@@ -11,6 +11,8 @@
 // orientation; its epilogue either stores C, stores C scaled elementwise by a
 // table (the inverse eigenvalue grid), or writes dst = src + omega C straight
 // into the padded u layout (the block update).
+#include <cstdint>
+
 #include "bs_internal.h"
 #include "plane.h"
 
@@ -24,11 +26,26 @@ constexpr int BM = 64, BN = 64, BK = 16;
 
 }  // namespace
 
+// Two-element group of a row starting at column c0 (zero beyond `lim`); one
+// 16-byte load when aligned and inside.
+__device__ __forceinline__ double2 load2(const double *row, int c0, int lim, bool vec)
+{
+    if (vec && c0 + 2 <= lim) return *reinterpret_cast<const double2 *>(row + c0);
+    double2 r;
+    r.x = c0 < lim ? row[c0] : 0.0;
+    r.y = c0 + 1 < lim ? row[c0 + 1] : 0.0;
+    return r;
+}
+
+// A 64 x 64 block of C per workgroup (four wavefronts, 32 x 32 each as 2 x 2
+// blocks of 16 x 16); K advances BK at a time through two LDS buffers, the
+// next tile fetched into registers while the current one feeds the matrix
+// cores (one barrier per step).
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
 {
-    __shared__ double As[BK][BM + 1];
-    __shared__ double Bs[BK][BN + 1];
+    __shared__ double As[2][BK][BM + 2];
+    __shared__ double Bs[2][BK][BN + 2];
     const int b = blockIdx.z;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const double *A = g.A + (int64_t)b * g.sA;
@@ -37,6 +54,8 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int l16 = lane & 15, lk = lane >> 4;
+    const bool avec = ((g.lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    const bool bvec = ((g.ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
 
     dbl4 acc[2][2];
 #pragma unroll
@@ -44,37 +63,55 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
-        // A tile BM x BK (rows coalesced along k), stored k-major
+    // A tile BM x BK: pair c -> row c / 8, k offset (c % 8) * 2 (two pairs a
+    // thread); B tile BK x BN: pair c -> k row c / 32, n offset (c % 32) * 2
+    double2 ra[2], rb[2];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < (BM * BK) / 256; ++q) {
-            const int e = tid + 256 * q;
-            const int r = e / BK, c = e % BK;
-            const int gr = m0 + r, gc = k0 + c;
-            As[c][r] = (gr < g.M && gc < g.K) ? A[(int64_t)gr * g.lda + gc] : 0.0;
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q;
+            const int r = c >> 3, kc = (c & 7) * 2;
+            const int gr = m0 + r;
+            ra[q] = gr < g.M ? load2(A + (int64_t)gr * g.lda, k0 + kc, g.K, avec) : double2{0.0, 0.0};
+            const int kr = c >> 5, nc = (c & 31) * 2;
+            const int gk = k0 + kr;
+            rb[q] = gk < g.K ? load2(B + (int64_t)gk * g.ldb, n0 + nc, g.N, bvec) : double2{0.0, 0.0};
         }
-        // B tile BK x BN
+    };
+    auto stash = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < (BK * BN) / 256; ++q) {
-            const int e = tid + 256 * q;
-            const int r = e / BN, c = e % BN;
-            const int gr = k0 + r, gc = n0 + c;
-            Bs[r][c] = (gr < g.K && gc < g.N) ? B[(int64_t)gr * g.ldb + gc] : 0.0;
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q;
+            const int r = c >> 3, kc = (c & 7) * 2;
+            As[buf][kc][r] = ra[q].x;
+            As[buf][kc + 1][r] = ra[q].y;
+            const int kr = c >> 5, nc = (c & 31) * 2;
+            Bs[buf][kr][nc] = rb[q].x;
+            Bs[buf][kr][nc + 1] = rb[q].y;
         }
-        __syncthreads();
+    };
+
+    const int nk = (g.K + BK - 1) / BK;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) fetch((kt + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double af[2], bf[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) af[i] = As[kk + lk][wm * 32 + i * 16 + l16];
+            for (int i = 0; i < 2; ++i) af[i] = As[cur][kk + lk][wm * 32 + i * 16 + l16];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bf[j] = Bs[kk + lk][wn * 32 + j * 16 + l16];
+            for (int j = 0; j < 2; ++j) bf[j] = Bs[cur][kk + lk][wn * 32 + j * 16 + l16];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
+        if (kt + 1 < nk) stash(cur ^ 1);
         __syncthreads();
     }
 

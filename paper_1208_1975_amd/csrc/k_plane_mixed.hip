@@ -1,10 +1,11 @@
-// Mixed-precision plane solves: the four fast-diagonalisation products in FP32
-// or BF16 on the matrix cores with FP32 accumulation, while the residual, the
-// defect of the refinement and the update stay in FP64.  For the plane block
-// M_P and residual R (FP64), the correction D solves M_P D = R by
+// Mixed-precision plane solves, FP32 form, and the FP64 helpers of both mixed
+// forms: the four fast-diagonalisation products in FP32 on the matrix cores
+// (v_mfma_f32_16x16x4_f32) while the residual, the defect of the refinement
+// and the update stay in FP64.  For the plane block M_P and residual R
+// (FP64), the correction D solves M_P D = R by
 //   D_0 = M~^{-1} R,  D_{j+1} = D_j + M~^{-1}(R - M_P D_j)   (j < refine)
 // with M~^{-1} the low-precision transform chain, M_P D_j applied in FP64,
-// and finally u += omega D in FP64.
+// and finally u += omega D in FP64.  (The BF16 products are in k_plane_bf16.)
 #include "bs_internal.h"
 #include "plane.h"
 
@@ -13,22 +14,19 @@ namespace bs {
 namespace {
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 64, BN = 64, BK = 32;
 
 }  // namespace
 
-// C_b = A_b B_b with float operands in memory.  PREC 1: FP32 products
-// (v_mfma_f32_16x16x4_f32); PREC 2: operands rounded to BF16
-// (v_mfma_f32_16x16x32_bf16).  FP32 accumulation in both.
-template <int PREC, int EPI>
+// C_b = A_b B_b with FP32 operands (v_mfma_f32_16x16x4_f32), FP32
+// accumulation.
+template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
 {
-    // A tile row-major [m][k]; B tile stored [n][k] (k contiguous) for BF16,
-    // [k][n] for FP32
+    // A tile row-major [m][k]; B tile [k][n]
     __shared__ float As[BM][BK + 1];
-    __shared__ float Bs[BK > BN ? BK : BN][(BK > BN ? BK : BN) + 1];
+    __shared__ float Bs[BK][BN + 1];
     const int b = blockIdx.z;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const float *A = g.A + (int64_t)b * g.sA;
@@ -57,43 +55,21 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
             const int e = tid + 256 * q;
             const int r = e / BN, c = e % BN;
             const int gr = k0 + r, gc = n0 + c;
-            const float v = (gr < g.K && gc < g.N) ? B[(int64_t)gr * g.ldb + gc] : 0.f;
-            if (PREC == 2)
-                Bs[c][r] = v;
-            else
-                Bs[r][c] = v;
+            Bs[r][c] = (gr < g.K && gc < g.N) ? B[(int64_t)gr * g.ldb + gc] : 0.f;
         }
         __syncthreads();
-        if (PREC == 1) {
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                float af[2], bfr[2];
+        for (int kk = 0; kk < BK; kk += 4) {
+            float af[2], bfr[2];
 #pragma unroll
-                for (int i = 0; i < 2; ++i) af[i] = As[wm * 32 + i * 16 + l16][kk + lk];
+            for (int i = 0; i < 2; ++i) af[i] = As[wm * 32 + i * 16 + l16][kk + lk];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) bfr[j] = Bs[kk + lk][wn * 32 + j * 16 + l16];
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
-            }
-        } else {
-            // one K=32 step: lane supplies k = 8*(lane/16) .. +7 of its row / column
-            bf8 af[2], bfr[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int t = 0; t < 8; ++t) af[i][t] = (__bf16)As[wm * 32 + i * 16 + l16][8 * lk + t];
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int t = 0; t < 8; ++t) bfr[j][t] = (__bf16)Bs[wn * 32 + j * 16 + l16][8 * lk + t];
+            for (int j = 0; j < 2; ++j) bfr[j] = Bs[kk + lk][wn * 32 + j * 16 + l16];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
@@ -125,10 +101,18 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
             }
 }
 
-// E = (float)(R - M_P D) on every cell of one patch (D may be null: E = R),
-// M_P the plane block with normal c: d D - eps_a (in-plane neighbours along a)
-// - eps_b (along b), zero beyond the plane's edges.  blockIdx.y: unused.
-__global__ void __launch_bounds__(256) k_plane_defect(const double *R, const double *D, float *E, int nx, int ny,
+__device__ __forceinline__ void put_lowp(float *E, int64_t c, double v) { E[c] = (float)v; }
+__device__ __forceinline__ void put_lowp(unsigned short *E, int64_t c, double v)
+{
+    E[c] = __builtin_bit_cast(unsigned short, static_cast<__bf16>(v));
+}
+
+// E = low-precision (R - M_P D) on every cell of one patch (D may be null:
+// E = R), M_P the plane block with normal c: d D - eps_a (in-plane neighbours
+// along a) - eps_b (along b), zero beyond the plane's edges.  T: float, or
+// unsigned short holding BF16 (rounded from FP64 directly).
+template <typename T>
+__global__ void __launch_bounds__(256) k_plane_defect(const double *R, const double *D, T *E, int nx, int ny,
                                                       int nz, int normal, double ex, double ey, double ez)
 {
     const int64_t n = (int64_t)nx * ny * nz;
@@ -155,7 +139,7 @@ __global__ void __launch_bounds__(256) k_plane_defect(const double *R, const dou
             }
             v -= md;
         }
-        E[c] = (float)v;
+        put_lowp(E, c, v);
     }
 }
 
@@ -177,24 +161,19 @@ __global__ void __launch_bounds__(256) k_plane_update(const double *D, const dou
     }
 }
 
-template <int PREC>
-static hipError_t launch_mixed_t(const GemmMixedArgs &g, int epi, hipStream_t s)
+hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStream_t s)
 {
+    if (prec != 1) return hipErrorInvalidValue;
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
     const dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
     switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL((k_gemm_mixed<PREC, kEpiStore>), grid, dim3(256), 0, s, g); break;
-    case kEpiScale: hipLaunchKernelGGL((k_gemm_mixed<PREC, kEpiScale>), grid, dim3(256), 0, s, g); break;
-    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_mixed<PREC, kEpiUpdate>), grid, dim3(256), 0, s, g); break;
-    case kEpiD64: hipLaunchKernelGGL((k_gemm_mixed<PREC, kEpiD64>), grid, dim3(256), 0, s, g); break;
+    case kEpiStore: hipLaunchKernelGGL((k_gemm_mixed<kEpiStore>), grid, dim3(256), 0, s, g); break;
+    case kEpiScale: hipLaunchKernelGGL((k_gemm_mixed<kEpiScale>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdate>), grid, dim3(256), 0, s, g); break;
+    case kEpiD64: hipLaunchKernelGGL((k_gemm_mixed<kEpiD64>), grid, dim3(256), 0, s, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStream_t s)
-{
-    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
-    return prec == 2 ? launch_mixed_t<2>(g, epi, s) : launch_mixed_t<1>(g, epi, s);
 }
 
 hipError_t launch_plane_defect(const double *R, const double *D, float *E, int nx, int ny, int nz, int normal,
@@ -202,8 +181,18 @@ hipError_t launch_plane_defect(const double *R, const double *D, float *E, int n
 {
     const int64_t n = (int64_t)nx * ny * nz;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_plane_defect, dim3(blocks), dim3(256), 0, s, R, D, E, nx, ny, nz, normal, eps[0], eps[1],
-                       eps[2]);
+    hipLaunchKernelGGL(k_plane_defect<float>, dim3(blocks), dim3(256), 0, s, R, D, E, nx, ny, nz, normal, eps[0],
+                       eps[1], eps[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_defect_bf16(const double *R, const double *D, unsigned short *E, int nx, int ny, int nz,
+                                    int normal, const double eps[3], hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_plane_defect<unsigned short>, dim3(blocks), dim3(256), 0, s, R, D, E, nx, ny, nz, normal,
+                       eps[0], eps[1], eps[2]);
     return hipGetLastError();
 }
 

@@ -66,7 +66,7 @@ struct bs_patchset {
     int64_t u_numel = 0, f_numel = 0;
     int32_t max_n[3] = {0, 0, 0};
     std::vector<bs::PatchDesc> desc;
-    bs::DevBuf desc_d, tab_d;
+    bs::DevBuf desc_d, tab_d, tab32_d;
     // residual reduction plan
     int32_t nrblocks = 0;
     bs::DevBuf rblock_patch_d, rblock_first_d, rpatch_first_d, rpartial_d;
@@ -75,6 +75,7 @@ struct bs_patchset {
     bool plane_ready = false;
     bs::DevBuf plane_tab_d, plane_r_d, plane_t_d;
     bs::DevBuf plane_tab32_d, plane_f1_d, plane_f2_d;   // FP32 copies and float scratch (mixed precision)
+    bs::DevBuf plane_tab16_d;                           // BF16 copies of the bases
     int mixed_dlayout = 0;
     std::vector<int64_t> basis_off, lam_off;   // [3 * npatch] each, offsets in doubles
     // cached work lists and tuned configurations

@@ -3,6 +3,8 @@
 // precision (FP32 / BF16 products, FP64 residual, defect and update).
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <cstring>
 
 #include "patchset.h"
 #include "plane.h"
@@ -14,6 +16,18 @@ namespace bs {
 namespace {
 
 constexpr int kMaxPlaneEdge = 1024;
+
+// FP64 -> BF16 bit pattern, rounded to nearest even through FP32 (finite
+// inputs; the tables hold O(1) values).
+uint16_t bf16_bits(double v)
+{
+    const float f = static_cast<float>(v);
+    uint32_t u;
+    std::memcpy(&u, &f, sizeof u);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return static_cast<uint16_t>(u >> 16);
+}
 
 // Bases S_x, S_y, S_z of every patch and the inverse eigenvalue grid of every
 // (patch, normal):  normal z: [q_y][p_x] = 1/(sigma_y,q + sigma_x,p + 2 eps_z);
@@ -31,7 +45,7 @@ bs_status build_plane_tables(bs_patchset *ps)
             ps->basis_off[3 * p + a] = static_cast<int64_t>(tab.size());
             const std::vector<double> S = sine_basis(n[a]);
             tab.insert(tab.end(), S.begin(), S.end());
-            while (tab.size() % 4) tab.push_back(0.0);
+            while (tab.size() % 8) tab.push_back(0.0);   // 16-byte aligned BF16 copies
             sg[a] = sine_eigenvalues(n[a], e[a]);
         }
         for (int c = 0; c < 3; ++c) {
@@ -41,13 +55,18 @@ bs_status build_plane_tables(bs_patchset *ps)
             for (int q = 0; q < n[ar]; ++q)
                 for (int r = 0; r < n[ac]; ++r)
                     tab.push_back(static_cast<double>(1.0L / (sg[ar][q] + sg[ac][r] + 2.0L * e[c])));
-            while (tab.size() % 4) tab.push_back(0.0);
+            while (tab.size() % 8) tab.push_back(0.0);
         }
     }
     bs_status st = upload(ps->plane_tab_d, tab.data(), tab.size() * sizeof(double), "plane tables");
     if (st != BS_OK) return st;
     std::vector<float> tab32(tab.begin(), tab.end());
     if ((st = upload(ps->plane_tab32_d, tab32.data(), tab32.size() * sizeof(float), "plane tables")) != BS_OK) return st;
+    // BF16 copy (round to nearest even from FP64) for the BF16 products
+    std::vector<uint16_t> tab16(tab.size());
+    for (size_t t = 0; t < tab.size(); ++t) tab16[t] = bf16_bits(tab[t]);
+    if ((st = upload(ps->plane_tab16_d, tab16.data(), tab16.size() * sizeof(uint16_t), "plane tables")) != BS_OK)
+        return st;
     if (!ps->plane_r_d.p) {
         if ((st = dev_alloc(ps->plane_r_d, static_cast<size_t>(ps->f_numel) * 8, "plane scratch")) != BS_OK) return st;
         if ((st = dev_alloc(ps->plane_t_d, static_cast<size_t>(ps->f_numel) * 8, "plane scratch")) != BS_OK) return st;
@@ -231,6 +250,52 @@ bs_status chain_lowp(bs_patchset *ps, int p, int c, int colour, int prec, int la
     return BS_OK;
 }
 
+// BF16 chain M~^{-1} E: E (BF16, f layout) in F1, scratch F2 (both BF16);
+// the bases are symmetric, so a basis B operand is passed as [n][k].
+bs_status chain_bf16(bs_patchset *ps, int p, int c, int colour, int last_epi, int accumulate, const double *src,
+                     double *dst, double omega, hipStream_t s)
+{
+    const Chain ch = plane_chain_geometry(ps, p, c, colour);
+    if (ch.empty) return BS_OK;
+    const uint16_t *tab = static_cast<const uint16_t *>(ps->plane_tab16_d.p);
+    const float *tab32 = static_cast<const float *>(ps->plane_tab32_d.p);
+    uint16_t *F1 = static_cast<uint16_t *>(ps->plane_f1_d.p) + ps->foff[p];
+    uint16_t *F2 = static_cast<uint16_t *>(ps->plane_f2_d.p) + ps->foff[p];
+    double *D = static_cast<double *>(ps->plane_t_d.p) + ps->foff[p];
+    for (int q = 0; q < 4; ++q) {
+        const Product &pr = ch.g[q];
+        GemmBf16Args g{};
+        g.A = operand_ptr<uint16_t>(ps, p, c, pr.A, F1, F2, tab);
+        g.lda = pr.A.ld; g.sA = pr.A.sb;
+        g.B = operand_ptr<uint16_t>(ps, p, c, pr.B, F1, F2, tab);
+        g.ldb = pr.B.ld; g.sB = pr.B.sb;
+        const int b_trans = (pr.B.buf == kSx || pr.B.buf == kSy || pr.B.buf == kSz) ? 1 : 0;
+        g.C = const_cast<uint16_t *>(operand_ptr<uint16_t>(ps, p, c, pr.C, F1, F2, tab));
+        g.ldc = pr.C.ld; g.sC = pr.C.sb;
+        g.M = pr.M; g.N = pr.N; g.K = pr.K; g.batch = pr.batch;
+        g.ncolour = -1;
+        int epi = kEpiStore;
+        if (q == 1) {
+            epi = kEpiScale;
+            g.scale = tab32 + ps->lam_off[3 * p + c];
+            g.sc_b = pr.sc_b; g.sc_m = pr.sc_m; g.sc_n = pr.sc_n;
+        } else if (q == 3) {
+            epi = last_epi;
+            if (epi == kEpiUpdate) {
+                g.usrc = src; g.udst = dst; g.omega = omega;
+                g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
+                if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
+            } else {
+                g.D = D + (g.C - F1);
+                g.accumulate = accumulate;
+            }
+        }
+        hipError_t e = launch_gemm_bf16(g, b_trans, epi, s);
+        if (e != hipSuccess) return hip_fail(e, "plane transform (BF16)");
+    }
+    return BS_OK;
+}
+
 // One plane pass (normal c, colour or -1) on every patch.  R = residual of
 // src must be in plane_r.  Mixed: D_0 = M~^{-1} R, refine defect corrections,
 // then dst = src + omega D.
@@ -248,18 +313,27 @@ bs_status plane_pass(bs_patchset *ps, int c, int colour, int prec, int refine, c
         double *D = static_cast<double *>(ps->plane_t_d.p) + ps->foff[p];
         float *F1 = static_cast<float *>(ps->plane_f1_d.p) + ps->foff[p];
         const double *eps = &ps->eps[3 * static_cast<size_t>(p)];
-        const int lp = prec == BS_MIXED_BF16 ? 2 : 1;
-        hipError_t e = launch_plane_defect(R, nullptr, F1, nx, ny, nz, c, eps, s);
+        const bool b16 = prec == BS_MIXED_BF16;
+        uint16_t *E16 = static_cast<uint16_t *>(ps->plane_f1_d.p) + ps->foff[p];
+        auto defect = [&](const double *Dp) {
+            return b16 ? launch_plane_defect_bf16(R, Dp, E16, nx, ny, nz, c, eps, s)
+                       : launch_plane_defect(R, Dp, F1, nx, ny, nz, c, eps, s);
+        };
+        auto chain = [&](int epi, int acc) {
+            return b16 ? chain_bf16(ps, p, c, colour, epi, acc, src, dst, omega, s)
+                       : chain_lowp(ps, p, c, colour, 1, epi, acc, src, dst, omega, s);
+        };
+        hipError_t e = defect(nullptr);
         if (e != hipSuccess) return hip_fail(e, "plane defect");
         bs_status st;
         if (refine == 0) {
-            if ((st = chain_lowp(ps, p, c, colour, lp, kEpiUpdate, 0, src, dst, omega, s)) != BS_OK) return st;
+            if ((st = chain(kEpiUpdate, 0)) != BS_OK) return st;
             continue;
         }
-        if ((st = chain_lowp(ps, p, c, colour, lp, kEpiD64, 0, src, dst, omega, s)) != BS_OK) return st;
+        if ((st = chain(kEpiD64, 0)) != BS_OK) return st;
         for (int j = 0; j < refine; ++j) {
-            if ((e = launch_plane_defect(R, D, F1, nx, ny, nz, c, eps, s)) != hipSuccess) return hip_fail(e, "plane defect");
-            if ((st = chain_lowp(ps, p, c, colour, lp, kEpiD64, 1, src, dst, omega, s)) != BS_OK) return st;
+            if ((e = defect(D)) != hipSuccess) return hip_fail(e, "plane defect");
+            if ((st = chain(kEpiD64, 1)) != BS_OK) return st;
         }
         if ((e = launch_plane_update(D, src, dst, ps->uoff[p], nx, ny, nz, c, colour, omega, s)) != hipSuccess)
             return hip_fail(e, "plane update");
@@ -357,12 +431,12 @@ int bsi_gemm_f64(const double *A, int64_t lda, int64_t sA, const double *B, int6
     return launch_gemm_f64(g, epi, s) == hipSuccess ? BS_OK : BS_ERR_HIP;
 }
 
-// The same with float operands: prec 1 (FP32) or 2 (BF16), store epilogue,
-// dlayout as in GemmMixedArgs.
+// The same with FP32 operands (prec 1), store epilogue, dlayout as in
+// GemmMixedArgs.
 int bsi_gemm_mixed(const float *A, int64_t lda, int64_t sA, const float *B, int64_t ldb, int64_t sB, float *C,
                    int64_t ldc, int64_t sC, int M, int N, int K, int batch, int prec, int dlayout, hipStream_t s)
 {
-    if (prec != 1 && prec != 2) return BS_ERR_INVALID;
+    if (prec != 1) return BS_ERR_INVALID;
     GemmMixedArgs g{};
     g.A = A; g.lda = lda; g.sA = sA;
     g.B = B; g.ldb = ldb; g.sB = sB;
@@ -371,6 +445,23 @@ int bsi_gemm_mixed(const float *A, int64_t lda, int64_t sA, const float *B, int6
     g.ncolour = -1;
     g.dlayout = dlayout;
     return launch_gemm_mixed(g, prec, kEpiStore, s) == hipSuccess ? BS_OK : BS_ERR_HIP;
+}
+
+// One batched BF16 product (operands and result as BF16 bit patterns): store
+// (epi 0) or scale (epi 1) epilogue; b_trans as in launch_gemm_bf16.
+int bsi_gemm_bf16(const uint16_t *A, int64_t lda, int64_t sA, const uint16_t *B, int64_t ldb, int64_t sB,
+                  int b_trans, uint16_t *C, int64_t ldc, int64_t sC, int M, int N, int K, int batch, int epi,
+                  const float *scale, int64_t sc_b, int64_t sc_m, int64_t sc_n, hipStream_t s)
+{
+    if (epi != kEpiStore && epi != kEpiScale) return BS_ERR_INVALID;
+    GemmBf16Args g{};
+    g.A = A; g.lda = lda; g.sA = sA;
+    g.B = B; g.ldb = ldb; g.sB = sB;
+    g.C = C; g.ldc = ldc; g.sC = sC;
+    g.M = M; g.N = N; g.K = K; g.batch = batch;
+    g.scale = scale; g.sc_b = sc_b; g.sc_m = sc_m; g.sc_n = sc_n;
+    g.ncolour = -1;
+    return launch_gemm_bf16(g, b_trans, epi, s) == hipSuccess ? BS_OK : BS_ERR_HIP;
 }
 
 // Register-to-row mapping used by the mixed products of this patch set.

@@ -58,8 +58,36 @@ struct GemmMixedArgs {
 };
 
 hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStream_t s);
+
+// The same product with BF16 operands in memory (unsigned short bit patterns)
+// and FP32 accumulation.  A is [m][k] (k contiguous, leading dimension lda);
+// B is [n][k] with leading dimension ldb when b_trans != 0, else [k][n].
+// Store / scale epilogues write BF16 C; kEpiD64 and kEpiUpdate as above.
+struct GemmBf16Args {
+    const unsigned short *A;
+    int64_t lda, sA;
+    const unsigned short *B;
+    int64_t ldb, sB;
+    unsigned short *C;
+    int64_t ldc, sC;
+    int M, N, K, batch;
+    const float *scale;
+    int64_t sc_b, sc_m, sc_n;
+    double *D;
+    int accumulate;
+    const double *usrc;
+    double *udst;
+    int64_t u0, u_b, u_m, u_n;
+    double omega;
+    int ncolour, colour_shift;
+};
+
+hipError_t launch_gemm_bf16(const GemmBf16Args &g, int b_trans, int epi, hipStream_t s);
 hipError_t launch_plane_defect(const double *R, const double *D, float *E, int nx, int ny, int nz, int normal,
                                const double eps[3], hipStream_t s);
+// The same defect rounded to BF16 (bit patterns).
+hipError_t launch_plane_defect_bf16(const double *R, const double *D, unsigned short *E, int nx, int ny, int nz,
+                                    int normal, const double eps[3], hipStream_t s);
 hipError_t launch_plane_update(const double *D, const double *src, double *dst, int64_t uoff, int nx, int ny, int nz,
                                int normal, int colour, double omega, hipStream_t s);
 

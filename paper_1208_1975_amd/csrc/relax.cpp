@@ -35,14 +35,20 @@ int tiles_of(const bs_patchset *ps, int p, int kind, int axis, int tx, int colou
 {
     const int nx = ps->dims[3 * p], ny = ps->dims[3 * p + 1], nz = ps->dims[3 * p + 2];
     if (kind == 1) {
-        const int64_t rows = static_cast<int64_t>(colour_mode ? (ny + 1) / 2 : ny) * nz;
+        const int64_t rows = static_cast<int64_t>(colour_mode == 1 ? (ny + 1) / 2 : ny) * nz;
         return static_cast<int>((rows + 63) / 64);
     }
     const int no = axis == 2 ? ny : nz;
-    const int span = colour_mode ? (nx + 1) / 2 : nx;
+    const int span = colour_mode == 1 ? (nx + 1) / 2 : nx;
     const int nti = (span + tx - 1) / tx;
     const int nto = (no + 64 / tx - 1) / (64 / tx);
     return nti * nto;
+}
+
+// Tile rows (along the other free axis) of one patch's strided tiles.
+int tiles_per_row(const bs_patchset *ps, int p, int tx)
+{
+    return (ps->dims[3 * p] + tx - 1) / tx;
 }
 
 // XCD-aware order: the hardware hands workgroup b to XCD b mod 8, so item j of
@@ -105,8 +111,15 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
         for (int p : order) {
             const int nt = tiles_of(ps, p, kind, axis, tx, colour_mode);
             wl->pfirst[c][p] = static_cast<int>(run.size());
-            wl->pcount[c][p] = nt;
-            for (int t = 0; t < nt; ++t) run.push_back(WorkItem{p, t, c, 0});
+            if (colour_mode == 2) {
+                // in-tile two-colour: all tiles, tile rows of parity c in run c
+                const int nti = tiles_per_row(ps, p, tx);
+                for (int t = 0; t < nt; ++t)
+                    if ((t / nti) % 2 == c) run.push_back(WorkItem{p, t, c, 0});
+            } else {
+                for (int t = 0; t < nt; ++t) run.push_back(WorkItem{p, t, c, 0});
+            }
+            wl->pcount[c][p] = static_cast<int>(run.size()) - wl->pfirst[c][p];
         }
         if (ps->npatch == 1) xcd_order(run);
         wl->count[c] = static_cast<int>(run.size());
@@ -137,7 +150,7 @@ LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode)
     c.Lmax = lmax_for(lr_max);
     c.nwaves = kPOpts[c.popt];
     if (axis != 0) {
-        const int span = colour_mode ? (ps->max_n[0] + 1) / 2 : ps->max_n[0];
+        const int span = colour_mode == 1 ? (ps->max_n[0] + 1) / 2 : ps->max_n[0];
         c.tx = std::min(64, pow2_ceil(std::max(1, span)));
     } else {
         c.tx = 64;
@@ -154,9 +167,11 @@ size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c)
         tsz = std::max(tsz, line_table_size(r.Lr, r.P));
         sd = std::max(sd, ps->dims[3 * p] | 1);
     }
-    // y/z lines: two buffers of chunk ends (the table is read through the
-    // scalar cache); x lines: table, chunk ends, the tile's rows, row offsets
-    if (axis != 0) return 2 * 2 * 64 * static_cast<size_t>(c.nwaves) * sizeof(double);
+    // y/z lines: the chunk values of u and two buffers of chunk ends (the
+    // table is read through the scalar cache); x lines: table, chunk ends, the
+    // tile's rows, row offsets
+    if (axis != 0)
+        return static_cast<size_t>((c.Lmax <= 16 ? c.Lmax : 0) + 4) * 64 * static_cast<size_t>(c.nwaves) * sizeof(double);
     size_t n = static_cast<size_t>((tsz + 1) & ~1) + 2 * 64 * static_cast<size_t>(c.nwaves);
     n += 64 * static_cast<size_t>(sd) + 128;
     return n * sizeof(double);
@@ -186,7 +201,7 @@ bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c)
 // pass to one patch's items (one launch per patch and run).
 bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
                     double *dst, const double *f, double omega, hipStream_t stream, int patch, int rhs_mode,
-                    int out_mode)
+                    int out_mode, int f32)
 {
     const int kind = axis == 0 ? 1 : 0;
     WorkList *wl = nullptr;
@@ -198,6 +213,8 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
     a.f = f;
     a.pd = static_cast<const PatchDesc *>(ps->desc_d.p);
     a.tab = static_cast<const double *>(ps->tab_d.p);
+    a.tab32 = static_cast<const float *>(ps->tab32_d.p);
+    a.f32 = f32;
     a.axis = axis;
     a.popt = c.popt;
     a.tx = c.tx;
@@ -216,6 +233,7 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
                                  : launch_line_strided(a, grid, c.Lmax, c.nwaves, lds, stream);
         return e == hipSuccess ? BS_OK : hip_fail(e, "line sweep kernel");
     };
+    if (colour_mode == 2) run = 2;   // in-tile two-colour: both tile-row groups in one pass
     if (patch >= 0) {
         const int runs = colour_mode ? (run == 2 ? 2 : 1) : 1;
         for (int k = 0; k < runs; ++k) {
@@ -239,18 +257,29 @@ const LineCfg &line_cfg(bs_patchset *ps, int axis, int colour_mode)
     return itr->second;
 }
 
+// Kernel mode of a scheme: Jacobi 0 (all lines, ping-pong); two-colour GS 1
+// (one colour per launch); chaotic GS 2 on y/z lines (contiguous tiles, the
+// two colours in turn inside each tile, even tile rows dispatched first) and 1
+// on x lines (both colours in one launch, colour 0 first).
+int scheme_mode(int axis, bs_scheme scheme)
+{
+    if (scheme == BS_JACOBI) return 0;
+    if (scheme == BS_CHAOTIC_GS && axis != 0) return 2;
+    return 1;
+}
+
 // The launch sequence of nsweeps line sweeps.  per_patch: one launch per
 // patch and colour run instead of one per run (the comparison baseline).
 bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const LineCfg &c, double omega,
                               int nsweeps, double *u, const double *f, double *work, hipStream_t stream,
-                              bool per_patch)
+                              bool per_patch, int f32)
 {
     const PatchDesc *pdd = static_cast<const PatchDesc *>(ps->desc_d.p);
     bs_status st;
     auto pass = [&](int cm, int run, const double *src, double *dst) -> bs_status {
-        if (!per_patch) return line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, -1, 0, 0);
+        if (!per_patch) return line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, -1, 0, 0, f32);
         for (int p = 0; p < ps->npatch; ++p) {
-            bs_status s2 = line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, p, 0, 0);
+            bs_status s2 = line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, p, 0, 0, f32);
             if (s2 != BS_OK) return s2;
         }
         return BS_OK;
@@ -269,12 +298,13 @@ bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const
         }
         return BS_OK;
     }
+    const int cm = scheme_mode(axis, scheme);
     for (int s = 0; s < nsweeps; ++s) {
         if (scheme == BS_COLORED_GS) {
-            if ((st = pass(1, 0, u, u)) != BS_OK) return st;
-            if ((st = pass(1, 1, u, u)) != BS_OK) return st;
+            if ((st = pass(cm, 0, u, u)) != BS_OK) return st;
+            if ((st = pass(cm, 1, u, u)) != BS_OK) return st;
         } else {
-            if ((st = pass(1, 2, u, u)) != BS_OK) return st;
+            if ((st = pass(cm, 2, u, u)) != BS_OK) return st;
         }
     }
     return BS_OK;
@@ -310,7 +340,6 @@ bs_status check_line_args(int32_t axis, bs_scheme scheme, double omega, int32_t 
     if (prec != BS_FP64 && prec != BS_MIXED_FP32 && prec != BS_MIXED_BF16)
         return fail(BS_ERR_INVALID, "%s: unknown precision", fn);
     if (prec == BS_MIXED_BF16) return fail(BS_ERR_UNSUPPORTED, "%s: BF16 is offered for planes only", fn);
-    if (prec == BS_MIXED_FP32) return fail(BS_ERR_UNSUPPORTED, "%s: FP32 line solves are not provided", fn);
     return BS_OK;
 }
 
@@ -339,21 +368,22 @@ bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double 
     if (scheme == BS_JACOBI && !work) return fail(BS_ERR_INVALID, "bs_line_relax: Jacobi needs a work buffer");
     if ((st = check_line_ps(ps, axis, "bs_line_relax")) != BS_OK) return st;
     if (nsweeps == 0) return BS_OK;
-    const int cm = scheme == BS_JACOBI ? 0 : 1;
+    const int cm = scheme_mode(axis, scheme);
     const LineCfg c = line_cfg(ps, axis, cm);
     if ((st = check_line_cfg(ps, axis, c)) != BS_OK) return st;
     if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;
     hipError_t e = prepare_line_kernels();
     if (e != hipSuccess) return hip_fail(e, "line kernel attributes");
+    const int f32 = prec == BS_MIXED_FP32 ? 1 : 0;
     if (!ps->use_graphs || nsweeps < 2)
-        return enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, stream, false);
+        return enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, stream, false, f32);
 
     // replay a captured graph of the whole sequence (captured on first use)
     int64_t obits;
     std::memcpy(&obits, &omega, sizeof obits);
     const std::vector<int64_t> key{0, axis, scheme, obits, nsweeps, reinterpret_cast<int64_t>(u),
                                    reinterpret_cast<int64_t>(f), reinterpret_cast<int64_t>(work), c.popt, c.tx,
-                                   c.grid, c.Lmax};
+                                   c.grid, c.Lmax, f32};
     auto itr = ps->graphs.find(key);
     if (itr == ps->graphs.end()) {
         if (ps->graphs.size() >= 64) clear_graphs(ps);
@@ -363,7 +393,7 @@ bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double 
         hipGraph_t graph = nullptr;
         if ((e = hipStreamBeginCapture(ps->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "hipStreamBeginCapture");
-        st = enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, ps->capture_stream, false);
+        st = enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, ps->capture_stream, false, f32);
         e = hipStreamEndCapture(ps->capture_stream, &graph);
         if (st != BS_OK) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -389,7 +419,7 @@ bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, cons
     if ((st = check_line_ps(ps, axis, "bs_autotune_line")) != BS_OK) return st;
     hipError_t e = prepare_line_kernels();
     if (e != hipSuccess) return hip_fail(e, "line kernel attributes");
-    const int cm = scheme == BS_JACOBI ? 0 : 1;
+    const int cm = scheme_mode(axis, scheme);
     DevBuf su, sw;
     const size_t bytes = static_cast<size_t>(ps->u_numel) * sizeof(double);
     if ((st = dev_alloc(su, bytes, "autotune scratch")) != BS_OK) return st;
@@ -468,7 +498,7 @@ bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, 
 {
     if (!ps || !cfg_host) return fail(BS_ERR_INVALID, "bs_line_config: null argument");
     if (axis < 0 || axis > 2) return fail(BS_ERR_INVALID, "bs_line_config: axis must be 0, 1 or 2");
-    const int cm = scheme == BS_JACOBI ? 0 : 1;
+    const int cm = scheme_mode(axis, scheme);
     auto itr = ps->line_cfg.find(std::make_pair(static_cast<int>(axis), cm));
     const bool set = itr != ps->line_cfg.end();
     const LineCfg c = set ? itr->second : default_line_cfg(ps, axis, cm);
@@ -482,13 +512,13 @@ bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, 
 
 // Host-side hooks (not part of the public header).
 
-// Set the launch configuration of line sweeps along `axis` for the Jacobi
-// (colour_mode 0) or Gauss-Seidel (colour_mode 1) kernels: popt indexes the
-// chunk counts {1,2,4,8,16}; tx is the strided kernel's lanes per row; grid is
-// the persistent grid size (0: one workgroup per work item).
-int bsi_set_line_cfg(bs_patchset *ps, int axis, int colour_mode, int popt, int tx, int grid)
+// Set the launch configuration of line sweeps along `axis` for one scheme:
+// popt indexes the chunk counts {1,2,4,8,16}; tx is the strided kernel's lanes
+// per row; grid is the persistent grid size (0: one workgroup per work item).
+int bsi_set_line_cfg(bs_patchset *ps, int axis, int scheme, int popt, int tx, int grid)
 {
-    if (!ps || axis < 0 || axis > 2 || colour_mode < 0 || colour_mode > 1) return BS_ERR_INVALID;
+    if (!ps || axis < 0 || axis > 2 || scheme < 0 || scheme > 2) return BS_ERR_INVALID;
+    const int colour_mode = scheme_mode(axis, static_cast<bs_scheme>(scheme));
     if (popt < 0 || popt >= kNumPOpt) return BS_ERR_INVALID;
     LineCfg c;
     c.popt = popt;
@@ -525,7 +555,7 @@ int bsi_line_relax_per_patch(bs_patchset *ps, int32_t axis, bs_scheme scheme, do
     if (st != BS_OK) return st;
     if (!ps || !u || !f || (scheme == BS_JACOBI && !work)) return BS_ERR_INVALID;
     if ((st = check_line_ps(ps, axis, "bsi_line_relax_per_patch")) != BS_OK) return st;
-    const int cm = scheme == BS_JACOBI ? 0 : 1;
+    const int cm = scheme_mode(axis, scheme);
     const LineCfg c = line_cfg(ps, axis, cm);
     if ((st = check_line_cfg(ps, axis, c)) != BS_OK) return st;
     if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;

@@ -39,8 +39,8 @@ class Single:
     def set_u(self, arr):
         self.ps.pack_u([arr], out=self.u)
 
-    def line(self, axis, scheme, omega, nsweeps):
-        self.ps.line_relax(axis, scheme, omega, nsweeps, self.u, self.f, self.work)
+    def line(self, axis, scheme, omega, nsweeps, prec="fp64"):
+        self.ps.line_relax(axis, scheme, omega, nsweeps, self.u, self.f, self.work, prec=prec)
 
     def plane(self, normal, scheme, omega, nsweeps, prec="fp64", refine=0):
         self.ps.plane_relax(normal, scheme, omega, nsweeps, self.u, self.f, self.work, prec=prec, refine=refine)
