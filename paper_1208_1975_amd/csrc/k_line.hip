@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a, const double 
     extern __shared__ double smem[];
     const int nw = blockDim.x >> 6;
     double *ucs = smem;
-    double *endb = smem + L * 64 * nw;
+    double *endb = smem + (L <= 16 ? L * 64 * nw : 0);   // u is held in LDS only for chunks <= 16
     int buf = 0;
     for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
         line_strided_item<L, CM, F32>(a, tabs, tabs32, a.items[i], endb + buf * (2 * 64 * nw),
@@ -176,6 +176,7 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
     const int nthr = blockDim.x;
     // chunks of up to 16 cells keep u in LDS for the update (16 waves x 64
     // lanes x 16 doubles = 128 KiB); longer chunks read it again from memory
+    // (the kernel places the LDS buffers by the same rule)
     constexpr bool kUcLds = L <= 16;
     const PatchDesc *pd = a.pd + it.patch;
     const int axis = a.axis;          // 1 or 2
@@ -433,7 +434,7 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const float *__re
     if (threadIdx.x < 64) {
         const int rho = it.tile * 64 + (int)threadIdx.x;
         int j, k;
-        if (a.colour_mode) {
+        if (a.colour_mode == 1) {
             const int M = (ny + 1) >> 1;
             k = rho / M;
             j = 2 * (rho % M) + ((k + it.colour) & 1);
@@ -516,6 +517,52 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const float *__re
             if (t < Lp) rb[lane * sd + t0 + t] = static_cast<double>(fma(anext, ew[t], fma(bprev, ev[t], r[t])));
     }
     __syncthreads();
+    if (a.colour_mode == 2) {
+        // In-tile two-colour (chaotic GS): the solve above is exact for the
+        // colour-0 rows ((j + k) even); the colour-1 rows solve again for the
+        // residual change caused by their updated colour-0 neighbours in this
+        // tile (rows rho +- 1 along y, rho +- ny along z) and add it (the line
+        // solve is linear).  Neighbours in other tiles are read as they were.
+        const int rho = it.tile * 64 + lane;
+        const int j = rho % ny, k = rho / ny;
+        const bool black = ((j + k) & 1) != 0;
+        const double om = a.omega;
+        auto nbr = [&](int row, bool ok) -> int { return (ok && row >= 0 && row < 64 && rowu[row] >= 0) ? row : -1; };
+        const int rjm = nbr(lane - 1, j > 0), rjp = nbr(lane + 1, j + 1 < ny);
+        const int rkm = nbr(lane - ny, k > 0), rkp = nbr(lane + ny, k + 1 < nz);
+        T r2[L];
+        T z0 = 0, zl = 0;
+        if (valid) {
+#pragma unroll
+            for (int t = 0; t < L; ++t) {
+                double c = 0.0;
+                if (black && t < Lp) {
+                    const int x = t0 + t;
+                    const double dy = (rjm >= 0 ? rb[rjm * sd + x] : 0.0) + (rjp >= 0 ? rb[rjp * sd + x] : 0.0);
+                    const double dz = (rkm >= 0 ? rb[rkm * sd + x] : 0.0) + (rkp >= 0 ? rb[rkp * sd + x] : 0.0);
+                    c = om * fma(ey, dy, ez * dz);
+                }
+                r2[t] = static_cast<T>(c);
+            }
+            if constexpr (F32)
+                chunk_solve_u<L, T>(r2, Lp, tabT, tabT + Lr, static_cast<T>(ex), z0, zl);
+            else
+                chunk_solve<L>(r2, Lp, Lr, tab, tab + Lr, ex, z0, zl);
+        }
+        ends[(p * 64 + lane) * 2 + 0] = z0;
+        ends[(p * 64 + lane) * 2 + 1] = zl;
+        __syncthreads();   // every colour-0 value above was read before any colour-1 row changes
+        if (valid && black) {
+            T bprev, anext;
+            interface_terms<T>(tabT, ends, Lr, P, p, lane, bprev, anext);
+            const T *ev = tabT + (p == P - 1 ? 4 * Lr : 2 * Lr);
+            const T *ew = ev + Lr;
+#pragma unroll
+            for (int t = 0; t < L; ++t)
+                if (t < Lp) rb[lane * sd + t0 + t] += static_cast<double>(fma(anext, ew[t], fma(bprev, ev[t], r2[t])));
+        }
+        __syncthreads();
+    }
 
     // phase 3: coalesced update (all reads of the tile happened before the barriers)
     const double om = a.omega;

@@ -44,8 +44,8 @@ __device__ __forceinline__ double2 load2(const double *row, int c0, int lim, boo
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
 {
-    __shared__ double As[2][BK][BM + 2];
-    __shared__ double Bs[2][BK][BN + 2];
+    __shared__ __attribute__((aligned(16))) double As[2][BK][BM + 2];
+    __shared__ __attribute__((aligned(16))) double Bs[2][BK][BN + 2];
     const int b = blockIdx.z;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const double *A = g.A + (int64_t)b * g.sA;

@@ -6,6 +6,8 @@
 //   D_0 = M~^{-1} R,  D_{j+1} = D_j + M~^{-1}(R - M_P D_j)   (j < refine)
 // with M~^{-1} the low-precision transform chain, M_P D_j applied in FP64,
 // and finally u += omega D in FP64.  (The BF16 products are in k_plane_bf16.)
+#include <cstdint>
+
 #include "bs_internal.h"
 #include "plane.h"
 
@@ -19,14 +21,28 @@ constexpr int BM = 64, BN = 64, BK = 32;
 
 }  // namespace
 
+// Four consecutive floats of a row starting at column c0 (zero beyond `lim`);
+// one 16-byte load when aligned and inside.
+__device__ __forceinline__ float4 load4f(const float *row, int c0, int lim, bool vec)
+{
+    if (vec && c0 + 4 <= lim) return *reinterpret_cast<const float4 *>(row + c0);
+    float4 r;
+    r.x = c0 < lim ? row[c0] : 0.f;
+    r.y = c0 + 1 < lim ? row[c0 + 1] : 0.f;
+    r.z = c0 + 2 < lim ? row[c0 + 2] : 0.f;
+    r.w = c0 + 3 < lim ? row[c0 + 3] : 0.f;
+    return r;
+}
+
 // C_b = A_b B_b with FP32 operands (v_mfma_f32_16x16x4_f32), FP32
-// accumulation.
+// accumulation.  A 64 x 64 block of C per workgroup (four wavefronts, 32 x 32
+// each); K advances BK at a time through two LDS buffers, the next tile
+// fetched into registers while the current one feeds the matrix cores.
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
 {
-    // A tile row-major [m][k]; B tile [k][n]
-    __shared__ float As[BM][BK + 1];
-    __shared__ float Bs[BK][BN + 1];
+    __shared__ __attribute__((aligned(16))) float As[2][BK][BM + 4];
+    __shared__ __attribute__((aligned(16))) float Bs[2][BK][BN + 4];
     const int b = blockIdx.z;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const float *A = g.A + (int64_t)b * g.sA;
@@ -35,6 +51,8 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int l16 = lane & 15, lk = lane >> 4;
+    const bool avec = ((g.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    const bool bvec = ((g.ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
 
     flt4 acc[2][2];
 #pragma unroll
@@ -42,35 +60,56 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
+    // A tile BM x BK: quad c -> row c / 8, k offset (c % 8) * 4; B tile BK x BN:
+    // quad c -> k row c / 16, n offset (c % 16) * 4 (two quads a thread)
+    float4 ra[2], rb[2];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < (BM * BK) / 256; ++q) {
-            const int e = tid + 256 * q;
-            const int r = e / BK, c = e % BK;
-            const int gr = m0 + r, gc = k0 + c;
-            As[r][c] = (gr < g.M && gc < g.K) ? A[(int64_t)gr * g.lda + gc] : 0.f;
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q;
+            const int r = c >> 3, kc = (c & 7) * 4;
+            const int gr = m0 + r;
+            ra[q] = gr < g.M ? load4f(A + (int64_t)gr * g.lda, k0 + kc, g.K, avec) : float4{0.f, 0.f, 0.f, 0.f};
+            const int kr = c >> 4, nc = (c & 15) * 4;
+            const int gk = k0 + kr;
+            rb[q] = gk < g.K ? load4f(B + (int64_t)gk * g.ldb, n0 + nc, g.N, bvec) : float4{0.f, 0.f, 0.f, 0.f};
         }
+    };
+    auto stash = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < (BK * BN) / 256; ++q) {
-            const int e = tid + 256 * q;
-            const int r = e / BN, c = e % BN;
-            const int gr = k0 + r, gc = n0 + c;
-            Bs[r][c] = (gr < g.K && gc < g.N) ? B[(int64_t)gr * g.ldb + gc] : 0.f;
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q;
+            const int r = c >> 3, kc = (c & 7) * 4;
+            As[buf][kc][r] = ra[q].x;
+            As[buf][kc + 1][r] = ra[q].y;
+            As[buf][kc + 2][r] = ra[q].z;
+            As[buf][kc + 3][r] = ra[q].w;
+            const int kr = c >> 4, nc = (c & 15) * 4;
+            *reinterpret_cast<float4 *>(&Bs[buf][kr][nc]) = rb[q];
         }
-        __syncthreads();
+    };
+
+    const int nk = (g.K + BK - 1) / BK;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) fetch((kt + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             float af[2], bfr[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) af[i] = As[wm * 32 + i * 16 + l16][kk + lk];
+            for (int i = 0; i < 2; ++i) af[i] = As[cur][kk + lk][wm * 32 + i * 16 + l16];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bfr[j] = Bs[kk + lk][wn * 32 + j * 16 + l16];
+            for (int j = 0; j < 2; ++j) bfr[j] = Bs[cur][kk + lk][wn * 32 + j * 16 + l16];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
+        if (kt + 1 < nk) stash(cur ^ 1);
         __syncthreads();
     }
 

@@ -113,7 +113,8 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
             wl->pfirst[c][p] = static_cast<int>(run.size());
             if (colour_mode == 2) {
                 // in-tile two-colour: all tiles, tile rows of parity c in run c
-                const int nti = tiles_per_row(ps, p, tx);
+                // (x lines: a tile is a block of rows, alternate tiles)
+                const int nti = kind == 1 ? 1 : tiles_per_row(ps, p, tx);
                 for (int t = 0; t < nt; ++t)
                     if ((t / nti) % 2 == c) run.push_back(WorkItem{p, t, c, 0});
             } else {
@@ -258,13 +259,14 @@ const LineCfg &line_cfg(bs_patchset *ps, int axis, int colour_mode)
 }
 
 // Kernel mode of a scheme: Jacobi 0 (all lines, ping-pong); two-colour GS 1
-// (one colour per launch); chaotic GS 2 on y/z lines (contiguous tiles, the
-// two colours in turn inside each tile, even tile rows dispatched first) and 1
-// on x lines (both colours in one launch, colour 0 first).
+// (one colour per launch); chaotic GS 2 (contiguous tiles, the two colours in
+// turn inside each tile, even tile rows -- alternate row blocks for x lines --
+// dispatched first).
 int scheme_mode(int axis, bs_scheme scheme)
 {
+    (void)axis;
     if (scheme == BS_JACOBI) return 0;
-    if (scheme == BS_CHAOTIC_GS && axis != 0) return 2;
+    if (scheme == BS_CHAOTIC_GS) return 2;
     return 1;
 }
 

@@ -72,12 +72,13 @@ def test_line_parity_small(dims, axis, scheme):
 
 
 @pytest.mark.parametrize("dims,axis", [((8, 8, 20), 2), ((16, 4, 30), 2), ((64, 1, 40), 2), ((7, 9, 5), 1),
-                                       ((3, 11, 2), 1), ((1, 1, 17), 2)])
+                                       ((3, 11, 2), 1), ((1, 1, 17), 2), ((20, 6, 8), 0), ((9, 4, 16), 0),
+                                       ((33, 1, 1), 0), ((256, 3, 5), 0)])
 def test_chaotic_single_tile_is_two_colour_gs(dims, axis):
-    """y/z-line chaotic GS updates each tile's colour-0 lines, then its colour-1
-    lines from the new in-tile values.  When one tile holds every line of the
-    patch, that is exactly the two-colour block GS sweep, so it must match the
-    oracle's to 1e-12."""
+    """Chaotic GS updates each tile's colour-0 lines, then its colour-1 lines
+    from the new in-tile values.  When one tile holds every line of the patch
+    (64 x-lines, or one tile of y/z lines), that is exactly the two-colour
+    block GS sweep, so it must match the oracle's to 1e-12."""
     p = small_patch(*dims, seed=61 + axis, eps=(1.0, 3.0, 7.0))
     for nsweeps in (1, 2, 3):
         log("chaotic single tile %s axis=%d nsweeps=%d" % (dims, axis, nsweeps))
