@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the other configurations")
+    ap.add_argument("--profile-planes", action="store_true",
+                    help="fixed plane-sweep sequence for rocprofv3 (512^3: FP64, FP32, BF16 refine 1; 2 sweeps each)")
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3 counter runs: a 1 GiB device copy (reference for FETCH_SIZE / "
                          "WRITE_SIZE scaling), then 10 z-line Jacobi and 10 chaotic GS sweep launches; no JSON")
@@ -69,6 +71,28 @@ def profile_run():
     ps.residual(u, f, None, n2)
     torch.cuda.synchronize()
     print("profile run done", flush=True)
+
+
+def profile_planes_run():
+    """Fixed plane-sweep sequence for kernel traces: 512^3 xy-plane Jacobi,
+    two sweeps in each precision."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import c3_patch
+
+    torch.cuda.set_device(0)
+    p = c3_patch()
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    f = ps.pack_f([p.f])
+    u0 = ps.pack_u([p.u0])
+    w = ps.empty_u()
+    for prec, refine in (("fp64", 0), ("fp32", 0), ("bf16", 1)):
+        u = u0.clone()
+        ps.plane_relax(2, "jacobi", 1.0, 2, u, f, w, prec=prec, refine=refine)
+        torch.cuda.synchronize()
+        print("profile planes %s refine %d done" % (prec, refine), flush=True)
+        del u
 
 
 def measured_traffic():
@@ -266,6 +290,9 @@ def cpu_baseline(patch, target_s):
 
 def main():
     args = parse()
+    if args.profile_planes:
+        profile_planes_run()
+        return
     if args.profile:
         profile_run()
         return
