@@ -12,8 +12,10 @@
 // operands are k-contiguous rows (A as [m][k], B as [n][k]), so each MFMA
 // operand of a lane -- eight consecutive k of one row or column -- is one
 // 128-bit LDS read.  B arrives either already k-contiguous (the sine bases
-// are symmetric, S = S^T) or as [k][n] (a field), which is transposed on its
-// way into LDS.
+// are symmetric, S = S^T, and fields that the previous product stored
+// transposed) or as [k][n] (a field), which is transposed on its way into
+// LDS.  The store epilogues can write C^T, so that the next product finds its
+// field operand k-contiguous.
 #include <cstdint>
 
 #include "bs_internal.h"
@@ -139,6 +141,40 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
 
     // register r of a lane holds row 4*(lane/16) + r, column lane%16 of its
     // 16 x 16 block (checked by the layout test)
+    if ((EPI == kEpiStore || EPI == kEpiScale) && g.c_trans) {
+        // C^T: a lane's four rows are consecutive in memory (one 8-byte store
+        // when aligned and inside)
+        const bool cvec = ((g.ldc & 3) == 0) && ((g.sC & 3) == 0) && ((reinterpret_cast<uintptr_t>(g.C) & 7) == 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row0 = m0 + wm * 64 + i * 16 + 4 * lk;
+                const int col = n0 + wn * 64 + j * 16 + l16;
+                if (col >= g.N) continue;
+                u16 h[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[i][j][r];
+                    if (EPI == kEpiScale)
+                        v *= g.scale[(int64_t)b * g.sc_b + (int64_t)(row0 + r < g.M ? row0 + r : 0) * g.sc_m +
+                                     (int64_t)col * g.sc_n];
+                    h[r] = to_bf16(v);
+                }
+                u16 *dst = g.C + (int64_t)b * g.sC + (int64_t)col * g.ldc + row0;
+                if (cvec && row0 + 4 <= g.M) {
+                    uint2 w2;
+                    w2.x = h[0] | ((uint32_t)h[1] << 16);
+                    w2.y = h[2] | ((uint32_t)h[3] << 16);
+                    *reinterpret_cast<uint2 *>(dst) = w2;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (row0 + r < g.M) dst[r] = h[r];
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll

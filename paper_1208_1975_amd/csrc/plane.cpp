@@ -262,6 +262,12 @@ bs_status chain_bf16(bs_patchset *ps, int p, int c, int colour, int last_epi, in
     uint16_t *F1 = static_cast<uint16_t *>(ps->plane_f1_d.p) + ps->foff[p];
     uint16_t *F2 = static_cast<uint16_t *>(ps->plane_f2_d.p) + ps->foff[p];
     double *D = static_cast<double *>(ps->plane_t_d.p) + ps->foff[p];
+    // Planes with x in-plane (normals y and z): the first two products store
+    // their result transposed in a compact per-plane layout (plane b at
+    // b*M*N, element (m, n) at n*M + m), so the second and third products
+    // read that field k-contiguous (no transposition through LDS).
+    const bool tr = c != 0;
+    const int64_t MN = static_cast<int64_t>(ch.g[0].M) * ch.g[0].N;
     for (int q = 0; q < 4; ++q) {
         const Product &pr = ch.g[q];
         GemmBf16Args g{};
@@ -269,9 +275,19 @@ bs_status chain_bf16(bs_patchset *ps, int p, int c, int colour, int last_epi, in
         g.lda = pr.A.ld; g.sA = pr.A.sb;
         g.B = operand_ptr<uint16_t>(ps, p, c, pr.B, F1, F2, tab);
         g.ldb = pr.B.ld; g.sB = pr.B.sb;
-        const int b_trans = (pr.B.buf == kSx || pr.B.buf == kSy || pr.B.buf == kSz) ? 1 : 0;
+        int b_trans = (pr.B.buf == kSx || pr.B.buf == kSy || pr.B.buf == kSz) ? 1 : 0;
         g.C = const_cast<uint16_t *>(operand_ptr<uint16_t>(ps, p, c, pr.C, F1, F2, tab));
         g.ldc = pr.C.ld; g.sC = pr.C.sb;
+        if (tr && (q == 1 || q == 2)) {   // B: the previous product's compact C^T, [n][k]
+            g.B = pr.B.buf == kIn ? F1 : F2;
+            g.ldb = pr.M; g.sB = MN;
+            b_trans = 1;
+        }
+        if (tr && (q == 0 || q == 1)) {   // C^T into the compact layout
+            g.C = pr.C.buf == kIn ? F1 : F2;
+            g.ldc = pr.M; g.sC = MN;
+            g.c_trans = 1;
+        }
         g.M = pr.M; g.N = pr.N; g.K = pr.K; g.batch = pr.batch;
         g.ncolour = -1;
         int epi = kEpiStore;

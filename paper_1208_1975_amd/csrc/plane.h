@@ -80,6 +80,7 @@ struct GemmBf16Args {
     int64_t u0, u_b, u_m, u_n;
     double omega;
     int ncolour, colour_shift;
+    int c_trans;   // store / scale epilogues: element (m, n) of C at b*sC + n*ldc + m (C^T)
 };
 
 hipError_t launch_gemm_bf16(const GemmBf16Args &g, int b_trans, int epi, hipStream_t s);

@@ -98,6 +98,28 @@ def test_persistent_grid_matches_one_workgroup_per_tile():
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("axis", [1, 2])
+def test_persistent_grid_strided_lines(axis):
+    """y/z lines: a persistent grid (each workgroup drains several tiles and
+    fetches the next tile's first loads early) gives the bitwise result of one
+    workgroup per tile for the deterministic schemes, which equals the oracle."""
+    s, ps = small_set(n=20, seed=9)
+    f = ps.pack_f(s.f)
+    for scheme, om, osch in (("jacobi", 0.8, oracle.JACOBI), ("colored", 1.0, oracle.COLORED_GS)):
+        outs = []
+        for grid in (0, 5, 300):
+            ps.set_line_config(axis, scheme, 16, tile=64, grid=grid)
+            u = ps.pack_u(s.u0)
+            w = ps.empty_u()
+            ps.line_relax(axis, scheme, om, 2, u, f, w)
+            torch.cuda.synchronize()
+            outs.append(u)
+        assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2]), (axis, scheme)
+        for p in range(ps.npatch):
+            ref = oracle.line_sweeps(s.u0[p], s.f[p], tuple(s.eps[p]), s.h[p], axis, osch, om, 2)
+            assert relerr(ps.view_u(outs[2], p).cpu().numpy(), ref) < TOL, (axis, scheme, p)
+
+
 @pytest.mark.timeout(900)
 def test_c4_full_set_chaotic_x_lines():
     """3000 uneven patches, x-line chaotic GS, 20 sweeps in one graph launch
