@@ -78,6 +78,8 @@ struct ResidArgs {
     const PatchDesc *pd;
     const int32_t *block_patch;   // block -> patch
     const int32_t *block_first;   // block -> first cell (within its patch)
+    float *e32;                   // optional FP32 copy of r (f layout), may be null
+    unsigned short *e16;          // optional BF16 copy of r (bit patterns), may be null
 };
 
 // Host launchers (defined in the .hip files).

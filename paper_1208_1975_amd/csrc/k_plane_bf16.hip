@@ -195,7 +195,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
                 } else {
                     if (g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour) continue;
                     const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
-                    g.udst[u] = fma(g.omega, (double)v, g.usrc[u]);
+                    const double du = EPI == kEpiUpdateAcc ? g.D[ci] + (double)v : (double)v;
+                    g.udst[u] = fma(g.omega, du, g.usrc[u]);
                 }
             }
 }
@@ -209,6 +210,7 @@ static hipError_t launch_bf16_t(const GemmBf16Args &g, int epi, hipStream_t s)
     case kEpiScale: hipLaunchKernelGGL((k_gemm_bf16<kEpiScale, BT>), grid, dim3(256), 0, s, g); break;
     case kEpiUpdate: hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdate, BT>), grid, dim3(256), 0, s, g); break;
     case kEpiD64: hipLaunchKernelGGL((k_gemm_bf16<kEpiD64, BT>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdateAcc: hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdateAcc, BT>), grid, dim3(256), 0, s, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -135,7 +135,8 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
                 } else {
                     if (g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour) continue;
                     const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
-                    g.udst[u] = fma(g.omega, (double)v, g.usrc[u]);
+                    const double du = EPI == kEpiUpdateAcc ? g.D[ci] + (double)v : (double)v;
+                    g.udst[u] = fma(g.omega, du, g.usrc[u]);
                 }
             }
 }
@@ -182,24 +183,6 @@ __global__ void __launch_bounds__(256) k_plane_defect(const double *R, const dou
     }
 }
 
-// dst = src + omega D on the interior cells of one patch whose plane index
-// (along `normal`) has parity `colour` (all cells if colour < 0).
-__global__ void __launch_bounds__(256) k_plane_update(const double *D, const double *src, double *dst, int64_t uoff,
-                                                      int nx, int ny, int nz, int normal, int colour, double omega)
-{
-    const int64_t n = (int64_t)nx * ny * nz;
-    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2);
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx);
-        const int j = (int)((c / nx) % ny);
-        const int k = (int)(c / ((int64_t)nx * ny));
-        const int s = normal == 0 ? i : (normal == 1 ? j : k);
-        if (colour >= 0 && (s & 1) != colour) continue;
-        const int64_t u = uoff + (int64_t)(k + 1) * sy + (int64_t)(j + 1) * sx + (i + 1);
-        dst[u] = fma(omega, D[c], src[u]);
-    }
-}
-
 hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStream_t s)
 {
     if (prec != 1) return hipErrorInvalidValue;
@@ -210,6 +193,7 @@ hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStrea
     case kEpiScale: hipLaunchKernelGGL((k_gemm_mixed<kEpiScale>), grid, dim3(256), 0, s, g); break;
     case kEpiUpdate: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdate>), grid, dim3(256), 0, s, g); break;
     case kEpiD64: hipLaunchKernelGGL((k_gemm_mixed<kEpiD64>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdateAcc: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdateAcc>), grid, dim3(256), 0, s, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -232,16 +216,6 @@ hipError_t launch_plane_defect_bf16(const double *R, const double *D, unsigned s
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_plane_defect<unsigned short>, dim3(blocks), dim3(256), 0, s, R, D, E, nx, ny, nz, normal,
                        eps[0], eps[1], eps[2]);
-    return hipGetLastError();
-}
-
-hipError_t launch_plane_update(const double *D, const double *src, double *dst, int64_t uoff, int nx, int ny, int nz,
-                               int normal, int colour, double omega, hipStream_t s)
-{
-    const int64_t n = (int64_t)nx * ny * nz;
-    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_plane_update, dim3(blocks), dim3(256), 0, s, D, src, dst, uoff, nx, ny, nz, normal, colour,
-                       omega);
     return hipGetLastError();
 }
 

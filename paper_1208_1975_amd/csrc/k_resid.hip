@@ -44,6 +44,18 @@ __global__ void __launch_bounds__(kResidThreads) k_residual(ResidArgs a)
         for (int m = 0; m < kResidPerThread; ++m)
             if (cfv[m] >= 0) a.r[pd->foff + cfv[m]] = rv[m];
     }
+    // low-precision copies for the mixed plane solves (rounded from FP64)
+    if (a.e32) {
+#pragma unroll
+        for (int m = 0; m < kResidPerThread; ++m)
+            if (cfv[m] >= 0) a.e32[pd->foff + cfv[m]] = (float)rv[m];
+    }
+    if (a.e16) {
+#pragma unroll
+        for (int m = 0; m < kResidPerThread; ++m)
+            if (cfv[m] >= 0)
+                a.e16[pd->foff + cfv[m]] = __builtin_bit_cast(unsigned short, static_cast<__bf16>(rv[m]));
+    }
     if (!a.partial) return;
     red[threadIdx.x] = acc;
     __syncthreads();

@@ -234,11 +234,12 @@ bs_status chain_lowp(bs_patchset *ps, int p, int c, int colour, int prec, int la
             g.sc_b = pr.sc_b; g.sc_m = pr.sc_m; g.sc_n = pr.sc_n;
         } else if (q == 3) {
             epi = last_epi;
-            if (epi == kEpiUpdate) {
+            if (epi == kEpiUpdate || epi == kEpiUpdateAcc) {
                 g.usrc = src; g.udst = dst; g.omega = omega;
                 g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
                 if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
-            } else {
+            }
+            if (epi == kEpiD64 || epi == kEpiUpdateAcc) {
                 // D shares the f-layout indexing of the chain's final field (kIn = F1)
                 g.D = D + (g.C - F1);
                 g.accumulate = accumulate;
@@ -297,11 +298,12 @@ bs_status chain_bf16(bs_patchset *ps, int p, int c, int colour, int last_epi, in
             g.sc_b = pr.sc_b; g.sc_m = pr.sc_m; g.sc_n = pr.sc_n;
         } else if (q == 3) {
             epi = last_epi;
-            if (epi == kEpiUpdate) {
+            if (epi == kEpiUpdate || epi == kEpiUpdateAcc) {
                 g.usrc = src; g.udst = dst; g.omega = omega;
                 g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
                 if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
-            } else {
+            }
+            if (epi == kEpiD64 || epi == kEpiUpdateAcc) {
                 g.D = D + (g.C - F1);
                 g.accumulate = accumulate;
             }
@@ -339,8 +341,7 @@ bs_status plane_pass(bs_patchset *ps, int c, int colour, int prec, int refine, c
             return b16 ? chain_bf16(ps, p, c, colour, epi, acc, src, dst, omega, s)
                        : chain_lowp(ps, p, c, colour, 1, epi, acc, src, dst, omega, s);
         };
-        hipError_t e = defect(nullptr);
-        if (e != hipSuccess) return hip_fail(e, "plane defect");
+        // E = low-precision R was written by the residual kernel
         bs_status st;
         if (refine == 0) {
             if ((st = chain(kEpiUpdate, 0)) != BS_OK) return st;
@@ -348,21 +349,27 @@ bs_status plane_pass(bs_patchset *ps, int c, int colour, int prec, int refine, c
         }
         if ((st = chain(kEpiD64, 0)) != BS_OK) return st;
         for (int j = 0; j < refine; ++j) {
-            if ((e = defect(D)) != hipSuccess) return hip_fail(e, "plane defect");
-            if ((st = chain(kEpiD64, 1)) != BS_OK) return st;
+            hipError_t e = defect(D);
+            if (e != hipSuccess) return hip_fail(e, "plane defect");
+            // the last defect step updates u straight from its product
+            if ((st = chain(j + 1 < refine ? kEpiD64 : kEpiUpdateAcc, 1)) != BS_OK) return st;
         }
-        if ((e = launch_plane_update(D, src, dst, ps->uoff[p], nx, ny, nz, c, colour, omega, s)) != hipSuccess)
-            return hip_fail(e, "plane update");
     }
     return BS_OK;
 }
 
-bs_status residual_into_scratch(bs_patchset *ps, const double *u, const double *f, hipStream_t s)
+// R = residual (f layout) for the FP64 chain and for refined mixed solves;
+// the mixed solves also get E = low-precision R in F1 (R itself is skipped
+// when nothing reads it).
+bs_status residual_into_scratch(bs_patchset *ps, const double *u, const double *f, hipStream_t s, int prec,
+                                int refine)
 {
     ResidArgs a{};
     a.u = u;
     a.f = f;
-    a.r = static_cast<double *>(ps->plane_r_d.p);
+    a.r = (prec == BS_FP64 || refine > 0) ? static_cast<double *>(ps->plane_r_d.p) : nullptr;
+    if (prec == BS_MIXED_FP32) a.e32 = static_cast<float *>(ps->plane_f1_d.p);
+    if (prec == BS_MIXED_BF16) a.e16 = static_cast<uint16_t *>(ps->plane_f1_d.p);
     a.partial = nullptr;
     a.pd = static_cast<const PatchDesc *>(ps->desc_d.p);
     a.block_patch = static_cast<const int32_t *>(ps->rblock_patch_d.p);
@@ -409,7 +416,7 @@ bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme,
         for (int sw = 0; sw < nsweeps; ++sw) {
             const double *src = (sw & 1) ? work : u;
             double *dst = (sw & 1) ? u : work;
-            if ((st = residual_into_scratch(ps, src, f, stream)) != BS_OK) return st;
+            if ((st = residual_into_scratch(ps, src, f, stream, prec, rf)) != BS_OK) return st;
             if ((st = plane_pass(ps, normal_axis, -1, prec, rf, src, dst, omega, stream)) != BS_OK) return st;
         }
         if (nsweeps & 1) {
@@ -422,7 +429,7 @@ bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme,
     // the same colour-major order), in place
     for (int sw = 0; sw < nsweeps; ++sw)
         for (int colour = 0; colour < 2; ++colour) {
-            if ((st = residual_into_scratch(ps, u, f, stream)) != BS_OK) return st;
+            if ((st = residual_into_scratch(ps, u, f, stream, prec, rf)) != BS_OK) return st;
             if ((st = plane_pass(ps, normal_axis, colour, prec, rf, u, u, omega, stream)) != BS_OK) return st;
         }
     return BS_OK;

@@ -6,7 +6,7 @@
 
 namespace bs {
 
-enum { kEpiStore = 0, kEpiScale = 1, kEpiUpdate = 2, kEpiD64 = 3 };
+enum { kEpiStore = 0, kEpiScale = 1, kEpiUpdate = 2, kEpiD64 = 3, kEpiUpdateAcc = 4 };
 
 // C_b = A_b B_b, row-major, b in [0, batch); a zero batch stride shares an
 // operand across the batch.  Epilogues:
@@ -62,7 +62,9 @@ hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStrea
 // The same product with BF16 operands in memory (unsigned short bit patterns)
 // and FP32 accumulation.  A is [m][k] (k contiguous, leading dimension lda);
 // B is [n][k] with leading dimension ldb when b_trans != 0, else [k][n].
-// Store / scale epilogues write BF16 C; kEpiD64 and kEpiUpdate as above.
+// Store / scale epilogues write BF16 C; kEpiD64 and kEpiUpdate as above;
+// kEpiUpdateAcc: udst[u] = usrc[u] + omega (D + C) (the last defect step of a
+// refined solve applied straight to u; D with C's indexing).
 struct GemmBf16Args {
     const unsigned short *A;
     int64_t lda, sA;
@@ -89,7 +91,5 @@ hipError_t launch_plane_defect(const double *R, const double *D, float *E, int n
 // The same defect rounded to BF16 (bit patterns).
 hipError_t launch_plane_defect_bf16(const double *R, const double *D, unsigned short *E, int nx, int ny, int nz,
                                     int normal, const double eps[3], hipStream_t s);
-hipError_t launch_plane_update(const double *D, const double *src, double *dst, int64_t uoff, int nx, int ny, int nz,
-                               int normal, int colour, double omega, hipStream_t s);
 
 }  // namespace bs
