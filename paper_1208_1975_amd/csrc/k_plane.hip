@@ -22,7 +22,8 @@ namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int kThreads = 512;   // eight wavefronts: 2 (rows) x 4 (columns) of 64 x 32
 
 }  // namespace
 
@@ -37,12 +38,13 @@ __device__ __forceinline__ double2 load2(const double *row, int c0, int lim, boo
     return r;
 }
 
-// A 64 x 64 block of C per workgroup (four wavefronts, 32 x 32 each as 2 x 2
-// blocks of 16 x 16); K advances BK at a time through two LDS buffers, the
-// next tile fetched into registers while the current one feeds the matrix
-// cores (one barrier per step).
-template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
+// A 128 x 128 block of C per workgroup (eight wavefronts, 64 x 32 each as
+// 4 x 2 blocks of 16 x 16: twice the flops per byte fetched from L2 of a
+// 64 x 64 block, which L2 bandwidth holds back); K advances BK at a time
+// through two LDS buffers, the next tile fetched into registers while the
+// current one feeds the matrix cores (one barrier per step).
+template <int EPI, int BT, int FOLD>
+__global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) double As[2][BK][BM + 2];
     __shared__ __attribute__((aligned(16))) double Bs[2][BK][BN + 2];
@@ -52,42 +54,67 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
     const double *B = g.B + (int64_t)b * g.sB;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
+    const int wm = w >> 2, wn = w & 3;
     const int l16 = lane & 15, lk = lane >> 4;
     const bool avec = ((g.lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
     const bool bvec = ((g.ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
 
-    dbl4 acc[2][2];
+    dbl4 acc[4][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
     // A tile BM x BK: pair c -> row c / 8, k offset (c % 8) * 2 (two pairs a
-    // thread); B tile BK x BN: pair c -> k row c / 32, n offset (c % 32) * 2
+    // thread); B tile BK x BN: pair c -> k row c / 64, n offset (c % 64) * 2,
+    // or with b_trans n row c / 8, k offset (c % 8) * 2.  Folded operands add
+    // the mirrored entry (k -> Kfull-1-k) with sign fsign.
+    const int Kf = g.Kfull;
+    const double fs = (double)g.fsign;
     double2 ra[2], rb[2];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int c = tid + 256 * q;
+            const int c = tid + kThreads * q;
             const int r = c >> 3, kc = (c & 7) * 2;
             const int gr = m0 + r;
-            ra[q] = gr < g.M ? load2(A + (int64_t)gr * g.lda, k0 + kc, g.K, avec) : double2{0.0, 0.0};
-            const int kr = c >> 5, nc = (c & 31) * 2;
-            const int gk = k0 + kr;
-            rb[q] = gk < g.K ? load2(B + (int64_t)gk * g.ldb, n0 + nc, g.N, bvec) : double2{0.0, 0.0};
+            const double *arow = A + (int64_t)gr * g.lda;
+            ra[q] = gr < g.M ? load2(arow, k0 + kc, g.K, avec) : double2{0.0, 0.0};
+            if (FOLD == 1 && gr < g.M) {
+                const int k1 = k0 + kc, k2 = k1 + 1;
+                if (k1 < g.K && Kf - 1 - k1 != k1) ra[q].x = fma(fs, arow[Kf - 1 - k1], ra[q].x);
+                if (k2 < g.K && Kf - 1 - k2 != k2) ra[q].y = fma(fs, arow[Kf - 1 - k2], ra[q].y);
+            }
+            if (BT) {
+                const int gn = n0 + r;
+                rb[q] = gn < g.N ? load2(B + (int64_t)gn * g.ldb, k0 + kc, g.K, bvec) : double2{0.0, 0.0};
+            } else {
+                const int kr = c >> 6, nc = (c & 63) * 2;
+                const int gk = k0 + kr;
+                rb[q] = gk < g.K ? load2(B + (int64_t)gk * g.ldb, n0 + nc, g.N, bvec) : double2{0.0, 0.0};
+                if (FOLD == 2 && gk < g.K && Kf - 1 - gk != gk) {
+                    const double2 m = load2(B + (int64_t)(Kf - 1 - gk) * g.ldb, n0 + nc, g.N, bvec);
+                    rb[q].x = fma(fs, m.x, rb[q].x);
+                    rb[q].y = fma(fs, m.y, rb[q].y);
+                }
+            }
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int c = tid + 256 * q;
+            const int c = tid + kThreads * q;
             const int r = c >> 3, kc = (c & 7) * 2;
             As[buf][kc][r] = ra[q].x;
             As[buf][kc + 1][r] = ra[q].y;
-            const int kr = c >> 5, nc = (c & 31) * 2;
-            Bs[buf][kr][nc] = rb[q].x;
-            Bs[buf][kr][nc + 1] = rb[q].y;
+            if (BT) {
+                Bs[buf][kc][r] = rb[q].x;
+                Bs[buf][kc + 1][r] = rb[q].y;
+            } else {
+                const int kr = c >> 6, nc = (c & 63) * 2;
+                Bs[buf][kr][nc] = rb[q].x;
+                Bs[buf][kr][nc + 1] = rb[q].y;
+            }
         }
     };
 
@@ -100,13 +127,13 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
         if (kt + 1 < nk) fetch((kt + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            double af[2], bf[2];
+            double af[4], bf[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) af[i] = As[cur][kk + lk][wm * 32 + i * 16 + l16];
+            for (int i = 0; i < 4; ++i) af[i] = As[cur][kk + lk][wm * 64 + i * 16 + l16];
 #pragma unroll
             for (int j = 0; j < 2; ++j) bf[j] = Bs[cur][kk + lk][wn * 32 + j * 16 + l16];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
@@ -118,14 +145,16 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
     // D layout of the FP64 16x16 block: register r of a lane holds row
     // 4*r + lane/16, column lane%16 (checked by the layout test)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 32 + i * 16 + r * 4 + lk;
-                const int col = n0 + wn * 32 + j * 16 + l16;
-                if (row >= g.M || col >= g.N) continue;
+                const int pr = m0 + wm * 64 + i * 16 + r * 4 + lk;
+                const int pcl = n0 + wn * 32 + j * 16 + l16;
+                if (pr >= g.M || pcl >= g.N) continue;
+                const int row = g.row_s ? pr * g.row_s + g.row_o : pr;
+                const int col = g.row_s ? pcl * g.col_s + g.col_o : pcl;
                 const double v = acc[i][j][r];
                 if (EPI == kEpiStore) {
                     g.C[(int64_t)b * g.sC + (int64_t)row * g.ldc + col] = v;
@@ -140,17 +169,27 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g)
             }
 }
 
-hipError_t launch_gemm_f64(const GemmArgs &g, int epi, hipStream_t s)
+template <int BT, int FOLD>
+static hipError_t launch_f64_t(const GemmArgs &g, int epi, hipStream_t s)
 {
-    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
     const dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
     switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL(k_gemm_f64<kEpiStore>, grid, dim3(256), 0, s, g); break;
-    case kEpiScale: hipLaunchKernelGGL(k_gemm_f64<kEpiScale>, grid, dim3(256), 0, s, g); break;
-    case kEpiUpdate: hipLaunchKernelGGL(k_gemm_f64<kEpiUpdate>, grid, dim3(256), 0, s, g); break;
+    case kEpiStore: hipLaunchKernelGGL((k_gemm_f64<kEpiStore, BT, FOLD>), grid, dim3(kThreads), 0, s, g); break;
+    case kEpiScale: hipLaunchKernelGGL((k_gemm_f64<kEpiScale, BT, FOLD>), grid, dim3(kThreads), 0, s, g); break;
+    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_f64<kEpiUpdate, BT, FOLD>), grid, dim3(kThreads), 0, s, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_gemm_f64(const GemmArgs &g, int epi, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.fold < 0 || g.fold > 2) return hipErrorInvalidValue;
+    // the combinations the plane chain uses (and the plain product)
+    if (g.fold == 0) return g.b_trans ? launch_f64_t<1, 0>(g, epi, s) : launch_f64_t<0, 0>(g, epi, s);
+    if (g.fold == 1) return g.b_trans ? launch_f64_t<1, 1>(g, epi, s) : launch_f64_t<0, 1>(g, epi, s);
+    return g.b_trans ? launch_f64_t<1, 2>(g, epi, s) : launch_f64_t<0, 2>(g, epi, s);
 }
 
 }  // namespace bs

@@ -167,6 +167,11 @@ const T *operand_ptr(const bs_patchset *ps, int p, int c, const Operand &o, cons
 }
 
 // FP64 chain for one patch: R (residual, f layout) is consumed as scratch.
+// Every product has a DST-I basis on one side; the basis obeys
+// S[n-1-i][j] = (-1)^j S[i][j], so each product splits into its even and its
+// odd output rows (left products) or columns (right products), each a product
+// over half the contraction with the field folded about its middle
+// (x[k] + x[n-1-k] for even, x[k] - x[n-1-k] for odd outputs): half the flops.
 bs_status chain_f64(bs_patchset *ps, int p, int c, int colour, const double *src, double *dst, double omega,
                     hipStream_t s)
 {
@@ -177,28 +182,50 @@ bs_status chain_f64(bs_patchset *ps, int p, int c, int colour, const double *src
     double *T = static_cast<double *>(ps->plane_t_d.p) + ps->foff[p];
     for (int q = 0; q < 4; ++q) {
         const Product &pr = ch.g[q];
-        GemmArgs g{};
-        g.A = operand_ptr<double>(ps, p, c, pr.A, R, T, tab);
-        g.lda = pr.A.ld; g.sA = pr.A.sb;
-        g.B = operand_ptr<double>(ps, p, c, pr.B, R, T, tab);
-        g.ldb = pr.B.ld; g.sB = pr.B.sb;
-        g.C = const_cast<double *>(operand_ptr<double>(ps, p, c, pr.C, R, T, tab));
-        g.ldc = pr.C.ld; g.sC = pr.C.sb;
-        g.M = pr.M; g.N = pr.N; g.K = pr.K; g.batch = pr.batch;
-        g.ncolour = -1;
-        int epi = kEpiStore;
-        if (q == 1) {
-            epi = kEpiScale;
-            g.scale = tab + ps->lam_off[3 * p + c];
-            g.sc_b = pr.sc_b; g.sc_m = pr.sc_m; g.sc_n = pr.sc_n;
-        } else if (q == 3) {
-            epi = kEpiUpdate;
-            g.usrc = src; g.udst = dst; g.omega = omega;
-            g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
-            if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
+        const bool right = pr.B.buf == kSx || pr.B.buf == kSy || pr.B.buf == kSz;   // C = A S, else C = S B
+        for (int par = 0; par < 2; ++par) {
+            GemmArgs g{};
+            g.A = operand_ptr<double>(ps, p, c, pr.A, R, T, tab);
+            g.lda = pr.A.ld; g.sA = pr.A.sb;
+            g.B = operand_ptr<double>(ps, p, c, pr.B, R, T, tab);
+            g.ldb = pr.B.ld; g.sB = pr.B.sb;
+            g.C = const_cast<double *>(operand_ptr<double>(ps, p, c, pr.C, R, T, tab));
+            g.ldc = pr.C.ld; g.sC = pr.C.sb;
+            g.M = pr.M; g.N = pr.N; g.batch = pr.batch;
+            g.Kfull = pr.K;
+            g.K = par == 0 ? (pr.K + 1) / 2 : pr.K / 2;
+            g.fsign = par == 0 ? 1 : -1;
+            g.row_s = 1; g.col_s = 1;
+            if (right) {   // columns n = 2n' + par; B' = rows 2n' + par of the (symmetric) basis
+                g.fold = 1;
+                g.b_trans = 1;
+                g.B += static_cast<int64_t>(par) * pr.B.ld;
+                g.ldb = 2 * pr.B.ld;
+                g.N = (pr.N + 1 - par) / 2;
+                g.col_s = 2; g.col_o = par;
+            } else {       // rows m = 2m' + par; A' = rows 2m' + par of the basis
+                g.fold = 2;
+                g.A += static_cast<int64_t>(par) * pr.A.ld;
+                g.lda = 2 * pr.A.ld;
+                g.M = (pr.M + 1 - par) / 2;
+                g.row_s = 2; g.row_o = par;
+            }
+            if (g.K <= 0) continue;
+            g.ncolour = -1;
+            int epi = kEpiStore;
+            if (q == 1) {
+                epi = kEpiScale;
+                g.scale = tab + ps->lam_off[3 * p + c];
+                g.sc_b = pr.sc_b; g.sc_m = pr.sc_m; g.sc_n = pr.sc_n;
+            } else if (q == 3) {
+                epi = kEpiUpdate;
+                g.usrc = src; g.udst = dst; g.omega = omega;
+                g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
+                if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
+            }
+            hipError_t e = launch_gemm_f64(g, epi, s);
+            if (e != hipSuccess) return hip_fail(e, "plane transform");
         }
-        hipError_t e = launch_gemm_f64(g, epi, s);
-        if (e != hipSuccess) return hip_fail(e, "plane transform");
     }
     return BS_OK;
 }

@@ -29,6 +29,17 @@ struct GemmArgs {
     int64_t u0, u_b, u_m, u_n;
     double omega;
     int ncolour, colour_shift;
+    // Options (zero-initialised = plain product):
+    //   b_trans: B stored as [n][k] (element (k, n) at n*ldb + k);
+    //   fold 1 / 2: the contraction runs over K entries of A's rows / B's
+    //     columns folded about the middle of a length-Kfull axis:
+    //     x'[k] = x[k] + fsign * x[Kfull-1-k] (x[k] alone where k = Kfull-1-k),
+    //     the even/odd split of a product with a DST-I basis;
+    //   row_s, row_o, col_s, col_o: the product's row m / column n stands for
+    //     the logical row m*row_s + row_o / column n*col_s + col_o of C, of the
+    //     scale grid and of the u mapping (1, 0, 1, 0 if row_s = 0).
+    int b_trans, fold, Kfull, fsign;
+    int row_s, row_o, col_s, col_o;
 };
 
 hipError_t launch_gemm_f64(const GemmArgs &g, int epi, hipStream_t s);
