@@ -82,8 +82,15 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
             ra[q] = gr < g.M ? load2(arow, k0 + kc, g.K, avec) : double2{0.0, 0.0};
             if (FOLD == 1 && gr < g.M) {
                 const int k1 = k0 + kc, k2 = k1 + 1;
-                if (k1 < g.K && Kf - 1 - k1 != k1) ra[q].x = fma(fs, arow[Kf - 1 - k1], ra[q].x);
-                if (k2 < g.K && Kf - 1 - k2 != k2) ra[q].y = fma(fs, arow[Kf - 1 - k2], ra[q].y);
+                if (avec && !(Kf & 1) && k2 < g.K) {
+                    // mirrored pair (Kf-2-k1, Kf-1-k1): one aligned 16-byte load (even Kf has no middle)
+                    const double2 m = *reinterpret_cast<const double2 *>(arow + (Kf - 2 - k1));
+                    ra[q].x = fma(fs, m.y, ra[q].x);
+                    ra[q].y = fma(fs, m.x, ra[q].y);
+                } else {
+                    if (k1 < g.K && Kf - 1 - k1 != k1) ra[q].x = fma(fs, arow[Kf - 1 - k1], ra[q].x);
+                    if (k2 < g.K && Kf - 1 - k2 != k2) ra[q].y = fma(fs, arow[Kf - 1 - k2], ra[q].y);
+                }
             }
             if (BT) {
                 const int gn = n0 + r;
