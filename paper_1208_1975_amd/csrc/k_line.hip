@@ -159,7 +159,9 @@ __global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a, const double 
     double *endb = smem + (L <= 16 ? L * 64 * nw : 0);   // u is held in LDS only for chunks <= 16
     int buf = 0;
     for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
-        line_strided_item<L, CM, F32>(a, tabs, tabs32, a.items[i], endb + buf * (2 * 64 * nw),
+        const WorkItem it = a.items[i];
+        if (it.patch < 0) continue;   // padding of the dispatch order
+        line_strided_item<L, CM, F32>(a, tabs, tabs32, it, endb + buf * (2 * 64 * nw),
                                       endb + (buf ^ 1) * (2 * 64 * nw), ucs);
         // one barrier per item alternates the buffers; the in-tile two-colour
         // mode uses both in every item behind two barriers
@@ -404,7 +406,9 @@ __global__ void __launch_bounds__(MAXT) k_line_x(LineArgs a, const float *__rest
 {
     extern __shared__ double smem[];
     for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
-        line_x_item<L, MAXT, F32>(a, tabs32, a.items[i], smem);
+        const WorkItem it = a.items[i];
+        if (it.patch < 0) continue;   // padding of the dispatch order
+        line_x_item<L, MAXT, F32>(a, tabs32, it, smem);
         __syncthreads();
     }
 }

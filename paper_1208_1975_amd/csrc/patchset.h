@@ -32,9 +32,12 @@ struct DevBuf {
 // lists), or a single run (all lines).
 struct WorkList {
     DevBuf buf;
+    // the launch runs (colour 0, colour 1) at the start of buf, in dispatch
+    // order (may hold empty items, patch < 0, that kernels skip)
     int count[2] = {0, 0};
-    // per colour run, per patch: first item (relative to the run) and count;
-    // a patch's items are contiguous within each run
+    // the same items per patch, contiguous, at pp_off[c] in buf: per colour
+    // run, per patch, first item (relative to pp_off) and count
+    int pp_off[2] = {0, 0};
     std::vector<int> pfirst[2], pcount[2];
 };
 
@@ -77,6 +80,7 @@ struct bs_patchset {
     bs::DevBuf plane_tab32_d, plane_f1_d, plane_f2_d;   // FP32 copies and float scratch (mixed precision)
     bs::DevBuf plane_tab16_d;                           // BF16 copies of the bases
     int mixed_dlayout = 0;
+    int chaotic_chunk = 0;   // tiles per even/odd chunk of the chaotic dispatch order (0: default)
     std::vector<int64_t> basis_off, lam_off;   // [3 * npatch] each, offsets in doubles
     // cached work lists and tuned configurations
     std::map<bs::WorkKey, std::unique_ptr<bs::WorkList>> lists;

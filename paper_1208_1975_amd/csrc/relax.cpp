@@ -65,6 +65,108 @@ void xcd_order(std::vector<WorkItem> &run)
     run.swap(out);
 }
 
+// Dispatch order for a patch set: whole patches go to one XCD each (greedy,
+// larger patches first, balancing line cells), each patch's items stay
+// consecutive in its XCD's sequence (neighbouring tiles then share that XCD's
+// L2), and the sequences are interleaved so that workgroup j*8 + x runs the
+// j-th item of XCD x; shorter sequences are padded with empty items.
+std::vector<WorkItem> xcd_group(const std::vector<WorkItem> &run, const std::vector<int> &order,
+                                const std::vector<int> &first, const std::vector<int> &count,
+                                const std::vector<int64_t> &weight)
+{
+    std::vector<std::vector<WorkItem>> lists(8);
+    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int p : order) {
+        if (count[p] == 0) continue;
+        int x = 0;
+        for (int k = 1; k < 8; ++k)
+            if (load[k] < load[x]) x = k;
+        for (int t = 0; t < count[p]; ++t) lists[x].push_back(run[first[p] + t]);
+        load[x] += weight[p];
+    }
+    size_t len = 0;
+    for (const auto &l : lists) len = std::max(len, l.size());
+    std::vector<WorkItem> out(8 * len, WorkItem{-1, 0, 0, 0});
+    for (int x = 0; x < 8; ++x)
+        for (size_t j = 0; j < lists[x].size(); ++j) out[j * 8 + x] = lists[x][j];
+    return out;
+}
+
+// Dispatch order of the in-tile two-colour (chaotic) runs: each XCD takes
+// contiguous tiles (one patch: an eighth of its tiles; a patch set: whole
+// patches, balanced), its sequence is cut into chunks of about kChaoticChunk
+// tiles, and each chunk runs its even tile rows before its odd ones.  The odd
+// tiles then find their neighbours' new values, still in that XCD's L2; only
+// chunk borders see older values (the asynchronous part of the scheme).  The
+// eight sequences are interleaved as in xcd_group.
+std::vector<WorkItem> chaotic_order(const bs_patchset *ps, const std::vector<WorkItem> run[2],
+                                    const std::vector<int> &order, const std::vector<int> pfirst[2],
+                                    const std::vector<int> pcount[2], int axis)
+{
+    // a chunk must be several times the ~32 workgroups an XCD runs at once, so
+    // that its odd tiles start after its even ones have finished (a patch set
+    // packs many small patches into one chunk)
+    const int kChaoticChunk = ps->chaotic_chunk > 0 ? ps->chaotic_chunk : (ps->npatch == 1 ? 64 : 512);
+    // per XCD: the sequence of units, a unit = (run-0 items, run-1 items) of one patch or one slice
+    struct Unit {
+        std::vector<WorkItem> it[2];
+    };
+    std::vector<std::vector<Unit>> xl(8);
+    if (ps->npatch == 1) {
+        // spatial order: tiles in increasing index, split into 8 contiguous blocks
+        std::vector<WorkItem> sp(run[0].begin(), run[0].end());
+        sp.insert(sp.end(), run[1].begin(), run[1].end());
+        std::sort(sp.begin(), sp.end(), [](const WorkItem &a, const WorkItem &b) { return a.tile < b.tile; });
+        const size_t n = sp.size();
+        for (int x = 0; x < 8; ++x) {
+            Unit u;
+            for (size_t j = n * x / 8; j < n * (x + 1) / 8; ++j) u.it[sp[j].colour].push_back(sp[j]);
+            xl[x].push_back(u);
+        }
+    } else {
+        int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int p : order) {
+            if (pcount[0][p] + pcount[1][p] == 0) continue;
+            int x = 0;
+            for (int k = 1; k < 8; ++k)
+                if (load[k] < load[x]) x = k;
+            Unit u;
+            for (int c = 0; c < 2; ++c)
+                for (int t = 0; t < pcount[c][p]; ++t) u.it[c].push_back(run[c][pfirst[c][p] + t]);
+            load[x] += static_cast<int64_t>(pcount[0][p] + pcount[1][p]) * ps->dims[3 * p + axis];
+            xl[x].push_back(u);
+        }
+    }
+    std::vector<std::vector<WorkItem>> lists(8);
+    for (int x = 0; x < 8; ++x) {
+        // chunks of consecutive tiles: even tiles of the chunk, then its odd tiles
+        std::vector<WorkItem> ev, od;
+        auto flush = [&]() {
+            lists[x].insert(lists[x].end(), ev.begin(), ev.end());
+            lists[x].insert(lists[x].end(), od.begin(), od.end());
+            ev.clear();
+            od.clear();
+        };
+        for (const Unit &u : xl[x]) {
+            // a single large unit is cut into chunks in its own spatial order
+            std::vector<WorkItem> merged(u.it[0].begin(), u.it[0].end());
+            merged.insert(merged.end(), u.it[1].begin(), u.it[1].end());
+            std::sort(merged.begin(), merged.end(), [](const WorkItem &a, const WorkItem &b) { return a.tile < b.tile; });
+            for (const WorkItem &w : merged) {
+                (w.colour == 0 ? ev : od).push_back(w);
+                if (static_cast<int>(ev.size() + od.size()) >= kChaoticChunk) flush();
+            }
+        }
+        flush();
+    }
+    size_t len = 0;
+    for (const auto &l : lists) len = std::max(len, l.size());
+    std::vector<WorkItem> out(8 * len, WorkItem{-1, 0, 0, 0});
+    for (int x = 0; x < 8; ++x)
+        for (size_t j = 0; j < lists[x].size(); ++j) out[j * 8 + x] = lists[x][j];
+    return out;
+}
+
 int device_cus()
 {
     static int cus = 0;
@@ -102,10 +204,11 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
         return ca > cb;
     });
     auto wl = std::make_unique<WorkList>();
-    std::vector<WorkItem> all;
+    std::vector<WorkItem> all, plain;
+    std::vector<WorkItem> runs[2];
     const int ncol = colour_mode ? 2 : 1;
     for (int c = 0; c < ncol; ++c) {
-        std::vector<WorkItem> run;
+        std::vector<WorkItem> &run = runs[c];
         wl->pfirst[c].assign(ps->npatch, 0);
         wl->pcount[c].assign(ps->npatch, 0);
         for (int p : order) {
@@ -122,10 +225,32 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
             }
             wl->pcount[c][p] = static_cast<int>(run.size()) - wl->pfirst[c][p];
         }
-        if (ps->npatch == 1) xcd_order(run);
-        wl->count[c] = static_cast<int>(run.size());
-        all.insert(all.end(), run.begin(), run.end());
+        wl->pp_off[c] = static_cast<int>(plain.size());
+        plain.insert(plain.end(), run.begin(), run.end());
     }
+    if (colour_mode == 2) {
+        // one launch runs both groups: local even-then-odd chunks per XCD
+        const std::vector<WorkItem> d = chaotic_order(ps, runs, order, wl->pfirst, wl->pcount, axis);
+        wl->count[0] = static_cast<int>(d.size());
+        wl->count[1] = 0;
+        all.insert(all.end(), d.begin(), d.end());
+    } else {
+        for (int c = 0; c < ncol; ++c) {
+            std::vector<WorkItem> run = runs[c];
+            if (ps->npatch == 1) {
+                xcd_order(run);
+            } else {
+                std::vector<int64_t> weight(ps->npatch);
+                for (int p = 0; p < ps->npatch; ++p)
+                    weight[p] = static_cast<int64_t>(wl->pcount[c][p]) * ps->dims[3 * p + axis];
+                run = xcd_group(run, order, wl->pfirst[c], wl->pcount[c], weight);
+            }
+            wl->count[c] = static_cast<int>(run.size());
+            all.insert(all.end(), run.begin(), run.end());
+        }
+    }
+    for (int c = 0; c < ncol; ++c) wl->pp_off[c] += static_cast<int>(all.size());
+    all.insert(all.end(), plain.begin(), plain.end());
     bs_status st = upload(wl->buf, all.data(), all.size() * sizeof(WorkItem), "work list");
     if (st != BS_OK) return st;
     *out = wl.get();
@@ -239,8 +364,7 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
         const int runs = colour_mode ? (run == 2 ? 2 : 1) : 1;
         for (int k = 0; k < runs; ++k) {
             const int cr = colour_mode ? (run == 2 ? k : run) : 0;
-            const int off = cr == 1 ? wl->count[0] : 0;
-            if ((st = launch(off + wl->pfirst[cr][patch], wl->pcount[cr][patch])) != BS_OK) return st;
+            if ((st = launch(wl->pp_off[cr] + wl->pfirst[cr][patch], wl->pcount[cr][patch])) != BS_OK) return st;
         }
         return BS_OK;
     }
@@ -536,6 +660,16 @@ int bsi_set_line_cfg(bs_patchset *ps, int axis, int scheme, int popt, int tx, in
     bs_status st = check_line_cfg(ps, axis, c);
     if (st != BS_OK) return st;
     ps->line_cfg[std::make_pair(axis, colour_mode)] = c;
+    clear_graphs(ps);
+    return BS_OK;
+}
+
+// Tiles per even/odd chunk of the chaotic dispatch order (0: default).
+int bsi_set_chaotic_chunk(bs_patchset *ps, int tiles)
+{
+    if (!ps || tiles < 0) return BS_ERR_INVALID;
+    ps->chaotic_chunk = tiles;
+    ps->lists.clear();
     clear_graphs(ps);
     return BS_OK;
 }
