@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the other configurations")
+    ap.add_argument("--profile-c4", action="store_true",
+                    help="fixed batched sequence for rocprofv3 (3000 AMR patches: 1 GiB copy, 3 x-line chaotic GS sweeps)")
     ap.add_argument("--profile-planes", action="store_true",
                     help="fixed plane-sweep sequence for rocprofv3 (512^3: FP64, FP32, BF16 refine 1; 2 sweeps each)")
     ap.add_argument("--profile", action="store_true",
@@ -71,6 +73,32 @@ def profile_run():
     ps.residual(u, f, None, n2)
     torch.cuda.synchronize()
     print("profile run done", flush=True)
+
+
+def profile_c4_run():
+    """Fixed batched sequence for counters: a 1 GiB copy (scale), then three
+    x-line chaotic GS sweeps of the 3000-patch set, one launch each."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import c4_patchset
+
+    torch.cuda.set_device(0)
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    s = c4_patchset()
+    ps = bs.PatchSet([tuple(d) for d in s.dims], [tuple(e) for e in s.eps], list(s.h))
+    u = ps.pack_u(s.u0)
+    f = ps.pack_f(s.f)
+    ps.set_graphs(False)
+    for _ in range(3):
+        ps.line_relax(0, "chaotic", 1.0, 1, u, f)
+    torch.cuda.synchronize()
+    print("profile c4 done", flush=True)
 
 
 def profile_planes_run():
@@ -295,6 +323,9 @@ def main():
     args = parse()
     if args.profile_planes:
         profile_planes_run()
+        return
+    if args.profile_c4:
+        profile_c4_run()
         return
     if args.profile:
         profile_run()
