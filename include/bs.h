@@ -168,11 +168,17 @@ bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme,
 bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, const double *u, const double *f,
                            hipStream_t stream);
 
-/* The launch configuration bs_line_relax uses for (axis, scheme):
- * cfg_host[0] chunks per line, [1] register chunk length, [2] tile width in
- * lanes, [3] persistent grid size (0: one workgroup per tile), [4] 1 if it
- * was set by the autotuner. */
-bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, int32_t cfg_host[5]);
+/* The launch configuration bs_line_relax uses for (axis, scheme), written to
+ * the caller's host array of six int32:
+ *   [5] kernel form: 0 = each line cut into chunks, one wavefront per chunk,
+ *       a lane per line; 1 = x-lines of up to 64 cells spread over the lanes
+ *       of a 16-lane row, four cells per lane (the default for such x-lines);
+ *   [0] form 0: chunks per line; form 1: wavefronts per workgroup;
+ *   [1] form 0: register chunk length; form 1: cells per lane (4);
+ *   [2] tile width in lanes (y/z lines);
+ *   [3] persistent grid size (0: one workgroup per tile);
+ *   [4] 1 if it was set by the autotuner. */
+bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, int32_t cfg_host[6]);
 
 /* Device workspace needed by bs_relax_backward for these arguments, or 0 on
  * invalid arguments. */

@@ -65,6 +65,8 @@ def lib():
     L.bs_line_config.argtypes = [vp, i32, ctypes.c_int, vp]
     L.bsi_set_line_cfg.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.bsi_set_line_cfg.restype = ctypes.c_int
+    L.bsi_set_xline_cfg.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.bsi_set_xline_cfg.restype = ctypes.c_int
     L.bsi_set_graphs.argtypes = [vp, ctypes.c_int]
     L.bsi_set_graphs.restype = ctypes.c_int
     L.bsi_line_relax_per_patch.argtypes = [vp, i32, ctypes.c_int, dbl, i32, vp, vp, vp, vp]
@@ -187,10 +189,12 @@ def bs_autotune_line(ps, axis, scheme, u, f, stream=None):
 
 
 def bs_line_config(ps, axis, scheme):
-    """dict(chunks, chunk_len, tile, grid, tuned) of the launch configuration in use."""
-    out = (ctypes.c_int32 * 5)()
+    """dict(chunks, chunk_len, tile, grid, tuned, form) of the launch configuration
+    in use (form 1, register x-lines: chunks = wavefronts per workgroup,
+    chunk_len = cells per lane)."""
+    out = (ctypes.c_int32 * 6)()
     _check(lib().bs_line_config(ps, int(axis), _scheme(scheme), out))
-    return dict(zip(("chunks", "chunk_len", "tile", "grid", "tuned"), list(out)))
+    return dict(zip(("chunks", "chunk_len", "tile", "grid", "tuned", "form"), list(out)))
 
 
 def bs_backward_workspace_bytes(ps, axis, nsweeps, ckpt_every):
@@ -294,6 +298,11 @@ class PatchSet:
     def set_line_config(self, axis, scheme, chunks, tile=64, grid=0):
         popt = (1, 2, 4, 8, 16).index(int(chunks))
         _check(lib().bsi_set_line_cfg(self.handle, int(axis), _scheme(scheme), popt, int(tile), int(grid)))
+
+    def set_xline_config(self, scheme, waves=4, grid=0):
+        """Register x-line kernel (x-lines of up to 64 cells across the lanes of
+        a 16-lane row) with `waves` wavefronts per workgroup."""
+        _check(lib().bsi_set_xline_cfg(self.handle, _scheme(scheme), int(waves), int(grid)))
 
     def set_graphs(self, enable):
         _check(lib().bsi_set_graphs(self.handle, 1 if enable else 0))

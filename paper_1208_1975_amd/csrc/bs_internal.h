@@ -12,6 +12,7 @@ namespace bs {
 constexpr int kNumPOpt = 5;
 constexpr int kPOpts[kNumPOpt] = {1, 2, 4, 8, 16};
 constexpr int kMaxChunkLen = 64;   // largest Lr a kernel instantiation holds in registers
+constexpr int kXregMaxN = 64;      // longest x-line of the register x-line kernel (16 lanes x 4 cells)
 
 struct LineTabRef {
     int64_t off;   // offset in doubles into the table buffer, -1 if not built
@@ -86,6 +87,7 @@ struct ResidArgs {
 // grid: workgroups launched (each drains items blockIdx.x, +grid, ... < a.nitems)
 hipError_t launch_line_strided(const LineArgs &a, int grid, int Lmax, int nwaves, size_t lds, hipStream_t s);
 hipError_t launch_line_x(const LineArgs &a, int grid, int Lmax, int nwaves, size_t lds, hipStream_t s);
+hipError_t launch_line_xr(const LineArgs &a, int grid, int nwaves, hipStream_t s);
 hipError_t prepare_line_kernels();
 hipError_t launch_residual(const ResidArgs &a, int nblocks, hipStream_t s);
 hipError_t launch_residual_final(const double *partial, const int32_t *patch_first_block,

@@ -51,6 +51,8 @@ struct LineCfg {
     int nwaves = 0;   // wavefronts per workgroup (= P_req)
     int tx = 64;      // strided kernel: lanes along x per row
     int grid = 0;     // persistent grid size (0: one workgroup per work item)
+    int form = 0;     // 0: a line's chunks on the wavefronts of a workgroup;
+                      // 1: x-lines across the lanes of a 16-lane row (nx <= 64)
 };
 
 bs_status fail(bs_status st, const char *fmt, ...);

@@ -282,11 +282,20 @@ LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode)
         c.tx = 64;
     }
     c.grid = 0;
+    if (axis == 0 && nmax <= kXregMaxN) {
+        // x-lines of up to 64 cells: across the lanes of a 16-lane row, four
+        // cells per lane, one line table (the line's own LU factors)
+        c.form = 1;
+        c.popt = 0;
+        c.Lmax = 4;
+        c.nwaves = 4;
+    }
     return c;
 }
 
 size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c)
 {
+    if (c.form == 1) return 0;
     int tsz = 0, sd = 1;
     for (int p = 0; p < ps->npatch; ++p) {
         const LineTabRef &r = ps->desc[p].line[axis][c.popt];
@@ -305,6 +314,19 @@ size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c)
 
 bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c)
 {
+    if (c.form == 1) {
+        if (axis != 0 || ps->max_n[0] > kXregMaxN)
+            return fail(BS_ERR_UNSUPPORTED, "line config: register x-lines need axis 0 and nx <= %d", kXregMaxN);
+        if (c.popt != 0 || c.Lmax != 4) return fail(BS_ERR_INVALID, "line config: bad register x-line form");
+        if (c.nwaves != 1 && c.nwaves != 2 && c.nwaves != 4)
+            return fail(BS_ERR_INVALID, "line config: register x-lines take 1, 2 or 4 wavefronts");
+        if (c.grid < 0) return fail(BS_ERR_INVALID, "line config: negative grid");
+        for (int p = 0; p < ps->npatch; ++p)
+            if (ps->desc[p].line[0][0].off < 0)
+                return fail(BS_ERR_UNSUPPORTED, "line config: patch %d has no x-line factor table", p);
+        return BS_OK;
+    }
+    if (c.form != 0) return fail(BS_ERR_INVALID, "line config: unknown kernel form");
     if (c.popt < 0 || c.popt >= kNumPOpt) return fail(BS_ERR_INVALID, "line config: bad chunk option");
     if (c.nwaves != kPOpts[c.popt]) return fail(BS_ERR_INVALID, "line config: waves != chunk count");
     if (c.tx < 1 || c.tx > 64 || (c.tx & (c.tx - 1))) return fail(BS_ERR_INVALID, "line config: bad tile width");
@@ -355,8 +377,9 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
         a.items = base + first;
         a.nitems = count;
         const int grid = c.grid > 0 ? std::min(count, c.grid) : count;
-        hipError_t e = axis == 0 ? launch_line_x(a, grid, c.Lmax, c.nwaves, lds, stream)
-                                 : launch_line_strided(a, grid, c.Lmax, c.nwaves, lds, stream);
+        hipError_t e = c.form == 1  ? launch_line_xr(a, grid, c.nwaves, stream)
+                       : axis == 0  ? launch_line_x(a, grid, c.Lmax, c.nwaves, lds, stream)
+                                    : launch_line_strided(a, grid, c.Lmax, c.nwaves, lds, stream);
         return e == hipSuccess ? BS_OK : hip_fail(e, "line sweep kernel");
     };
     if (colour_mode == 2) run = 2;   // in-tile two-colour: both tile-row groups in one pass
@@ -579,6 +602,18 @@ bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, cons
             }
         }
     }
+    if (axis == 0 && ps->max_n[0] <= kXregMaxN) {
+        for (int nw : {1, 2, 4}) {
+            LineCfg c;
+            c.form = 1;
+            c.popt = 0;
+            c.Lmax = 4;
+            c.nwaves = nw;
+            c.tx = 64;
+            c.grid = 0;
+            if (check_line_cfg(ps, axis, c) == BS_OK) cands.push_back(c);
+        }
+    }
     if (cands.empty()) return fail(BS_ERR_UNSUPPORTED, "bs_autotune_line: no valid configuration");
     hipEvent_t e0, e1;
     if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event");
@@ -620,7 +655,7 @@ bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, cons
     return BS_OK;
 }
 
-bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, int32_t cfg_host[5])
+bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, int32_t cfg_host[6])
 {
     if (!ps || !cfg_host) return fail(BS_ERR_INVALID, "bs_line_config: null argument");
     if (axis < 0 || axis > 2) return fail(BS_ERR_INVALID, "bs_line_config: axis must be 0, 1 or 2");
@@ -628,11 +663,12 @@ bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, 
     auto itr = ps->line_cfg.find(std::make_pair(static_cast<int>(axis), cm));
     const bool set = itr != ps->line_cfg.end();
     const LineCfg c = set ? itr->second : default_line_cfg(ps, axis, cm);
-    cfg_host[0] = kPOpts[c.popt];
+    cfg_host[0] = c.form == 1 ? c.nwaves : kPOpts[c.popt];
     cfg_host[1] = c.Lmax;
     cfg_host[2] = c.tx;
     cfg_host[3] = c.grid;
     cfg_host[4] = set ? 1 : 0;
+    cfg_host[5] = c.form;
     return BS_OK;
 }
 
@@ -660,6 +696,27 @@ int bsi_set_line_cfg(bs_patchset *ps, int axis, int scheme, int popt, int tx, in
     bs_status st = check_line_cfg(ps, axis, c);
     if (st != BS_OK) return st;
     ps->line_cfg[std::make_pair(axis, colour_mode)] = c;
+    clear_graphs(ps);
+    return BS_OK;
+}
+
+// Select the register x-line kernel (lines across the lanes of a 16-lane row)
+// for `scheme`, with nwaves wavefronts per workgroup and a persistent grid
+// (0: one workgroup per work item).
+int bsi_set_xline_cfg(bs_patchset *ps, int scheme, int nwaves, int grid)
+{
+    if (!ps || scheme < 0 || scheme > 2) return BS_ERR_INVALID;
+    const int colour_mode = scheme_mode(0, static_cast<bs_scheme>(scheme));
+    LineCfg c;
+    c.form = 1;
+    c.popt = 0;
+    c.Lmax = 4;
+    c.nwaves = nwaves;
+    c.tx = 64;
+    c.grid = grid;
+    bs_status st = check_line_cfg(ps, 0, c);
+    if (st != BS_OK) return st;
+    ps->line_cfg[std::make_pair(0, colour_mode)] = c;
     clear_graphs(ps);
     return BS_OK;
 }
