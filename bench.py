@@ -76,8 +76,9 @@ def profile_run():
 
 
 def profile_c4_run():
-    """Fixed batched sequence for counters: a 1 GiB copy (scale), then three
-    x-line chaotic GS sweeps of the 3000-patch set, one launch each."""
+    """Fixed batched sequence for counters: a 1 GiB copy (scale), then the
+    autotuner's trials and three x-line chaotic GS sweeps of the 3000-patch
+    set in the configuration it picks, one launch each."""
     import torch
 
     import paper_1208_1975_amd as bs
@@ -94,6 +95,9 @@ def profile_c4_run():
     ps = bs.PatchSet([tuple(d) for d in s.dims], [tuple(e) for e in s.eps], list(s.h))
     u = ps.pack_u(s.u0)
     f = ps.pack_f(s.f)
+    ps.autotune_line(0, "chaotic", u, f)
+    torch.cuda.synchronize()
+    print("profile c4 config %s" % json.dumps(ps.line_config(0, "chaotic")), flush=True)
     ps.set_graphs(False)
     for _ in range(3):
         ps.line_relax(0, "chaotic", 1.0, 1, u, f)

@@ -120,6 +120,29 @@ __device__ __forceinline__ void interface_terms(const T *tab, const double *ends
     }
 }
 
+// The same for a table in memory no kernel writes, read as constant memory:
+// the rows are wave-uniform, so they come through the scalar cache.
+template <typename T>
+__device__ __forceinline__ void interface_terms_k(const __attribute__((address_space(4))) T *tab, const double *ends,
+                                                  int Lr, int P, int p, int lane, T &bprev, T &anext)
+{
+    const __attribute__((address_space(4))) T *Kb = tab + 6 * Lr + p * 2 * P;
+    const __attribute__((address_space(4))) T *Ka = tab + 6 * Lr + 2 * P * P + p * 2 * P;
+    bprev = 0;
+    anext = 0;
+    for (int jj = 0; jj < 2 * P; ++jj) {
+        const T Y = static_cast<T>(ends[((jj >> 1) * 64 + lane) * 2 + (jj & 1)]);
+        bprev = fma(Kb[jj], Y, bprev);
+        anext = fma(Ka[jj], Y, anext);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
 // ---------------------------------------------------------------------------
 // y- and z-lines.  Lanes run along x (coalesced), a tile is tx lanes along x
 // by 64/tx along the other free axis; wavefront p of the workgroup holds
@@ -320,9 +343,9 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
         for (int t = 0; t < L; ++t) uo[kUcLds ? 0 : t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
     }
     T bprev, anext;
-    interface_terms<T>(tab, ends, Lr, P, pc, lane, bprev, anext);
-    const T *ev = tab + (pc == P - 1 ? 4 * Lr : 2 * Lr);
-    const T *ew = ev + Lr;
+    interface_terms_k<T>(as_const(tab), ends, Lr, P, pc, lane, bprev, anext);
+    const __attribute__((address_space(4))) T *ev = as_const(tab) + (pc == P - 1 ? 4 * Lr : 2 * Lr);
+    const __attribute__((address_space(4))) T *ew = ev + Lr;
     const double om = a.omega;
     char *db = reinterpret_cast<char *>(a.dst + pd->uoff);
     if (CM == 2) {
@@ -362,9 +385,9 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
         ends2[(p * 64 + lane) * 2 + 0] = y0;
         ends2[(p * 64 + lane) * 2 + 1] = yl;
         __syncthreads();
-        interface_terms<T>(tab2, ends2, Lr, P, pc, lane, bprev, anext);
-        const T *ev2 = tab2 + (pc == P - 1 ? 4 * Lr : 2 * Lr);
-        const T *ew2 = ev2 + Lr;
+        interface_terms_k<T>(as_const(tab2), ends2, Lr, P, pc, lane, bprev, anext);
+        const __attribute__((address_space(4))) T *ev2 = as_const(tab2) + (pc == P - 1 ? 4 * Lr : 2 * Lr);
+        const __attribute__((address_space(4))) T *ew2 = ev2 + Lr;
         if (valid) {
 #pragma unroll
             for (int t = 0; t < L; ++t) {

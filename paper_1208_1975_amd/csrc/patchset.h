@@ -53,6 +53,7 @@ struct LineCfg {
     int grid = 0;     // persistent grid size (0: one workgroup per work item)
     int form = 0;     // 0: a line's chunks on the wavefronts of a workgroup;
                       // 1: x-lines across the lanes of a 16-lane row (nx <= 64)
+    int tuned = 0;    // 1: chosen by bs_autotune_line
 };
 
 bs_status fail(bs_status st, const char *fmt, ...);

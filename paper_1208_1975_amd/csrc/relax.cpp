@@ -650,6 +650,7 @@ bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, cons
     (void)hipEventDestroy(e1);
     if (st != BS_OK) return st;
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "autotune");
+    best.tuned = 1;
     ps->line_cfg[std::make_pair(static_cast<int>(axis), cm)] = best;
     clear_graphs(ps);
     return BS_OK;
@@ -667,7 +668,7 @@ bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, 
     cfg_host[1] = c.Lmax;
     cfg_host[2] = c.tx;
     cfg_host[3] = c.grid;
-    cfg_host[4] = set ? 1 : 0;
+    cfg_host[4] = c.tuned;
     cfg_host[5] = c.form;
     return BS_OK;
 }
