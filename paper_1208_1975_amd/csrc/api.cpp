@@ -198,12 +198,12 @@ bs_status bs_create_patchset(int32_t npatch, const int32_t *dims_host, const dou
     bs_status st = build_tables(ps.get());
     if (st != BS_OK) return st;
 
-    // residual reduction plan: blocks of kResidCellsPerBlock cells, never spanning patches
+    // adjoint reduction plan: blocks of kBlockCells cells, never spanning patches
     std::vector<int32_t> bp, bf, pf(npatch + 1);
     for (int p = 0; p < npatch; ++p) {
         pf[p] = static_cast<int32_t>(bp.size());
         const int64_t nc = static_cast<int64_t>(ps->dims[3 * p]) * ps->dims[3 * p + 1] * ps->dims[3 * p + 2];
-        for (int64_t c = 0; c < nc; c += kResidCellsPerBlock) {
+        for (int64_t c = 0; c < nc; c += kBlockCells) {
             if (c > INT32_MAX) return fail(BS_ERR_UNSUPPORTED, "bs_create_patchset: patch too large");
             bp.push_back(p);
             bf.push_back(static_cast<int32_t>(c));
@@ -214,7 +214,27 @@ bs_status bs_create_patchset(int32_t npatch, const int32_t *dims_host, const dou
     if ((st = upload(ps->rblock_patch_d, bp.data(), bp.size() * 4, "residual plan")) != BS_OK) return st;
     if ((st = upload(ps->rblock_first_d, bf.data(), bf.size() * 4, "residual plan")) != BS_OK) return st;
     if ((st = upload(ps->rpatch_first_d, pf.data(), pf.size() * 4, "residual plan")) != BS_OK) return st;
-    if ((st = dev_alloc(ps->rpartial_d, bp.size() * 8, "residual partials")) != BS_OK) return st;
+    // residual tiles: tx x ty columns (tx the power of two in [1, 64] nearest
+    // above nx, ty = 256 / tx) by kResidPlanes planes, in patch order
+    std::vector<ResidTile> tl;
+    std::vector<int32_t> tf(npatch + 1);
+    for (int p = 0; p < npatch; ++p) {
+        tf[p] = static_cast<int32_t>(tl.size());
+        const int nx = ps->dims[3 * p], ny = ps->dims[3 * p + 1], nz = ps->dims[3 * p + 2];
+        int tx = 64;
+        while (tx > 1 && (tx >> 1) >= nx) tx >>= 1;
+        const int ty = 256 / tx;
+        for (int z0 = 0; z0 < nz; z0 += kResidPlanes)
+            for (int y0 = 0; y0 < ny; y0 += ty)
+                for (int x0 = 0; x0 < nx; x0 += tx) tl.push_back(ResidTile{p, x0, y0, z0});
+    }
+    tf[npatch] = static_cast<int32_t>(tl.size());
+    if (tl.size() > static_cast<size_t>(INT32_MAX)) return fail(BS_ERR_UNSUPPORTED, "bs_create_patchset: too many tiles");
+    ps->nrtiles = static_cast<int32_t>(tl.size());
+    if ((st = upload(ps->rtile_d, tl.data(), tl.size() * sizeof(ResidTile), "residual tiles")) != BS_OK) return st;
+    if ((st = upload(ps->rtile_first_d, tf.data(), tf.size() * 4, "residual tiles")) != BS_OK) return st;
+    const size_t npart = std::max(bp.size(), tl.size());
+    if ((st = dev_alloc(ps->rpartial_d, npart * 8, "residual partials")) != BS_OK) return st;
     *out = ps.release();
     return BS_OK;
 }
@@ -260,12 +280,11 @@ bs_status bs_residual(const bs_patchset *ps, const double *u, const double *f, d
     a.r = r;
     a.partial = rnorm2 ? static_cast<double *>(ps->rpartial_d.p) : nullptr;
     a.pd = static_cast<const PatchDesc *>(ps->desc_d.p);
-    a.block_patch = static_cast<const int32_t *>(ps->rblock_patch_d.p);
-    a.block_first = static_cast<const int32_t *>(ps->rblock_first_d.p);
-    hipError_t e = launch_residual(a, ps->nrblocks, stream);
+    a.tiles = static_cast<const ResidTile *>(ps->rtile_d.p);
+    hipError_t e = launch_residual(a, ps->nrtiles, stream);
     if (e != hipSuccess) return hip_fail(e, "residual kernel");
     if (rnorm2) {
-        e = launch_residual_final(a.partial, static_cast<const int32_t *>(ps->rpatch_first_d.p), ps->npatch,
+        e = launch_residual_final(a.partial, static_cast<const int32_t *>(ps->rtile_first_d.p), ps->npatch,
                                   rnorm2, stream);
         if (e != hipSuccess) return hip_fail(e, "residual reduction kernel");
     }

@@ -71,14 +71,20 @@ struct LineArgs {
     int32_t f32;            // 1: block solve in FP32 (residual and update stay FP64)
 };
 
+// Residual tile (one workgroup): columns x0.., y0.. of a patch marched along
+// z over planes z0 .. z0 + kResidPlanes - 1 (clipped).
+struct ResidTile {
+    int32_t patch, x0, y0, z0;
+};
+constexpr int kResidPlanes = 32;
+
 struct ResidArgs {
     const double *u;
     const double *f;
     double *r;              // may be null
-    double *partial;        // per-block partial sums (may be null)
+    double *partial;        // per-tile partial sums of r^2 (may be null)
     const PatchDesc *pd;
-    const int32_t *block_patch;   // block -> patch
-    const int32_t *block_first;   // block -> first cell (within its patch)
+    const ResidTile *tiles;
     float *e32;                   // optional FP32 copy of r (f layout), may be null
     unsigned short *e16;          // optional BF16 copy of r (bit patterns), may be null
 };
@@ -89,7 +95,7 @@ hipError_t launch_line_strided(const LineArgs &a, int grid, int Lmax, int nwaves
 hipError_t launch_line_x(const LineArgs &a, int grid, int Lmax, int nwaves, size_t lds, hipStream_t s);
 hipError_t launch_line_xr(const LineArgs &a, int grid, int nwaves, hipStream_t s);
 hipError_t prepare_line_kernels();
-hipError_t launch_residual(const ResidArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_residual(const ResidArgs &a, int ntiles, hipStream_t s);
 hipError_t launch_residual_final(const double *partial, const int32_t *patch_first_block,
                                  int npatch, double *out, hipStream_t s);
 hipError_t launch_ghost_copy(const double *src, double *dst, const PatchDesc *pd, int npatch,
@@ -97,7 +103,29 @@ hipError_t launch_ghost_copy(const double *src, double *dst, const PatchDesc *pd
 hipError_t launch_interior_copy(const double *src, double *dst, const PatchDesc *pd, int npatch,
                                 hipStream_t s);
 
-constexpr int kResidCellsPerBlock = 2048;   // cells per residual block (256 threads x 8)
+constexpr int kBlockCells = 2048;   // cells per block of the adjoint's reductions (256 threads x 8)
+
+// n / d for 0 <= n < 2^31 and d >= 1, given rd = 1.0 / d: the double product
+// is within 1e-6 of the quotient, so one correction step makes it exact (a
+// 32-bit integer division is some forty instructions on the GPU).
+__device__ __forceinline__ int div_rd(int n, int d, double rd)
+{
+    int q = static_cast<int>(static_cast<double>(n) * rd);
+    const int r = n - q * d;
+    q += r >= d ? 1 : 0;
+    q -= r < 0 ? 1 : 0;
+    return q;
+}
+
+// Logical block of workgroup b out of nb: the hardware hands workgroup b to
+// XCD b mod 8, so each XCD receives a contiguous range of logical blocks and
+// neighbouring cells share that XCD's L2.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int full = nb & ~7;
+    if (b >= full) return b;
+    return (b & 7) * (full >> 3) + (b >> 3);
+}
 
 // Adjoint of damped Jacobi line sweeps (k_adjoint.hip).
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);

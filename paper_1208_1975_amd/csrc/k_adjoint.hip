@@ -29,7 +29,7 @@ struct AdjArgs {
 };
 
 constexpr int kAdjThreads = 256;
-constexpr int kAdjPerThread = kResidCellsPerBlock / kAdjThreads;
+constexpr int kAdjPerThread = kBlockCells / kAdjThreads;
 
 __global__ void __launch_bounds__(256) k_fill(double *x, int64_t n, double v)
 {
@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(256) k_adj_init(const double *gK, double *gbar
 __global__ void __launch_bounds__(kAdjThreads) k_adj_step(AdjArgs a)
 {
     __shared__ double red[3][kAdjThreads];
-    const int b = blockIdx.x;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
     const PatchDesc *pd = a.pd + a.block_patch[b];
     const int nx = pd->n[0], ny = pd->n[1], nz = pd->n[2];
     const int ncell = nx * ny * nz;
@@ -63,11 +63,12 @@ __global__ void __launch_bounds__(kAdjThreads) k_adj_step(AdjArgs a)
     const int64_t st[3] = {1, sx, sy};
     const int first = a.block_first[b];
     const double om = a.omega;
+    const double rnx = 1.0 / nx, rny = 1.0 / ny;
     double part[3] = {0.0, 0.0, 0.0};
     for (int m = 0; m < kAdjPerThread; ++m) {
         const int cf = first + m * kAdjThreads + (int)threadIdx.x;
         if (cf >= ncell) break;
-        const int i = cf % nx, jk = cf / nx, j = jk % ny, k = jk / ny;
+        const int jk = div_rd(cf, nx, rnx), i = cf - jk * nx, k = div_rd(jk, ny, rny), j = jk - k * ny;
         const int64_t c = pd->uoff + (int64_t)(k + 1) * sy + (int64_t)(j + 1) * sx + (i + 1);
         const double l = a.lam[c];
         double al = 0.0;

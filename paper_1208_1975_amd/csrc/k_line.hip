@@ -450,6 +450,7 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const float *__re
     const int Lr = tr.Lr, P = tr.P, Llast = tr.Llast;
     const int tsz = line_table_size(Lr, P);
     const int sd = nx | 1;                 // odd row stride in LDS (bank spread)
+    const double rnx = 1.0 / nx;
     const int nw = blockDim.x >> 6;
 
     double *tab = smem;
@@ -491,7 +492,7 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const float *__re
         for (int m = 0; m < 4; ++m) {
             const int idx = i0 + m * (int)blockDim.x;
             const int idc = idx < ncell ? idx : ncell - 1;
-            const int row = idc / nx, i = idc - row * nx;
+            const int row = div_rd(idc, nx, rnx), i = idc - row * nx;
             const int64_t bu = rowu[row];
             at[m] = (idx < ncell && bu >= 0) ? row * sd + i : -1;
             const int64_t c = (bu >= 0 ? bu : safe_u) + i;
@@ -600,7 +601,7 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const float *__re
         for (int m = 0; m < 4; ++m) {
             const int idx = i0 + m * (int)blockDim.x;
             const int idc = idx < ncell ? idx : ncell - 1;
-            const int row = idc / nx, i = idc - row * nx;
+            const int row = div_rd(idc, nx, rnx), i = idc - row * nx;
             const int64_t bu = rowu[row];
             dst[m] = (idx < ncell && bu >= 0) ? bu + i : -1;
             val[m] = a.out_mode ? rb[row * sd + i] : fma(om, rb[row * sd + i], s[(bu >= 0 ? bu : safe_u) + i]);

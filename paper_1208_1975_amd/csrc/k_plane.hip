@@ -150,30 +150,48 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
     }
 
     // D layout of the FP64 16x16 block: register r of a lane holds row
-    // 4*r + lane/16, column lane%16 (checked by the layout test)
+    // 4*r + lane/16, column lane%16 (checked by the layout test).  Per block,
+    // the values the four outputs of a lane read (scale or u) are loaded
+    // before any of their stores, so they are in flight together.
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
+            double in[4];
+            bool ok[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int pr = m0 + wm * 64 + i * 16 + r * 4 + lk;
                 const int pcl = n0 + wn * 32 + j * 16 + l16;
-                if (pr >= g.M || pcl >= g.N) continue;
+                bool o = pr < g.M && pcl < g.N;
+                const int row = o ? (g.row_s ? pr * g.row_s + g.row_o : pr) : 0;
+                const int col = o ? (g.row_s ? pcl * g.col_s + g.col_o : pcl) : 0;
+                if (EPI == kEpiUpdate) o = o && !(g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour);
+                ok[r] = o;
+                in[r] = 0.0;
+                if (EPI == kEpiScale)
+                    in[r] = g.scale[(int64_t)b * g.sc_b + (int64_t)(o ? row : 0) * g.sc_m + (int64_t)(o ? col : 0) * g.sc_n];
+                if (EPI == kEpiUpdate)
+                    in[r] = g.usrc[g.u0 + (int64_t)b * g.u_b + (int64_t)(o ? row : 0) * g.u_m + (int64_t)(o ? col : 0) * g.u_n];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!ok[r]) continue;
+                const int pr = m0 + wm * 64 + i * 16 + r * 4 + lk;
+                const int pcl = n0 + wn * 32 + j * 16 + l16;
                 const int row = g.row_s ? pr * g.row_s + g.row_o : pr;
                 const int col = g.row_s ? pcl * g.col_s + g.col_o : pcl;
                 const double v = acc[i][j][r];
                 if (EPI == kEpiStore) {
                     g.C[(int64_t)b * g.sC + (int64_t)row * g.ldc + col] = v;
                 } else if (EPI == kEpiScale) {
-                    const double s = g.scale[(int64_t)b * g.sc_b + (int64_t)row * g.sc_m + (int64_t)col * g.sc_n];
-                    g.C[(int64_t)b * g.sC + (int64_t)row * g.ldc + col] = v * s;
+                    g.C[(int64_t)b * g.sC + (int64_t)row * g.ldc + col] = v * in[r];
                 } else {
-                    if (g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour) continue;
                     const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
-                    g.udst[u] = fma(g.omega, v, g.usrc[u]);
+                    g.udst[u] = fma(g.omega, v, in[r]);
                 }
             }
+        }
 }
 
 template <int BT, int FOLD>

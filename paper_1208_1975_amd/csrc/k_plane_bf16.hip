@@ -57,7 +57,7 @@ __device__ __forceinline__ uint4 load8(const u16 *row, int c0, int lim, bool vec
 }  // namespace
 
 template <int EPI, int BT>
-__global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_gemm_bf16(GemmBf16Args g)
 {
     __shared__ __attribute__((aligned(16))) u16 As[2][TM * PK];
     __shared__ __attribute__((aligned(16))) u16 Bs[2][TN * PK];
@@ -175,30 +175,57 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
             }
         return;
     }
+    // The four outputs of a lane in one 16 x 16 block at a time: every value
+    // they read (scale, D, u) is loaded before any of their stores, so those
+    // loads are in flight together instead of one round trip per element.
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int jh = 0; jh < 4; ++jh) {
+            double in1[1][4], in2[1][4];
+            bool ok[1][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 64 + i * 16 + 4 * lk + r;
-                const int col = n0 + wn * 64 + j * 16 + l16;
-                if (row >= g.M || col >= g.N) continue;
-                const float v = acc[i][j][r];
-                const int64_t ci = (int64_t)b * g.sC + (int64_t)row * g.ldc + col;
-                if (EPI == kEpiStore) {
-                    g.C[ci] = to_bf16(v);
-                } else if (EPI == kEpiScale) {
-                    g.C[ci] = to_bf16(v * g.scale[(int64_t)b * g.sc_b + (int64_t)row * g.sc_m + (int64_t)col * g.sc_n]);
-                } else if (EPI == kEpiD64) {
-                    g.D[ci] = g.accumulate ? g.D[ci] + (double)v : (double)v;
-                } else {
-                    if (g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour) continue;
-                    const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
-                    const double du = EPI == kEpiUpdateAcc ? g.D[ci] + (double)v : (double)v;
-                    g.udst[u] = fma(g.omega, du, g.usrc[u]);
+            for (int jj = 0; jj < 1; ++jj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + wm * 64 + i * 16 + 4 * lk + r;
+                    const int col = n0 + wn * 64 + (jh + jj) * 16 + l16;
+                    bool o = row < g.M && col < g.N;
+                    if (EPI == kEpiUpdate || EPI == kEpiUpdateAcc)
+                        o = o && !(g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour);
+                    ok[jj][r] = o;
+                    const int rr = o ? row : 0, cc = o ? col : 0;   // in-range addresses for every lane
+                    const int64_t ci = (int64_t)b * g.sC + (int64_t)rr * g.ldc + cc;
+                    in1[jj][r] = 0.0;
+                    in2[jj][r] = 0.0;
+                    if (EPI == kEpiScale)
+                        in1[jj][r] = g.scale[(int64_t)b * g.sc_b + (int64_t)rr * g.sc_m + (int64_t)cc * g.sc_n];
+                    if (EPI == kEpiUpdateAcc || (EPI == kEpiD64 && g.accumulate)) in1[jj][r] = g.D[ci];
+                    if (EPI == kEpiUpdate || EPI == kEpiUpdateAcc)
+                        in2[jj][r] = g.usrc[g.u0 + (int64_t)b * g.u_b + (int64_t)rr * g.u_m + (int64_t)cc * g.u_n];
                 }
-            }
+#pragma unroll
+            for (int jj = 0; jj < 1; ++jj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (!ok[jj][r]) continue;
+                    const int row = m0 + wm * 64 + i * 16 + 4 * lk + r;
+                    const int col = n0 + wn * 64 + (jh + jj) * 16 + l16;
+                    const float v = acc[i][jh + jj][r];
+                    const int64_t ci = (int64_t)b * g.sC + (int64_t)row * g.ldc + col;
+                    if (EPI == kEpiStore) {
+                        g.C[ci] = to_bf16(v);
+                    } else if (EPI == kEpiScale) {
+                        g.C[ci] = to_bf16(v * static_cast<float>(in1[jj][r]));
+                    } else if (EPI == kEpiD64) {
+                        g.D[ci] = g.accumulate ? in1[jj][r] + (double)v : (double)v;
+                    } else {
+                        const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
+                        const double du = EPI == kEpiUpdateAcc ? in1[jj][r] + (double)v : (double)v;
+                        g.udst[u] = fma(g.omega, du, in2[jj][r]);
+                    }
+                }
+        }
 }
 
 template <int BT>

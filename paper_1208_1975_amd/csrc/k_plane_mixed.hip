@@ -114,31 +114,52 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
     }
 
     // D layout of the FP32 16x16 block: register r of a lane holds row
-    // 4*(lane/16) + r, column lane%16 (checked by the layout test)
+    // 4*(lane/16) + r, column lane%16 (checked by the layout test).  Per block,
+    // the values the four outputs of a lane read (scale, D, u) are loaded
+    // before any of their stores, so they are in flight together.
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
+            double in1[4], in2[4];
+            bool ok[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm * 32 + i * 16 + (g.dlayout ? r * 4 + lk : lk * 4 + r);
                 const int col = n0 + wn * 32 + j * 16 + l16;
-                if (row >= g.M || col >= g.N) continue;
+                bool o = row < g.M && col < g.N;
+                if (EPI == kEpiUpdate || EPI == kEpiUpdateAcc)
+                    o = o && !(g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour);
+                ok[r] = o;
+                const int rr = o ? row : 0, cc = o ? col : 0;   // in-range addresses for every lane
+                const int64_t ci = (int64_t)b * g.sC + (int64_t)rr * g.ldc + cc;
+                in1[r] = 0.0;
+                in2[r] = 0.0;
+                if (EPI == kEpiScale) in1[r] = g.scale[(int64_t)b * g.sc_b + (int64_t)rr * g.sc_m + (int64_t)cc * g.sc_n];
+                if (EPI == kEpiUpdateAcc || (EPI == kEpiD64 && g.accumulate)) in1[r] = g.D[ci];
+                if (EPI == kEpiUpdate || EPI == kEpiUpdateAcc)
+                    in2[r] = g.usrc[g.u0 + (int64_t)b * g.u_b + (int64_t)rr * g.u_m + (int64_t)cc * g.u_n];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!ok[r]) continue;
+                const int row = m0 + wm * 32 + i * 16 + (g.dlayout ? r * 4 + lk : lk * 4 + r);
+                const int col = n0 + wn * 32 + j * 16 + l16;
                 const float v = acc[i][j][r];
                 const int64_t ci = (int64_t)b * g.sC + (int64_t)row * g.ldc + col;
                 if (EPI == kEpiStore) {
                     g.C[ci] = v;
                 } else if (EPI == kEpiScale) {
-                    g.C[ci] = v * g.scale[(int64_t)b * g.sc_b + (int64_t)row * g.sc_m + (int64_t)col * g.sc_n];
+                    g.C[ci] = v * static_cast<float>(in1[r]);
                 } else if (EPI == kEpiD64) {
-                    g.D[ci] = g.accumulate ? g.D[ci] + (double)v : (double)v;
+                    g.D[ci] = g.accumulate ? in1[r] + (double)v : (double)v;
                 } else {
-                    if (g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour) continue;
                     const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
-                    const double du = EPI == kEpiUpdateAcc ? g.D[ci] + (double)v : (double)v;
-                    g.udst[u] = fma(g.omega, du, g.usrc[u]);
+                    const double du = EPI == kEpiUpdateAcc ? in1[r] + (double)v : (double)v;
+                    g.udst[u] = fma(g.omega, du, in2[r]);
                 }
             }
+        }
 }
 
 __device__ __forceinline__ void put_lowp(float *E, int64_t c, double v) { E[c] = (float)v; }
@@ -155,14 +176,16 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_plane_defect(const double *R, const double *D, T *E, int nx, int ny,
                                                       int nz, int normal, double ex, double ey, double ez)
 {
-    const int64_t n = (int64_t)nx * ny * nz;
+    const int n = nx * ny * nz;   // < 2^31: patches are below 4 GiB
     const double d = 2.0 * (ex + ey + ez);
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+    const double rnx = 1.0 / nx, rny = 1.0 / ny;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
         double v = R[c];
         if (D) {
-            const int i = (int)(c % nx);
-            const int j = (int)((c / nx) % ny);
-            const int k = (int)(c / ((int64_t)nx * ny));
+            const int jk = div_rd(c, nx, rnx);
+            const int i = c - jk * nx;
+            const int k = div_rd(jk, ny, rny);
+            const int j = jk - k * ny;
             double md = d * D[c];
             if (normal != 0) {
                 if (i > 0) md -= ex * D[c - 1];

@@ -6,55 +6,86 @@
 namespace bs {
 
 constexpr int kResidThreads = 256;
-constexpr int kResidPerThread = kResidCellsPerBlock / kResidThreads;
 
-// Block b covers cells [first, first + 2048) of patch block_patch[b] in f order.
+// Value of lane l-1 (DIR < 0) or l+1 (DIR > 0) of the wavefront (DPP wave shift).
+template <int DIR>
+__device__ __forceinline__ double wave_nb(double v)
+{
+    constexpr int ctrl = DIR < 0 ? 0x138 : 0x130;   // wave_shr:1 / wave_shl:1
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// One tile: a workgroup of tx x ty columns (tx lanes along x, tx the power of
+// two in [1, 64] nearest above nx, ty = 256 / tx) marched along z.  The z
+// neighbours stay in registers (each u plane is read once per tile, plus one
+// halo plane on each side), the x neighbours come from the adjacent lanes
+// (DPP), except at a row's ends, which load theirs, and every load of the
+// next plane (centre u two planes ahead, f, the y-neighbour rows, the row-end
+// x values) is issued one step ahead.  The tile's sum of r^2 is accumulated
+// per thread in increasing z and reduced in a fixed tree: the norm is
+// bit-reproducible.
 __global__ void __launch_bounds__(kResidThreads) k_residual(ResidArgs a)
 {
     __shared__ double red[kResidThreads];
-    const int b = blockIdx.x;
-    const PatchDesc *pd = a.pd + a.block_patch[b];
+    const int b = xcd_block(blockIdx.x, gridDim.x);   // tiles in patch, z, y, x order: an XCD gets a contiguous run
+    const ResidTile t = a.tiles[b];
+    const PatchDesc *pd = a.pd + t.patch;
     const int nx = pd->n[0], ny = pd->n[1], nz = pd->n[2];
-    const int64_t ncell = (int64_t)nx * ny * nz;
-    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2);
+    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2), pf = (int64_t)nx * ny;
     const double ex = pd->eps[0], ey = pd->eps[1], ez = pd->eps[2];
-    const double d = 2.0 * (ex + ey + ez);
-    const int first = a.block_first[b];
-    const int ncell32 = (int)ncell;
-    const double *u = a.u;
+    const double d = 2.0 * (ex + ey + ez), h2 = pd->h2;
+    int tx = 64;
+    while (tx > 1 && (tx >> 1) >= nx) tx >>= 1;
+    const int li = (int)(threadIdx.x & (tx - 1));
+    const int i = t.x0 + li;
+    const int j = t.y0 + (int)(threadIdx.x / tx);
+    const bool valid = i < nx && j < ny;
+    const int ic = i < nx ? i : nx - 1, jc = j < ny ? j : ny - 1;   // in-patch addresses for every lane
+    const bool need_l = li == 0, need_r = li == tx - 1 || i >= nx - 1;
+    const int64_t xo = need_l ? -1 : 1;                            // the row-end lane's own neighbour
+    const int k0 = t.z0, k1 = t.z0 + kResidPlanes < nz ? t.z0 + kResidPlanes : nz;
+    const double *u = a.u + pd->uoff + (int64_t)(jc + 1) * sx + (ic + 1);   // column (i, j), plane index k + 1
+    const int64_t fo = pd->foff + (int64_t)jc * nx + ic;                     // f / r column, plane index k
+    double uzm = u[(int64_t)k0 * sy];
+    double uc = u[(int64_t)(k0 + 1) * sy];
+    double uzp = u[(int64_t)(k0 + 2) * sy];
+    const double *u1 = u + (int64_t)(k0 + 1) * sy;
+    double fv = a.f[fo + (int64_t)k0 * pf];
+    double ym = u1[-sx], yp = u1[sx], xa = u1[xo], xb = tx == 1 ? u1[1] : 0.0;
     double acc = 0.0;
-    double rv[kResidPerThread];
-    int cfv[kResidPerThread];
-#pragma unroll
-    for (int m = 0; m < kResidPerThread; ++m) {
-        const int cf0 = first + m * kResidThreads + (int)threadIdx.x;
-        const int cf = cf0 < ncell32 ? cf0 : ncell32 - 1;      // clamped: loads need no branch
-        const int i = cf % nx;
-        const int jk = cf / nx;
-        const int j = jk % ny, k = jk / ny;
-        const int64_t c = pd->uoff + (int64_t)(k + 1) * sy + (int64_t)(j + 1) * sx + (i + 1);
-        const double nb = ex * (u[c - 1] + u[c + 1]) + ey * (u[c - sx] + u[c + sx]) + ez * (u[c - sy] + u[c + sy]);
-        const double r = fma(-d, u[c], fma(pd->h2, a.f[pd->foff + cf], nb));
-        rv[m] = r;
-        cfv[m] = cf0 < ncell32 ? cf : -1;
-        acc = cf0 < ncell32 ? fma(r, r, acc) : acc;
-    }
-    if (a.r) {
-#pragma unroll
-        for (int m = 0; m < kResidPerThread; ++m)
-            if (cfv[m] >= 0) a.r[pd->foff + cfv[m]] = rv[m];
-    }
-    // low-precision copies for the mixed plane solves (rounded from FP64)
-    if (a.e32) {
-#pragma unroll
-        for (int m = 0; m < kResidPerThread; ++m)
-            if (cfv[m] >= 0) a.e32[pd->foff + cfv[m]] = (float)rv[m];
-    }
-    if (a.e16) {
-#pragma unroll
-        for (int m = 0; m < kResidPerThread; ++m)
-            if (cfv[m] >= 0)
-                a.e16[pd->foff + cfv[m]] = __builtin_bit_cast(unsigned short, static_cast<__bf16>(rv[m]));
+    for (int k = k0; k < k1; ++k) {
+        // the next step's loads (clamped inside the patch on the last step)
+        const int kn = k + 1 < nz ? k + 1 : nz - 1;
+        const double *un = u + (int64_t)(kn + 1) * sy;
+        const double uzp_n = un[sy];
+        const double f_n = a.f[fo + (int64_t)kn * pf];
+        const double ym_n = un[-sx], yp_n = un[sx], xa_n = un[xo];
+        const double xb_n = tx == 1 ? un[1] : 0.0;
+        // the moves run under full EXEC: the empty asm pins their results
+        // before the selects, which the compiler may turn into branches
+        double dl = wave_nb<-1>(uc), dr = wave_nb<+1>(uc);
+        asm volatile("" : "+v"(dl), "+v"(dr));
+        const double left = need_l ? xa : dl;
+        const double right = need_r ? (need_l ? xb : xa) : dr;
+        const double nb = fma(ex, left + right, fma(ey, ym + yp, ez * (uzm + uzp)));
+        const double r = fma(-d, uc, fma(h2, fv, nb));
+        if (valid) {
+            const int64_t c = fo + (int64_t)k * pf;
+            if (a.r) a.r[c] = r;
+            if (a.e32) a.e32[c] = (float)r;
+            if (a.e16) a.e16[c] = __builtin_bit_cast(unsigned short, static_cast<__bf16>(r));
+            acc = fma(r, r, acc);
+        }
+        uzm = uc;
+        uc = uzp;
+        uzp = uzp_n;
+        fv = f_n;
+        ym = ym_n;
+        yp = yp_n;
+        xa = xa_n;
+        xb = xb_n;
     }
     if (!a.partial) return;
     red[threadIdx.x] = acc;
@@ -66,7 +97,7 @@ __global__ void __launch_bounds__(kResidThreads) k_residual(ResidArgs a)
     if (threadIdx.x == 0) a.partial[b] = red[0];
 }
 
-// One workgroup per patch: fixed-order sum of the patch's block partials.
+// One workgroup per patch: fixed-order sum of the patch's tile (or block) partials.
 __global__ void __launch_bounds__(256) k_residual_final(const double *partial, const int32_t *first_block,
                                                         double *out)
 {
@@ -127,9 +158,10 @@ __global__ void __launch_bounds__(256) k_interior_copy(const double *src, double
     }
 }
 
-hipError_t launch_residual(const ResidArgs &a, int nblocks, hipStream_t s)
+hipError_t launch_residual(const ResidArgs &a, int ntiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_residual, dim3(nblocks), dim3(kResidThreads), 0, s, a);
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_residual, dim3(ntiles), dim3(kResidThreads), 0, s, a);
     return hipGetLastError();
 }
 

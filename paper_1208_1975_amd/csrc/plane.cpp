@@ -399,9 +399,8 @@ bs_status residual_into_scratch(bs_patchset *ps, const double *u, const double *
     if (prec == BS_MIXED_BF16) a.e16 = static_cast<uint16_t *>(ps->plane_f1_d.p);
     a.partial = nullptr;
     a.pd = static_cast<const PatchDesc *>(ps->desc_d.p);
-    a.block_patch = static_cast<const int32_t *>(ps->rblock_patch_d.p);
-    a.block_first = static_cast<const int32_t *>(ps->rblock_first_d.p);
-    hipError_t e = launch_residual(a, ps->nrblocks, s);
+    a.tiles = static_cast<const ResidTile *>(ps->rtile_d.p);
+    hipError_t e = launch_residual(a, ps->nrtiles, s);
     if (e != hipSuccess) return hip_fail(e, "plane residual");
     return BS_OK;
 }
