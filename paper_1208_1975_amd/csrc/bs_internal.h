@@ -76,7 +76,7 @@ struct LineArgs {
 struct ResidTile {
     int32_t patch, x0, y0, z0;
 };
-constexpr int kResidPlanes = 32;
+constexpr int kResidPlanes = 64;
 
 struct ResidArgs {
     const double *u;
