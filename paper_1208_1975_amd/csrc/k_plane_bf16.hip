@@ -57,7 +57,7 @@ __device__ __forceinline__ uint4 load8(const u16 *row, int c0, int lim, bool vec
 }  // namespace
 
 template <int EPI, int BT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_gemm_bf16(GemmBf16Args g)
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
 {
     __shared__ __attribute__((aligned(16))) u16 As[2][TM * PK];
     __shared__ __attribute__((aligned(16))) u16 Bs[2][TN * PK];
