@@ -290,7 +290,12 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
                 const uint32_t tt = (uint32_t)(t < Lp ? t : Lp - 1);
                 const uint32_t c = cu + tt * Sa8;
                 ub4[k] = ldb(ub, c);
-                fb[k] = ldb(fbase, cf + tt * Fa8);
+                // Jacobi: f with a nontemporal load (measured 117 -> 102 us per
+                // 256^3 sweep; the in-place schemes are slower with it)
+                if constexpr (CM == 0)
+                    fb[k] = __builtin_nontemporal_load(reinterpret_cast<const double *>(fbase + (cf + tt * Fa8)));
+                else
+                    fb[k] = ldb(fbase, cf + tt * Fa8);
                 om[k] = ldb(ubm, c);
                 op[k] = ldb(ubp, c);
                 xa[k] = ldb(ub, c + xo);
