@@ -27,23 +27,18 @@ constexpr int kThreads = 512;   // eight wavefronts: 2 (rows) x 4 (columns) of 6
 
 }  // namespace
 
-// Two-element group of a row starting at column c0 (zero beyond `lim`); one
-// 16-byte load when aligned and inside.
-__device__ __forceinline__ double2 load2(const double *row, int c0, int lim, bool vec)
-{
-    if (vec && c0 + 2 <= lim) return *reinterpret_cast<const double2 *>(row + c0);
-    double2 r;
-    r.x = c0 < lim ? row[c0] : 0.0;
-    r.y = c0 + 1 < lim ? row[c0 + 1] : 0.0;
-    return r;
-}
-
 // A 128 x 128 block of C per workgroup (eight wavefronts, 64 x 32 each as
 // 4 x 2 blocks of 16 x 16: twice the flops per byte fetched from L2 of a
 // 64 x 64 block, which L2 bandwidth holds back); K advances BK at a time
 // through two LDS buffers, the next tile fetched into registers while the
 // current one feeds the matrix cores (one barrier per step).
-template <int EPI, int BT, int FOLD>
+//
+// Operand tiles are fetched branch-free: indices are clamped into range and
+// out-of-range values replaced by zero with selects, so all of a step's loads
+// are in flight together (conditional loads made the compiler wait for each
+// one in turn).  VEC: both operands' rows are 16-byte aligned with even
+// lengths (and an even folded axis), so pairs are single 16-byte loads.
+template <int EPI, int BT, int FOLD, bool VEC>
 __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) double As[2][BK][BM + 2];
@@ -56,8 +51,92 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w >> 2, wn = w & 3;
     const int l16 = lane & 15, lk = lane >> 4;
-    const bool avec = ((g.lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-    const bool bvec = ((g.ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    // Raw operand pairs of the next step are loaded in fetch (clamped, in-range
+    // addresses only) and completed in stash -- zeroed outside the operands,
+    // mirrored halves added -- so the loads stay in flight while the matrix
+    // cores work on the current step.
+    auto ld2 = [](const double *row, int c0, int lim) -> double2 {   // c0 even
+        if constexpr (VEC) {
+            return *reinterpret_cast<const double2 *>(row + (c0 < lim ? c0 : lim - 2));
+        } else {
+            double2 v;
+            v.x = row[c0 < lim ? c0 : lim - 1];
+            v.y = row[c0 + 1 < lim ? c0 + 1 : lim - 1];
+            return v;
+        }
+    };
+    auto keep = [](double2 v, int c0, int lim) -> double2 {
+        v.x = c0 < lim ? v.x : 0.0;
+        v.y = c0 + 1 < lim ? v.y : 0.0;
+        return v;
+    };
+    const int Kf = g.Kfull;
+    const double fs = (double)g.fsign;
+    double2 la[2], lb[2], lm[2];   // A pair, B pair, mirrored pair (A for FOLD 1, B for FOLD 2)
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + kThreads * q;
+            const int r = c >> 3, kc = (c & 7) * 2;
+            const int gr = m0 + r;
+            const double *arow = A + (int64_t)(gr < g.M ? gr : g.M - 1) * g.lda;
+            la[q] = ld2(arow, k0 + kc, g.K);
+            if (FOLD == 1) {
+                const int k1 = k0 + kc, k2 = k1 + 1;
+                if constexpr (VEC) {
+                    // mirrored pair (Kf-2-k1, Kf-1-k1): one aligned 16-byte load (even Kf has no middle)
+                    lm[q] = *reinterpret_cast<const double2 *>(arow + (Kf - 2 - (k1 < g.K ? k1 : g.K - 2)));
+                } else {
+                    lm[q].x = arow[Kf - 1 - (k1 < g.K ? k1 : g.K - 1)];
+                    lm[q].y = arow[Kf - 1 - (k2 < g.K ? k2 : g.K - 1)];
+                }
+            }
+            if (BT) {
+                const int gn = n0 + r;
+                lb[q] = ld2(B + (int64_t)(gn < g.N ? gn : g.N - 1) * g.ldb, k0 + kc, g.K);
+            } else {
+                const int kr = c >> 6, nc = (c & 63) * 2;
+                const int gk = k0 + kr, gkc = gk < g.K ? gk : g.K - 1;
+                lb[q] = ld2(B + (int64_t)gkc * g.ldb, n0 + nc, g.N);
+                if (FOLD == 2) lm[q] = ld2(B + (int64_t)(Kf - 1 - gkc) * g.ldb, n0 + nc, g.N);
+            }
+        }
+    };
+    auto stash = [&](int buf, int k0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + kThreads * q;
+            const int r = c >> 3, kc = (c & 7) * 2;
+            const int gr = m0 + r;
+            const int k1 = k0 + kc, k2 = k1 + 1;
+            double2 a2 = keep(la[q], k1, g.K);
+            if (FOLD == 1) {
+                const double mx = VEC ? lm[q].y : lm[q].x, my = VEC ? lm[q].x : lm[q].y;
+                a2.x = (k1 < g.K && Kf - 1 - k1 != k1) ? fma(fs, mx, a2.x) : a2.x;
+                a2.y = (k2 < g.K && Kf - 1 - k2 != k2) ? fma(fs, my, a2.y) : a2.y;
+            }
+            As[buf][kc][r] = gr < g.M ? a2.x : 0.0;
+            As[buf][kc + 1][r] = gr < g.M ? a2.y : 0.0;
+            if (BT) {
+                const int gn = n0 + r;
+                const double2 b2 = keep(lb[q], k1, g.K);
+                Bs[buf][kc][r] = gn < g.N ? b2.x : 0.0;
+                Bs[buf][kc + 1][r] = gn < g.N ? b2.y : 0.0;
+            } else {
+                const int kr = c >> 6, nc = (c & 63) * 2;
+                const int gk = k0 + kr;
+                double2 b2 = keep(lb[q], n0 + nc, g.N);
+                if (FOLD == 2) {
+                    const double2 m = keep(lm[q], n0 + nc, g.N);
+                    const bool use = Kf - 1 - gk != gk;
+                    b2.x = use ? fma(fs, m.x, b2.x) : b2.x;
+                    b2.y = use ? fma(fs, m.y, b2.y) : b2.y;
+                }
+                Bs[buf][kr][nc] = gk < g.K ? b2.x : 0.0;
+                Bs[buf][kr][nc + 1] = gk < g.K ? b2.y : 0.0;
+            }
+        }
+    };
 
     dbl4 acc[4][2];
 #pragma unroll
@@ -65,69 +144,9 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    // A tile BM x BK: pair c -> row c / 8, k offset (c % 8) * 2 (two pairs a
-    // thread); B tile BK x BN: pair c -> k row c / 64, n offset (c % 64) * 2,
-    // or with b_trans n row c / 8, k offset (c % 8) * 2.  Folded operands add
-    // the mirrored entry (k -> Kfull-1-k) with sign fsign.
-    const int Kf = g.Kfull;
-    const double fs = (double)g.fsign;
-    double2 ra[2], rb[2];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + kThreads * q;
-            const int r = c >> 3, kc = (c & 7) * 2;
-            const int gr = m0 + r;
-            const double *arow = A + (int64_t)gr * g.lda;
-            ra[q] = gr < g.M ? load2(arow, k0 + kc, g.K, avec) : double2{0.0, 0.0};
-            if (FOLD == 1 && gr < g.M) {
-                const int k1 = k0 + kc, k2 = k1 + 1;
-                if (avec && !(Kf & 1) && k2 < g.K) {
-                    // mirrored pair (Kf-2-k1, Kf-1-k1): one aligned 16-byte load (even Kf has no middle)
-                    const double2 m = *reinterpret_cast<const double2 *>(arow + (Kf - 2 - k1));
-                    ra[q].x = fma(fs, m.y, ra[q].x);
-                    ra[q].y = fma(fs, m.x, ra[q].y);
-                } else {
-                    if (k1 < g.K && Kf - 1 - k1 != k1) ra[q].x = fma(fs, arow[Kf - 1 - k1], ra[q].x);
-                    if (k2 < g.K && Kf - 1 - k2 != k2) ra[q].y = fma(fs, arow[Kf - 1 - k2], ra[q].y);
-                }
-            }
-            if (BT) {
-                const int gn = n0 + r;
-                rb[q] = gn < g.N ? load2(B + (int64_t)gn * g.ldb, k0 + kc, g.K, bvec) : double2{0.0, 0.0};
-            } else {
-                const int kr = c >> 6, nc = (c & 63) * 2;
-                const int gk = k0 + kr;
-                rb[q] = gk < g.K ? load2(B + (int64_t)gk * g.ldb, n0 + nc, g.N, bvec) : double2{0.0, 0.0};
-                if (FOLD == 2 && gk < g.K && Kf - 1 - gk != gk) {
-                    const double2 m = load2(B + (int64_t)(Kf - 1 - gk) * g.ldb, n0 + nc, g.N, bvec);
-                    rb[q].x = fma(fs, m.x, rb[q].x);
-                    rb[q].y = fma(fs, m.y, rb[q].y);
-                }
-            }
-        }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + kThreads * q;
-            const int r = c >> 3, kc = (c & 7) * 2;
-            As[buf][kc][r] = ra[q].x;
-            As[buf][kc + 1][r] = ra[q].y;
-            if (BT) {
-                Bs[buf][kc][r] = rb[q].x;
-                Bs[buf][kc + 1][r] = rb[q].y;
-            } else {
-                const int kr = c >> 6, nc = (c & 63) * 2;
-                Bs[buf][kr][nc] = rb[q].x;
-                Bs[buf][kr][nc + 1] = rb[q].y;
-            }
-        }
-    };
-
     const int nk = (g.K + BK - 1) / BK;
     fetch(0);
-    stash(0);
+    stash(0, 0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
@@ -145,7 +164,7 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
-        if (kt + 1 < nk) stash(cur ^ 1);
+        if (kt + 1 < nk) stash(cur ^ 1, (kt + 1) * BK);
         __syncthreads();
     }
 
@@ -194,17 +213,29 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
         }
 }
 
-template <int BT, int FOLD>
-static hipError_t launch_f64_t(const GemmArgs &g, int epi, hipStream_t s)
+template <int BT, int FOLD, bool VEC>
+static hipError_t launch_f64_v(const GemmArgs &g, int epi, hipStream_t s)
 {
     const dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
     switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL((k_gemm_f64<kEpiStore, BT, FOLD>), grid, dim3(kThreads), 0, s, g); break;
-    case kEpiScale: hipLaunchKernelGGL((k_gemm_f64<kEpiScale, BT, FOLD>), grid, dim3(kThreads), 0, s, g); break;
-    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_f64<kEpiUpdate, BT, FOLD>), grid, dim3(kThreads), 0, s, g); break;
+    case kEpiStore: hipLaunchKernelGGL((k_gemm_f64<kEpiStore, BT, FOLD, VEC>), grid, dim3(kThreads), 0, s, g); break;
+    case kEpiScale: hipLaunchKernelGGL((k_gemm_f64<kEpiScale, BT, FOLD, VEC>), grid, dim3(kThreads), 0, s, g); break;
+    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_f64<kEpiUpdate, BT, FOLD, VEC>), grid, dim3(kThreads), 0, s, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int BT, int FOLD>
+static hipError_t launch_f64_t(const GemmArgs &g, int epi, hipStream_t s)
+{
+    // 16-byte pairs: aligned operand bases and row strides, even row lengths
+    // (K for A and for B given [n][k], N for B given [k][n]) and, for A's
+    // mirrored pairs, an even folded axis; every batch stride keeps alignment
+    const bool vec = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0) &&
+                     g.lda % 2 == 0 && g.ldb % 2 == 0 && g.sA % 2 == 0 && g.sB % 2 == 0 && g.K % 2 == 0 &&
+                     (BT || g.N % 2 == 0) && (FOLD != 1 || g.Kfull % 2 == 0) && g.K >= 2 && (BT || g.N >= 2);
+    return vec ? launch_f64_v<BT, FOLD, true>(g, epi, s) : launch_f64_v<BT, FOLD, false>(g, epi, s);
 }
 
 hipError_t launch_gemm_f64(const GemmArgs &g, int epi, hipStream_t s)
