@@ -38,25 +38,14 @@ __device__ __forceinline__ u16 to_bf16(float v)
     return __builtin_bit_cast(u16, h);
 }
 
-// Eight consecutive BF16 of a row starting at column c0 (zero beyond `lim`);
-// `vec` allows one 16-byte load when the whole group is inside.
-__device__ __forceinline__ uint4 load8(const u16 *row, int c0, int lim, bool vec)
-{
-    if (vec && c0 + 8 <= lim) return *reinterpret_cast<const uint4 *>(row + c0);
-    u16 v[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (c0 + e < lim) ? row[c0 + e] : (u16)0;
-    uint4 r;
-    r.x = v[0] | ((uint32_t)v[1] << 16);
-    r.y = v[2] | ((uint32_t)v[3] << 16);
-    r.z = v[4] | ((uint32_t)v[5] << 16);
-    r.w = v[6] | ((uint32_t)v[7] << 16);
-    return r;
-}
-
 }  // namespace
 
-template <int EPI, int BT>
+// Operand chunks are loaded branch-free into registers (clamped, in-range
+// addresses) and completed in stash (zeroed outside the operands), so the
+// next step's loads stay in flight while the matrix cores work on the current
+// one.  VEC: every row 16-byte aligned and every row length a multiple of 8,
+// so a chunk is one 16-byte load.
+template <int EPI, int BT, bool VEC>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
 {
     __shared__ __attribute__((aligned(16))) u16 As[2][TM * PK];
@@ -69,8 +58,30 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int l16 = lane & 15, lk = lane >> 4;
-    const bool avec = ((g.lda & 7) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-    const bool bvec = ((g.ldb & 7) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    // eight consecutive entries c0.. c0 + 7 (c0 a multiple of 8) of a row of
+    // length lim, loaded from in-range addresses; keep8 zeroes those at or
+    // beyond lim
+    auto ld8 = [](const u16 *row, int c0, int lim) -> uint4 {
+        if constexpr (VEC) {
+            return *reinterpret_cast<const uint4 *>(row + (c0 < lim ? c0 : lim - 8));
+        } else {
+            u16 v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = row[c0 + e < lim ? c0 + e : lim - 1];
+            uint4 r;
+            r.x = v[0] | ((uint32_t)v[1] << 16);
+            r.y = v[2] | ((uint32_t)v[3] << 16);
+            r.z = v[4] | ((uint32_t)v[5] << 16);
+            r.w = v[6] | ((uint32_t)v[7] << 16);
+            return r;
+        }
+    };
+    auto keep8 = [](uint4 v, int c0, int lim) -> uint4 {
+        auto m = [&](int e) -> uint32_t {   // mask of the 32-bit word holding entries e, e + 1
+            return (c0 + e < lim ? 0xffffu : 0u) | (c0 + e + 1 < lim ? 0xffff0000u : 0u);
+        };
+        return uint4{v.x & m(0), v.y & m(2), v.z & m(4), v.w & m(6)};
+    };
 
     flt4 acc[4][4];
 #pragma unroll
@@ -87,28 +98,32 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
             const int c = tid + 256 * q;
             const int r = c >> 2, kc = (c & 3) * 8;
             const int gr = m0 + r;
-            ra[q] = gr < g.M ? load8(A + (int64_t)gr * g.lda, k0 + kc, g.K, avec) : uint4{0, 0, 0, 0};
+            ra[q] = ld8(A + (int64_t)(gr < g.M ? gr : g.M - 1) * g.lda, k0 + kc, g.K);
             if (BT) {
                 const int gn = n0 + r;
-                rb[q] = gn < g.N ? load8(B + (int64_t)gn * g.ldb, k0 + kc, g.K, bvec) : uint4{0, 0, 0, 0};
+                rb[q] = ld8(B + (int64_t)(gn < g.N ? gn : g.N - 1) * g.ldb, k0 + kc, g.K);
             } else {
                 const int kr = c >> 4, nc = (c & 15) * 8;
                 const int gk = k0 + kr;
-                rb[q] = gk < g.K ? load8(B + (int64_t)gk * g.ldb, n0 + nc, g.N, bvec) : uint4{0, 0, 0, 0};
+                rb[q] = ld8(B + (int64_t)(gk < g.K ? gk : g.K - 1) * g.ldb, n0 + nc, g.N);
             }
         }
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf, int k0) {
+        const uint4 z{0, 0, 0, 0};
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int c = tid + 256 * q;
             const int r = c >> 2, kc = (c & 3) * 8;
-            *reinterpret_cast<uint4 *>(&As[buf][r * PK + kc]) = ra[q];
+            const int gr = m0 + r;
+            *reinterpret_cast<uint4 *>(&As[buf][r * PK + kc]) = gr < g.M ? keep8(ra[q], k0 + kc, g.K) : z;
             if (BT) {
-                *reinterpret_cast<uint4 *>(&Bs[buf][r * PK + kc]) = rb[q];
+                const int gn = n0 + r;
+                *reinterpret_cast<uint4 *>(&Bs[buf][r * PK + kc]) = gn < g.N ? keep8(rb[q], k0 + kc, g.K) : z;
             } else {
                 const int kr = c >> 4, nc = (c & 15) * 8;
-                const uint32_t wv[4] = {rb[q].x, rb[q].y, rb[q].z, rb[q].w};
+                const uint4 v = (k0 + kr) < g.K ? keep8(rb[q], n0 + nc, g.N) : z;
+                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
                     Bs[buf][(nc + e) * PK + kr] = (u16)((wv[e >> 1] >> (16 * (e & 1))) & 0xffff);
@@ -118,7 +133,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
 
     const int nk = (g.K + TK - 1) / TK;
     fetch(0);
-    stash(0);
+    stash(0, 0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
@@ -135,7 +150,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-        if (kt + 1 < nk) stash(cur ^ 1);
+        if (kt + 1 < nk) stash(cur ^ 1, (kt + 1) * TK);
         __syncthreads();
     }
 
@@ -228,19 +243,30 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
         }
 }
 
-template <int BT>
-static hipError_t launch_bf16_t(const GemmBf16Args &g, int epi, hipStream_t s)
+template <int BT, bool VEC>
+static hipError_t launch_bf16_v(const GemmBf16Args &g, int epi, hipStream_t s)
 {
     const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, g.batch);
     switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL((k_gemm_bf16<kEpiStore, BT>), grid, dim3(256), 0, s, g); break;
-    case kEpiScale: hipLaunchKernelGGL((k_gemm_bf16<kEpiScale, BT>), grid, dim3(256), 0, s, g); break;
-    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdate, BT>), grid, dim3(256), 0, s, g); break;
-    case kEpiD64: hipLaunchKernelGGL((k_gemm_bf16<kEpiD64, BT>), grid, dim3(256), 0, s, g); break;
-    case kEpiUpdateAcc: hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdateAcc, BT>), grid, dim3(256), 0, s, g); break;
+    case kEpiStore: hipLaunchKernelGGL((k_gemm_bf16<kEpiStore, BT, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiScale: hipLaunchKernelGGL((k_gemm_bf16<kEpiScale, BT, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdate, BT, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiD64: hipLaunchKernelGGL((k_gemm_bf16<kEpiD64, BT, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdateAcc: hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdateAcc, BT, VEC>), grid, dim3(256), 0, s, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int BT>
+static hipError_t launch_bf16_t(const GemmBf16Args &g, int epi, hipStream_t s)
+{
+    // 16-byte chunks: aligned bases, strides that keep alignment, row lengths
+    // (K for A and for B given [n][k], N for B given [k][n]) multiples of 8
+    const bool vec = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0) &&
+                     g.lda % 8 == 0 && g.ldb % 8 == 0 && g.sA % 8 == 0 && g.sB % 8 == 0 && g.K % 8 == 0 &&
+                     (BT || g.N % 8 == 0);
+    return vec ? launch_bf16_v<BT, true>(g, epi, s) : launch_bf16_v<BT, false>(g, epi, s);
 }
 
 hipError_t launch_gemm_bf16(const GemmBf16Args &g, int b_trans, int epi, hipStream_t s)

@@ -21,24 +21,14 @@ constexpr int BM = 64, BN = 64, BK = 32;
 
 }  // namespace
 
-// Four consecutive floats of a row starting at column c0 (zero beyond `lim`);
-// one 16-byte load when aligned and inside.
-__device__ __forceinline__ float4 load4f(const float *row, int c0, int lim, bool vec)
-{
-    if (vec && c0 + 4 <= lim) return *reinterpret_cast<const float4 *>(row + c0);
-    float4 r;
-    r.x = c0 < lim ? row[c0] : 0.f;
-    r.y = c0 + 1 < lim ? row[c0 + 1] : 0.f;
-    r.z = c0 + 2 < lim ? row[c0 + 2] : 0.f;
-    r.w = c0 + 3 < lim ? row[c0 + 3] : 0.f;
-    return r;
-}
-
 // C_b = A_b B_b with FP32 operands (v_mfma_f32_16x16x4_f32), FP32
 // accumulation.  A 64 x 64 block of C per workgroup (four wavefronts, 32 x 32
 // each); K advances BK at a time through two LDS buffers, the next tile
 // fetched into registers while the current one feeds the matrix cores.
-template <int EPI>
+// The fetch is branch-free (clamped in-range addresses, zeroing deferred to
+// the LDS store), so those loads stay in flight during the products; VEC:
+// aligned rows whose lengths are multiples of 4, one 16-byte load per quad.
+template <int EPI, bool VEC>
 __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
 {
     __shared__ __attribute__((aligned(16))) float As[2][BK][BM + 4];
@@ -51,8 +41,25 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int l16 = lane & 15, lk = lane >> 4;
-    const bool avec = ((g.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-    const bool bvec = ((g.ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    auto ld4 = [](const float *row, int c0, int lim) -> float4 {   // c0 a multiple of 4
+        if constexpr (VEC) {
+            return *reinterpret_cast<const float4 *>(row + (c0 < lim ? c0 : lim - 4));
+        } else {
+            float4 v;
+            v.x = row[c0 < lim ? c0 : lim - 1];
+            v.y = row[c0 + 1 < lim ? c0 + 1 : lim - 1];
+            v.z = row[c0 + 2 < lim ? c0 + 2 : lim - 1];
+            v.w = row[c0 + 3 < lim ? c0 + 3 : lim - 1];
+            return v;
+        }
+    };
+    auto keep4 = [](float4 v, int c0, int lim, bool row_ok) -> float4 {
+        v.x = row_ok && c0 < lim ? v.x : 0.f;
+        v.y = row_ok && c0 + 1 < lim ? v.y : 0.f;
+        v.z = row_ok && c0 + 2 < lim ? v.z : 0.f;
+        v.w = row_ok && c0 + 3 < lim ? v.w : 0.f;
+        return v;
+    };
 
     flt4 acc[2][2];
 #pragma unroll
@@ -69,29 +76,30 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
             const int c = tid + 256 * q;
             const int r = c >> 3, kc = (c & 7) * 4;
             const int gr = m0 + r;
-            ra[q] = gr < g.M ? load4f(A + (int64_t)gr * g.lda, k0 + kc, g.K, avec) : float4{0.f, 0.f, 0.f, 0.f};
+            ra[q] = ld4(A + (int64_t)(gr < g.M ? gr : g.M - 1) * g.lda, k0 + kc, g.K);
             const int kr = c >> 4, nc = (c & 15) * 4;
             const int gk = k0 + kr;
-            rb[q] = gk < g.K ? load4f(B + (int64_t)gk * g.ldb, n0 + nc, g.N, bvec) : float4{0.f, 0.f, 0.f, 0.f};
+            rb[q] = ld4(B + (int64_t)(gk < g.K ? gk : g.K - 1) * g.ldb, n0 + nc, g.N);
         }
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf, int k0) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int c = tid + 256 * q;
             const int r = c >> 3, kc = (c & 7) * 4;
-            As[buf][kc][r] = ra[q].x;
-            As[buf][kc + 1][r] = ra[q].y;
-            As[buf][kc + 2][r] = ra[q].z;
-            As[buf][kc + 3][r] = ra[q].w;
+            const float4 a4 = keep4(ra[q], k0 + kc, g.K, m0 + r < g.M);
+            As[buf][kc][r] = a4.x;
+            As[buf][kc + 1][r] = a4.y;
+            As[buf][kc + 2][r] = a4.z;
+            As[buf][kc + 3][r] = a4.w;
             const int kr = c >> 4, nc = (c & 15) * 4;
-            *reinterpret_cast<float4 *>(&Bs[buf][kr][nc]) = rb[q];
+            *reinterpret_cast<float4 *>(&Bs[buf][kr][nc]) = keep4(rb[q], n0 + nc, g.N, k0 + kr < g.K);
         }
     };
 
     const int nk = (g.K + BK - 1) / BK;
     fetch(0);
-    stash(0);
+    stash(0, 0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
@@ -109,7 +117,7 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
-        if (kt + 1 < nk) stash(cur ^ 1);
+        if (kt + 1 < nk) stash(cur ^ 1, (kt + 1) * BK);
         __syncthreads();
     }
 
@@ -206,20 +214,29 @@ __global__ void __launch_bounds__(256) k_plane_defect(const double *R, const dou
     }
 }
 
+template <bool VEC>
+static hipError_t launch_mixed_v(const GemmMixedArgs &g, int epi, dim3 grid, hipStream_t s)
+{
+    switch (epi) {
+    case kEpiStore: hipLaunchKernelGGL((k_gemm_mixed<kEpiStore, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiScale: hipLaunchKernelGGL((k_gemm_mixed<kEpiScale, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdate, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiD64: hipLaunchKernelGGL((k_gemm_mixed<kEpiD64, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdateAcc: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdateAcc, VEC>), grid, dim3(256), 0, s, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStream_t s)
 {
     if (prec != 1) return hipErrorInvalidValue;
     if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
     const dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
-    switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL((k_gemm_mixed<kEpiStore>), grid, dim3(256), 0, s, g); break;
-    case kEpiScale: hipLaunchKernelGGL((k_gemm_mixed<kEpiScale>), grid, dim3(256), 0, s, g); break;
-    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdate>), grid, dim3(256), 0, s, g); break;
-    case kEpiD64: hipLaunchKernelGGL((k_gemm_mixed<kEpiD64>), grid, dim3(256), 0, s, g); break;
-    case kEpiUpdateAcc: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdateAcc>), grid, dim3(256), 0, s, g); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const bool vec = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0) &&
+                     g.lda % 4 == 0 && g.ldb % 4 == 0 && g.sA % 4 == 0 && g.sB % 4 == 0 && g.K % 4 == 0 &&
+                     g.N % 4 == 0;
+    return vec ? launch_mixed_v<true>(g, epi, grid, s) : launch_mixed_v<false>(g, epi, grid, s);
 }
 
 hipError_t launch_plane_defect(const double *R, const double *D, float *E, int nx, int ny, int nz, int normal,
