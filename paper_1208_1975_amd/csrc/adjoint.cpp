@@ -24,7 +24,7 @@ BackwardPlan plan_backward(const bs_patchset *ps, int K, int c)
     b.ncp = K > 0 ? (K + c - 1) / c : 1;
     b.nseg = std::max(0, std::min(c, K) - 1);
     b.state_bytes = (static_cast<size_t>(ps->u_numel) * sizeof(double) + 255) / 256 * 256;
-    b.acc_bytes = (static_cast<size_t>(ps->nrblocks) * 3 * sizeof(double) + 255) / 256 * 256;
+    b.acc_bytes = (static_cast<size_t>(ps->nrtiles) * 3 * sizeof(double) + 255) / 256 * 256;
     // checkpoints + segment states + lambda + w + gbar (when grad_u0 is not given) + accumulators
     b.total = static_cast<size_t>(b.ncp + b.nseg + 3) * b.state_bytes + b.acc_bytes;
     return b;
@@ -80,9 +80,8 @@ bs_status bs_relax_backward(bs_patchset *ps, int32_t axis, double omega, int32_t
     double *gbar = grad_u0 ? grad_u0 : gbar_ws;
 
     const PatchDesc *pdd = static_cast<const PatchDesc *>(ps->desc_d.p);
-    const int32_t *bpatch = static_cast<const int32_t *>(ps->rblock_patch_d.p);
-    const int32_t *bfirst = static_cast<const int32_t *>(ps->rblock_first_d.p);
-    const int32_t *pfirst = static_cast<const int32_t *>(ps->rpatch_first_d.p);
+    const ResidTile *tiles = static_cast<const ResidTile *>(ps->rtile_d.p);
+    const int32_t *pfirst = static_cast<const int32_t *>(ps->rtile_first_d.p);
     auto chk = [&](hipError_t err, const char *what) -> bs_status {
         return err == hipSuccess ? BS_OK : hip_fail(err, what);
     };
@@ -108,7 +107,7 @@ bs_status bs_relax_backward(bs_patchset *ps, int32_t axis, double omega, int32_t
     // adjoint state
     if ((st = chk(launch_fill(lam, ps->u_numel, 0.0, stream), "fill")) != BS_OK) return st;
     if ((st = chk(launch_fill(w, ps->u_numel, 0.0, stream), "fill")) != BS_OK) return st;
-    if ((st = chk(launch_fill(acc, static_cast<int64_t>(ps->nrblocks) * 3, 0.0, stream), "fill")) != BS_OK) return st;
+    if ((st = chk(launch_fill(acc, static_cast<int64_t>(ps->nrtiles) * 3, 0.0, stream), "fill")) != BS_OK) return st;
     if (grad_f && (st = chk(launch_fill(grad_f, ps->f_numel, 0.0, stream), "fill")) != BS_OK) return st;
     if ((st = chk(launch_adj_init(grad_uK, gbar, pdd, ps->npatch, stream), "adjoint init")) != BS_OK) return st;
     // reverse, one segment at a time
@@ -120,8 +119,8 @@ bs_status bs_relax_backward(bs_patchset *ps, int32_t axis, double omega, int32_t
             const double *Uk = k == k0 ? ckpt[s] : seg[k - k0 - 1];
             if ((st = line_pass(ps, axis, c, 0, 0, Uk, w, f, omega, stream, -1, 0, 1)) != BS_OK) return st;
             if ((st = line_pass(ps, axis, c, 0, 0, gbar, lam, f, omega, stream, -1, 1, 1)) != BS_OK) return st;
-            if ((st = chk(launch_adj_step(lam, Uk, w, gbar, grad_f, acc, pdd, bpatch, bfirst, ps->nrblocks, axis,
-                                          omega, stream),
+            if ((st = chk(launch_adj_step(lam, Uk, w, gbar, grad_f, acc, pdd, tiles, ps->nrtiles, axis, omega,
+                                          stream),
                           "adjoint step")) != BS_OK)
                 return st;
         }

@@ -198,43 +198,38 @@ bs_status bs_create_patchset(int32_t npatch, const int32_t *dims_host, const dou
     bs_status st = build_tables(ps.get());
     if (st != BS_OK) return st;
 
-    // adjoint reduction plan: blocks of kBlockCells cells, never spanning patches
-    std::vector<int32_t> bp, bf, pf(npatch + 1);
-    for (int p = 0; p < npatch; ++p) {
-        pf[p] = static_cast<int32_t>(bp.size());
-        const int64_t nc = static_cast<int64_t>(ps->dims[3 * p]) * ps->dims[3 * p + 1] * ps->dims[3 * p + 2];
-        for (int64_t c = 0; c < nc; c += kBlockCells) {
-            if (c > INT32_MAX) return fail(BS_ERR_UNSUPPORTED, "bs_create_patchset: patch too large");
-            bp.push_back(p);
-            bf.push_back(static_cast<int32_t>(c));
-        }
-    }
-    pf[npatch] = static_cast<int32_t>(bp.size());
-    ps->nrblocks = static_cast<int32_t>(bp.size());
-    if ((st = upload(ps->rblock_patch_d, bp.data(), bp.size() * 4, "residual plan")) != BS_OK) return st;
-    if ((st = upload(ps->rblock_first_d, bf.data(), bf.size() * 4, "residual plan")) != BS_OK) return st;
-    if ((st = upload(ps->rpatch_first_d, pf.data(), pf.size() * 4, "residual plan")) != BS_OK) return st;
-    // residual tiles: tx x ty columns (tx the power of two in [1, 64] nearest
-    // above nx, ty = 256 / tx) by kResidPlanes planes, in patch order
+    // residual (and adjoint) tiles: tx x ty columns (tx the power of two in
+    // [1, 64] nearest above nx, ty = 256 / tx) by kz planes, in patch order;
+    // the per-patch sums add the patch's tiles in order.  kz starts at
+    // kResidPlanes and halves while the set has fewer than kResidMinTiles.
     std::vector<ResidTile> tl;
     std::vector<int32_t> tf(npatch + 1);
-    for (int p = 0; p < npatch; ++p) {
-        tf[p] = static_cast<int32_t>(tl.size());
-        const int nx = ps->dims[3 * p], ny = ps->dims[3 * p + 1], nz = ps->dims[3 * p + 2];
-        int tx = 64;
-        while (tx > 1 && (tx >> 1) >= nx) tx >>= 1;
-        const int ty = 256 / tx;
-        for (int z0 = 0; z0 < nz; z0 += kResidPlanes)
-            for (int y0 = 0; y0 < ny; y0 += ty)
-                for (int x0 = 0; x0 < nx; x0 += tx) tl.push_back(ResidTile{p, x0, y0, z0});
-    }
+    auto tile_pass = [&](int kz, bool emit) -> int64_t {
+        int64_t n = 0;
+        for (int p = 0; p < npatch; ++p) {
+            if (emit) tf[p] = static_cast<int32_t>(tl.size());
+            const int nx = ps->dims[3 * p], ny = ps->dims[3 * p + 1], nz = ps->dims[3 * p + 2];
+            int tx = 64;
+            while (tx > 1 && (tx >> 1) >= nx) tx >>= 1;
+            const int ty = 256 / tx;
+            for (int z0 = 0; z0 < nz; z0 += kz)
+                for (int y0 = 0; y0 < ny; y0 += ty)
+                    for (int x0 = 0; x0 < nx; x0 += tx) {
+                        ++n;
+                        if (emit) tl.push_back(ResidTile{p, x0, y0, z0, std::min(nz, z0 + kz)});
+                    }
+        }
+        return n;
+    };
+    int kz = kResidPlanes;
+    while (kz > 4 && tile_pass(kz, false) < kResidMinTiles) kz >>= 1;
+    if (tile_pass(kz, false) > INT32_MAX) return fail(BS_ERR_UNSUPPORTED, "bs_create_patchset: too many tiles");
+    tile_pass(kz, true);
     tf[npatch] = static_cast<int32_t>(tl.size());
-    if (tl.size() > static_cast<size_t>(INT32_MAX)) return fail(BS_ERR_UNSUPPORTED, "bs_create_patchset: too many tiles");
     ps->nrtiles = static_cast<int32_t>(tl.size());
     if ((st = upload(ps->rtile_d, tl.data(), tl.size() * sizeof(ResidTile), "residual tiles")) != BS_OK) return st;
     if ((st = upload(ps->rtile_first_d, tf.data(), tf.size() * 4, "residual tiles")) != BS_OK) return st;
-    const size_t npart = std::max(bp.size(), tl.size());
-    if ((st = dev_alloc(ps->rpartial_d, npart * 8, "residual partials")) != BS_OK) return st;
+    if ((st = dev_alloc(ps->rpartial_d, tl.size() * 8, "residual partials")) != BS_OK) return st;
     *out = ps.release();
     return BS_OK;
 }

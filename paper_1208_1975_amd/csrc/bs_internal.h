@@ -69,14 +69,17 @@ struct LineArgs {
     double omega;
     const float *tab32;     // FP32 copy of tab (same offsets)
     int32_t f32;            // 1: block solve in FP32 (residual and update stay FP64)
+    int32_t f_stream;       // 1: colour mode 0 reads f with nontemporal loads (data beyond the Infinity Cache)
 };
+constexpr int64_t kMallBytes = 256ll << 20;   // MI355X Infinity Cache
 
-// Residual tile (one workgroup): columns x0.., y0.. of a patch marched along
-// z over planes z0 .. z0 + kResidPlanes - 1 (clipped).
+// Residual / adjoint tile (one workgroup): columns x0.., y0.. of a patch
+// marched along z over planes z0 .. z1 - 1.
 struct ResidTile {
-    int32_t patch, x0, y0, z0;
+    int32_t patch, x0, y0, z0, z1;
 };
-constexpr int kResidPlanes = 64;
+constexpr int kResidPlanes = 64;      // planes per tile, halved while a patch set has too few tiles
+constexpr int kResidMinTiles = 1024;  // about four workgroups per CU
 
 struct ResidArgs {
     const double *u;
@@ -103,7 +106,6 @@ hipError_t launch_ghost_copy(const double *src, double *dst, const PatchDesc *pd
 hipError_t launch_interior_copy(const double *src, double *dst, const PatchDesc *pd, int npatch,
                                 hipStream_t s);
 
-constexpr int kBlockCells = 2048;   // cells per block of the adjoint's reductions (256 threads x 8)
 
 // n / d for 0 <= n < 2^31 and d >= 1, given rd = 1.0 / d: the double product
 // is within 1e-6 of the quotient, so one correction step makes it exact (a
@@ -131,8 +133,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);
 hipError_t launch_adj_init(const double *gK, double *gbar, const PatchDesc *pd, int npatch, hipStream_t s);
 hipError_t launch_adj_step(const double *lam, const double *U, const double *w, double *gbar, double *gf,
-                           double *acc, const PatchDesc *pd, const int32_t *block_patch,
-                           const int32_t *block_first, int nblocks, int axis, double omega, hipStream_t s);
+                           double *acc, const PatchDesc *pd, const ResidTile *tiles, int ntiles, int axis,
+                           double omega, hipStream_t s);
 hipError_t launch_eps_final(const double *acc, const int32_t *first_block, int npatch, double omega, double *out,
                             hipStream_t s);
 

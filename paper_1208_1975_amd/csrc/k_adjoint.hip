@@ -20,16 +20,14 @@ struct AdjArgs {
     const double *w;      // w^k, u layout, zero ghosts
     double *gbar;         // u layout: interior = gbar (updated), face ghosts accumulate dL/dg
     double *gf;           // f layout, accumulates dL/dF (may be null)
-    double *acc;          // [nblocks][3] per-block accumulators of <lambda, ...>
+    double *acc;          // [ntiles][3] per-tile accumulators of <lambda, ...>
     const PatchDesc *pd;
-    const int32_t *block_patch;
-    const int32_t *block_first;
+    const ResidTile *tiles;
     int axis;
     double omega;
 };
 
 constexpr int kAdjThreads = 256;
-constexpr int kAdjPerThread = kBlockCells / kAdjThreads;
 
 __global__ void __launch_bounds__(256) k_fill(double *x, int64_t n, double v)
 {
@@ -51,52 +49,77 @@ __global__ void __launch_bounds__(256) k_adj_init(const double *gK, double *gbar
     }
 }
 
+// One tile of the residual's tiling (tx x ty columns marched along z): the
+// z-neighbours of lambda, U and w stay in registers and the next plane's
+// values are fetched a step ahead; each column's partial sums run in
+// increasing z and the tile's sums reduce in a fixed tree, so the epsilon
+// gradient is bit-reproducible.
 __global__ void __launch_bounds__(kAdjThreads) k_adj_step(AdjArgs a)
 {
     __shared__ double red[3][kAdjThreads];
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const PatchDesc *pd = a.pd + a.block_patch[b];
+    const ResidTile t = a.tiles[b];
+    const PatchDesc *pd = a.pd + t.patch;
     const int nx = pd->n[0], ny = pd->n[1], nz = pd->n[2];
-    const int ncell = nx * ny * nz;
-    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2);
-    const double e[3] = {pd->eps[0], pd->eps[1], pd->eps[2]};
-    const int64_t st[3] = {1, sx, sy};
-    const int first = a.block_first[b];
-    const double om = a.omega;
-    const double rnx = 1.0 / nx, rny = 1.0 / ny;
-    double part[3] = {0.0, 0.0, 0.0};
-    for (int m = 0; m < kAdjPerThread; ++m) {
-        const int cf = first + m * kAdjThreads + (int)threadIdx.x;
-        if (cf >= ncell) break;
-        const int jk = div_rd(cf, nx, rnx), i = cf - jk * nx, k = div_rd(jk, ny, rny), j = jk - k * ny;
-        const int64_t c = pd->uoff + (int64_t)(k + 1) * sy + (int64_t)(j + 1) * sx + (i + 1);
-        const double l = a.lam[c];
-        double al = 0.0;
-        double contrib[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int64_t s = st[d];
-            al = fma(e[d], 2.0 * l - a.lam[c - s] - a.lam[c + s], al);
-            const double du = 2.0 * a.U[c] - a.U[c - s] - a.U[c + s];
-            const double mw = d == a.axis ? 2.0 * a.w[c] - a.w[c - s] - a.w[c + s] : 2.0 * a.w[c];
-            contrib[d] = l * (du + mw);
+    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2), pf = (int64_t)nx * ny;
+    const double e0 = pd->eps[0], e1 = pd->eps[1], e2 = pd->eps[2];
+    const double om = a.omega, omh2 = a.omega * pd->h2;
+    const int ax = a.axis;
+    int tx = 64;
+    while (tx > 1 && (tx >> 1) >= nx) tx >>= 1;
+    const int i = t.x0 + (int)(threadIdx.x & (tx - 1));
+    const int j = t.y0 + (int)(threadIdx.x / tx);
+    const bool valid = i < nx && j < ny;
+    const int ic = i < nx ? i : nx - 1, jc = j < ny ? j : ny - 1;   // in-patch addresses for every lane
+    const int k0 = t.z0, k1 = t.z1;
+    const int64_t col = pd->uoff + (int64_t)(jc + 1) * sx + (ic + 1);   // column (i, j); plane index k + 1
+    const int64_t fo = pd->foff + (int64_t)jc * nx + ic;
+    double lm = a.lam[col + (int64_t)k0 * sy], lc = a.lam[col + (int64_t)(k0 + 1) * sy];
+    double um = a.U[col + (int64_t)k0 * sy], uc = a.U[col + (int64_t)(k0 + 1) * sy];
+    double wm = a.w[col + (int64_t)k0 * sy], wc = a.w[col + (int64_t)(k0 + 1) * sy];
+    double lp = a.lam[col + (int64_t)(k0 + 2) * sy], up = a.U[col + (int64_t)(k0 + 2) * sy];
+    double wp = a.w[col + (int64_t)(k0 + 2) * sy];
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const int64_t c = col + (int64_t)(k + 1) * sy;
+        // the next step's plane (clamped inside the patch on the last step)
+        const int64_t cn = col + (int64_t)((k + 1 < nz ? k + 1 : nz - 1) + 2) * sy;
+        const double lp_n = a.lam[cn], up_n = a.U[cn], wp_n = a.w[cn];
+        const double lxm = a.lam[c - 1], lxp = a.lam[c + 1], lym = a.lam[c - sx], lyp = a.lam[c + sx];
+        const double uxm = a.U[c - 1], uxp = a.U[c + 1], uym = a.U[c - sx], uyp = a.U[c + sx];
+        const int64_t sa = ax == 0 ? 1 : sx;   // the line axis' neighbours (x or y; z from registers)
+        const double wam = a.w[c - sa], wap = a.w[c + sa];
+        const double g0 = a.gbar[c];
+        const double gf0 = a.gf ? a.gf[fo + (int64_t)k * pf] : 0.0;
+        double al = fma(e0, 2.0 * lc - lxm - lxp, 0.0);
+        al = fma(e1, 2.0 * lc - lym - lyp, al);
+        al = fma(e2, 2.0 * lc - lm - lp, al);
+        const double w2 = 2.0 * wc;
+        const double mw0 = ax == 0 ? w2 - wam - wap : w2;
+        const double mw1 = ax == 1 ? w2 - wam - wap : w2;
+        const double mw2 = ax == 2 ? w2 - wm - wp : w2;
+        if (valid) {
+            p0 += lc * ((2.0 * uc - uxm - uxp) + mw0);
+            p1 += lc * ((2.0 * uc - uym - uyp) + mw1);
+            p2 += lc * ((2.0 * uc - um - up) + mw2);
+            a.gbar[c] = fma(-om, al, g0);
+            if (a.gf) a.gf[fo + (int64_t)k * pf] = fma(omh2, lc, gf0);
+            // face ghosts: each is next to exactly one interior cell, so no two
+            // threads touch the same entry
+            if (i == 0) a.gbar[c - 1] = fma(om * e0, lc, a.gbar[c - 1]);
+            if (i == nx - 1) a.gbar[c + 1] = fma(om * e0, lc, a.gbar[c + 1]);
+            if (j == 0) a.gbar[c - sx] = fma(om * e1, lc, a.gbar[c - sx]);
+            if (j == ny - 1) a.gbar[c + sx] = fma(om * e1, lc, a.gbar[c + sx]);
+            if (k == 0) a.gbar[c - sy] = fma(om * e2, lc, a.gbar[c - sy]);
+            if (k == nz - 1) a.gbar[c + sy] = fma(om * e2, lc, a.gbar[c + sy]);
         }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) part[d] += contrib[d];
-        a.gbar[c] = fma(-om, al, a.gbar[c]);
-        if (a.gf) a.gf[pd->foff + cf] = fma(om * pd->h2, l, a.gf[pd->foff + cf]);
-        // face ghosts: each is next to exactly one interior cell, so no two
-        // threads touch the same entry
-        const int idx[3] = {i, j, k};
-        const int nn[3] = {nx, ny, nz};
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            if (idx[d] == 0) a.gbar[c - st[d]] = fma(om * e[d], l, a.gbar[c - st[d]]);
-            if (idx[d] == nn[d] - 1) a.gbar[c + st[d]] = fma(om * e[d], l, a.gbar[c + st[d]]);
-        }
+        lm = lc; lc = lp; lp = lp_n;
+        um = uc; uc = up; up = up_n;
+        wm = wc; wc = wp; wp = wp_n;
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = part[d];
+    red[0][threadIdx.x] = p0;
+    red[1][threadIdx.x] = p1;
+    red[2][threadIdx.x] = p2;
     __syncthreads();
     for (int s = kAdjThreads / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s)
@@ -107,7 +130,7 @@ __global__ void __launch_bounds__(kAdjThreads) k_adj_step(AdjArgs a)
     if (threadIdx.x < 3) a.acc[3 * (int64_t)b + threadIdx.x] += red[threadIdx.x][0];
 }
 
-// grad_eps[3p + d] = -omega * (fixed-order sum of the patch's block accumulators)
+// grad_eps[3p + d] = -omega * (fixed-order sum of the patch's tile accumulators)
 __global__ void __launch_bounds__(256) k_eps_final(const double *acc, const int32_t *first_block, double omega,
                                                    double *out)
 {
@@ -145,11 +168,12 @@ hipError_t launch_adj_init(const double *gK, double *gbar, const PatchDesc *pd, 
 }
 
 hipError_t launch_adj_step(const double *lam, const double *U, const double *w, double *gbar, double *gf,
-                           double *acc, const PatchDesc *pd, const int32_t *block_patch,
-                           const int32_t *block_first, int nblocks, int axis, double omega, hipStream_t s)
+                           double *acc, const PatchDesc *pd, const ResidTile *tiles, int ntiles, int axis,
+                           double omega, hipStream_t s)
 {
-    AdjArgs a{lam, U, w, gbar, gf, acc, pd, block_patch, block_first, axis, omega};
-    hipLaunchKernelGGL(k_adj_step, dim3(nblocks), dim3(kAdjThreads), 0, s, a);
+    if (ntiles <= 0) return hipSuccess;
+    AdjArgs a{lam, U, w, gbar, gf, acc, pd, tiles, axis, omega};
+    hipLaunchKernelGGL(k_adj_step, dim3(ntiles), dim3(kAdjThreads), 0, s, a);
     return hipGetLastError();
 }
 

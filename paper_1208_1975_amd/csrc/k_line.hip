@@ -152,9 +152,10 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(c
 // Register economy decides the speed of this kernel: a patch is addressed
 // with wave-uniform base pointers and 32-bit byte offsets (one VGPR per
 // address), the chunk factors and interface rows are wave-uniform and come
-// through the scalar cache, and u is read again for the update instead of
-// being held through the solve.  LDS holds only the chunk ends (two buffers,
-// so consecutive items need no trailing barrier).
+// through the scalar cache (read as constant memory), and u waits for the
+// update in LDS (chunks of up to 16 cells; longer chunks read it again from
+// memory).  The chunk ends take two LDS buffers, so consecutive items need
+// no trailing barrier.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double ldb(const char *base, uint32_t off)
 {
@@ -290,9 +291,11 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
                 const uint32_t tt = (uint32_t)(t < Lp ? t : Lp - 1);
                 const uint32_t c = cu + tt * Sa8;
                 ub4[k] = ldb(ub, c);
-                // Jacobi: f with a nontemporal load (measured 117 -> 102 us per
-                // 256^3 sweep; the in-place schemes are slower with it)
-                if constexpr (CM == 0)
+                // CM 3 (Jacobi on data larger than the 256 MiB Infinity Cache):
+                // f with a nontemporal load (measured 117 -> 102 us per 256^3
+                // sweep; data that fits the cache, and the in-place schemes,
+                // are slower with it)
+                if constexpr (CM == 3)
                     fb[k] = __builtin_nontemporal_load(reinterpret_cast<const double *>(fbase + (cf + tt * Fa8)));
                 else
                     fb[k] = ldb(fbase, cf + tt * Fa8);
@@ -622,7 +625,12 @@ static void launch_strided_p(const LineArgs &a, int grid, int nwaves, size_t lds
 {
     const dim3 g(grid), b(64 * nwaves);
     switch (a.colour_mode) {
-    case 0: hipLaunchKernelGGL((k_line_strided<L, MAXT, 0, F32>), g, b, lds, s, a, a.tab, a.tab32); break;
+    case 0:
+        if (a.f_stream)
+            hipLaunchKernelGGL((k_line_strided<L, MAXT, 3, F32>), g, b, lds, s, a, a.tab, a.tab32);
+        else
+            hipLaunchKernelGGL((k_line_strided<L, MAXT, 0, F32>), g, b, lds, s, a, a.tab, a.tab32);
+        break;
     case 1: hipLaunchKernelGGL((k_line_strided<L, MAXT, 1, F32>), g, b, lds, s, a, a.tab, a.tab32); break;
     default: hipLaunchKernelGGL((k_line_strided<L, MAXT, 2, F32>), g, b, lds, s, a, a.tab, a.tab32); break;
     }
@@ -683,7 +691,10 @@ static hipError_t allow_all_p()
                         reinterpret_cast<const void *>(k_line_strided<L, 1024, 1, F32>),
                         reinterpret_cast<const void *>(k_line_strided<L, 256, 2, F32>),
                         reinterpret_cast<const void *>(k_line_strided<L, 512, 2, F32>),
-                        reinterpret_cast<const void *>(k_line_strided<L, 1024, 2, F32>)};
+                        reinterpret_cast<const void *>(k_line_strided<L, 1024, 2, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 256, 3, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 512, 3, F32>),
+                        reinterpret_cast<const void *>(k_line_strided<L, 1024, 3, F32>)};
     for (const void *k : ks) {
         hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (r != hipSuccess) e = r;

@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(kResidThreads) k_residual(ResidArgs a)
     const int ic = i < nx ? i : nx - 1, jc = j < ny ? j : ny - 1;   // in-patch addresses for every lane
     const bool need_l = li == 0, need_r = li == tx - 1 || i >= nx - 1;
     const int64_t xo = need_l ? -1 : 1;                            // the row-end lane's own neighbour
-    const int k0 = t.z0, k1 = t.z0 + kResidPlanes < nz ? t.z0 + kResidPlanes : nz;
+    const int k0 = t.z0, k1 = t.z1;
     const double *u = a.u + pd->uoff + (int64_t)(jc + 1) * sx + (ic + 1);   // column (i, j), plane index k + 1
     const int64_t fo = pd->foff + (int64_t)jc * nx + ic;                     // f / r column, plane index k
     double uzm = u[(int64_t)k0 * sy];

@@ -74,10 +74,8 @@ struct bs_patchset {
     std::vector<bs::PatchDesc> desc;
     bs::DevBuf desc_d, tab_d, tab32_d;
     // residual reduction plan
-    int32_t nrblocks = 0;   // cell blocks of the adjoint's reductions
-    bs::DevBuf rblock_patch_d, rblock_first_d, rpatch_first_d, rpartial_d;
-    int32_t nrtiles = 0;    // residual tiles
-    bs::DevBuf rtile_d, rtile_first_d;
+    int32_t nrtiles = 0;    // residual and adjoint tiles
+    bs::DevBuf rtile_d, rtile_first_d, rpartial_d;
     // plane solves: sine bases per patch and axis, inverse eigenvalue grids per
     // patch and normal axis (built on first use), and two f-layout scratch fields
     bool plane_ready = false;

@@ -363,6 +363,10 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
     a.tab = static_cast<const double *>(ps->tab_d.p);
     a.tab32 = static_cast<const float *>(ps->tab32_d.p);
     a.f32 = f32;
+    // Jacobi on u, v and f that together exceed the Infinity Cache: f is
+    // streamed past it so that u and v stay cached from sweep to sweep
+    a.f_stream = (colour_mode == 0 && (2 * ps->u_numel + ps->f_numel) * static_cast<int64_t>(sizeof(double)) >
+                                         kMallBytes) ? 1 : 0;
     a.axis = axis;
     a.popt = c.popt;
     a.tx = c.tx;
