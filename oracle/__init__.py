@@ -64,6 +64,8 @@ def _load():
     lib.bso_line_jacobi_adjoint.restype = I
     lib.bso_line_jacobi_eps_tangent.argtypes = [I, I, I, P, D, I, D, I, P, P, P, P]
     lib.bso_line_jacobi_eps_tangent.restype = I
+    lib.bso_cube_sweeps.argtypes = [I, I, I, P, D, I, I, I, I, D, I, P, P]
+    lib.bso_cube_sweeps.restype = I
     lib.bso_set_threads.argtypes = [I]
     lib.bso_set_threads.restype = None
     lib.bso_get_threads.argtypes = []
@@ -141,6 +143,21 @@ def plane_sweeps(u, f, eps, h, normal, scheme, omega, nsweeps):
                               float(omega), int(nsweeps), _p(out), _p(f))
     if rc:
         raise ValueError("bso_plane_sweeps failed (%d)" % rc)
+    return out
+
+
+def cube_sweeps(u, f, eps, h, block, scheme, omega, nsweeps):
+    """Return u after nsweeps sweeps over geometric blocks of block = (bx, by, bz)
+    cells (shorter last blocks where an edge does not divide the patch; each
+    block solved exactly).  u is not modified."""
+    lib = _load()
+    nx, ny, nz = _check(u, f)
+    bx, by, bz = (int(b) for b in block)
+    out = u.copy()
+    rc = lib.bso_cube_sweeps(nx, ny, nz, _p(_eps(eps)), float(h), bx, by, bz, int(scheme),
+                             float(omega), int(nsweeps), _p(out), _p(f))
+    if rc:
+        raise ValueError("bso_cube_sweeps failed (%d)" % rc)
     return out
 
 

@@ -524,6 +524,147 @@ int bso_line_update_some(int nx, int ny, int nz, const double eps[3], double h, 
 }
 
 /* ------------------------------------------------------------------------- */
+/* Geometric cube blocks (section 2: lexicographically ordered geometric       */
+/* blocks of bx*by*bz cells; Algorithm 1 and the GPU block Jacobi algorithm    */
+/* with the block inverse).  Blocks tile the patch from its origin; along an   */
+/* axis whose length is not a multiple of the block edge the last block is     */
+/* shorter, with its own block matrix (the option of the block-inversion      */
+/* section that precomputes every inverse instead of overlapping blocks).      */
+/* Block (bi,bj,bk) covers cells i in [bi*bx, min((bi+1)bx, nx)), etc.; its    */
+/* cells are numbered x fastest.  The block matrix A_b is A restricted to the  */
+/* block's cells (coupling to cells outside the block goes to the residual);   */
+/* it is symmetric positive definite, and each block system is solved by a    */
+/* Cholesky factorisation formed on every call (the definition, not a fast    */
+/* method).                                                                    */
+/* Schemes: Jacobi; lexicographic block GS (bi fastest, then bj, then bk);     */
+/* coloured block GS with colour (bi+bj+bk) mod 2, colour 0 first.             */
+/* ------------------------------------------------------------------------- */
+
+/* In-place Cholesky A = L L^T of an n x n SPD matrix (row-major; only the
+ * lower triangle is read, and it is overwritten by L), then x = A^{-1} b by
+ * two triangular solves.
+ * x may alias b.  Returns nonzero if a pivot is not positive. */
+static int chol_solve(int n, double *A, const double *b, double *x)
+{
+    for (int j = 0; j < n; ++j) {
+        double s = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+        if (!(s > 0.0)) return 1;
+        double ljj = sqrt(s);
+        A[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+            A[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    for (int i = 0; i < n; ++i) {          /* L y = b */
+        double t = b[i];
+        for (int k = 0; k < i; ++k) t -= A[(size_t)i * n + k] * x[k];
+        x[i] = t / A[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {     /* L^T x = y */
+        double t = x[i];
+        for (int k = i + 1; k < n; ++k) t -= A[(size_t)k * n + i] * x[k];
+        x[i] = t / A[(size_t)i * n + i];
+    }
+    return 0;
+}
+
+/* One update of cube block (bi,bj,bk): residual of its cells from usrc, exact
+ * block solve, udst = usrc + omega*du on its cells.  All residuals are formed
+ * before any write, so usrc == udst is allowed.  buf: nb*nb + nb doubles,
+ * nb = bx*by*bz. */
+static int cube_update(const grid_t *g, int bx, int by, int bz, int bi, int bj, int bk,
+                       const double *usrc, double *udst, const double *f, double omega, double *buf)
+{
+    int i0 = bi * bx, j0 = bj * by, k0 = bk * bz;
+    int ni = g->nx - i0 < bx ? g->nx - i0 : bx;
+    int nj = g->ny - j0 < by ? g->ny - j0 : by;
+    int nk = g->nz - k0 < bz ? g->nz - k0 : bz;
+    int nb = ni * nj * nk;
+    double d = 2.0 * (g->ex + g->ey + g->ez);
+    double *A = buf, *r = buf + (size_t)nb * nb;
+    memset(A, 0, sizeof(double) * (size_t)nb * nb);
+    for (int ck = 0; ck < nk; ++ck)
+        for (int cj = 0; cj < nj; ++cj)
+            for (int ci = 0; ci < ni; ++ci) {
+                int c = (ck * nj + cj) * ni + ci;
+                r[c] = cell_res(g, usrc, f, i0 + ci, j0 + cj, k0 + ck);
+                A[(size_t)c * nb + c] = d;
+                if (ci > 0) A[(size_t)c * nb + c - 1] = -g->ex;
+                if (ci + 1 < ni) A[(size_t)c * nb + c + 1] = -g->ex;
+                if (cj > 0) A[(size_t)c * nb + c - ni] = -g->ey;
+                if (cj + 1 < nj) A[(size_t)c * nb + c + ni] = -g->ey;
+                if (ck > 0) A[(size_t)c * nb + c - ni * nj] = -g->ez;
+                if (ck + 1 < nk) A[(size_t)c * nb + c + ni * nj] = -g->ez;
+            }
+    if (chol_solve(nb, A, r, r)) return 1;
+    for (int ck = 0; ck < nk; ++ck)
+        for (int cj = 0; cj < nj; ++cj)
+            for (int ci = 0; ci < ni; ++ci) {
+                ptrdiff_t c = uidx(g, i0 + ci, j0 + cj, k0 + ck);
+                udst[c] = usrc[c] + omega * r[(ck * nj + cj) * ni + ci];
+            }
+    return 0;
+}
+
+/* Cube-block sweeps.  scheme: 0 Jacobi, 1 lexicographic GS, 2 coloured GS.
+ * Returns 0 on success, nonzero on bad arguments. */
+int bso_cube_sweeps(int nx, int ny, int nz, const double eps[3], double h, int bx, int by, int bz,
+                    int scheme, double omega, int nsweeps, double *u, const double *f)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || bx < 1 || by < 1 || bz < 1 || nsweeps < 0) return 1;
+    if (scheme < BSO_JACOBI || scheme > BSO_COLORED_GS) return 2;
+    grid_t g = mkgrid(nx, ny, nz, eps, h);
+    if (bx > nx) bx = nx;
+    if (by > ny) by = ny;
+    if (bz > nz) bz = nz;
+    int mi = (nx + bx - 1) / bx, mj = (ny + by - 1) / by, mk = (nz + bz - 1) / bz;
+    size_t nb = (size_t)bx * by * bz, bufn = nb * nb + nb;
+    size_t tot = (size_t)(nz + 2) * (size_t)g.sy;
+    double *v = NULL;
+    int bad = 0;
+    if (scheme == BSO_JACOBI) {
+        v = (double *)malloc(tot * sizeof(double));
+        copy_padded(&g, u, v);
+    }
+    for (int s = 0; s < nsweeps && !bad; ++s) {
+        if (scheme == BSO_LEX_GS) {
+            double *buf = (double *)malloc(sizeof(double) * bufn);
+            for (int bk = 0; bk < mk; ++bk)
+                for (int bj = 0; bj < mj; ++bj)
+                    for (int bi = 0; bi < mi; ++bi)
+                        bad |= cube_update(&g, bx, by, bz, bi, bj, bk, u, u, f, omega, buf);
+            free(buf);
+            continue;
+        }
+        /* Jacobi: one pass from u into v; coloured: two in-place passes */
+        for (int colour = 0; colour < (scheme == BSO_JACOBI ? 1 : 2); ++colour) {
+            double *dst = scheme == BSO_JACOBI ? v : u;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(NT) reduction(| : bad)
+#endif
+            {
+                double *buf = (double *)malloc(sizeof(double) * bufn);
+#ifdef _OPENMP
+#pragma omp for collapse(3) schedule(dynamic)
+#endif
+                for (int bk = 0; bk < mk; ++bk)
+                    for (int bj = 0; bj < mj; ++bj)
+                        for (int bi = 0; bi < mi; ++bi)
+                            if (scheme == BSO_JACOBI || ((bi + bj + bk) & 1) == colour)
+                                bad |= cube_update(&g, bx, by, bz, bi, bj, bk, u, dst, f, omega, buf);
+                free(buf);
+            }
+        }
+        if (scheme == BSO_JACOBI) copy_padded(&g, v, u);
+    }
+    free(v);
+    return bad ? 3 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Adjoint of K damped Jacobi line sweeps (reverse mode, every state stored). */
 /*                                                                            */
 /* Forward: x^{k+1} = x^k + omega M^{-1} r(x^k), r = h^2 F + B g - A_int x,   */

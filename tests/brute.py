@@ -55,10 +55,22 @@ def block_ids(nx, ny, nz, kind, axis):
 
     Lines along `axis` are named by their free indices (p, q), p the lower
     remaining axis; lexicographic order is p fastest.  Planes with normal
-    `axis` are named by their index s."""
+    `axis` are named by their index s.  Cube blocks: `axis` is the block
+    shape (bx, by, bz)."""
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     coords = {0: i, 1: j, 2: k}
     dims = {0: nx, 1: ny, 2: nz}
+    if kind == "cube":
+        # geometric blocks of axis = (bx, by, bz) cells from the origin, shorter
+        # at the upper ends; lexicographic order bi fastest; colour bi+bj+bk
+        bx, by, bz = axis
+        mi, mj = -(-nx // bx), -(-ny // by)
+        mk = -(-nz // bz)
+        bid = ((k // bz) * mj * mi + (j // by) * mi + i // bx).reshape(-1)
+        ids = np.arange(mi * mj * mk)
+        order = ids
+        colour = (ids % mi + (ids // mi) % mj + ids // (mi * mj)) % 2
+        return bid, order, colour
     if kind == "line":
         others = [a for a in (0, 1, 2) if a != axis]
         p, q = coords[others[0]], coords[others[1]]
