@@ -160,6 +160,42 @@ bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme,
                          int32_t nsweeps, bs_precision prec, int32_t refine, double *u,
                          const double *f, double *work, hipStream_t stream);
 
+/* Geometric cube blocks (section 2's lexicographically ordered geometric
+ * blocks; the block Jacobi algorithm on GPUs; the block-inversion section).
+ * Blocks of bx x by x bz cells tile every patch from its origin; an edge
+ * longer than the patch is clipped to it, and along an axis that is not a
+ * multiple of the edge the last block is shorter.  Each distinct block shape
+ * of each patch gets the dense inverse of its block matrix (the stencil
+ * restricted to the block's cells), computed once, on the host, by
+ * bs_cube_prepare; patches with equal dims, eps and h share them.
+ *
+ * bs_cube_prepare: builds the inverses, block tables and a residual scratch
+ * of 8 bytes per cell of the largest group of equally shaped blocks for this
+ * block size; synchronous (allocates device memory).  Repeated calls with a
+ * prepared size return BS_OK at once; bs_set_eps rebuilds every prepared
+ * size.  BS_ERR_INVALID for an edge < 1; BS_ERR_UNSUPPORTED for blocks of
+ * more than 512 cells after clipping (8^3 is the paper's largest) or more
+ * than 1 GiB of inverses in total. */
+bs_status bs_cube_prepare(bs_patchset *ps, int32_t bx, int32_t by, int32_t bz);
+
+/* nsweeps sweeps of cube-block relaxation with a prepared block size: per
+ * block, its residual r_b = h^2 f_b - (A u)_b (neighbours outside the block
+ * and ghosts included), du_b = Ainv_b r_b, u_b += omega du_b (Algorithm 1 in
+ * the residual-correction form).  The blocks' products with their inverses
+ * run as one FP64 matrix-core product per block shape (blocks as rows).
+ *   BS_JACOBI:     every block from the same iterate, into `work` (the
+ *                  second vector), pointer swap; the result ends in u.
+ *   BS_COLORED_GS: blocks with (bi+bj+bk) even, then odd, in place.
+ *   BS_CHAOTIC_GS: in place, in the same colour-major order (one of the
+ *                  orders a chaotic sweep may take; deterministic).
+ * prec must be BS_FP64 (BS_ERR_UNSUPPORTED otherwise).  Asynchronous on
+ * `stream`; two or more sweeps are captured into a HIP graph on their first
+ * call and replayed later, as bs_line_relax.  BS_ERR_INVALID if the block
+ * size was not prepared, and for the argument errors of bs_line_relax. */
+bs_status bs_cube_relax(bs_patchset *ps, int32_t bx, int32_t by, int32_t bz, bs_scheme scheme, double omega,
+                        int32_t nsweeps, bs_precision prec, double *u, const double *f, double *work,
+                        hipStream_t stream);
+
 /* Autotuner: time the candidate launch configurations of line sweeps along
  * `axis` for `scheme` (chunk count per line, tile width, one workgroup per
  * tile or a persistent grid) on copies of u -- the caller's buffers are not

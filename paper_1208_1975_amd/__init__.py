@@ -29,7 +29,8 @@ _STATUS = {1: "BS_ERR_INVALID", 2: "BS_ERR_UNSUPPORTED", 3: "BS_ERR_OOM", 4: "BS
 
 # Every symbol the public header declares.
 EXPORTS = ("bs_layout_plan", "bs_create_patchset", "bs_destroy_patchset", "bs_set_eps", "bs_layout",
-           "bs_residual", "bs_line_relax", "bs_plane_relax", "bs_autotune_line", "bs_line_config",
+           "bs_residual", "bs_line_relax", "bs_plane_relax", "bs_cube_prepare", "bs_cube_relax",
+           "bs_autotune_line", "bs_line_config",
            "bs_backward_workspace_bytes", "bs_relax_backward", "bs_last_error")
 
 
@@ -61,6 +62,8 @@ def lib():
     L.bs_residual.argtypes = [vp, vp, vp, vp, vp, vp]
     L.bs_line_relax.argtypes = [vp, i32, ctypes.c_int, dbl, i32, ctypes.c_int, vp, vp, vp, vp]
     L.bs_plane_relax.argtypes = [vp, i32, ctypes.c_int, dbl, i32, ctypes.c_int, i32, vp, vp, vp, vp]
+    L.bs_cube_prepare.argtypes = [vp, i32, i32, i32]
+    L.bs_cube_relax.argtypes = [vp, i32, i32, i32, ctypes.c_int, dbl, i32, ctypes.c_int, vp, vp, vp, vp]
     L.bs_autotune_line.argtypes = [vp, i32, ctypes.c_int, vp, vp, vp]
     L.bs_line_config.argtypes = [vp, i32, ctypes.c_int, vp]
     L.bsi_set_line_cfg.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -184,6 +187,15 @@ def bs_plane_relax(ps, normal_axis, scheme, omega, nsweeps, prec, refine, u, f, 
                                 _prec(prec), int(refine), _ptr(u), _ptr(f), _ptr(work), _stream(stream)))
 
 
+def bs_cube_prepare(ps, bx, by, bz):
+    _check(lib().bs_cube_prepare(ps, int(bx), int(by), int(bz)))
+
+
+def bs_cube_relax(ps, bx, by, bz, scheme, omega, nsweeps, prec, u, f, work=None, stream=None):
+    _check(lib().bs_cube_relax(ps, int(bx), int(by), int(bz), _scheme(scheme), float(omega), int(nsweeps),
+                               _prec(prec), _ptr(u), _ptr(f), _ptr(work), _stream(stream)))
+
+
 def bs_autotune_line(ps, axis, scheme, u, f, stream=None):
     _check(lib().bs_autotune_line(ps, int(axis), _scheme(scheme), _ptr(u), _ptr(f), _stream(stream)))
 
@@ -287,6 +299,12 @@ class PatchSet:
     def plane_relax(self, normal_axis, scheme, omega, nsweeps, u, f, work=None, prec="fp64", refine=0,
                     stream=None):
         bs_plane_relax(self.handle, normal_axis, scheme, omega, nsweeps, prec, refine, u, f, work, stream)
+
+    def cube_prepare(self, block):
+        bs_cube_prepare(self.handle, *block)
+
+    def cube_relax(self, block, scheme, omega, nsweeps, u, f, work=None, prec="fp64", stream=None):
+        bs_cube_relax(self.handle, *block, scheme, omega, nsweeps, prec, u, f, work, stream)
 
     def autotune_line(self, axis, scheme, u, f, stream=None):
         bs_autotune_line(self.handle, axis, scheme, u, f, stream)

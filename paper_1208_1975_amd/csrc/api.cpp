@@ -250,7 +250,9 @@ bs_status bs_set_eps(bs_patchset *ps, const double *eps_host)
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     ps->eps.assign(eps_host, eps_host + 3 * static_cast<size_t>(ps->npatch));
-    return build_tables(ps);
+    bs_status st = build_tables(ps);
+    if (st != BS_OK) return st;
+    return cube_rebuild_all(ps);   // block inverses depend on eps
 }
 
 bs_status bs_layout(const bs_patchset *ps, int64_t *u_numel, int64_t *f_numel, int64_t *u_off_host,

@@ -129,6 +129,21 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return (b & 7) * (full >> 3) + (b >> 3);
 }
 
+// Geometric cube blocks (k_cube.hip): residuals of nblk equally shaped blocks
+// into R[block][cell]; cell c of block b is u[ubase[b] + uoff[c]] and
+// f[fbase[b] + foff[c]].
+struct CubeResidArgs {
+    const double *u;
+    const double *f;
+    double *R;
+    const int64_t *ubase, *fbase;
+    const int32_t *uoff, *foff;
+    int32_t nb, nblk, per;      // cells per block, blocks, blocks per workgroup
+    int64_t sy, sz;             // u strides of y and z
+    double ex, ey, ez, h2;
+};
+hipError_t launch_cube_resid(const CubeResidArgs &a, hipStream_t s);
+
 // Adjoint of damped Jacobi line sweeps (k_adjoint.hip).
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);
 hipError_t launch_adj_init(const double *gK, double *gbar, const PatchDesc *pd, int npatch, hipStream_t s);

@@ -1,0 +1,385 @@
+// Geometric cube blocks: the paper's own block kind (section 2: geometric
+// blocks of bx x by x bz cells in lexicographic order; the block Jacobi
+// algorithm on GPUs; the block-inversion section).  Each block's correction is
+// the precomputed dense inverse of its block matrix applied to its residual:
+//   step 1  R[block][cell] = h^2 f - A u          (k_cube_resid)
+//   step 2  DU = R Ainv^T                          (FP64 matrix cores)
+//   step 3  u' = u + omega DU                      (the product's epilogue)
+// The blocks of a patch of equal shape share one inverse (constant
+// coefficients), so step 2 is one dense product per shape: the blocks are the
+// rows, which is what makes it a matrix-core contraction rather than the
+// paper's one matrix-vector product per thread block.
+//
+// Where an edge of the patch is not a multiple of the block edge, the last
+// block along that axis is shorter and has its own inverse (the block-inversion
+// section's option of precomputing every inverse; at most 8 shapes a patch).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <tuple>
+#include <vector>
+
+#include "patchset.h"
+#include "plane.h"
+#include "relax.h"
+
+namespace bs {
+
+namespace {
+
+constexpr int kCubeMaxCells = 512;                      // cells per block (8^3, the paper's largest)
+constexpr int64_t kCubeMaxInvBytes = int64_t(1) << 30;  // all inverses of one block size
+
+// Orthonormal DST-I basis S[i][p] = sqrt(2/(n+1)) sin((i+1)(p+1) pi/(n+1)) of
+// tridiag(-1, 2, -1) (n x n) and its eigenvalues 4 sin^2((p+1) pi/(2(n+1))).
+// The sine argument is reduced modulo 2(n+1) in integers first.
+void dst1(int n, std::vector<double> &S, std::vector<double> &sig)
+{
+    S.assign(size_t(n) * n, 0.0);
+    sig.assign(n, 0.0);
+    const double sc = std::sqrt(2.0 / (n + 1)), pi = std::acos(-1.0);
+    for (int i = 0; i < n; ++i)
+        for (int p = 0; p < n; ++p) {
+            const int m = ((i + 1) * (p + 1)) % (2 * (n + 1));
+            S[size_t(i) * n + p] = sc * std::sin(pi * m / (n + 1));
+        }
+    for (int p = 0; p < n; ++p) {
+        const double t = std::sin((p + 1) * pi / (2.0 * (n + 1)));
+        sig[p] = 4.0 * t * t;
+    }
+}
+
+// Dense inverse of the block matrix of an ni x nj x nk block,
+//   A_b = ex (I (x) I (x) T_ni) + ey (I (x) T_nj (x) I) + ez (T_nk (x) I (x) I),
+// (the stencil restricted to the block; T_n = tridiag(-1, 2, -1)), from its
+// eigen-decomposition: A_b^{-1} = S diag(1/lambda) S with S = S_k (x) S_j (x) S_i
+// symmetric and lambda_pqr = ex sig_p + ey sig_q + ez sig_r.  Column c' is
+// S (lambda^{-1} .* S e_c'), S e_c' being the product of one row of each basis;
+// the outer S is applied one axis at a time.  Cells are numbered x fastest.
+void block_inverse(int ni, int nj, int nk, double ex, double ey, double ez, double *out)
+{
+    std::vector<double> Si, Sj, Sk, si, sj, sk;
+    dst1(ni, Si, si);
+    dst1(nj, Sj, sj);
+    dst1(nk, Sk, sk);
+    const int nb = ni * nj * nk;
+    std::vector<double> w(nb), t1(nb), t2(nb);
+    for (int ck2 = 0; ck2 < nk; ++ck2)
+        for (int cj2 = 0; cj2 < nj; ++cj2)
+            for (int ci2 = 0; ci2 < ni; ++ci2) {
+                const int col = (ck2 * nj + cj2) * ni + ci2;
+                for (int r = 0; r < nk; ++r)
+                    for (int q = 0; q < nj; ++q)
+                        for (int p = 0; p < ni; ++p)
+                            w[(r * nj + q) * ni + p] = Si[size_t(ci2) * ni + p] * Sj[size_t(cj2) * nj + q] *
+                                                       Sk[size_t(ck2) * nk + r] /
+                                                       (ex * si[p] + ey * sj[q] + ez * sk[r]);
+                for (int r = 0; r < nk; ++r)   // along x
+                    for (int q = 0; q < nj; ++q)
+                        for (int ci = 0; ci < ni; ++ci) {
+                            double acc = 0.0;
+                            for (int p = 0; p < ni; ++p) acc += Si[size_t(ci) * ni + p] * w[(r * nj + q) * ni + p];
+                            t1[(r * nj + q) * ni + ci] = acc;
+                        }
+                for (int r = 0; r < nk; ++r)   // along y
+                    for (int cj = 0; cj < nj; ++cj)
+                        for (int ci = 0; ci < ni; ++ci) {
+                            double acc = 0.0;
+                            for (int q = 0; q < nj; ++q) acc += Sj[size_t(cj) * nj + q] * t1[(r * nj + q) * ni + ci];
+                            t2[(r * nj + cj) * ni + ci] = acc;
+                        }
+                for (int ck = 0; ck < nk; ++ck)   // along z
+                    for (int cj = 0; cj < nj; ++cj)
+                        for (int ci = 0; ci < ni; ++ci) {
+                            double acc = 0.0;
+                            for (int r = 0; r < nk; ++r) acc += Sk[size_t(ck) * nk + r] * t2[(r * nj + cj) * ni + ci];
+                            out[size_t((ck * nj + cj) * ni + ci) * nb + col] = acc;
+                        }
+            }
+}
+
+// Host image of a plan's device buffer: 256-byte aligned pieces.
+struct HostImage {
+    std::vector<char> bytes;
+    int64_t put(const void *src, size_t n)
+    {
+        const int64_t off = int64_t((bytes.size() + 255) & ~size_t(255));
+        bytes.resize(size_t(off) + n);
+        if (n) std::memcpy(bytes.data() + off, src, n);
+        return off;
+    }
+};
+
+bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &plan)
+{
+    // classes of patches with equal dims, eps and h share inverses and offsets
+    using ClassKey = std::tuple<int, int, int, double, double, double, double>;
+    std::vector<std::pair<ClassKey, std::vector<int>>> classes;
+    for (int p = 0; p < ps->npatch; ++p) {
+        const ClassKey k{ps->dims[3 * p], ps->dims[3 * p + 1], ps->dims[3 * p + 2], ps->eps[3 * p],
+                         ps->eps[3 * p + 1], ps->eps[3 * p + 2], ps->h[p]};
+        auto it = std::find_if(classes.begin(), classes.end(), [&](const auto &c) { return c.first == k; });
+        if (it == classes.end()) classes.push_back({k, {p}});
+        else it->second.push_back(p);
+    }
+    HostImage img;
+    int64_t rmax = 0, inv_bytes = 0;
+    plan.groups.clear();
+    for (const auto &cl : classes) {
+        const int nx = std::get<0>(cl.first), ny = std::get<1>(cl.first), nz = std::get<2>(cl.first);
+        const double ex = std::get<3>(cl.first), ey = std::get<4>(cl.first), ez = std::get<5>(cl.first);
+        const double h = std::get<6>(cl.first);
+        const int cb[3] = {std::min(bx, nx), std::min(by, ny), std::min(bz, nz)};
+        const int n[3] = {nx, ny, nz};
+        const int64_t SY = nx + 2, SZ = int64_t(nx + 2) * (ny + 2);
+        // per axis: the full edge and, if the axis is not a multiple of it, the remainder
+        std::vector<int> ext[3];
+        for (int a = 0; a < 3; ++a) {
+            if (n[a] / cb[a] > 0) ext[a].push_back(cb[a]);
+            if (n[a] % cb[a]) ext[a].push_back(n[a] % cb[a]);
+        }
+        for (int sx : ext[0])
+            for (int sy : ext[1])
+                for (int sz : ext[2]) {
+                    const int nb = sx * sy * sz;
+                    inv_bytes += int64_t(nb) * nb * 8;
+                    if (inv_bytes > kCubeMaxInvBytes)
+                        return fail(BS_ERR_UNSUPPORTED,
+                                    "bs_cube_prepare: the block inverses of this patch set exceed %lld bytes",
+                                    (long long)kCubeMaxInvBytes);
+                    CubeGroup g;
+                    g.nb = nb;
+                    g.ex = ex;
+                    g.ey = ey;
+                    g.ez = ez;
+                    g.h2 = h * h;
+                    g.sy = SY;
+                    g.sz = SZ;
+                    std::vector<double> inv(size_t(nb) * nb);
+                    block_inverse(sx, sy, sz, ex, ey, ez, inv.data());
+                    g.o_ainv = img.put(inv.data(), inv.size() * 8);
+                    std::vector<int32_t> uo(nb), fo(nb);
+                    for (int ck = 0; ck < sz; ++ck)
+                        for (int cj = 0; cj < sy; ++cj)
+                            for (int ci = 0; ci < sx; ++ci) {
+                                const int c = (ck * sy + cj) * sx + ci;
+                                uo[c] = int32_t(ck * SZ + cj * SY + ci);
+                                fo[c] = int32_t((int64_t(ck) * ny + cj) * nx + ci);
+                            }
+                    g.o_uoff = img.put(uo.data(), uo.size() * 4);
+                    g.o_foff = img.put(fo.data(), fo.size() * 4);
+                    // this shape's blocks: origin index i0 = bi * cb runs over the
+                    // full blocks if the edge is the full one, else the last block
+                    std::vector<int64_t> ub[2], fb[2];
+                    auto origins = [&](int a, int s) {
+                        std::vector<int> o;
+                        if (s == cb[a] && n[a] / cb[a] > 0)
+                            for (int t = 0; t < n[a] / cb[a]; ++t) o.push_back(t * cb[a]);
+                        else
+                            o.push_back(n[a] - n[a] % cb[a]);
+                        return o;
+                    };
+                    const std::vector<int> oi = origins(0, sx), oj = origins(1, sy), ok = origins(2, sz);
+                    for (int p : cl.second)
+                        for (int k0 : ok)
+                            for (int j0 : oj)
+                                for (int i0 : oi) {
+                                    const int col = (i0 / cb[0] + j0 / cb[1] + k0 / cb[2]) & 1;
+                                    ub[col].push_back(ps->uoff[p] + (k0 + 1) * SZ + (j0 + 1) * SY + (i0 + 1));
+                                    fb[col].push_back(ps->foff[p] + (int64_t(k0) * ny + j0) * nx + i0);
+                                }
+                    g.ncol0 = int(ub[0].size());
+                    g.nblk = int(ub[0].size() + ub[1].size());
+                    ub[0].insert(ub[0].end(), ub[1].begin(), ub[1].end());
+                    fb[0].insert(fb[0].end(), fb[1].begin(), fb[1].end());
+                    g.o_ubase = img.put(ub[0].data(), ub[0].size() * 8);
+                    g.o_fbase = img.put(fb[0].data(), fb[0].size() * 8);
+                    rmax = std::max(rmax, int64_t(g.nblk) * nb);
+                    plan.groups.push_back(g);
+                }
+    }
+    bs_status st = upload(plan.buf, img.bytes.data(), img.bytes.size(), "cube tables");
+    if (st != BS_OK) return st;
+    plan.inv_bytes = inv_bytes;
+    if (plan.rbuf.bytes < size_t(rmax) * 8) {
+        plan.rbuf.reset();
+        if ((st = dev_alloc(plan.rbuf, size_t(rmax) * 8, "cube residual scratch")) != BS_OK) return st;
+    }
+    return BS_OK;
+}
+
+// Steps 1-3 for blocks [lo, lo + n) of group g: src -> dst.
+bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, int lo, int n, const double *src, double *dst,
+                    const double *f, double omega, hipStream_t stream)
+{
+    if (n <= 0) return BS_OK;
+    const char *base = static_cast<const char *>(plan.buf.p);
+    const int64_t *ub = reinterpret_cast<const int64_t *>(base + g.o_ubase) + lo;
+    const int64_t *fb = reinterpret_cast<const int64_t *>(base + g.o_fbase) + lo;
+    const int32_t *uo = reinterpret_cast<const int32_t *>(base + g.o_uoff);
+    CubeResidArgs a{};
+    a.u = src;
+    a.f = f;
+    a.R = static_cast<double *>(plan.rbuf.p);
+    a.ubase = ub;
+    a.fbase = fb;
+    a.uoff = uo;
+    a.foff = reinterpret_cast<const int32_t *>(base + g.o_foff);
+    a.nb = g.nb;
+    a.nblk = n;
+    a.per = g.nb >= 256 ? 1 : 256 / g.nb;
+    a.sy = g.sy;
+    a.sz = g.sz;
+    a.ex = g.ex;
+    a.ey = g.ey;
+    a.ez = g.ez;
+    a.h2 = g.h2;
+    hipError_t e = launch_cube_resid(a, stream);
+    if (e != hipSuccess) return hip_fail(e, "cube residual");
+    GemmArgs m{};
+    m.A = a.R;
+    m.lda = g.nb;
+    m.B = reinterpret_cast<const double *>(base + g.o_ainv);
+    m.ldb = g.nb;
+    m.M = n;
+    m.N = g.nb;
+    m.K = g.nb;
+    m.batch = 1;
+    m.b_trans = 1;
+    m.usrc = src;
+    m.udst = dst;
+    m.omega = omega;
+    m.ebase = ub;
+    m.eoff = uo;
+    e = launch_gemm_f64(m, kEpiGather, stream);
+    if (e != hipSuccess) return hip_fail(e, "cube block product");
+    return BS_OK;
+}
+
+bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme scheme, double omega, int nsweeps,
+                              double *u, const double *f, double *work, hipStream_t stream)
+{
+    const PatchDesc *pdd = static_cast<const PatchDesc *>(ps->desc_d.p);
+    bs_status st;
+    if (scheme == BS_JACOBI) {
+        hipError_t e = launch_ghost_copy(u, work, pdd, ps->npatch, stream);
+        if (e != hipSuccess) return hip_fail(e, "ghost copy");
+        for (int s = 0; s < nsweeps; ++s) {
+            const double *src = (s & 1) ? work : u;
+            double *dst = (s & 1) ? u : work;
+            for (const CubeGroup &g : plan.groups)
+                if ((st = cube_pass(plan, g, 0, g.nblk, src, dst, f, omega, stream)) != BS_OK) return st;
+        }
+        if (nsweeps & 1) {
+            e = launch_interior_copy(work, u, pdd, ps->npatch, stream);
+            if (e != hipSuccess) return hip_fail(e, "interior copy");
+        }
+        return BS_OK;
+    }
+    // coloured (and chaotic) block GS: colour-0 blocks of every group, then colour 1, in place
+    for (int s = 0; s < nsweeps; ++s)
+        for (int col = 0; col < 2; ++col)
+            for (const CubeGroup &g : plan.groups) {
+                const int lo = col ? g.ncol0 : 0, n = col ? g.nblk - g.ncol0 : g.ncol0;
+                if ((st = cube_pass(plan, g, lo, n, u, u, f, omega, stream)) != BS_OK) return st;
+            }
+    return BS_OK;
+}
+
+bs_status check_block(const bs_patchset *ps, int32_t bx, int32_t by, int32_t bz, const char *fn)
+{
+    if (!ps) return fail(BS_ERR_INVALID, "%s: null patch set", fn);
+    if (bx < 1 || by < 1 || bz < 1) return fail(BS_ERR_INVALID, "%s: block edges must be >= 1", fn);
+    if (int64_t(std::min(bx, ps->max_n[0])) * std::min(by, ps->max_n[1]) * std::min(bz, ps->max_n[2]) >
+        kCubeMaxCells)
+        return fail(BS_ERR_UNSUPPORTED, "%s: blocks of more than %d cells", fn, kCubeMaxCells);
+    return BS_OK;
+}
+
+}  // namespace
+
+bs_status cube_rebuild_all(bs_patchset *ps)
+{
+    for (auto &kv : ps->cube) {
+        bs_status st = build_plan(ps, std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), *kv.second);
+        if (st != BS_OK) return st;
+    }
+    return BS_OK;
+}
+
+}  // namespace bs
+
+using namespace bs;
+
+extern "C" {
+
+bs_status bs_cube_prepare(bs_patchset *ps, int32_t bx, int32_t by, int32_t bz)
+{
+    bs_status st = check_block(ps, bx, by, bz, "bs_cube_prepare");
+    if (st != BS_OK) return st;
+    const auto key = std::make_tuple(int(bx), int(by), int(bz));
+    if (ps->cube.count(key)) return BS_OK;
+    hipError_t e = hipSetDevice(ps->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    std::unique_ptr<CubePlan> plan(new CubePlan);
+    if ((st = build_plan(ps, bx, by, bz, *plan)) != BS_OK) return st;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    ps->cube.emplace(key, std::move(plan));
+    return BS_OK;
+}
+
+bs_status bs_cube_relax(bs_patchset *ps, int32_t bx, int32_t by, int32_t bz, bs_scheme scheme, double omega,
+                        int32_t nsweeps, bs_precision prec, double *u, const double *f, double *work,
+                        hipStream_t stream)
+{
+    bs_status st = check_block(ps, bx, by, bz, "bs_cube_relax");
+    if (st != BS_OK) return st;
+    if (scheme != BS_JACOBI && scheme != BS_CHAOTIC_GS && scheme != BS_COLORED_GS)
+        return fail(BS_ERR_INVALID, "bs_cube_relax: unknown scheme");
+    if (!(omega > 0.0 && omega < 2.0)) return fail(BS_ERR_INVALID, "bs_cube_relax: omega must be in (0, 2)");
+    if (nsweeps < 0) return fail(BS_ERR_INVALID, "bs_cube_relax: nsweeps < 0");
+    if (prec != BS_FP64 && prec != BS_MIXED_FP32 && prec != BS_MIXED_BF16)
+        return fail(BS_ERR_INVALID, "bs_cube_relax: unknown precision");
+    if (prec != BS_FP64) return fail(BS_ERR_UNSUPPORTED, "bs_cube_relax: cube blocks run in FP64 only");
+    if (!u || !f) return fail(BS_ERR_INVALID, "bs_cube_relax: null u or f");
+    if (scheme == BS_JACOBI && !work) return fail(BS_ERR_INVALID, "bs_cube_relax: Jacobi needs a work buffer");
+    auto it = ps->cube.find(std::make_tuple(int(bx), int(by), int(bz)));
+    if (it == ps->cube.end())
+        return fail(BS_ERR_INVALID, "bs_cube_relax: block size %dx%dx%d not prepared (bs_cube_prepare)", bx, by, bz);
+    if (nsweeps == 0) return BS_OK;
+    const CubePlan &plan = *it->second;
+    if (!ps->use_graphs || nsweeps < 2) return enqueue_cube_sweeps(ps, plan, scheme, omega, nsweeps, u, f, work, stream);
+
+    // replay a captured graph of the whole sequence (captured on first use)
+    int64_t obits;
+    std::memcpy(&obits, &omega, sizeof obits);
+    const std::vector<int64_t> key{2, bx, by, bz, scheme, obits, nsweeps, reinterpret_cast<int64_t>(u),
+                                   reinterpret_cast<int64_t>(f), reinterpret_cast<int64_t>(work)};
+    auto itr = ps->graphs.find(key);
+    hipError_t e;
+    if (itr == ps->graphs.end()) {
+        if (ps->graphs.size() >= 64) clear_graphs(ps);
+        if (!ps->capture_stream &&
+            (e = hipStreamCreateWithFlags(&ps->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "capture stream");
+        hipGraph_t graph = nullptr;
+        if ((e = hipStreamBeginCapture(ps->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        st = enqueue_cube_sweeps(ps, plan, scheme, omega, nsweeps, u, f, work, ps->capture_stream);
+        e = hipStreamEndCapture(ps->capture_stream, &graph);
+        if (st != BS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        itr = ps->graphs.emplace(key, exec).first;
+    }
+    if ((e = hipGraphLaunch(itr->second, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return BS_OK;
+}
+
+}  // extern "C"

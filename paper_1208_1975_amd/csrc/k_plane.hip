@@ -10,7 +10,8 @@
 // shared across the batch with a zero batch stride) serves every plane
 // orientation; its epilogue either stores C, stores C scaled elementwise by a
 // table (the inverse eigenvalue grid), or writes dst = src + omega C straight
-// into the padded u layout (the block update).
+// into the padded u layout (the block update; for cube blocks through a
+// per-row / per-column offset table).
 #include <cstdint>
 
 #include "bs_internal.h"
@@ -192,6 +193,7 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
                     in[r] = g.scale[(int64_t)b * g.sc_b + (int64_t)(o ? row : 0) * g.sc_m + (int64_t)(o ? col : 0) * g.sc_n];
                 if (EPI == kEpiUpdate)
                     in[r] = g.usrc[g.u0 + (int64_t)b * g.u_b + (int64_t)(o ? row : 0) * g.u_m + (int64_t)(o ? col : 0) * g.u_n];
+                if (EPI == kEpiGather) in[r] = g.usrc[o ? g.ebase[pr] + g.eoff[pcl] : g.ebase[0]];
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -205,6 +207,8 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
                     g.C[(int64_t)b * g.sC + (int64_t)row * g.ldc + col] = v;
                 } else if (EPI == kEpiScale) {
                     g.C[(int64_t)b * g.sC + (int64_t)row * g.ldc + col] = v * in[r];
+                } else if (EPI == kEpiGather) {
+                    g.udst[g.ebase[pr] + g.eoff[pcl]] = fma(g.omega, v, in[r]);
                 } else {
                     const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
                     g.udst[u] = fma(g.omega, v, in[r]);
@@ -221,6 +225,13 @@ static hipError_t launch_f64_v(const GemmArgs &g, int epi, hipStream_t s)
     case kEpiStore: hipLaunchKernelGGL((k_gemm_f64<kEpiStore, BT, FOLD, VEC>), grid, dim3(kThreads), 0, s, g); break;
     case kEpiScale: hipLaunchKernelGGL((k_gemm_f64<kEpiScale, BT, FOLD, VEC>), grid, dim3(kThreads), 0, s, g); break;
     case kEpiUpdate: hipLaunchKernelGGL((k_gemm_f64<kEpiUpdate, BT, FOLD, VEC>), grid, dim3(kThreads), 0, s, g); break;
+    case kEpiGather:
+        if constexpr (BT == 1 && FOLD == 0) {
+            hipLaunchKernelGGL((k_gemm_f64<kEpiGather, BT, FOLD, VEC>), grid, dim3(kThreads), 0, s, g);
+            break;
+        } else {
+            return hipErrorInvalidValue;
+        }
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -56,7 +56,25 @@ struct LineCfg {
     int tuned = 0;    // 1: chosen by bs_autotune_line
 };
 
+// Geometric cube blocks of one block size: one group per (class of patches
+// with equal dims, eps and h; block shape), its blocks colour 0 first.
+struct CubeGroup {
+    int nb = 0, nblk = 0, ncol0 = 0;   // cells per block, blocks, colour-0 blocks
+    // byte offsets into CubePlan::buf: inverse (nb x nb, row-major), per-cell
+    // u / f offsets (nb int32 each), per-block u / f bases (nblk int64 each)
+    int64_t o_ainv = 0, o_uoff = 0, o_foff = 0, o_ubase = 0, o_fbase = 0;
+    double ex = 0, ey = 0, ez = 0, h2 = 0;
+    int64_t sy = 0, sz = 0;
+};
+struct CubePlan {
+    std::vector<CubeGroup> groups;
+    DevBuf buf;    // tables and inverses
+    DevBuf rbuf;   // block-major residual scratch (largest group)
+    int64_t inv_bytes = 0;
+};
+
 bs_status fail(bs_status st, const char *fmt, ...);
+bs_status cube_rebuild_all(bs_patchset *ps);   // after an eps change
 bs_status hip_fail(hipError_t e, const char *what);
 bs_status upload(DevBuf &b, const void *src, size_t bytes, const char *what);
 bs_status dev_alloc(DevBuf &b, size_t bytes, const char *what);
@@ -88,6 +106,8 @@ struct bs_patchset {
     // cached work lists and tuned configurations
     std::map<bs::WorkKey, std::unique_ptr<bs::WorkList>> lists;
     std::map<std::pair<int, int>, bs::LineCfg> line_cfg;   // (axis, colour_mode) -> cfg
+    // cube-block plans, per block size (bx, by, bz), built by bs_cube_prepare
+    std::map<std::tuple<int, int, int>, std::unique_ptr<bs::CubePlan>> cube;
     // captured sweep sequences, replayed with one graph launch
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
     hipStream_t capture_stream = nullptr;

@@ -6,7 +6,7 @@
 
 namespace bs {
 
-enum { kEpiStore = 0, kEpiScale = 1, kEpiUpdate = 2, kEpiD64 = 3, kEpiUpdateAcc = 4 };
+enum { kEpiStore = 0, kEpiScale = 1, kEpiUpdate = 2, kEpiD64 = 3, kEpiUpdateAcc = 4, kEpiGather = 5 };
 
 // C_b = A_b B_b, row-major, b in [0, batch); a zero batch stride shares an
 // operand across the batch.  Epilogues:
@@ -14,6 +14,9 @@ enum { kEpiStore = 0, kEpiScale = 1, kEpiUpdate = 2, kEpiD64 = 3, kEpiUpdateAcc 
 //   kEpiScale:  C = (A B) .* scale[b*sc_b + m*sc_m + n*sc_n]
 //   kEpiUpdate: udst[u] = usrc[u] + omega (A B), u = u0 + b*u_b + m*u_m + n*u_n,
 //               for columns n with (n + colour_shift) % 2 == ncolour (all if ncolour < 0)
+//   kEpiGather: udst[u] = usrc[u] + omega (A B), u = ebase[m] + eoff[n] (rows
+//               are cube blocks, columns the cells of a block; FP64 only,
+//               b_trans = 1, fold = 0)
 struct GemmArgs {
     const double *A;
     int64_t lda, sA;
@@ -40,6 +43,8 @@ struct GemmArgs {
     //     scale grid and of the u mapping (1, 0, 1, 0 if row_s = 0).
     int b_trans, fold, Kfull, fsign;
     int row_s, row_o, col_s, col_o;
+    const int64_t *ebase;
+    const int32_t *eoff;
 };
 
 hipError_t launch_gemm_f64(const GemmArgs &g, int epi, hipStream_t s);

@@ -134,6 +134,25 @@ def c4_patchset(npatch: int = 3000, seed: int = 4, edges=EDGE_CHOICES) -> PatchS
     return PatchSet(dims=dims, eps=eps, h=h, u0=us, f=fs)
 
 
+def uniform_patchset(npatch: int = 64, n: int = 64, seed: int = 6, eps=(1.0, 1.0, 1.0)) -> PatchSet:
+    """npatch equal patches of n^3 cells (the block-size study's 64 patches of
+    64^3): eps as given, h = 1/n, then per patch f, u, ghosts ~ U[-1,1]."""
+    rng = rng_for(seed)
+    dims = np.full((npatch, 3), n, dtype=np.int32)
+    epsa = np.tile(np.asarray(eps, dtype=np.float64), (npatch, 1))
+    h = np.full(npatch, 1.0 / n)
+    gm = ghost_mask(n, n, n)
+    us, fs = [], []
+    for _ in range(npatch):
+        f = rng.uniform(-1.0, 1.0, size=(n, n, n))
+        u = np.empty((n + 2, n + 2, n + 2))
+        u[1:-1, 1:-1, 1:-1] = rng.uniform(-1.0, 1.0, size=(n, n, n))
+        u[gm] = rng.uniform(-1.0, 1.0, size=int(gm.sum()))
+        us.append(u)
+        fs.append(f)
+    return PatchSet(dims=dims, eps=epsa, h=h, u0=us, f=fs)
+
+
 def small_patch(nx, ny, nz, seed, eps=None, ghosts="uniform", u0="uniform", f="uniform") -> Patch:
     """A small random test patch; eps defaults to distinct per-axis weights."""
     if eps is None:
