@@ -39,6 +39,11 @@ def parse():
                     help="fixed batched sequence for rocprofv3 (3000 AMR patches: 1 GiB copy, 3 x-line chaotic GS sweeps)")
     ap.add_argument("--profile-planes", action="store_true",
                     help="fixed plane-sweep sequence for rocprofv3 (512^3: FP64, FP32, BF16 refine 1; 2 sweeps each)")
+    ap.add_argument("--cubes", action="store_true",
+                    help="only the cube-block timings (64 patches of 64^3), printed as JSON")
+    ap.add_argument("--profile-cubes", action="store_true",
+                    help="fixed cube-block sequence for rocprofv3 (64 patches of 64^3: 1 GiB copy, then one "
+                         "Jacobi sweep each with 8^3 and 4^3 blocks)")
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3 counter runs: a 1 GiB device copy (reference for FETCH_SIZE / "
                          "WRITE_SIZE scaling), then 10 z-line Jacobi and 10 chaotic GS sweep launches; no JSON")
@@ -127,6 +132,30 @@ def profile_planes_run():
         del u
 
 
+def profile_cubes_run():
+    """Fixed cube-block sequence for kernel traces and counters."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import uniform_patchset
+
+    torch.cuda.set_device(0)
+    x = torch.empty(2 ** 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    s = uniform_patchset()
+    ps = bs.PatchSet([tuple(d) for d in s.dims], [tuple(e) for e in s.eps], list(s.h))
+    ps.set_graphs(False)
+    u, f, w = ps.pack_u(s.u0), ps.pack_f(s.f), ps.empty_u()
+    for blk in ((8, 8, 8), (4, 4, 4)):
+        ps.cube_prepare(blk)
+        ps.cube_relax(blk, "jacobi", 0.8, 1, u, f, w)
+        torch.cuda.synchronize()
+        print("profile cubes %s done" % (blk,), flush=True)
+
+
 def measured_traffic():
     """HBM bytes per launch of the z-line sweep kernel from the committed
     counter summary (FETCH_SIZE / WRITE_SIZE, scaled by a copy of known size),
@@ -179,6 +208,35 @@ def ev_ms(fn, reps=3):
         ts.append(a.elapsed_time(b))
     ts.sort()
     return ts[len(ts) // 2]
+
+
+def cube_forms(blocks=((2, 2, 2), (4, 4, 4), (8, 8, 8)), nsweeps=3):
+    """Cube-block sweeps on 64 patches of 64^3: ms per sweep, cells per second,
+    and the block products' rate (2 nb flop per cell for blocks of nb cells)."""
+    import paper_1208_1975_amd as bs
+    from workloads import uniform_patchset
+
+    s = uniform_patchset()
+    ps = bs.PatchSet([tuple(d) for d in s.dims], [tuple(e) for e in s.eps], list(s.h))
+    u0, f, w = ps.pack_u(s.u0), ps.pack_f(s.f), ps.empty_u()
+    u = u0.clone()
+    cells = s.cells()
+    res = {}
+    for blk in blocks:
+        nb = blk[0] * blk[1] * blk[2]
+        ps.cube_prepare(blk)
+        for scheme, omega in (("jacobi", 0.8), ("chaotic", 1.0)):
+            ps.cube_relax(blk, scheme, omega, nsweeps, u, f, w)   # capture the graph
+            ms = ev_ms(lambda: ps.cube_relax(blk, scheme, omega, nsweeps, u, f, w), reps=5)
+            per = ms / nsweeps
+            res["%dx%dx%d_%s" % (blk + (scheme,))] = {
+                "ms_per_sweep": round(per, 4), "glups": round(cells / (per * 1e-3) / 1e9, 3),
+                "product_tflops": round(2.0 * nb * cells / (per * 1e-3) / 1e12, 2),
+                "mfma_frac_fp64": round(2.0 * nb * cells / (per * 1e-3) / 78.6e12, 4),
+                "hbm_frac_24B": round(24.0 * cells / (per * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+            u.copy_(u0)
+    ps.close()
+    return res
 
 
 def forms():
@@ -275,6 +333,11 @@ def forms():
     del u, f
     torch.cuda.empty_cache()
 
+    # geometric cube blocks (the paper's own block kind) on the block-size
+    # study's 64 patches of 64^3, eps = 1: 3 sweeps per block size and scheme
+    out["cube_blocks_64x64cube"] = cube_forms()
+    torch.cuda.empty_cache()
+
     # 128^3 differentiable smoother: K = 20 z-line Jacobi, checkpoint every 5
     p = c5_patch()
     ps = bs.PatchSet([p.dims], [p.eps], [p.h])
@@ -331,11 +394,19 @@ def main():
     if args.profile_c4:
         profile_c4_run()
         return
+    if args.profile_cubes:
+        profile_cubes_run()
+        return
+    if args.cubes:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(cube_forms()), flush=True)
+        return
     if args.profile:
         profile_run()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only; --gpus %d is not supported by this build" % args.gpus)
+        print("bench.py measures one GPU; --gpus %d is not supported" % args.gpus)
         sys.exit(2)
 
     import torch

@@ -169,9 +169,9 @@ bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme,
  * restricted to the block's cells), computed once, on the host, by
  * bs_cube_prepare; patches with equal dims, eps and h share them.
  *
- * bs_cube_prepare: builds the inverses, block tables and a residual scratch
- * of 8 bytes per cell of the largest group of equally shaped blocks for this
- * block size; synchronous (allocates device memory).  Repeated calls with a
+ * bs_cube_prepare: builds the inverses, block tables and, for blocks of more
+ * than 64 cells, a residual scratch of 8 bytes per cell of the largest group
+ * of equally shaped blocks; synchronous (allocates device memory).  Repeated calls with a
  * prepared size return BS_OK at once; bs_set_eps rebuilds every prepared
  * size.  BS_ERR_INVALID for an edge < 1; BS_ERR_UNSUPPORTED for blocks of
  * more than 512 cells after clipping (8^3 is the paper's largest) or more

@@ -129,20 +129,26 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return (b & 7) * (full >> 3) + (b >> 3);
 }
 
-// Geometric cube blocks (k_cube.hip): residuals of nblk equally shaped blocks
-// into R[block][cell]; cell c of block b is u[ubase[b] + uoff[c]] and
-// f[fbase[b] + foff[c]].
-struct CubeResidArgs {
+// Geometric cube blocks (k_cube.hip), nblk equally shaped blocks of nb cells;
+// cell c of block b is u[ubase[b] + uoff[c]] and f[fbase[b] + foff[c]].
+//   launch_cube_resid: residuals into R[block][cell] (any nb);
+//   launch_cube_small: nb <= 64, fused: residuals, product with the inverse
+//     ainv (nb x nb, row-major) and update dst = u + omega du in one kernel.
+struct CubeArgs {
     const double *u;
+    double *dst;
     const double *f;
     double *R;
+    const double *ainv;
     const int64_t *ubase, *fbase;
     const int32_t *uoff, *foff;
-    int32_t nb, nblk, per;      // cells per block, blocks, blocks per workgroup
+    int32_t nb, nblk, per;      // cells per block, blocks, blocks per workgroup (residual kernel)
     int64_t sy, sz;             // u strides of y and z
-    double ex, ey, ez, h2;
+    double ex, ey, ez, h2, omega;
 };
-hipError_t launch_cube_resid(const CubeResidArgs &a, hipStream_t s);
+constexpr int kCubeSmallCells = 64;
+hipError_t launch_cube_resid(const CubeArgs &a, hipStream_t s);
+hipError_t launch_cube_small(const CubeArgs &a, hipStream_t s);
 
 // Adjoint of damped Jacobi line sweeps (k_adjoint.hip).
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);

@@ -5,6 +5,7 @@
 //   step 1  R[block][cell] = h^2 f - A u          (k_cube_resid)
 //   step 2  DU = R Ainv^T                          (FP64 matrix cores)
 //   step 3  u' = u + omega DU                      (the product's epilogue)
+// or, for blocks of up to 64 cells, all three in one kernel (k_cube_small).
 // The blocks of a patch of equal shape share one inverse (constant
 // coefficients), so step 2 is one dense product per shape: the blocks are the
 // rows, which is what makes it a matrix-core contraction rather than the
@@ -194,17 +195,16 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
                     fb[0].insert(fb[0].end(), fb[1].begin(), fb[1].end());
                     g.o_ubase = img.put(ub[0].data(), ub[0].size() * 8);
                     g.o_fbase = img.put(fb[0].data(), fb[0].size() * 8);
-                    rmax = std::max(rmax, int64_t(g.nblk) * nb);
+                    if (nb > kCubeSmallCells) rmax = std::max(rmax, int64_t(g.nblk) * nb);
                     plan.groups.push_back(g);
                 }
     }
     bs_status st = upload(plan.buf, img.bytes.data(), img.bytes.size(), "cube tables");
     if (st != BS_OK) return st;
     plan.inv_bytes = inv_bytes;
-    if (plan.rbuf.bytes < size_t(rmax) * 8) {
-        plan.rbuf.reset();
-        if ((st = dev_alloc(plan.rbuf, size_t(rmax) * 8, "cube residual scratch")) != BS_OK) return st;
-    }
+    if (plan.rbuf.bytes < size_t(rmax) * 8 &&
+        (st = dev_alloc(plan.rbuf, size_t(rmax) * 8, "cube residual scratch")) != BS_OK)
+        return st;
     return BS_OK;
 }
 
@@ -217,10 +217,13 @@ bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, int lo, int n, con
     const int64_t *ub = reinterpret_cast<const int64_t *>(base + g.o_ubase) + lo;
     const int64_t *fb = reinterpret_cast<const int64_t *>(base + g.o_fbase) + lo;
     const int32_t *uo = reinterpret_cast<const int32_t *>(base + g.o_uoff);
-    CubeResidArgs a{};
+    CubeArgs a{};
     a.u = src;
+    a.dst = dst;
     a.f = f;
     a.R = static_cast<double *>(plan.rbuf.p);
+    a.ainv = reinterpret_cast<const double *>(base + g.o_ainv);
+    a.omega = omega;
     a.ubase = ub;
     a.fbase = fb;
     a.uoff = uo;
@@ -234,6 +237,10 @@ bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, int lo, int n, con
     a.ey = g.ey;
     a.ez = g.ez;
     a.h2 = g.h2;
+    if (g.nb <= kCubeSmallCells) {   // all three steps in one kernel
+        hipError_t e = launch_cube_small(a, stream);
+        return e == hipSuccess ? BS_OK : hip_fail(e, "cube blocks (fused)");
+    }
     hipError_t e = launch_cube_resid(a, stream);
     if (e != hipSuccess) return hip_fail(e, "cube residual");
     GemmArgs m{};

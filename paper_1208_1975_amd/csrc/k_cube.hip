@@ -1,20 +1,34 @@
-// Geometric cube blocks (section 2; the block Jacobi algorithm on GPUs, step
-// 1): the residual of every cell of a run of equally shaped blocks, gathered
-// into a block-major matrix R[block][cell] (cells of a block numbered x
-// fastest).  Step 2, the product with the precomputed block inverse, is the
-// FP64 matrix-core product R Ainv^T, whose epilogue applies step 3 (the
-// update) through the same offset tables.
+// Geometric cube blocks (section 2; the block Jacobi algorithm on GPUs).
+//
+// Large blocks (more than 64 cells): step 1, the residual of every cell of a
+// run of equally shaped blocks, is gathered into a block-major matrix
+// R[block][cell] (cells of a block numbered x fastest); step 2, the product
+// with the precomputed block inverse, is the FP64 matrix-core product
+// R Ainv^T, whose epilogue applies step 3 (the update) through the same
+// offset tables.
+//
+// Small blocks (up to 64 cells): all three steps in one kernel.  The inverse
+// (at most 64 x 64) sits in LDS and each wavefront forms its blocks'
+// residuals in registers, multiplies them by the inverse on the matrix cores
+// and writes the updated cells: u and f are read once and the result written
+// once, with no residual matrix in HBM.
 #include <cstdint>
 
 #include "bs_internal.h"
 
 namespace bs {
 
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+}  // namespace
+
 // A workgroup owns `per` consecutive blocks (256 / nb of them for blocks of
 // up to 256 cells, else one); its threads walk the per * nb cells with the
 // cell index fastest, so the x-runs of a block are read with consecutive
 // lanes and R is written contiguously.
-__global__ void __launch_bounds__(256) k_cube_resid(CubeResidArgs a)
+__global__ void __launch_bounds__(256) k_cube_resid(CubeArgs a)
 {
     const int b0 = blockIdx.x * a.per;
     const int tot = a.per * a.nb;
@@ -32,12 +46,123 @@ __global__ void __launch_bounds__(256) k_cube_resid(CubeResidArgs a)
     }
 }
 
-hipError_t launch_cube_resid(const CubeResidArgs &a, hipStream_t s)
+hipError_t launch_cube_resid(const CubeArgs &a, hipStream_t s)
 {
     if (a.nblk <= 0) return hipSuccess;
     if (a.nb <= 0 || a.per <= 0) return hipErrorInvalidValue;
     const int grid = (a.nblk + a.per - 1) / a.per;
     hipLaunchKernelGGL(k_cube_resid, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Fused small blocks: NP = nb rounded up to 16, 32 or 64.  Wavefront w of a
+// workgroup owns blocks 16w..16w+15 (rows of the product) and forms their
+// residuals straight into the matrix-core operand layout: lane l holds the
+// residual of cell k + l/16 of block l%16 for k = 0, 4, ..., NP-4 -- the A
+// operand of v_mfma_f64_16x16x4 -- so residuals never touch LDS or HBM; only
+// the inverse (Bs[k][n] = Ainv[n][k], zero outside nb x nb) and the cell
+// offsets are staged in LDS.  With consecutive blocks along x, one load
+// instruction reads 16 blocks x 4 cells of a row: for 4-cell block edges a
+// contiguous x-run of 64 cells.  All loads use in-range (clamped) indices;
+// padding cells and blocks past the end give zero through selects, so the
+// loads of all NP/4 operands can be in flight together.  Result layout as in
+// the plane products: register r holds row 4r + l/16, column l%16.
+// Workgroups are mapped XCD-contiguously, so neighbouring blocks (which read
+// each other's faces) share an L2.
+template <int NP>
+__global__ void __launch_bounds__(256) k_cube_small(CubeArgs a)
+{
+    __shared__ double Bs[NP][NP + 1];
+    __shared__ int32_t So[2][NP];   // u and f offsets of each cell (cell 0's past nb)
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int nb = a.nb;
+    const int b0 = xcd_block(blockIdx.x, gridDim.x) * 64;
+
+#pragma unroll
+    for (int e = tid; e < NP * NP; e += 256) {
+        const int n = e / NP, k = e % NP;
+        Bs[k][n] = (n < nb && k < nb) ? a.ainv[n * nb + k] : 0.0;
+    }
+    if (tid < NP) {
+        So[0][tid] = a.uoff[tid < nb ? tid : 0];
+        So[1][tid] = a.foff[tid < nb ? tid : 0];
+    }
+    const int ba = b0 + w * 16 + l16;            // this lane's block for the operand
+    const bool bok = ba < a.nblk;
+    const int64_t ub = a.ubase[bok ? ba : b0], fb = a.fbase[bok ? ba : b0];
+    __syncthreads();
+
+    // operands in batches of four: the 32 loads of a batch are issued before
+    // any of them is consumed
+    double ra[NP / 4];
+#pragma unroll
+    for (int t0 = 0; t0 < NP / 4; t0 += 4) {
+        double v[4][8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = 4 * (t0 + q) + lk;
+            const int64_t iu = ub + So[0][c];
+            v[q][0] = a.u[iu];
+            v[q][1] = a.u[iu - 1];
+            v[q][2] = a.u[iu + 1];
+            v[q][3] = a.u[iu - a.sy];
+            v[q][4] = a.u[iu + a.sy];
+            v[q][5] = a.u[iu - a.sz];
+            v[q][6] = a.u[iu + a.sz];
+            v[q][7] = a.f[fb + So[1][c]];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = 4 * (t0 + q) + lk;
+            const double uc = v[q][0];
+            const double ax = a.ex * (2.0 * uc - v[q][1] - v[q][2]);
+            const double ay = a.ey * (2.0 * uc - v[q][3] - v[q][4]);
+            const double az = a.ez * (2.0 * uc - v[q][5] - v[q][6]);
+            const double r = a.h2 * v[q][7] - (ax + ay + az);
+            ra[t0 + q] = (bok && c < nb) ? r : 0.0;
+        }
+    }
+
+    dbl4 acc[NP / 16];
+#pragma unroll
+    for (int j = 0; j < NP / 16; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NP / 4; ++t)
+#pragma unroll
+        for (int j = 0; j < NP / 16; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[t], Bs[4 * t + lk][j * 16 + l16], acc[j], 0, 0, 0);
+
+    // every value a lane's outputs read is loaded before any of its stores
+    int64_t idx[NP / 16][4];
+    double in[NP / 16][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int b = b0 + w * 16 + 4 * r + lk;
+        const int64_t base = a.ubase[b < a.nblk ? b : b0];
+#pragma unroll
+        for (int j = 0; j < NP / 16; ++j) {
+            idx[j][r] = base + So[0][j * 16 + l16];
+            in[j][r] = a.u[idx[j][r]];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int b = b0 + w * 16 + 4 * r + lk;
+#pragma unroll
+        for (int j = 0; j < NP / 16; ++j)
+            if (b < a.nblk && j * 16 + l16 < nb) a.dst[idx[j][r]] = fma(a.omega, acc[j][r], in[j][r]);
+    }
+}
+
+hipError_t launch_cube_small(const CubeArgs &a, hipStream_t s)
+{
+    if (a.nblk <= 0) return hipSuccess;
+    if (a.nb <= 0 || a.nb > kCubeSmallCells) return hipErrorInvalidValue;
+    const dim3 grid((a.nblk + 63) / 64);
+    if (a.nb <= 16) hipLaunchKernelGGL(k_cube_small<16>, grid, dim3(256), 0, s, a);
+    else if (a.nb <= 32) hipLaunchKernelGGL(k_cube_small<32>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_cube_small<64>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
