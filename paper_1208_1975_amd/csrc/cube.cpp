@@ -171,7 +171,6 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
                     g.o_foff = img.put(fo.data(), fo.size() * 4);
                     // this shape's blocks: origin index i0 = bi * cb runs over the
                     // full blocks if the edge is the full one, else the last block
-                    std::vector<int64_t> ub[2], fb[2];
                     auto origins = [&](int a, int s) {
                         std::vector<int> o;
                         if (s == cb[a] && n[a] / cb[a] > 0)
@@ -181,20 +180,39 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
                         return o;
                     };
                     const std::vector<int> oi = origins(0, sx), oj = origins(1, sy), ok = origins(2, sz);
-                    for (int p : cl.second)
-                        for (int k0 : ok)
-                            for (int j0 : oj)
-                                for (int i0 : oi) {
-                                    const int col = (i0 / cb[0] + j0 / cb[1] + k0 / cb[2]) & 1;
-                                    ub[col].push_back(ps->uoff[p] + (k0 + 1) * SZ + (j0 + 1) * SY + (i0 + 1));
-                                    fb[col].push_back(ps->foff[p] + (int64_t(k0) * ny + j0) * nx + i0);
-                                }
-                    g.ncol0 = int(ub[0].size());
-                    g.nblk = int(ub[0].size() + ub[1].size());
-                    ub[0].insert(ub[0].end(), ub[1].begin(), ub[1].end());
-                    fb[0].insert(fb[0].end(), fb[1].begin(), fb[1].end());
-                    g.o_ubase = img.put(ub[0].data(), ub[0].size() * 8);
-                    g.o_fbase = img.put(fb[0].data(), fb[0].size() * 8);
+                    // Block lists in dispatch order: x fastest, then y within a band of
+                    // G block rows, then z, then the next band, so that a run of 64
+                    // blocks (one workgroup of the fused kernel) is a slab one block
+                    // thick in z and the next run is its z-neighbour: the face both
+                    // read is fetched once into the XCD's L2.  `want`: the colour to
+                    // list (-1: every block, the Jacobi list).
+                    std::vector<int64_t> ub, fb;
+                    auto emit = [&](int want) {
+                        const int per_row = want < 0 ? int(oi.size()) : int(oi.size() + 1) / 2;
+                        const int G = std::max(1, 64 / std::max(1, per_row));
+                        for (int p : cl.second)
+                            for (size_t jg = 0; jg < oj.size(); jg += G)
+                                for (int k0 : ok)
+                                    for (size_t jj = jg; jj < std::min(oj.size(), jg + G); ++jj)
+                                        for (int i0 : oi) {
+                                            const int j0 = oj[jj];
+                                            const int col = (i0 / cb[0] + j0 / cb[1] + k0 / cb[2]) & 1;
+                                            if (want >= 0 && col != want) continue;
+                                            ub.push_back(ps->uoff[p] + (k0 + 1) * SZ + (j0 + 1) * SY + (i0 + 1));
+                                            fb.push_back(ps->foff[p] + (int64_t(k0) * ny + j0) * nx + i0);
+                                        }
+                    };
+                    emit(-1);
+                    g.nblk = int(ub.size());
+                    g.o_jbase = img.put(ub.data(), ub.size() * 8);
+                    g.o_jfbase = img.put(fb.data(), fb.size() * 8);
+                    ub.clear();
+                    fb.clear();
+                    emit(0);
+                    g.ncol0 = int(ub.size());
+                    emit(1);
+                    g.o_ubase = img.put(ub.data(), ub.size() * 8);
+                    g.o_fbase = img.put(fb.data(), fb.size() * 8);
                     if (nb > kCubeSmallCells) rmax = std::max(rmax, int64_t(g.nblk) * nb);
                     plan.groups.push_back(g);
                 }
@@ -209,13 +227,13 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
 }
 
 // Steps 1-3 for blocks [lo, lo + n) of group g: src -> dst.
-bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, int lo, int n, const double *src, double *dst,
-                    const double *f, double omega, hipStream_t stream)
+bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, bool jacobi, int lo, int n, const double *src,
+                    double *dst, const double *f, double omega, hipStream_t stream)
 {
     if (n <= 0) return BS_OK;
     const char *base = static_cast<const char *>(plan.buf.p);
-    const int64_t *ub = reinterpret_cast<const int64_t *>(base + g.o_ubase) + lo;
-    const int64_t *fb = reinterpret_cast<const int64_t *>(base + g.o_fbase) + lo;
+    const int64_t *ub = reinterpret_cast<const int64_t *>(base + (jacobi ? g.o_jbase : g.o_ubase)) + lo;
+    const int64_t *fb = reinterpret_cast<const int64_t *>(base + (jacobi ? g.o_jfbase : g.o_fbase)) + lo;
     const int32_t *uo = reinterpret_cast<const int32_t *>(base + g.o_uoff);
     CubeArgs a{};
     a.u = src;
@@ -275,7 +293,7 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
             const double *src = (s & 1) ? work : u;
             double *dst = (s & 1) ? u : work;
             for (const CubeGroup &g : plan.groups)
-                if ((st = cube_pass(plan, g, 0, g.nblk, src, dst, f, omega, stream)) != BS_OK) return st;
+                if ((st = cube_pass(plan, g, true, 0, g.nblk, src, dst, f, omega, stream)) != BS_OK) return st;
         }
         if (nsweeps & 1) {
             e = launch_interior_copy(work, u, pdd, ps->npatch, stream);
@@ -288,7 +306,7 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
         for (int col = 0; col < 2; ++col)
             for (const CubeGroup &g : plan.groups) {
                 const int lo = col ? g.ncol0 : 0, n = col ? g.nblk - g.ncol0 : g.ncol0;
-                if ((st = cube_pass(plan, g, lo, n, u, u, f, omega, stream)) != BS_OK) return st;
+                if ((st = cube_pass(plan, g, false, lo, n, u, u, f, omega, stream)) != BS_OK) return st;
             }
     return BS_OK;
 }

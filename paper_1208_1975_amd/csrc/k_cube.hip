@@ -27,10 +27,11 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // A workgroup owns `per` consecutive blocks (256 / nb of them for blocks of
 // up to 256 cells, else one); its threads walk the per * nb cells with the
 // cell index fastest, so the x-runs of a block are read with consecutive
-// lanes and R is written contiguously.
+// lanes and R is written contiguously.  Workgroups map XCD-contiguously:
+// neighbouring blocks share cache lines and faces in one L2.
 __global__ void __launch_bounds__(256) k_cube_resid(CubeArgs a)
 {
-    const int b0 = blockIdx.x * a.per;
+    const int b0 = xcd_block(blockIdx.x, gridDim.x) * a.per;
     const int tot = a.per * a.nb;
     for (int e = threadIdx.x; e < tot; e += 256) {
         const int lb = e / a.nb;

@@ -45,7 +45,10 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
     __shared__ __attribute__((aligned(16))) double As[2][BK][BM + 2];
     __shared__ __attribute__((aligned(16))) double Bs[2][BK][BN + 2];
     const int b = blockIdx.z;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    // tiles of one product map XCD-contiguously, column tiles of a row tile
+    // together: the workgroups that read the same rows of A share an L2
+    const int tile = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int m0 = (tile / gridDim.x) * BM, n0 = (tile % gridDim.x) * BN;
     const double *A = g.A + (int64_t)b * g.sA;
     const double *B = g.B + (int64_t)b * g.sB;
     const int tid = threadIdx.x;

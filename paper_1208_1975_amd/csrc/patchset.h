@@ -57,12 +57,14 @@ struct LineCfg {
 };
 
 // Geometric cube blocks of one block size: one group per (class of patches
-// with equal dims, eps and h; block shape), its blocks colour 0 first.
+// with equal dims, eps and h; block shape).
 struct CubeGroup {
     int nb = 0, nblk = 0, ncol0 = 0;   // cells per block, blocks, colour-0 blocks
     // byte offsets into CubePlan::buf: inverse (nb x nb, row-major), per-cell
     // u / f offsets (nb int32 each), per-block u / f bases (nblk int64 each)
-    int64_t o_ainv = 0, o_uoff = 0, o_foff = 0, o_ubase = 0, o_fbase = 0;
+    // in colour order (Gauss-Seidel) and in dispatch order without colours
+    // (Jacobi)
+    int64_t o_ainv = 0, o_uoff = 0, o_foff = 0, o_ubase = 0, o_fbase = 0, o_jbase = 0, o_jfbase = 0;
     double ex = 0, ey = 0, ez = 0, h2 = 0;
     int64_t sy = 0, sz = 0;
 };
