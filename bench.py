@@ -239,6 +239,47 @@ def cube_forms(blocks=((2, 2, 2), (4, 4, 4), (8, 8, 8)), nsweeps=3):
     return res
 
 
+def cube_convergence(n=64, long_sweeps=10000):
+    """The block-size study (section 3) on the GPU: one 64^3 patch, eps = 1,
+    f = 0, random initial guess, zero ghosts.  Relative residual after 3
+    sweeps per block size and scheme, and the Jacobi convergence factor
+    (r_{2K} / r_K)^(1/K) for K = long_sweeps / 2, the window starting near
+    sweep 5000 as in the paper (point blocks: closed form
+    1 - 1.6 sin^2(pi / (2 (n + 1))))."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import make_patch
+
+    p = make_patch(n, n, n, (1.0, 1.0, 1.0), 1.0 / n, seed=8, f="zero", u0="uniform", ghosts="zero")
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    u0, f, w = ps.pack_u([p.u0]), ps.pack_f([p.f]), ps.empty_u()
+    n2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def rnorm(u):
+        ps.residual(u, f, None, n2)
+        return math.sqrt(float(n2.item()))
+
+    r0 = rnorm(u0)
+    half = long_sweeps // 2
+    res = {"closed_form_point_jacobi_factor": 1.0 - 1.6 * math.sin(math.pi / (2 * (n + 1))) ** 2}
+    for b in ((1, 1, 1), (2, 2, 2), (4, 2, 2), (4, 4, 2), (4, 4, 4), (8, 4, 4), (8, 8, 4), (8, 8, 8)):
+        ps.cube_prepare(b)
+        e = {}
+        for scheme, omega in (("jacobi", 0.8), ("chaotic", 1.0)):
+            u = u0.clone()
+            ps.cube_relax(b, scheme, omega, 3, u, f, w)
+            e[scheme + "_rel_residual_3"] = round(rnorm(u) / r0, 6)
+        u = u0.clone()
+        ps.cube_relax(b, "jacobi", 0.8, half, u, f, w)
+        ra = rnorm(u)
+        ps.cube_relax(b, "jacobi", 0.8, half, u, f, w)
+        e["jacobi_factor"] = round((rnorm(u) / ra) ** (1.0 / half), 7)
+        res["%dx%dx%d" % b] = e
+    ps.close()
+    return res
+
+
 def forms():
     """The other configurations on the same GPU: timings, rates and errors."""
     import torch
@@ -336,6 +377,7 @@ def forms():
     # geometric cube blocks (the paper's own block kind) on the block-size
     # study's 64 patches of 64^3, eps = 1: 3 sweeps per block size and scheme
     out["cube_blocks_64x64cube"] = cube_forms()
+    out["cube_block_size_study_64"] = cube_convergence()
     torch.cuda.empty_cache()
 
     # 128^3 differentiable smoother: K = 20 z-line Jacobi, checkpoint every 5
@@ -400,7 +442,7 @@ def main():
     if args.cubes:
         import torch
         torch.cuda.set_device(0)
-        print(json.dumps(cube_forms()), flush=True)
+        print(json.dumps({"timings": cube_forms(), "block_size_study": cube_convergence()}), flush=True)
         return
     if args.profile:
         profile_run()

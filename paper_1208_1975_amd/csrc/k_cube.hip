@@ -103,6 +103,10 @@ __global__ void __launch_bounds__(256) k_cube_small(CubeArgs a)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int c = 4 * (t0 + q) + lk;
+            if (NP == 16 && 4 * (t0 + q) >= nb) {   // rows wholly past a block of <= 12 cells (uniform)
+                for (int m = 0; m < 8; ++m) v[q][m] = 0.0;
+                continue;
+            }
             const int64_t iu = ub + So[0][c];
             v[q][0] = a.u[iu];
             v[q][1] = a.u[iu - 1];
@@ -129,10 +133,12 @@ __global__ void __launch_bounds__(256) k_cube_small(CubeArgs a)
 #pragma unroll
     for (int j = 0; j < NP / 16; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t < NP / 4; ++t)
+    for (int t = 0; t < NP / 4; ++t) {
+        if (NP == 16 && 4 * t >= nb) break;   // zero operand rows (uniform)
 #pragma unroll
         for (int j = 0; j < NP / 16; ++j)
             acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[t], Bs[4 * t + lk][j * 16 + l16], acc[j], 0, 0, 0);
+    }
 
     // every value a lane's outputs read is loaded before any of its stores
     int64_t idx[NP / 16][4];

@@ -167,3 +167,46 @@ def test_block_size_study_workload(block):
             log("cubes 64 x 64^3 block %s %s patch %d" % (block, scheme, p))
             ref = oracle.cube_sweeps(s.u0[p], s.f[p], tuple(s.eps[p]), s.h[p], block, osch, omega, 1)
             assert relerr(ps.view_u(u, p).cpu().numpy(), ref) < TOL, (block, scheme, p)
+
+
+def test_block_size_study_on_the_gpu():
+    """The block-size study's workload (one 64^3 patch, eps = 1, f = 0, random
+    initial guess): three sweeps improve monotonically with the block size for
+    both schemes; two sizes equal the oracle; point-block Jacobi converges at
+    the closed-form rate 1 - 1.6 sin^2(pi/130)."""
+    import math
+    from workloads import make_patch
+    n = 64
+    p = make_patch(n, n, n, (1.0, 1.0, 1.0), 1.0 / n, seed=8, f="zero", u0="uniform", ghosts="zero")
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    u0, f, w = ps.pack_u([p.u0]), ps.pack_f([p.f]), ps.empty_u()
+    n2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def rnorm(u):
+        ps.residual(u, f, None, n2)
+        torch.cuda.synchronize()
+        return math.sqrt(float(n2.item()))
+
+    r0 = rnorm(u0)
+    sizes = [(1, 1, 1), (2, 2, 2), (4, 2, 2), (4, 4, 2), (4, 4, 4), (8, 4, 4), (8, 8, 4), (8, 8, 8)]
+    for scheme, omega, osch in (("jacobi", 0.8, oracle.JACOBI), ("chaotic", 1.0, oracle.COLORED_GS)):
+        rel = []
+        for b in sizes:
+            ps.cube_prepare(b)
+            u = u0.clone()
+            ps.cube_relax(b, scheme, omega, 3, u, f, w)
+            rel.append(rnorm(u) / r0)
+            if b in ((4, 2, 2), (8, 8, 8)) and scheme == "jacobi":
+                log("study parity %s %s" % (b, scheme))
+                ref = oracle.cube_sweeps(p.u0, p.f, p.eps, p.h, b, osch, omega, 3)
+                assert relerr(ps.view_u(u, 0).cpu().numpy(), ref) < TOL, b
+        log("study %s %s" % (scheme, ["%.4f" % v for v in rel]))
+        assert all(a > b for a, b in zip(rel, rel[1:])), (scheme, rel)
+    u = u0.clone()
+    ps.cube_relax((1, 1, 1), "jacobi", 0.8, 2000, u, f, w)
+    ra = rnorm(u)
+    ps.cube_relax((1, 1, 1), "jacobi", 0.8, 2000, u, f, w)
+    factor = (rnorm(u) / ra) ** (1.0 / 2000)
+    rho = 1.0 - 1.6 * math.sin(math.pi / (2 * (n + 1))) ** 2
+    log("point Jacobi factor %.8f closed form %.8f" % (factor, rho))
+    assert abs(factor - rho) < 1e-4

@@ -99,3 +99,22 @@ def test_blocks_larger_than_the_patch_are_clipped():
     a = oracle.cube_sweeps(p.u0, p.f, p.eps, p.h, (8, 8, 8), oracle.JACOBI, 0.8, 2)
     b = oracle.cube_sweeps(p.u0, p.f, p.eps, p.h, (3, 4, 2), oracle.JACOBI, 0.8, 2)
     assert np.array_equal(a, b)
+
+
+STUDY_SIZES = [(2, 2, 2), (4, 2, 2), (4, 4, 2), (4, 4, 4), (8, 4, 4), (8, 8, 4), (8, 8, 8)]
+
+
+@pytest.mark.parametrize("scheme,omega", [("jacobi", 0.8), ("colored", 1.0)])
+def test_block_size_study_improves_monotonically(scheme, omega):
+    """The block-size study (section 3): random initial guess, f = 0, three
+    sweeps; the relative residual improves monotonically with the block sizes
+    the paper lists (here on a 16^3 patch; point blocks first)."""
+    from workloads import make_patch
+    p = make_patch(16, 16, 16, (1.0, 1.0, 1.0), 1.0 / 16, seed=7, f="zero", u0="uniform", ghosts="zero")
+    r0 = np.sqrt(oracle.residual(p.u0, p.f, p.eps, p.h)[1])
+    rel = []
+    for b in [(1, 1, 1)] + STUDY_SIZES:
+        u = oracle.cube_sweeps(p.u0, p.f, p.eps, p.h, b, CODE[scheme], omega, 3)
+        rel.append(np.sqrt(oracle.residual(u, p.f, p.eps, p.h)[1]) / r0)
+    assert all(a > b for a, b in zip(rel, rel[1:])), rel
+    assert rel[-1] < 0.5 * rel[0]
