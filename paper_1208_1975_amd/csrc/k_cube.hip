@@ -65,9 +65,11 @@ hipError_t launch_cube_resid(const CubeArgs &a, hipStream_t s)
 // offsets are staged in LDS.  With consecutive blocks along x, one load
 // instruction reads 16 blocks x 4 cells of a row: for 4-cell block edges a
 // contiguous x-run of 64 cells.  All loads use in-range (clamped) indices;
-// padding cells and blocks past the end give zero through selects, so the
-// loads of all NP/4 operands can be in flight together.  Result layout as in
-// the plane products: register r holds row 4r + l/16, column l%16.
+// padding cells and blocks past the end give zero through selects, so a
+// batch's loads are in flight together.  Result layout as in the plane
+// products: register r holds row 4r + l/16, column l%16; the update reads u
+// from the registers the residual loaded it into (through an exact identity
+// product), so the epilogue only stores.
 // Workgroups are mapped XCD-contiguously, so neighbouring blocks (which read
 // each other's faces) share an L2.
 template <int NP>
@@ -96,7 +98,17 @@ __global__ void __launch_bounds__(256) k_cube_small(CubeArgs a)
 
     // operands in batches of four: the 32 loads of a batch are issued before
     // any of them is consumed
-    double ra[NP / 4];
+    // Operands in batches of four (the 32 loads of a batch are issued before
+    // any is consumed), each multiplied into the result as soon as it is
+    // formed.  A second product with the identity, exact (one term u * 1 per
+    // output, the rest zeros), re-expresses the loaded centre values in the
+    // result layout, so the update needs no second load of u.
+    dbl4 acc[NP / 16], accu[NP / 16];
+#pragma unroll
+    for (int j = 0; j < NP / 16; ++j) {
+        acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        accu[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
 #pragma unroll
     for (int t0 = 0; t0 < NP / 4; t0 += 4) {
         double v[4][8];
@@ -119,46 +131,32 @@ __global__ void __launch_bounds__(256) k_cube_small(CubeArgs a)
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int c = 4 * (t0 + q) + lk;
+            const int t = t0 + q;
+            if (NP == 16 && 4 * t >= nb) break;   // zero operand rows (uniform)
+            const int c = 4 * t + lk;
             const double uc = v[q][0];
             const double ax = a.ex * (2.0 * uc - v[q][1] - v[q][2]);
             const double ay = a.ey * (2.0 * uc - v[q][3] - v[q][4]);
             const double az = a.ez * (2.0 * uc - v[q][5] - v[q][6]);
-            const double r = a.h2 * v[q][7] - (ax + ay + az);
-            ra[t0 + q] = (bok && c < nb) ? r : 0.0;
+            const double r = (bok && c < nb) ? a.h2 * v[q][7] - (ax + ay + az) : 0.0;
+#pragma unroll
+            for (int j = 0; j < NP / 16; ++j) {
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(r, Bs[c][j * 16 + l16], acc[j], 0, 0, 0);
+                accu[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(uc, c == j * 16 + l16 ? 1.0 : 0.0, accu[j], 0, 0, 0);
+            }
         }
     }
 
-    dbl4 acc[NP / 16];
-#pragma unroll
-    for (int j = 0; j < NP / 16; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < NP / 4; ++t) {
-        if (NP == 16 && 4 * t >= nb) break;   // zero operand rows (uniform)
-#pragma unroll
-        for (int j = 0; j < NP / 16; ++j)
-            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[t], Bs[4 * t + lk][j * 16 + l16], acc[j], 0, 0, 0);
-    }
-
-    // every value a lane's outputs read is loaded before any of its stores
-    int64_t idx[NP / 16][4];
-    double in[NP / 16][4];
+    // result register r of a lane: block 4r + l/16 of the wavefront, whose
+    // base the operand lane 4r + l/16 holds
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int b = b0 + w * 16 + 4 * r + lk;
-        const int64_t base = a.ubase[b < a.nblk ? b : b0];
-#pragma unroll
-        for (int j = 0; j < NP / 16; ++j) {
-            idx[j][r] = base + So[0][j * 16 + l16];
-            in[j][r] = a.u[idx[j][r]];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int b = b0 + w * 16 + 4 * r + lk;
+        const int m = 4 * r + lk;
+        const int64_t base = __shfl(ub, m);
+        const bool ok = b0 + w * 16 + m < a.nblk;
 #pragma unroll
         for (int j = 0; j < NP / 16; ++j)
-            if (b < a.nblk && j * 16 + l16 < nb) a.dst[idx[j][r]] = fma(a.omega, acc[j][r], in[j][r]);
+            if (ok && j * 16 + l16 < nb) a.dst[base + So[0][j * 16 + l16]] = fma(a.omega, acc[j][r], accu[j][r]);
     }
 }
 
