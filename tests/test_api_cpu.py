@@ -188,3 +188,11 @@ def test_line_table_solves_exactly(n, preq, eps):
     ref = scipy.linalg.solve_banded((1, 1), ab, r)
     got = partitioned_solve(tab, info, e, r)
     assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def test_cube_entry_points_validate_before_any_launch():
+    L = _lib()
+    rc, msg = _status(L.bs_cube_prepare(None, 4, 4, 4))
+    assert rc == bsmod.BS_ERR_INVALID and "null" in msg
+    rc, msg = _status(L.bs_cube_relax(None, 4, 4, 4, 0, 0.8, 1, 0, None, None, None, None))
+    assert rc == bsmod.BS_ERR_INVALID and "null" in msg
