@@ -370,6 +370,17 @@ def forms():
         "hbm_frac": round((24.0 * cells * 20) / (ms_one * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "per_patch_launches_ms": round(ms_pp, 3), "launches_per_patch_path": 20 * 2 * s.npatch,
         "speedup_vs_per_patch": round(ms_pp / ms_one, 2)}
+    # the same set with 4^3 cube blocks (every patch its own inverse): one fused
+    # launch per colour pass for all 3000 patches, 20 chaotic sweeps
+    t0 = time.time()
+    ps.cube_prepare((4, 4, 4))
+    prep_s = time.time() - t0
+    ps.cube_relax((4, 4, 4), "chaotic", 1.0, 20, u, f)                 # capture the graph
+    ms_c = ev_ms(lambda: ps.cube_relax((4, 4, 4), "chaotic", 1.0, 20, u, f), reps=3)
+    out["c4_amr3000_cube4_chaotic"] = {
+        "cells": cells, "prepare_s": round(prep_s, 3), "ms_20_sweeps": round(ms_c, 3),
+        "glups": round(cells * 20 / (ms_c * 1e-3) / 1e9, 3),
+        "hbm_frac": round((24.0 * cells * 20) / (ms_c * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
     ps.close()
     del u, f
     torch.cuda.empty_cache()

@@ -131,9 +131,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 
 // Geometric cube blocks (k_cube.hip), nblk equally shaped blocks of nb cells;
 // cell c of block b is u[ubase[b] + uoff[c]] and f[fbase[b] + foff[c]].
-//   launch_cube_resid: residuals into R[block][cell] (any nb);
-//   launch_cube_small: nb <= 64, fused: residuals, product with the inverse
-//     ainv (nb x nb, row-major) and update dst = u + omega du in one kernel.
+//   launch_cube_resid: residuals into R[block][cell] (any nb).
 struct CubeArgs {
     const double *u;
     double *dst;
@@ -148,7 +146,33 @@ struct CubeArgs {
 };
 constexpr int kCubeSmallCells = 64;
 hipError_t launch_cube_resid(const CubeArgs &a, hipStream_t s);
-hipError_t launch_cube_small(const CubeArgs &a, hipStream_t s);
+
+//   launch_cube_small: blocks of nb <= 64 cells of any number of groups in one
+//   launch, fused (residuals, product with the inverse ainv (nb x nb,
+//   row-major), update dst = u + omega du): one workgroup per chunk of at most
+//   64 consecutive blocks of one group's list; np = 16, 32 or 64, the same
+//   rounding of nb for every group of the launch.
+struct CubeGroupDev {
+    const double *ainv;
+    const int32_t *uoff, *foff;
+    const int64_t *ubase[2], *fbase[2];   // [0] colour-major list, [1] colour-free (Jacobi) list
+    int32_t nb, pad;
+    int64_t sy, sz;
+    double ex, ey, ez, h2;
+};
+struct CubeChunk {
+    int32_t group, first, end, pad;      // blocks [first, end) of the group's list
+};
+struct CubeBatchArgs {
+    const double *u;
+    double *dst;
+    const double *f;
+    const CubeGroupDev *groups;
+    const CubeChunk *chunks;
+    int32_t list;                        // index into ubase / fbase
+    double omega;
+};
+hipError_t launch_cube_small(const CubeBatchArgs &a, int nchunks, int np, hipStream_t s);
 
 // Adjoint of damped Jacobi line sweeps (k_adjoint.hip).
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);

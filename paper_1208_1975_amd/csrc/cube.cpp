@@ -5,7 +5,8 @@
 //   step 1  R[block][cell] = h^2 f - A u          (k_cube_resid)
 //   step 2  DU = R Ainv^T                          (FP64 matrix cores)
 //   step 3  u' = u + omega DU                      (the product's epilogue)
-// or, for blocks of up to 64 cells, all three in one kernel (k_cube_small).
+// or, for blocks of up to 64 cells, all three in one kernel (k_cube_small),
+// one launch per operand size for every patch class and shape of the set.
 // The blocks of a patch of equal shape share one inverse (constant
 // coefficients), so step 2 is one dense product per shape: the blocks are the
 // rows, which is what makes it a matrix-core contraction rather than the
@@ -219,6 +220,48 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
     }
     bs_status st = upload(plan.buf, img.bytes.data(), img.bytes.size(), "cube tables");
     if (st != BS_OK) return st;
+    // blocks of up to 64 cells: every group in one launch per operand size
+    const char *base = static_cast<const char *>(plan.buf.p);
+    std::vector<CubeGroupDev> gd;
+    std::vector<CubeChunk> lists[3][3];
+    for (const CubeGroup &g : plan.groups) {
+        if (g.nb > kCubeSmallCells) continue;
+        const int gi = int(gd.size());
+        CubeGroupDev d{};
+        d.ainv = reinterpret_cast<const double *>(base + g.o_ainv);
+        d.uoff = reinterpret_cast<const int32_t *>(base + g.o_uoff);
+        d.foff = reinterpret_cast<const int32_t *>(base + g.o_foff);
+        d.ubase[0] = reinterpret_cast<const int64_t *>(base + g.o_ubase);
+        d.fbase[0] = reinterpret_cast<const int64_t *>(base + g.o_fbase);
+        d.ubase[1] = reinterpret_cast<const int64_t *>(base + g.o_jbase);
+        d.fbase[1] = reinterpret_cast<const int64_t *>(base + g.o_jfbase);
+        d.nb = g.nb;
+        d.sy = g.sy;
+        d.sz = g.sz;
+        d.ex = g.ex;
+        d.ey = g.ey;
+        d.ez = g.ez;
+        d.h2 = g.h2;
+        gd.push_back(d);
+        const int npc = g.nb <= 16 ? 0 : (g.nb <= 32 ? 1 : 2);
+        auto cut = [&](std::vector<CubeChunk> &v, int lo, int hi) {
+            for (int b = lo; b < hi; b += 64) v.push_back(CubeChunk{gi, b, std::min(b + 64, hi), 0});
+        };
+        cut(lists[npc][0], 0, g.nblk);        // Jacobi: the colour-free list
+        cut(lists[npc][1], 0, g.ncol0);       // colour 0 of the colour-major list
+        cut(lists[npc][2], g.ncol0, g.nblk);  // colour 1
+    }
+    std::vector<CubeChunk> all;
+    for (int p = 0; p < 3; ++p)
+        for (int k = 0; k < 3; ++k) {
+            plan.chunk_off[p][k] = int(all.size());
+            plan.chunk_cnt[p][k] = int(lists[p][k].size());
+            all.insert(all.end(), lists[p][k].begin(), lists[p][k].end());
+        }
+    if ((st = upload(plan.gdesc, gd.data(), gd.size() * sizeof(CubeGroupDev), "cube group descriptors")) != BS_OK)
+        return st;
+    if ((st = upload(plan.chunks, all.data(), all.size() * sizeof(CubeChunk), "cube chunk lists")) != BS_OK)
+        return st;
     plan.inv_bytes = inv_bytes;
     if (plan.rbuf.bytes < size_t(rmax) * 8 &&
         (st = dev_alloc(plan.rbuf, size_t(rmax) * 8, "cube residual scratch")) != BS_OK)
@@ -241,7 +284,7 @@ bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, bool jacobi, int l
     a.f = f;
     a.R = static_cast<double *>(plan.rbuf.p);
     a.ainv = reinterpret_cast<const double *>(base + g.o_ainv);
-    a.omega = omega;
+    a.omega = omega;   // (blocks of over 64 cells: residual gather, then the product)
     a.ubase = ub;
     a.fbase = fb;
     a.uoff = uo;
@@ -255,10 +298,6 @@ bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, bool jacobi, int l
     a.ey = g.ey;
     a.ez = g.ez;
     a.h2 = g.h2;
-    if (g.nb <= kCubeSmallCells) {   // all three steps in one kernel
-        hipError_t e = launch_cube_small(a, stream);
-        return e == hipSuccess ? BS_OK : hip_fail(e, "cube blocks (fused)");
-    }
     hipError_t e = launch_cube_resid(a, stream);
     if (e != hipSuccess) return hip_fail(e, "cube residual");
     GemmArgs m{};
@@ -281,6 +320,27 @@ bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, bool jacobi, int l
     return BS_OK;
 }
 
+// Blocks of up to 64 cells of every group, list k (0 Jacobi, 1 colour 0,
+// 2 colour 1): one fused launch per operand size.
+bs_status small_pass(const CubePlan &plan, int k, const double *src, double *dst, const double *f, double omega,
+                     hipStream_t stream)
+{
+    for (int p = 0; p < 3; ++p) {
+        if (!plan.chunk_cnt[p][k]) continue;
+        CubeBatchArgs a{};
+        a.u = src;
+        a.dst = dst;
+        a.f = f;
+        a.groups = static_cast<const CubeGroupDev *>(plan.gdesc.p);
+        a.chunks = static_cast<const CubeChunk *>(plan.chunks.p) + plan.chunk_off[p][k];
+        a.list = k == 0 ? 1 : 0;
+        a.omega = omega;
+        hipError_t e = launch_cube_small(a, plan.chunk_cnt[p][k], 16 << p, stream);
+        if (e != hipSuccess) return hip_fail(e, "cube blocks (fused)");
+    }
+    return BS_OK;
+}
+
 bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme scheme, double omega, int nsweeps,
                               double *u, const double *f, double *work, hipStream_t stream)
 {
@@ -292,8 +352,11 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
         for (int s = 0; s < nsweeps; ++s) {
             const double *src = (s & 1) ? work : u;
             double *dst = (s & 1) ? u : work;
+            if ((st = small_pass(plan, 0, src, dst, f, omega, stream)) != BS_OK) return st;
             for (const CubeGroup &g : plan.groups)
-                if ((st = cube_pass(plan, g, true, 0, g.nblk, src, dst, f, omega, stream)) != BS_OK) return st;
+                if (g.nb > kCubeSmallCells &&
+                    (st = cube_pass(plan, g, true, 0, g.nblk, src, dst, f, omega, stream)) != BS_OK)
+                    return st;
         }
         if (nsweeps & 1) {
             e = launch_interior_copy(work, u, pdd, ps->npatch, stream);
@@ -303,11 +366,14 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
     }
     // coloured (and chaotic) block GS: colour-0 blocks of every group, then colour 1, in place
     for (int s = 0; s < nsweeps; ++s)
-        for (int col = 0; col < 2; ++col)
+        for (int col = 0; col < 2; ++col) {
+            if ((st = small_pass(plan, 1 + col, u, u, f, omega, stream)) != BS_OK) return st;
             for (const CubeGroup &g : plan.groups) {
+                if (g.nb <= kCubeSmallCells) continue;
                 const int lo = col ? g.ncol0 : 0, n = col ? g.nblk - g.ncol0 : g.ncol0;
                 if ((st = cube_pass(plan, g, false, lo, n, u, u, f, omega, stream)) != BS_OK) return st;
             }
+        }
     return BS_OK;
 }
 

@@ -56,8 +56,10 @@ hipError_t launch_cube_resid(const CubeArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// Fused small blocks: NP = nb rounded up to 16, 32 or 64.  Wavefront w of a
-// workgroup owns blocks 16w..16w+15 (rows of the product) and forms their
+// Fused small blocks: NP = nb rounded up to 16, 32 or 64.  A workgroup takes
+// one chunk (up to 64 consecutive blocks of one group's list; the group gives
+// the inverse, offsets and stencil weights, so one launch covers every group
+// of the same NP).  Wavefront w owns blocks 16w..16w+15 (rows of the product) and forms their
 // residuals straight into the matrix-core operand layout: lane l holds the
 // residual of cell k + l/16 of block l%16 for k = 0, 4, ..., NP-4 -- the A
 // operand of v_mfma_f64_16x16x4 -- so residuals never touch LDS or HBM; only
@@ -73,27 +75,36 @@ hipError_t launch_cube_resid(const CubeArgs &a, hipStream_t s)
 // Workgroups are mapped XCD-contiguously, so neighbouring blocks (which read
 // each other's faces) share an L2.
 template <int NP>
-__global__ void __launch_bounds__(256) k_cube_small(CubeArgs a)
+__global__ void __launch_bounds__(256) k_cube_small(CubeBatchArgs ba_)
 {
     __shared__ double Bs[NP][NP + 1];
     __shared__ int32_t So[2][NP];   // u and f offsets of each cell (cell 0's past nb)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int l16 = lane & 15, lk = lane >> 4;
-    const int nb = a.nb;
-    const int b0 = xcd_block(blockIdx.x, gridDim.x) * 64;
+    const CubeChunk ch = ba_.chunks[xcd_block(blockIdx.x, gridDim.x)];
+    const CubeGroupDev &g = ba_.groups[ch.group];
+    struct {
+        const double *u, *f;
+        double *dst;
+        int64_t sy, sz;
+        double ex, ey, ez, h2, omega;
+    } a = {ba_.u, ba_.f, ba_.dst, g.sy, g.sz, g.ex, g.ey, g.ez, g.h2, ba_.omega};
+    const int nb = g.nb;
+    const int b0 = ch.first, bend = ch.end;
+    const int64_t *ubase = g.ubase[ba_.list], *fbase = g.fbase[ba_.list];
 
 #pragma unroll
     for (int e = tid; e < NP * NP; e += 256) {
         const int n = e / NP, k = e % NP;
-        Bs[k][n] = (n < nb && k < nb) ? a.ainv[n * nb + k] : 0.0;
+        Bs[k][n] = (n < nb && k < nb) ? g.ainv[n * nb + k] : 0.0;
     }
     if (tid < NP) {
-        So[0][tid] = a.uoff[tid < nb ? tid : 0];
-        So[1][tid] = a.foff[tid < nb ? tid : 0];
+        So[0][tid] = g.uoff[tid < nb ? tid : 0];
+        So[1][tid] = g.foff[tid < nb ? tid : 0];
     }
     const int ba = b0 + w * 16 + l16;            // this lane's block for the operand
-    const bool bok = ba < a.nblk;
-    const int64_t ub = a.ubase[bok ? ba : b0], fb = a.fbase[bok ? ba : b0];
+    const bool bok = ba < bend;
+    const int64_t ub = ubase[bok ? ba : b0], fb = fbase[bok ? ba : b0];
     __syncthreads();
 
     // operands in batches of four: the 32 loads of a batch are issued before
@@ -153,21 +164,21 @@ __global__ void __launch_bounds__(256) k_cube_small(CubeArgs a)
     for (int r = 0; r < 4; ++r) {
         const int m = 4 * r + lk;
         const int64_t base = __shfl(ub, m);
-        const bool ok = b0 + w * 16 + m < a.nblk;
+        const bool ok = b0 + w * 16 + m < bend;
 #pragma unroll
         for (int j = 0; j < NP / 16; ++j)
             if (ok && j * 16 + l16 < nb) a.dst[base + So[0][j * 16 + l16]] = fma(a.omega, acc[j][r], accu[j][r]);
     }
 }
 
-hipError_t launch_cube_small(const CubeArgs &a, hipStream_t s)
+hipError_t launch_cube_small(const CubeBatchArgs &a, int nchunks, int np, hipStream_t s)
 {
-    if (a.nblk <= 0) return hipSuccess;
-    if (a.nb <= 0 || a.nb > kCubeSmallCells) return hipErrorInvalidValue;
-    const dim3 grid((a.nblk + 63) / 64);
-    if (a.nb <= 16) hipLaunchKernelGGL(k_cube_small<16>, grid, dim3(256), 0, s, a);
-    else if (a.nb <= 32) hipLaunchKernelGGL(k_cube_small<32>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_cube_small<64>, grid, dim3(256), 0, s, a);
+    if (nchunks <= 0) return hipSuccess;
+    const dim3 grid(nchunks);
+    if (np == 16) hipLaunchKernelGGL(k_cube_small<16>, grid, dim3(256), 0, s, a);
+    else if (np == 32) hipLaunchKernelGGL(k_cube_small<32>, grid, dim3(256), 0, s, a);
+    else if (np == 64) hipLaunchKernelGGL(k_cube_small<64>, grid, dim3(256), 0, s, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

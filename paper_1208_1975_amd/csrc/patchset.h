@@ -71,8 +71,12 @@ struct CubeGroup {
 struct CubePlan {
     std::vector<CubeGroup> groups;
     DevBuf buf;    // tables and inverses
-    DevBuf rbuf;   // block-major residual scratch (largest group)
+    DevBuf rbuf;   // block-major residual scratch (largest group of blocks over 64 cells)
     int64_t inv_bytes = 0;
+    // blocks of up to 64 cells: device group descriptors and chunk lists, per
+    // operand size (16, 32, 64) and list (Jacobi, colour 0, colour 1)
+    DevBuf gdesc, chunks;
+    int chunk_off[3][3] = {}, chunk_cnt[3][3] = {};
 };
 
 bs_status fail(bs_status st, const char *fmt, ...);

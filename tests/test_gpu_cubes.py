@@ -210,3 +210,26 @@ def test_block_size_study_on_the_gpu():
     rho = 1.0 - 1.6 * math.sin(math.pi / (2 * (n + 1))) ** 2
     log("point Jacobi factor %.8f closed form %.8f" % (factor, rho))
     assert abs(factor - rho) < 1e-4
+
+
+def test_many_classes_one_launch_per_operand_size():
+    """40 uneven patches, each its own class (own dims and eps): blocks of up to
+    64 cells of all of them run in one fused launch per operand size; with
+    8 x 8 x 2 blocks the same sweep also runs the two-kernel form for the
+    128-cell blocks.  Every patch equals the oracle."""
+    s = c4_patchset(npatch=40, seed=29, edges=(6, 9, 12, 16, 20))
+    dims = [tuple(d) for d in s.dims]
+    eps = [tuple(e) for e in s.eps]
+    ps = bs.PatchSet(dims, eps, list(s.h))
+    f = ps.pack_f(s.f)
+    for block in ((4, 4, 4), (2, 3, 2), (8, 8, 2)):
+        ps.cube_prepare(block)
+        for scheme, omega, osch in SCHEMES:
+            u = ps.pack_u(s.u0)
+            w = ps.empty_u()
+            ps.cube_relax(block, scheme, omega, 3, u, f, w)
+            torch.cuda.synchronize()
+            log("cubes 40 classes block %s %s" % (block, scheme))
+            for p in range(ps.npatch):
+                ref = oracle.cube_sweeps(s.u0[p], s.f[p], eps[p], s.h[p], block, osch, omega, 3)
+                assert relerr(ps.view_u(u, p).cpu().numpy(), ref) < TOL, (block, scheme, p)
