@@ -134,15 +134,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 //   launch_cube_resid: residuals into R[block][cell] (any nb).
 struct CubeArgs {
     const double *u;
-    double *dst;
     const double *f;
     double *R;
-    const double *ainv;
     const int64_t *ubase, *fbase;
     const int32_t *uoff, *foff;
-    int32_t nb, nblk, per;      // cells per block, blocks, blocks per workgroup (residual kernel)
+    int32_t nb, nblk, per;      // cells per block, blocks, blocks per workgroup
     int64_t sy, sz;             // u strides of y and z
-    double ex, ey, ez, h2, omega;
+    double ex, ey, ez, h2;
 };
 constexpr int kCubeSmallCells = 64;
 hipError_t launch_cube_resid(const CubeArgs &a, hipStream_t s);

@@ -269,7 +269,8 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
     return BS_OK;
 }
 
-// Steps 1-3 for blocks [lo, lo + n) of group g: src -> dst.
+// Steps 1-3 for blocks [lo, lo + n) of a group of blocks over 64 cells:
+// src -> dst, in two kernels.
 bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, bool jacobi, int lo, int n, const double *src,
                     double *dst, const double *f, double omega, hipStream_t stream)
 {
@@ -278,13 +279,11 @@ bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, bool jacobi, int l
     const int64_t *ub = reinterpret_cast<const int64_t *>(base + (jacobi ? g.o_jbase : g.o_ubase)) + lo;
     const int64_t *fb = reinterpret_cast<const int64_t *>(base + (jacobi ? g.o_jfbase : g.o_fbase)) + lo;
     const int32_t *uo = reinterpret_cast<const int32_t *>(base + g.o_uoff);
+    // blocks of over 64 cells: residual gather, then the product
     CubeArgs a{};
     a.u = src;
-    a.dst = dst;
     a.f = f;
     a.R = static_cast<double *>(plan.rbuf.p);
-    a.ainv = reinterpret_cast<const double *>(base + g.o_ainv);
-    a.omega = omega;   // (blocks of over 64 cells: residual gather, then the product)
     a.ubase = ub;
     a.fbase = fb;
     a.uoff = uo;
