@@ -242,10 +242,11 @@ def cube_forms(blocks=((2, 2, 2), (4, 4, 4), (8, 8, 8)), nsweeps=3):
 def cube_convergence(n=64, long_sweeps=10000):
     """The block-size study (section 3) on the GPU: one 64^3 patch, eps = 1,
     f = 0, random initial guess, zero ghosts.  Relative residual after 3
-    sweeps per block size and scheme, and the Jacobi convergence factor
-    (r_{2K} / r_K)^(1/K) for K = long_sweeps / 2, the window starting near
-    sweep 5000 as in the paper (point blocks: closed form
-    1 - 1.6 sin^2(pi / (2 (n + 1))))."""
+    sweeps per block size and scheme, and the convergence factor
+    (r_{2K} / r_K)^(1/K): Jacobi with K = long_sweeps / 2, the window starting
+    near sweep 5000 as in the paper (point blocks: closed form
+    1 - 1.6 sin^2(pi / (2 (n + 1)))); chaotic GS with half that K (it
+    converges about twice as fast, so the residual stays far above rounding)."""
     import torch
 
     import paper_1208_1975_amd as bs
@@ -270,11 +271,12 @@ def cube_convergence(n=64, long_sweeps=10000):
             u = u0.clone()
             ps.cube_relax(b, scheme, omega, 3, u, f, w)
             e[scheme + "_rel_residual_3"] = round(rnorm(u) / r0, 6)
-        u = u0.clone()
-        ps.cube_relax(b, "jacobi", 0.8, half, u, f, w)
-        ra = rnorm(u)
-        ps.cube_relax(b, "jacobi", 0.8, half, u, f, w)
-        e["jacobi_factor"] = round((rnorm(u) / ra) ** (1.0 / half), 7)
+        for scheme, omega, k in (("jacobi", 0.8, half), ("chaotic", 1.0, half // 2)):
+            u = u0.clone()
+            ps.cube_relax(b, scheme, omega, k, u, f, w)
+            ra = rnorm(u)
+            ps.cube_relax(b, scheme, omega, k, u, f, w)
+            e[scheme + "_factor"] = round((rnorm(u) / ra) ** (1.0 / k), 7)
         res["%dx%dx%d" % b] = e
     ps.close()
     return res

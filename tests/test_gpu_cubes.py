@@ -172,8 +172,9 @@ def test_block_size_study_workload(block):
 def test_block_size_study_on_the_gpu():
     """The block-size study's workload (one 64^3 patch, eps = 1, f = 0, random
     initial guess): three sweeps improve monotonically with the block size for
-    both schemes; two sizes equal the oracle; point-block Jacobi converges at
-    the closed-form rate 1 - 1.6 sin^2(pi/130)."""
+    both schemes; two sizes equal the oracle; point blocks converge at the
+    closed-form rates: damped Jacobi 1 - 1.6 sin^2(pi/130), two-colour GS
+    cos^2(pi/65)."""
     import math
     from workloads import make_patch
     n = 64
@@ -203,12 +204,21 @@ def test_block_size_study_on_the_gpu():
         log("study %s %s" % (scheme, ["%.4f" % v for v in rel]))
         assert all(a > b for a, b in zip(rel, rel[1:])), (scheme, rel)
     u = u0.clone()
-    ps.cube_relax((1, 1, 1), "jacobi", 0.8, 2000, u, f, w)
+    ps.cube_relax((1, 1, 1), "jacobi", 0.8, 4000, u, f, w)
     ra = rnorm(u)
-    ps.cube_relax((1, 1, 1), "jacobi", 0.8, 2000, u, f, w)
-    factor = (rnorm(u) / ra) ** (1.0 / 2000)
+    ps.cube_relax((1, 1, 1), "jacobi", 0.8, 4000, u, f, w)
+    factor = (rnorm(u) / ra) ** (1.0 / 4000)
     rho = 1.0 - 1.6 * math.sin(math.pi / (2 * (n + 1))) ** 2
     log("point Jacobi factor %.8f closed form %.8f" % (factor, rho))
+    assert abs(factor - rho) < 1e-4
+    # two-colour point GS (omega 1): rho_J^2 with rho_J = cos(pi/(n+1))
+    u = u0.clone()
+    ps.cube_relax((1, 1, 1), "chaotic", 1.0, 2000, u, f)
+    ra = rnorm(u)
+    ps.cube_relax((1, 1, 1), "chaotic", 1.0, 2000, u, f)
+    factor = (rnorm(u) / ra) ** (1.0 / 2000)
+    rho = math.cos(math.pi / (n + 1)) ** 2
+    log("point two-colour GS factor %.8f closed form %.8f" % (factor, rho))
     assert abs(factor - rho) < 1e-4
 
 
