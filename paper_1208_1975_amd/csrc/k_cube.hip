@@ -107,8 +107,6 @@ __global__ void __launch_bounds__(256) k_cube_small(CubeBatchArgs ba_)
     const int64_t ub = ubase[bok ? ba : b0], fb = fbase[bok ? ba : b0];
     __syncthreads();
 
-    // operands in batches of four: the 32 loads of a batch are issued before
-    // any of them is consumed
     // Operands in batches of four (the 32 loads of a batch are issued before
     // any is consumed), each multiplied into the result as soon as it is
     // formed.  A second product with the identity, exact (one term u * 1 per
