@@ -210,9 +210,10 @@ def ev_ms(fn, reps=3):
     return ts[len(ts) // 2]
 
 
-def cube_forms(blocks=((2, 2, 2), (4, 4, 4), (8, 8, 8)), nsweeps=3):
-    """Cube-block sweeps on 64 patches of 64^3: ms per sweep, cells per second,
-    and the block products' rate (2 nb flop per cell for blocks of nb cells)."""
+def cube_forms(blocks=((2, 2, 2), (4, 2, 2), (4, 4, 2), (4, 4, 4), (8, 4, 4), (8, 8, 4), (8, 8, 8)), nsweeps=3):
+    """Cube-block sweeps on 64 patches of 64^3 for the block sizes of the
+    paper's study: ms per sweep, cells per second, and the block products'
+    rate (2 nb flop per cell for blocks of nb cells)."""
     import paper_1208_1975_amd as bs
     from workloads import uniform_patchset
 
