@@ -243,3 +243,26 @@ def test_many_classes_one_launch_per_operand_size():
             for p in range(ps.npatch):
                 ref = oracle.cube_sweeps(s.u0[p], s.f[p], eps[p], s.h[p], block, osch, omega, 3)
                 assert relerr(ps.view_u(u, p).cpu().numpy(), ref) < TOL, (block, scheme, p)
+
+
+def test_set_eps_after_a_captured_sequence():
+    """A captured two-sweep sequence, then an eps change (new inverses and
+    tables), then the same call: the replay must use the new inverses."""
+    p = small_patch(16, 12, 10, seed=14)
+    ps = bs.PatchSet([tuple(p.dims)], [p.eps], [p.h])
+    u = ps.pack_u([p.u0])
+    f = ps.pack_f([p.f])
+    w = ps.empty_u()
+    for block in ((4, 4, 4), (8, 4, 4)):
+        ps.cube_prepare(block)
+    for block in ((4, 4, 4), (8, 4, 4)):
+        ps.cube_relax(block, "jacobi", 0.8, 2, u, f, w)      # captured
+    new_eps = (5.0, 0.25, 2.0)
+    ps.set_eps([new_eps])
+    for block in ((4, 4, 4), (8, 4, 4)):
+        ps.pack_u([p.u0], out=u)
+        ps.cube_relax(block, "jacobi", 0.8, 2, u, f, w)
+        torch.cuda.synchronize()
+        ref = oracle.cube_sweeps(p.u0, p.f, new_eps, p.h, block, oracle.JACOBI, 0.8, 2)
+        log("cubes eps change after capture %s" % (block,))
+        assert relerr(ps.view_u(u, 0).cpu().numpy(), ref) < TOL, block
