@@ -173,7 +173,8 @@ bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme,
  * than 64 cells, a residual scratch of 8 bytes per cell of the largest group
  * of equally shaped blocks; synchronous (allocates device memory).  Repeated calls with a
  * prepared size return BS_OK at once; bs_set_eps rebuilds every prepared
- * size.  BS_ERR_INVALID for an edge < 1; BS_ERR_UNSUPPORTED for blocks of
+ * size (a size whose rebuild fails, e.g. for lack of memory, is dropped and
+ * must be prepared again).  BS_ERR_INVALID for an edge < 1; BS_ERR_UNSUPPORTED for blocks of
  * more than 512 cells after clipping (8^3 is the paper's largest) or more
  * than 1 GiB of inverses in total. */
 bs_status bs_cube_prepare(bs_patchset *ps, int32_t bx, int32_t by, int32_t bz);
