@@ -324,35 +324,53 @@ def forms():
     ps.close()
     del u, f, w
 
-    # 512^3 xy-plane Jacobi: FP64 fast diagonalisation vs mixed forms, 5 sweeps
+    # 512^3 xy-plane Jacobi, the full 50 sweeps: FP64 fast diagonalisation vs
+    # mixed forms; errors against the FP64 iterate and residual ratios every
+    # 10 sweeps
     p = c3_patch()
     ps = bs.PatchSet([p.dims], [p.eps], [p.h])
     f = ps.pack_f([p.f])
     u0 = ps.pack_u([p.u0])
     w = ps.empty_u()
+    n2 = torch.zeros(1, dtype=torch.float64, device="cuda")
     cells = 512 ** 3
     # four products per plane over 512 planes; the FP64 chain folds each about
     # the sine basis's even/odd symmetry (half of 2 n^3 per product and plane)
     flops = 4 * 512 ** 4 * 1.0
     res = {}
-    u64 = None
+    u64, r64 = {}, {}
     for name, prec, refine in (("fp64", "fp64", 0), ("fp32", "fp32", 0), ("fp32_r1", "fp32", 1),
                                ("bf16", "bf16", 0), ("bf16_r1", "bf16", 1), ("bf16_r2", "bf16", 2)):
         u = u0.clone()
-        ps.plane_relax(2, "jacobi", 1.0, 1, u, f, w, prec=prec, refine=refine)   # warm (tables, scratch)
+        ps.plane_relax(2, "jacobi", 1.0, 10, u, f, w, prec=prec, refine=refine)   # warm (tables, scratch, graph)
         u.copy_(u0)
-        ms = ev_ms(lambda: ps.plane_relax(2, "jacobi", 1.0, 5, u, f, w, prec=prec, refine=refine), reps=1)
-        entry = {"ms_per_sweep": round(ms / 5, 3), "glups": round(cells * 5 / (ms * 1e-3) / 1e9, 3)}
+        ms = 0.0
+        errs, rrat = [], []
+        for k in range(10, 51, 10):
+            ms += ev_ms(lambda: ps.plane_relax(2, "jacobi", 1.0, 10, u, f, w, prec=prec, refine=refine), reps=1)
+            ps.residual(u, f, None, n2)
+            rk = math.sqrt(float(n2.item()))
+            if name == "fp64":
+                u64[k] = u.clone()
+                r64[k] = rk
+            else:
+                errs.append(float((u - u64[k]).abs().max() / u64[k].abs().max()))
+                rrat.append(round(rk / r64[k], 7))
+        entry = {"ms_per_sweep": round(ms / 50, 3), "glups": round(cells * 50 / (ms * 1e-3) / 1e9, 3)}
         if name == "fp64":
-            u64 = u.clone()
-            entry["mfma_tflops"] = round(flops * 5 / (ms * 1e-3) / 1e12, 2)
-            entry["mfma_frac_fp64"] = round(flops * 5 / (ms * 1e-3) / 78.6e12, 4)
+            entry["mfma_tflops"] = round(flops * 50 / (ms * 1e-3) / 1e12, 2)
+            entry["mfma_frac_fp64"] = round(flops * 50 / (ms * 1e-3) / 78.6e12, 4)
             entry["flop_per_sweep"] = flops
         else:
-            entry["relerr_vs_fp64_5_sweeps"] = float((u - u64).abs().max() / u64.abs().max())
+            entry["relerr_vs_fp64_at_sweeps_10_20_30_40_50"] = errs
+            entry["residual_ratio_vs_fp64_at_sweeps_10_20_30_40_50"] = rrat
+            if name == "bf16":
+                entry["caveat"] = ("no error bound: the BF16 solve error (~3e-3) exceeds the 1.9e-5 stability "
+                                   "margin of the z-checkerboard mode at omega 1, so the iteration is not a "
+                                   "contraction")
         res[name] = entry
         del u
-    out["c3_xyplane_jacobi_512"] = res
+    out["c3_xyplane_jacobi_512_50_sweeps"] = res
     ps.close()
     del f, u0, w, u64
     torch.cuda.empty_cache()
@@ -418,28 +436,68 @@ def forms():
     return out
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(patch, target_s):
+    """The oracle on the host: z-line Jacobi + lexicographic GS sweep pairs of
+    the full grid, at the default thread count and at 1 thread, median of 3
+    timed runs each; target_s bounds the whole measurement."""
     import oracle
-    oracle.set_threads(0)
-    threads = oracle.get_threads()
     cells = patch.f.size
-    # probe one sweep of each scheme, then size the sample to about target_s seconds
-    t0 = time.perf_counter()
-    u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.JACOBI, 0.8, 1)
-    tj = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.LEX_GS, 1.0, 1, lex_form=1)
-    tg = time.perf_counter() - t0
-    per_pair = tj + tg
-    k = max(1, int(target_s / per_pair))
-    t0 = time.perf_counter()
-    u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.JACOBI, 0.8, k)
-    u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.LEX_GS, 1.0, k, lex_form=1)
-    dt = time.perf_counter() - t0
-    del u
-    return {"value": round(cells * 2 * k / dt / 1e9, 5), "unit": "GLUP/s", "cores": threads, "kind": "oracle",
+    runs = {}
+    for label, nt, share in (("all", 0, 0.45), ("one", 1, 0.55)):
+        oracle.set_threads(nt)
+        threads = oracle.get_threads()
+        t0 = time.perf_counter()
+        u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.JACOBI, 0.8, 1)
+        u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.LEX_GS, 1.0, 1, lex_form=1)
+        per_pair = time.perf_counter() - t0
+        k = max(1, int(target_s * share / 3 / per_pair))
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.JACOBI, 0.8, k)
+            u = oracle.line_sweeps(patch.u0, patch.f, patch.eps, patch.h, 2, oracle.LEX_GS, 1.0, k, lex_form=1)
+            ts.append(time.perf_counter() - t0)
+        del u
+        ts.sort()
+        runs[label] = {"threads": threads, "pairs": k, "median_s": ts[1], "glups": cells * 2 * k / ts[1] / 1e9}
+    oracle.set_threads(0)
+    a, o = runs["all"], runs["one"]
+    return {"value": round(a["glups"], 5), "unit": "GLUP/s", "cores": a["threads"], "kind": "oracle",
+            "value_1_thread": round(o["glups"], 5), "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": "%d^3 z-lines, eps (1,1,100): %d Jacobi + %d lexicographic GS sweeps (anti-diagonal form) "
-                      "on the full grid, %.1f s" % (N, k, k, dt)}
+                      "of the full grid, median of 3 runs (%.2f s) at %d threads; %d + %d sweeps, median of 3 "
+                      "(%.2f s) at 1 thread" % (N, a["pairs"], a["pairs"], a["median_s"], a["threads"], o["pairs"],
+                                                o["pairs"], o["median_s"])}
+
+
+def stream_ceiling(n, reps=7):
+    """Measured streaming ceiling (GB/s) for 24 bytes per element over n
+    doubles per operand (the size of one sweep's u, f and v): the library's
+    triad probe, plain and with nontemporal loads of the second operand."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    n += n & 1
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    out = {}
+    for mode, name in ((0, "triad"), (1, "triad_nontemporal")):
+        bs.stream_triad(a, b, c, mode)
+        ms = ev_ms(lambda: bs.stream_triad(a, b, c, mode), reps=reps)
+        out[name + "_GBs"] = round(24.0 * n / (ms * 1e-3) / 1e9, 1)
+    del a, b, c
+    return out
 
 
 def main():
@@ -525,6 +583,10 @@ def main():
                       "jacobi_frac": round(bytes_per_launch / (jac_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                       "chaotic_frac": round(bytes_per_launch / (cha_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
     rn = norms.cpu().numpy()
+    ceil = stream_ceiling(cells)
+    best = max(ceil.values())
+    roof["measured_ceiling"] = dict(ceil, frac_of_measured=round(achieved / best, 4),
+                                    note="triad c = a + b over %d doubles per operand on this GPU" % cells)
 
     ps.close()
     del uj, uc, u0, f, work

@@ -106,7 +106,13 @@ bs_status bs_create_patchset(int32_t npatch, const int32_t *dims_host, const dou
 void bs_destroy_patchset(bs_patchset *ps);
 
 /* Replace every patch's eps ([3*npatch], > 0) and rebuild the tables that
- * depend on it.  Synchronous. */
+ * depend on it.  Synchronous.  The new line tables are built aside and swapped
+ * in only when every allocation and copy succeeded: on BS_ERR_OOM / BS_ERR_HIP
+ * from that step the patch set keeps its previous eps and stays usable.  Cube
+ * block sizes prepared with bs_cube_prepare are rebuilt afterwards; if one of
+ * those rebuilds fails, the call returns its status with the new eps in force,
+ * and that size and every prepared size not yet rebuilt are dropped (they must
+ * be prepared again). */
 bs_status bs_set_eps(bs_patchset *ps, const double *eps_host);
 
 /* Layout of an existing patch set (same meaning as bs_layout_plan). */
@@ -144,6 +150,17 @@ bs_status bs_residual(const bs_patchset *ps, const double *u, const double *f, d
  * new in-tile values, in place, tiles of even tile rows dispatched first.  A
  * sequence of two or more sweeps is captured into a HIP graph on its first
  * call and replayed by later calls with the same arguments and buffers.
+ * When a patch set has fewer tiles of lines than one even/odd dispatch chunk per
+ * XCD (so that every tile would run at once and tiles could not see their
+ * neighbours' new values), BS_CHAOTIC_GS is dispatched colour-major instead:
+ * all colour-0 lines in one launch, then all colour-1 lines, which is the
+ * two-colour sweep (one of the orders a chaotic sweep may take).
+ * Line lengths: every line is solved whole; the supported lengths are x-lines
+ * of up to 256 cells and y- or z-lines of up to 1024 cells (the kernels hold a
+ * line in the registers of at most 16 wavefronts, and 64 x-lines of a tile in
+ * LDS).  A longer line along `axis` in any patch of the set returns
+ * BS_ERR_UNSUPPORTED before anything is enqueued (split such patches, or use
+ * plane blocks, which accept in-plane edges up to 1024).
  * BS_ERR_UNSUPPORTED for BS_MIXED_BF16 (BF16 is offered for planes only). */
 bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double omega,
                         int32_t nsweeps, bs_precision prec, double *u, const double *f,
@@ -218,7 +235,10 @@ bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, cons
 bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, int32_t cfg_host[6]);
 
 /* Device workspace needed by bs_relax_backward for these arguments, or 0 on
- * invalid arguments. */
+ * invalid arguments.  `axis` (0..2) is the line axis bs_relax_backward will
+ * get; it is validated so that the query takes the same arguments as the call
+ * it sizes.  The size itself (checkpointed states, one recompute segment and
+ * the adjoint work fields) does not depend on the axis. */
 size_t bs_backward_workspace_bytes(const bs_patchset *ps, int32_t axis, int32_t nsweeps,
                                    int32_t ckpt_every);
 

@@ -74,6 +74,8 @@ def lib():
     L.bsi_set_graphs.restype = ctypes.c_int
     L.bsi_line_relax_per_patch.argtypes = [vp, i32, ctypes.c_int, dbl, i32, vp, vp, vp, vp]
     L.bsi_line_relax_per_patch.restype = ctypes.c_int
+    L.bsi_stream_triad.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp]
+    L.bsi_stream_triad.restype = ctypes.c_int
     L.bs_backward_workspace_bytes.argtypes = [vp, i32, i32, i32]
     L.bs_backward_workspace_bytes.restype = sz
     L.bs_relax_backward.argtypes = [vp, i32, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -221,6 +223,17 @@ def bs_relax_backward(ps, axis, omega, nsweeps, ckpt_every, u0, f, grad_uK, grad
                                    _ptr(workspace), wb, _stream(stream)))
 
 
+def stream_triad(a, b, c, mode=0, stream=None):
+    """Device streaming probe c = a + b (float64, n even): the 24 bytes per
+    element of a line sweep at the HBM ceiling (mode 1: nontemporal b)."""
+    n = c.numel()
+    if a.numel() < n or b.numel() < n or not all(t.dtype == torch.float64 for t in (a, b, c)):
+        raise ValueError("stream_triad: float64 buffers of at least c's size")
+    st = lib().bsi_stream_triad(_ptr(a), _ptr(b), _ptr(c), n, int(mode), _stream(stream))
+    if st != 0:
+        raise BSError(st, "bsi_stream_triad failed")
+
+
 def bs_last_error():
     return lib().bs_last_error().decode(errors="replace")
 
@@ -255,8 +268,9 @@ class PatchSet:
             pass
 
     def set_eps(self, eps):
-        self.eps = [tuple(float(v) for v in t) for t in eps]
-        bs_set_eps(self.handle, self.eps)
+        new = [tuple(float(v) for v in t) for t in eps]
+        bs_set_eps(self.handle, new)   # raises on failure; the library then keeps its old eps
+        self.eps = new
 
     def empty_u(self):
         return torch.zeros(self.u_numel, dtype=torch.float64, device=self.device)

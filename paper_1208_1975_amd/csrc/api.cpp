@@ -95,13 +95,16 @@ void plan_layout(int32_t npatch, const int32_t *dims, std::vector<int64_t> &uoff
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // (Re)build every table that depends on eps and upload descriptors + tables.
+// The new device buffers are built aside and swapped in only once every
+// allocation and copy has succeeded, so a failure leaves the patch set exactly
+// as it was (old tables, work lists and captured graphs all still valid).
 bs_status build_tables(bs_patchset *ps)
 {
     std::vector<double> tab;
     tab.reserve(4096);
-    ps->desc.assign(ps->npatch, PatchDesc{});
+    std::vector<PatchDesc> desc(ps->npatch, PatchDesc{});
     for (int p = 0; p < ps->npatch; ++p) {
-        PatchDesc &d = ps->desc[p];
+        PatchDesc &d = desc[p];
         for (int a = 0; a < 3; ++a) d.n[a] = ps->dims[3 * p + a];
         d.uoff = ps->uoff[p];
         d.foff = ps->foff[p];
@@ -132,14 +135,23 @@ bs_status build_tables(bs_patchset *ps)
             d.plane[a].na = d.plane[a].nb = 0;
         }
     }
-    bs_status st = upload(ps->tab_d, tab.data(), tab.size() * sizeof(double), "tables");
+    DevBuf tab_d, tab32_d, desc_d;
+    bs_status st = upload(tab_d, tab.data(), tab.size() * sizeof(double), "tables");
     if (st != BS_OK) return st;
     const std::vector<float> tab32(tab.begin(), tab.end());   // for FP32 block solves
-    if ((st = upload(ps->tab32_d, tab32.data(), tab32.size() * sizeof(float), "tables")) != BS_OK) return st;
+    if ((st = upload(tab32_d, tab32.data(), tab32.size() * sizeof(float), "tables")) != BS_OK) return st;
+    if ((st = upload(desc_d, desc.data(), desc.size() * sizeof(PatchDesc), "patch descriptors")) != BS_OK)
+        return st;
+    // commit: work lists and graphs refer to the old buffers, which are freed
+    // when the locals go out of scope
     ps->lists.clear();
     clear_graphs(ps);
     ps->plane_ready = false;   // plane tables depend on eps; rebuilt on next use
-    return upload(ps->desc_d, ps->desc.data(), ps->desc.size() * sizeof(PatchDesc), "patch descriptors");
+    ps->tab_d.swap(tab_d);
+    ps->tab32_d.swap(tab32_d);
+    ps->desc_d.swap(desc_d);
+    ps->desc.swap(desc);
+    return BS_OK;
 }
 
 }  // namespace
@@ -249,9 +261,13 @@ bs_status bs_set_eps(bs_patchset *ps, const double *eps_host)
             return fail(BS_ERR_INVALID, "bs_set_eps: eps[%lld] must be finite and > 0", (long long)t);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    std::vector<double> old(ps->eps);
     ps->eps.assign(eps_host, eps_host + 3 * static_cast<size_t>(ps->npatch));
     bs_status st = build_tables(ps);
-    if (st != BS_OK) return st;
+    if (st != BS_OK) {
+        ps->eps.swap(old);   // the old tables are untouched: the set keeps its old eps
+        return st;
+    }
     return cube_rebuild_all(ps);   // block inverses depend on eps
 }
 

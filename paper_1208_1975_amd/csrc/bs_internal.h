@@ -98,6 +98,9 @@ hipError_t launch_line_strided(const LineArgs &a, int grid, int Lmax, int nwaves
 hipError_t launch_line_x(const LineArgs &a, int grid, int Lmax, int nwaves, size_t lds, hipStream_t s);
 hipError_t launch_line_xr(const LineArgs &a, int grid, int nwaves, hipStream_t s);
 hipError_t prepare_line_kernels();
+// Workgroups per compute unit that a line-kernel configuration can hold at once.
+int line_occupancy(int axis, int Lmax, int nwaves, size_t lds, int colour_mode, int f32);
+int line_xr_occupancy(int nwaves, int f32);
 hipError_t launch_residual(const ResidArgs &a, int ntiles, hipStream_t s);
 hipError_t launch_residual_final(const double *partial, const int32_t *patch_first_block,
                                  int npatch, double *out, hipStream_t s);

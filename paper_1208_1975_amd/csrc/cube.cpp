@@ -390,17 +390,18 @@ bs_status check_block(const bs_patchset *ps, int32_t bx, int32_t by, int32_t bz,
 
 bs_status cube_rebuild_all(bs_patchset *ps)
 {
-    // each plan is rebuilt aside and swapped in whole; a size whose rebuild
-    // fails is dropped (it must be prepared again), never left half-built
-    for (auto it = ps->cube.begin(); it != ps->cube.end();) {
+    // each plan is rebuilt aside and swapped in whole.  When a rebuild fails,
+    // that size and every size not rebuilt yet are dropped (they hold inverses
+    // of the old eps and must be prepared again); sizes rebuilt before it keep
+    // their new plans
+    for (auto it = ps->cube.begin(); it != ps->cube.end(); ++it) {
         std::unique_ptr<CubePlan> fresh(new CubePlan);
         bs_status st = build_plan(ps, std::get<0>(it->first), std::get<1>(it->first), std::get<2>(it->first), *fresh);
         if (st != BS_OK) {
-            ps->cube.erase(it);
+            ps->cube.erase(it, ps->cube.end());
             return st;
         }
         it->second.swap(fresh);
-        ++it;
     }
     return BS_OK;
 }

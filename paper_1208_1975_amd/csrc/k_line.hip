@@ -721,6 +721,55 @@ hipError_t prepare_line_kernels()
     return e;
 }
 
+// Workgroups of one line-kernel instantiation that a compute unit holds at
+// once (registers, LDS and waves permitting); 1 if the query fails.
+template <typename K>
+static int occupancy_of(K kern, int threads, size_t lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
+template <int L, int MAXT>
+static int line_occupancy_t(int axis, int threads, size_t lds, int colour_mode, int f32)
+{
+    if (axis == 0)
+        return f32 ? occupancy_of(k_line_x<L, MAXT, true>, threads, lds)
+                   : occupancy_of(k_line_x<L, MAXT, false>, threads, lds);
+    // the chaotic mode is the one whose dispatch depends on it
+    if (colour_mode == 2)
+        return f32 ? occupancy_of(k_line_strided<L, MAXT, 2, true>, threads, lds)
+                   : occupancy_of(k_line_strided<L, MAXT, 2, false>, threads, lds);
+    if (colour_mode == 1)
+        return f32 ? occupancy_of(k_line_strided<L, MAXT, 1, true>, threads, lds)
+                   : occupancy_of(k_line_strided<L, MAXT, 1, false>, threads, lds);
+    return f32 ? occupancy_of(k_line_strided<L, MAXT, 0, true>, threads, lds)
+               : occupancy_of(k_line_strided<L, MAXT, 0, false>, threads, lds);
+}
+
+template <int L>
+static int line_occupancy_b(int axis, int nwaves, size_t lds, int colour_mode, int f32)
+{
+    const int t = 64 * nwaves;
+    if (t <= 256) return line_occupancy_t<L, 256>(axis, t, lds, colour_mode, f32);
+    if (t <= 512) return line_occupancy_t<L, 512>(axis, t, lds, colour_mode, f32);
+    return line_occupancy_t<L, 1024>(axis, t, lds, colour_mode, f32);
+}
+
+int line_occupancy(int axis, int Lmax, int nwaves, size_t lds, int colour_mode, int f32)
+{
+    switch (Lmax) {
+    case 8: return line_occupancy_b<8>(axis, nwaves, lds, colour_mode, f32);
+    case 16: return line_occupancy_b<16>(axis, nwaves, lds, colour_mode, f32);
+    case 32: return line_occupancy_b<32>(axis, nwaves, lds, colour_mode, f32);
+    default: return line_occupancy_b<64>(axis, nwaves, lds, colour_mode, f32);
+    }
+}
+
 hipError_t launch_line_strided(const LineArgs &a, int nitems, int Lmax, int nwaves, size_t lds,
                                hipStream_t s)
 {

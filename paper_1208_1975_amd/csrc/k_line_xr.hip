@@ -315,6 +315,18 @@ __global__ void __launch_bounds__(256) k_line_xr(LineArgs a)
     }
 }
 
+int line_xr_occupancy(int nwaves, int f32)
+{
+    int n = 0;
+    const hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_line_xr<true>, 64 * nwaves, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_line_xr<false>, 64 * nwaves, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
 hipError_t launch_line_xr(const LineArgs &a, int grid, int nwaves, hipStream_t s)
 {
     if (nwaves < 1 || nwaves > 4) return hipErrorInvalidValue;

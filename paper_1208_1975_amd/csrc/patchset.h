@@ -6,6 +6,7 @@
 #include <memory>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "bs.h"
@@ -26,6 +27,11 @@ struct DevBuf {
         p = nullptr;
         bytes = 0;
     }
+    void swap(DevBuf &o)
+    {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
 };
 
 // A device work list: items of colour 0 first, then colour 1 (colour-split
@@ -41,8 +47,9 @@ struct WorkList {
     std::vector<int> pfirst[2], pcount[2];
 };
 
-// Key: kernel kind (0 strided y/z, 1 x), axis, chunk option, tile width, colour mode.
-using WorkKey = std::tuple<int, int, int, int, int>;
+// Key: kernel kind (0 strided y/z, 1 x), axis, chunk option, tile width, colour
+// mode, tiles per even/odd chunk of the chaotic dispatch order (0 otherwise).
+using WorkKey = std::tuple<int, int, int, int, int, int>;
 
 // A tuned launch configuration for one (axis, scheme class) of a patch set.
 struct LineCfg {
@@ -108,6 +115,7 @@ struct bs_patchset {
     bs::DevBuf plane_tab16_d;                           // BF16 copies of the bases
     int mixed_dlayout = 0;
     int chaotic_chunk = 0;   // tiles per even/odd chunk of the chaotic dispatch order (0: default)
+    std::map<std::vector<int>, int> chaotic_chunks;   // per line configuration: tiles per chunk
     std::vector<int64_t> basis_off, lam_off;   // [3 * npatch] each, offsets in doubles
     // cached work lists and tuned configurations
     std::map<bs::WorkKey, std::unique_ptr<bs::WorkList>> lists;

@@ -101,12 +101,8 @@ std::vector<WorkItem> xcd_group(const std::vector<WorkItem> &run, const std::vec
 // eight sequences are interleaved as in xcd_group.
 std::vector<WorkItem> chaotic_order(const bs_patchset *ps, const std::vector<WorkItem> run[2],
                                     const std::vector<int> &order, const std::vector<int> pfirst[2],
-                                    const std::vector<int> pcount[2], int axis)
+                                    const std::vector<int> pcount[2], int axis, int kChaoticChunk)
 {
-    // a chunk must be several times the ~32 workgroups an XCD runs at once, so
-    // that its odd tiles start after its even ones have finished (a patch set
-    // packs many small patches into one chunk)
-    const int kChaoticChunk = ps->chaotic_chunk > 0 ? ps->chaotic_chunk : (ps->npatch == 1 ? 64 : 512);
     // per XCD: the sequence of units, a unit = (run-0 items, run-1 items) of one patch or one slice
     struct Unit {
         std::vector<WorkItem> it[2];
@@ -187,9 +183,12 @@ void clear_graphs(bs_patchset *ps)
     ps->graphs.clear();
 }
 
-bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, int colour_mode, WorkList **out)
+bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, int colour_mode, WorkList **out,
+                       int chunk)
 {
-    const WorkKey key{kind, axis, popt, tx, colour_mode};
+    if (colour_mode != 2) chunk = 0;
+    if (colour_mode == 2 && chunk <= 0) chunk = ps->npatch == 1 ? 64 : 512;
+    const WorkKey key{kind, axis, popt, tx, colour_mode, chunk};
     auto itr = ps->lists.find(key);
     if (itr != ps->lists.end()) {
         *out = itr->second.get();
@@ -230,7 +229,7 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
     }
     if (colour_mode == 2) {
         // one launch runs both groups: local even-then-odd chunks per XCD
-        const std::vector<WorkItem> d = chaotic_order(ps, runs, order, wl->pfirst, wl->pcount, axis);
+        const std::vector<WorkItem> d = chaotic_order(ps, runs, order, wl->pfirst, wl->pcount, axis, chunk);
         wl->count[0] = static_cast<int>(d.size());
         wl->count[1] = 0;
         all.insert(all.end(), d.begin(), d.end());
@@ -353,7 +352,8 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
 {
     const int kind = axis == 0 ? 1 : 0;
     WorkList *wl = nullptr;
-    bs_status st = get_worklist(ps, kind, axis, c.popt, c.tx, colour_mode, &wl);
+    bs_status st = get_worklist(ps, kind, axis, c.popt, c.tx, colour_mode, &wl,
+                                colour_mode == 2 ? chaotic_chunk_for(ps, axis, c) : 0);
     if (st != BS_OK) return st;
     LineArgs a{};
     a.src = src;
@@ -452,6 +452,24 @@ bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const
         return BS_OK;
     }
     const int cm = scheme_mode(axis, scheme);
+    if (scheme == BS_CHAOTIC_GS && chaotic_colour_major(ps, axis, c)) {
+        // every tile would run at once: colour-major in two launches (all
+        // colour-0 lines, then all colour-1 lines), the two-colour sweep
+        const LineCfg c1 = line_cfg(ps, axis, 1);
+        for (int s = 0; s < nsweeps; ++s) {
+            for (int run = 0; run < 2; ++run) {
+                if (!per_patch) {
+                    st = line_pass(ps, axis, c1, 1, run, u, u, f, omega, stream, -1, 0, 0, f32);
+                } else {
+                    st = BS_OK;
+                    for (int p = 0; p < ps->npatch && st == BS_OK; ++p)
+                        st = line_pass(ps, axis, c1, 1, run, u, u, f, omega, stream, p, 0, 0, f32);
+                }
+                if (st != BS_OK) return st;
+            }
+        }
+        return BS_OK;
+    }
     for (int s = 0; s < nsweeps; ++s) {
         if (scheme == BS_COLORED_GS) {
             if ((st = pass(cm, 0, u, u)) != BS_OK) return st;
@@ -463,11 +481,50 @@ bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const
     return BS_OK;
 }
 
+// Chaotic GS in one launch orders each XCD's tiles in chunks, even tile rows
+// before odd ones, so that a chunk's odd tiles read their even neighbours' new
+// values; that holds only if the odd tiles start after the even ones have
+// finished, i.e. if a chunk is at least twice the workgroups an XCD holds at
+// once.  The chunk is therefore sized from the configuration's occupancy.
+int chaotic_chunk_for(bs_patchset *ps, int axis, const LineCfg &c)
+{
+    if (ps->chaotic_chunk > 0) return ps->chaotic_chunk;
+    const std::vector<int> key{axis, c.form, c.popt, c.Lmax, c.nwaves, c.tx, c.grid};
+    auto itr = ps->chaotic_chunks.find(key);
+    if (itr != ps->chaotic_chunks.end()) return itr->second;
+    const int occ = c.form == 1 ? line_xr_occupancy(c.nwaves, 0)
+                                : line_occupancy(axis, c.Lmax, c.nwaves, line_lds_bytes(ps, axis, c), 2, 0);
+    int64_t resident = static_cast<int64_t>(occ) * device_cus();
+    if (c.grid > 0) resident = std::min<int64_t>(resident, c.grid);
+    const int per_xcd = static_cast<int>(std::max<int64_t>(1, (resident + 7) / 8));
+    const int chunk = std::max(ps->npatch == 1 ? 64 : 512, 2 * per_xcd);
+    ps->chaotic_chunks.emplace(key, chunk);
+    return chunk;
+}
+
+// With fewer tiles than one chunk per XCD, every tile runs at once and the
+// one-launch order cannot act (the sweep would converge like block Jacobi
+// across tile borders); such sweeps are dispatched colour-major instead.
+bool chaotic_colour_major(bs_patchset *ps, int axis, const LineCfg &c)
+{
+    const int kind = axis == 0 ? 1 : 0;
+    int64_t tiles = 0;
+    for (int p = 0; p < ps->npatch; ++p) tiles += tiles_of(ps, p, kind, axis, c.tx, 2);
+    return tiles < 8 * static_cast<int64_t>(chaotic_chunk_for(ps, axis, c));
+}
+
 // Build every work list a sequence needs before any capture begins.
 bs_status prepare_lists(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode)
 {
     WorkList *wl;
-    return get_worklist(ps, axis == 0 ? 1 : 0, axis, c.popt, c.tx, colour_mode, &wl);
+    if (colour_mode == 2 && chaotic_colour_major(ps, axis, c)) {
+        const LineCfg &c1 = line_cfg(ps, axis, 1);
+        bs_status st = check_line_cfg(ps, axis, c1);
+        if (st != BS_OK) return st;
+        return get_worklist(ps, axis == 0 ? 1 : 0, axis, c1.popt, c1.tx, 1, &wl);
+    }
+    return get_worklist(ps, axis == 0 ? 1 : 0, axis, c.popt, c.tx, colour_mode, &wl,
+                        colour_mode == 2 ? chaotic_chunk_for(ps, axis, c) : 0);
 }
 
 }  // namespace bs
@@ -731,6 +788,7 @@ int bsi_set_chaotic_chunk(bs_patchset *ps, int tiles)
 {
     if (!ps || tiles < 0) return BS_ERR_INVALID;
     ps->chaotic_chunk = tiles;
+    ps->chaotic_chunks.clear();
     ps->lists.clear();
     clear_graphs(ps);
     return BS_OK;

@@ -6,7 +6,8 @@
 namespace bs {
 
 int scheme_mode(int axis, bs_scheme scheme);
-bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, int colour_mode, WorkList **out);
+bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, int colour_mode, WorkList **out,
+                       int chunk = 0);
 LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode);
 bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c);
 size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c);
@@ -21,6 +22,10 @@ bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const
                               int nsweeps, double *u, const double *f, double *work, hipStream_t stream,
                               bool per_patch, int f32 = 0);
 bs_status prepare_lists(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode);
+// Chaotic GS dispatch: tiles per even/odd chunk of the one-launch order, and
+// whether the sweep is instead dispatched colour-major in two launches.
+int chaotic_chunk_for(bs_patchset *ps, int axis, const LineCfg &c);
+bool chaotic_colour_major(bs_patchset *ps, int axis, const LineCfg &c);
 void clear_graphs(bs_patchset *ps);
 bs_status check_line_ps_ext(const bs_patchset *ps, int32_t axis, const char *fn);
 

@@ -122,8 +122,9 @@ def test_persistent_grid_strided_lines(axis):
 
 @pytest.mark.timeout(900)
 def test_c4_full_set_chaotic_x_lines():
-    """3000 uneven patches, x-line chaotic GS, 20 sweeps in one graph launch
-    per call: sampled patches within 1.15x the oracle's two-colour GS."""
+    """3000 uneven patches, x-line chaotic GS, 20 sweeps (four graph launches of
+    5 sweeps): at sweeps 5, 10, 15 and 20, every sampled patch's residual within
+    1.15x the oracle's two-colour GS from the same start."""
     s = c4_patchset()
     log("C4: %d patches, %d cells" % (s.npatch, s.cells()))
     ps = bs.PatchSet([tuple(d) for d in s.dims], [tuple(e) for e in s.eps], list(s.h))
@@ -131,18 +132,24 @@ def test_c4_full_set_chaotic_x_lines():
     f = ps.pack_f(s.f)
     n0 = torch.zeros(ps.npatch, dtype=torch.float64, device="cuda")
     ps.residual(u, f, None, n0)
-    ps.line_relax(0, "chaotic", 1.0, 20, u, f)
-    n1 = torch.zeros(ps.npatch, dtype=torch.float64, device="cuda")
-    ps.residual(u, f, None, n1)
+    norms = []
+    for blk in range(4):
+        ps.line_relax(0, "chaotic", 1.0, 5, u, f)
+        n1 = torch.zeros(ps.npatch, dtype=torch.float64, device="cuda")
+        ps.residual(u, f, None, n1)
+        norms.append(n1)
     torch.cuda.synchronize()
     r0 = n0.sqrt().cpu().numpy()
-    r1 = n1.sqrt().cpu().numpy()
+    rk = [n.sqrt().cpu().numpy() for n in norms]
     rng = np.random.default_rng(0)
-    worst = 0.0
+    worst = [0.0] * 4
     for p in rng.choice(ps.npatch, 24, replace=False):
-        ref = oracle.line_sweeps(s.u0[p], s.f[p], tuple(s.eps[p]), s.h[p], 0, oracle.COLORED_GS, 1.0, 20)
-        rr = math.sqrt(oracle.residual(ref, s.f[p], tuple(s.eps[p]), s.h[p])[1])
-        ratio = (r1[p] / r0[p]) / (rr / r0[p])
-        worst = max(worst, ratio)
-        assert ratio <= 1.15, (p, ratio)
-    log("C4 worst sampled chaotic/two-colour residual ratio %.4f" % worst)
+        ref = s.u0[p]
+        for blk in range(4):
+            ref = oracle.line_sweeps(ref, s.f[p], tuple(s.eps[p]), s.h[p], 0, oracle.COLORED_GS, 1.0, 5)
+            rr = math.sqrt(oracle.residual(ref, s.f[p], tuple(s.eps[p]), s.h[p])[1])
+            ratio = rk[blk][p] / rr
+            worst[blk] = max(worst[blk], ratio)
+            assert ratio <= 1.15, (p, 5 * (blk + 1), ratio)
+    log("C4 worst sampled chaotic/two-colour residual ratio at sweeps 5/10/15/20: %s"
+        % " ".join("%.4f" % w for w in worst))

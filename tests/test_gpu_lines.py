@@ -2,13 +2,10 @@
 
 FP64 Jacobi and two-colour GS: max-norm relative error <= 1e-12 (the blocks
 are well conditioned, so the only differences are rounding order and FMA
-contraction).  Chaotic GS has no unique result.  Where the dispatch order can
-act (more tiles than the chip holds at once, the 256^3 case) its residual must
-stay within 1.15x of the oracle's two-colour GS at every checked sweep; on
-grids so small that all tiles run at once the updates are effectively
-simultaneous, so it must lie between block GS and block Jacobi: residual no
-worse than 1.10x the oracle's Jacobi (omega 1) per sweep and a windowed
-convergence factor no worse than rho_J."""
+contraction).  Chaotic GS has no unique result: at every checked sweep its
+residual must stay within 1.15x of the oracle's two-colour GS, and its
+asymptotic rate must be a Gauss-Seidel rate (at least 0.97x the oracle's
+lexicographic GS rate, which the closed form rho_J^2 pins)."""
 import math
 
 import numpy as np
@@ -90,9 +87,11 @@ def test_chaotic_single_tile_is_two_colour_gs(dims, axis):
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_chaotic_gs_small_grid_per_sweep(axis):
-    """48x40x36: every tile is resident at once, so chaotic GS runs close to
-    block Jacobi; per sweep its residual is no worse than 1.10x the oracle's
-    Jacobi (omega 1).  The two-colour and lexicographic GS residuals are logged."""
+    """48x40x36: every sweep's residual within 1.15x the oracle's two-colour
+    GS (the lexicographic and Jacobi residuals are logged beside it).  On a grid
+    this small every tile would run at once, so the library dispatches the
+    chaotic sweep colour-major (one of the orders an asynchronous sweep may
+    take); it must then also agree with two-colour GS to 1e-12."""
     eps = [1.0, 1.0, 1.0]
     eps[axis] = 100.0
     p = make_patch(48, 40, 36, tuple(eps), 1 / 48, seed=7)
@@ -100,7 +99,6 @@ def test_chaotic_gs_small_grid_per_sweep(axis):
     u_rb = u_lex = u_j = p.u0
     r0 = math.sqrt(oracle.residual(p.u0, p.f, p.eps, p.h)[1])
     assert s.rnorm() == pytest.approx(r0, rel=1e-12)
-    prev = 1.0
     for k in range(1, 21):
         s.line(axis, "chaotic", 1.0, 1)
         u_rb = oracle.line_sweeps(u_rb, p.f, p.eps, p.h, axis, oracle.COLORED_GS, 1.0, 1)
@@ -110,18 +108,17 @@ def test_chaotic_gs_small_grid_per_sweep(axis):
         rb = math.sqrt(oracle.residual(u_rb, p.f, p.eps, p.h)[1]) / r0
         rl = math.sqrt(oracle.residual(u_lex, p.f, p.eps, p.h)[1]) / r0
         rj = math.sqrt(oracle.residual(u_j, p.f, p.eps, p.h)[1]) / r0
-        log("chaotic axis=%d sweep %d: gpu %.4e  jacobi %.4e  two-colour %.4e  lex %.4e" % (axis, k, rg, rj, rb, rl))
-        assert rg <= 1.10 * rj, (k, rg, rj)
-        assert rg < prev, (k, rg, prev)
-        prev = rg
+        log("chaotic axis=%d sweep %d: gpu %.4e  two-colour %.4e  lex %.4e  jacobi %.4e" % (axis, k, rg, rb, rl, rj))
+        assert rg <= 1.15 * rb, (k, rg, rb)
+    assert relerr(s.u_np(), u_rb) < TOL
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_chaotic_gs_asymptotic_rate(axis):
     """Windowed convergence factor (||r_{i+k}||/||r_i||)^(1/k) (section 3): the
     oracle's lexicographic GS reaches the closed form rho_J^2, and chaotic GS
-    on this small grid (all tiles resident, updates near simultaneous) is no
-    worse than rho_J."""
+    must converge at a Gauss-Seidel rate: its rate -ln(factor) at least 0.97
+    times lexicographic GS's (block Jacobi's rate is half of it)."""
     dims, eps = (16, 12, 20), (1.0, 3.0, 7.0)
     p = small_patch(*dims, seed=19, eps=eps, ghosts="zero", f="zero")
     th = [math.pi / (n + 1) for n in dims]
@@ -141,11 +138,7 @@ def test_chaotic_gs_asymptotic_rate(axis):
     fac_lex = (l_b / l_a) ** (1 / 40)
     log("axis %d: chaotic %.6f lex %.6f rho_J^2 %.6f rho_J %.6f" % (axis, fac, fac_lex, rho_j ** 2, rho_j))
     assert fac_lex == pytest.approx(rho_j ** 2, rel=2e-3)
-    # the upper bound is the point: no worse than block Jacobi.  The mix of old
-    # and new values changes from run to run and may beat a consistent
-    # ordering's rho_J^2 a little (0.9507 against 0.9554 measured), so the
-    # lower bound is only a sanity floor
-    assert 0.9 * rho_j ** 2 <= fac <= rho_j * (1 + 1e-3)
+    assert math.log(fac) <= 0.97 * math.log(fac_lex), (fac, fac_lex)
 
 
 # FP32 line solves (residual and update in FP64): each solve returns the
@@ -273,15 +266,22 @@ def test_c2_z_line_jacobi_full():
 @pytest.mark.timeout(900)
 def test_c2_z_line_chaotic_gs_full():
     """256^3 chaotic z-line GS, 100 sweeps, residual every 10 sweeps: within 1.15x
-    the oracle's two-colour GS; the lexicographic ratio is logged."""
+    the oracle's two-colour GS at every check; the ratio to the oracle's
+    lexicographic GS is logged beside it (on this grid two-colour GS itself
+    stays 1.6-1.9x above lexicographic GS for all 100 sweeps, while both share
+    the asymptotic rate rho_J^2)."""
     p = c2_patch()
     s = Single(p)
     r0 = math.sqrt(oracle.residual(p.u0, p.f, p.eps, p.h)[1])
     u = p.u0
+    ul = p.u0
     for blk in range(10):
         s.line(2, "chaotic", 1.0, 10)
         u = oracle.line_sweeps(u, p.f, p.eps, p.h, 2, oracle.COLORED_GS, 1.0, 10)
+        ul = oracle.line_sweeps(ul, p.f, p.eps, p.h, 2, oracle.LEX_GS, 1.0, 10, lex_form=1)
         rg = s.rnorm() / r0
         rb = math.sqrt(oracle.residual(u, p.f, p.eps, p.h)[1]) / r0
-        log("C2 chaotic sweep %d: gpu %.6e two-colour %.6e ratio %.4f" % (10 * (blk + 1), rg, rb, rg / rb))
+        rl = math.sqrt(oracle.residual(ul, p.f, p.eps, p.h)[1]) / r0
+        log("C2 chaotic sweep %d: gpu %.6e two-colour %.6e lex %.6e  gpu/two-colour %.4f gpu/lex %.4f"
+            % (10 * (blk + 1), rg, rb, rl, rg / rb, rg / rl))
         assert rg <= 1.15 * rb

@@ -5,6 +5,8 @@ FP64 Jacobi and two-colour GS: max-norm relative error <= 1e-12 (the plane
 blocks are well conditioned, kappa <= 3 for the tested weights).  The chaotic
 scheme for planes runs the same colour-major order as the two-colour scheme,
 so it is checked against the oracle's two-colour GS too."""
+import math
+
 import numpy as np
 import pytest
 
@@ -125,22 +127,88 @@ def test_mixed_plane_fixed_point(prec):
         assert relerr(s.u_np(), p.u0) < 1e-13
 
 
+def _dev_relerr(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
 @pytest.mark.timeout(900)
 def test_c3_mixed_forms_error_statement():
-    """512^3, eps (1,100,100), xy-plane Jacobi omega 1: five sweeps per form;
-    error of each mixed form against the FP64 GPU result (itself checked
-    against the oracle plane by plane above)."""
+    """512^3, eps (1,100,100), xy-plane Jacobi omega 1, the full 50 sweeps:
+    every 10 sweeps, the max-norm error of each mixed form against the FP64
+    GPU iterate (itself checked against the oracle plane by plane above) stays
+    within k * omega * eta^(refine+1), and its residual within 1e-3 of the FP64
+    one.  BF16 without refinement is logged but carries no bound: its solve
+    error (about 3e-3) exceeds the 1.9e-5 stability margin of the
+    z-checkerboard mode at omega 1, so the iteration is not a contraction."""
+    import torch
     p = c3_patch()
     ref = Single(p)
-    ref.plane(2, "jacobi", 1.0, 5)
-    u64 = ref.u_np()
-    r64 = ref.rnorm()
-    for prec, refine in (("fp32", 0), ("fp32", 1), ("bf16", 1), ("bf16", 2)):
-        bound = mixed_bound(prec, refine, 5)
+    u64, r64 = {}, {}
+    for k in range(10, 51, 10):
+        ref.plane(2, "jacobi", 1.0, 10)
+        u64[k] = ref.u.clone()
+        r64[k] = ref.rnorm()
+    del ref
+    for prec, refine in (("fp32", 0), ("fp32", 1), ("bf16", 1), ("bf16", 2), ("bf16", 0)):
         s = Single(p)
-        s.plane(2, "jacobi", 1.0, 5, prec=prec, refine=refine)
-        e = relerr(s.u_np(), u64)
-        rr = s.rnorm() / r64
-        log("C3 %s refine %d: relerr vs FP64 %.3e (bound %.1e), residual ratio %.6f" % (prec, refine, e, bound, rr))
-        assert e < bound
-        assert abs(rr - 1.0) < 1e-3
+        for k in range(10, 51, 10):
+            s.plane(2, "jacobi", 1.0, 10, prec=prec, refine=refine)
+            torch.cuda.synchronize()
+            e = _dev_relerr(s.u, u64[k])
+            rr = s.rnorm() / r64[k]
+            if prec == "bf16" and refine == 0:
+                log("C3 bf16 refine 0 sweep %d: relerr vs FP64 %.3e (no bound), residual ratio %.6f" % (k, e, rr))
+                continue
+            bound = mixed_bound(prec, refine, k)
+            log("C3 %s refine %d sweep %d: relerr vs FP64 %.3e (bound %.1e), residual ratio %.6f"
+                % (prec, refine, k, e, bound, rr))
+            assert e < bound, (prec, refine, k)
+            assert abs(rr - 1.0) < 1e-3, (prec, refine, k)
+        del s
+
+
+@pytest.mark.timeout(600)
+def test_c3_z_checkerboard_amplification():
+    """Stability of the mixed forms at omega 1 (the residual-correction form of
+    eq. blockiteration2 with an inexact block solve): on 512^3 with eps
+    (1,100,100), f = 0 and zero ghosts, the mode sin((i+1)pi/513)
+    sin((j+1)pi/513) sin(512(k+1)pi/513) is damped by one xy-plane Jacobi sweep
+    to g u with g = nu/mu = -(1 - 3.77e-5) (closed form, which the FP64 sweep
+    must reproduce).  The low-precision solves must not amplify it:
+    ||u_1|| / ||u_0|| <= 1 for FP32 (refine 0, 1) and BF16 with refine 2.
+    BF16 with refine 0 and 1 are logged (predicted unstable / borderline)."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    n = 512
+    eps = (1.0, 100.0, 100.0)
+    h = 1.0 / n
+    th = [math.pi / (n + 1), math.pi / (n + 1), n * math.pi / (n + 1)]
+    mu = 4 * eps[0] * math.sin(th[0] / 2) ** 2 + 4 * eps[1] * math.sin(th[1] / 2) ** 2 + 2 * eps[2]
+    nu = 2 * eps[2] * math.cos(th[2])
+    g = nu / mu
+    log("z-checkerboard: g = %.10f, 1 - |g| = %.3e" % (g, 1 - abs(g)))
+    ps = bs.PatchSet([(n, n, n)], [eps], [h])
+    idx = torch.arange(1, n + 1, dtype=torch.float64, device="cuda")
+    sx = torch.sin(th[0] * idx)
+    sz = torch.sin(th[2] * idx)
+    f = ps.empty_f()
+    u0 = ps.empty_u()
+    ps.view_u(u0, 0)[1:-1, 1:-1, 1:-1] = sz[:, None, None] * sx[None, :, None] * sx[None, None, :]
+    n0 = float(torch.linalg.vector_norm(u0))
+    w = ps.empty_u()
+    for prec, refine, must in (("fp64", 0, True), ("fp32", 0, True), ("fp32", 1, True), ("bf16", 2, True),
+                               ("bf16", 1, False), ("bf16", 0, False)):
+        u = u0.clone()
+        ps.plane_relax(2, "jacobi", 1.0, 1, u, f, w, prec=prec, refine=refine)
+        torch.cuda.synchronize()
+        amp = float(torch.linalg.vector_norm(u)) / n0
+        dev = float(torch.linalg.vector_norm(u - g * u0)) / n0
+        log("z-checkerboard %s refine %d: ||u1||/||u0|| = %.10f (1 - amp %.3e), ||u1 - g u0||/||u0|| = %.3e"
+            % (prec, refine, amp, 1 - amp, dev))
+        if prec == "fp64":
+            assert dev < 1e-10
+        elif must:
+            assert amp <= 1.0, (prec, refine, amp)
+        del u
+    ps.close()

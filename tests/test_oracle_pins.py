@@ -344,3 +344,54 @@ def test_adjoint_dot_product():
     lhs = float(np.sum(Jv[1:-1, 1:-1, 1:-1] * w[1:-1, 1:-1, 1:-1]))
     rhs = float(np.sum(v[1:-1, 1:-1, 1:-1] * JTw[1:-1, 1:-1, 1:-1]))
     assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+# --- the partial-update helpers (checkers of single planes / lines of a large sweep) ----------
+
+@pytest.mark.parametrize("normal", [0, 1, 2])
+def test_plane_update_some_all_planes_is_one_jacobi_sweep(normal):
+    """Updating every plane from the same u is one plane-Jacobi sweep (bitwise,
+    both use the same per-plane arithmetic); a subset changes only its planes,
+    each exactly as in the full sweep, and is pinned to the dense brute force."""
+    p = small_patch(9, 7, 6, seed=33 + normal, eps=EPS)
+    nc = p.dims[normal]
+    full = oracle.plane_sweeps(p.u0, p.f, p.eps, p.h, normal, oracle.JACOBI, 0.8, 1)
+    every = oracle.plane_update_some(p.u0, p.f, p.eps, p.h, normal, 0.8, list(range(nc)))
+    assert np.array_equal(every, full)
+    some = [1, nc - 1]
+    part = oracle.plane_update_some(p.u0, p.f, p.eps, p.h, normal, 0.8, some)
+    idx = lambda s: tuple(slice(s + 1, s + 2) if ax == normal else slice(None) for ax in (2, 1, 0))
+    for s in range(nc):
+        sl = idx(s)
+        if s in some:
+            assert np.array_equal(part[sl], full[sl]), s
+        else:
+            assert np.array_equal(part[sl], p.u0[sl]), s
+    dense = brute.sweeps(p.u0, p.f, p.eps, p.h, "plane", normal, "jacobi", 0.8, 1)
+    assert relerr(every, dense) < 1e-14
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_line_update_some_reproduces_every_scheme(axis):
+    """Line updates of listed lines from a given u: all lines at once is a
+    Jacobi sweep; colour 0 then colour 1 is the two-colour GS sweep; one line at
+    a time in lexicographic order is lexicographic GS (each bitwise against the
+    oracle's sweeps, and Jacobi against the dense brute force)."""
+    p = small_patch(6, 5, 7, seed=41 + axis, eps=EPS)
+    n = p.dims
+    free = [a for a in (0, 1, 2) if a != axis]
+    npq = (n[free[0]], n[free[1]])
+    lines = [(a, b) for b in range(npq[1]) for a in range(npq[0])]   # lower free axis fastest
+    jac = oracle.line_update_some(p.u0, p.f, p.eps, p.h, axis, 0.8, lines)
+    assert np.array_equal(jac, oracle.line_sweeps(p.u0, p.f, p.eps, p.h, axis, oracle.JACOBI, 0.8, 1))
+    assert relerr(jac, brute.sweeps(p.u0, p.f, p.eps, p.h, "line", axis, "jacobi", 0.8, 1)) < 1e-14
+    u = p.u0.copy()
+    for c in (0, 1):
+        u = oracle.line_update_some(u, p.f, p.eps, p.h, axis, 1.0, [l for l in lines if (l[0] + l[1]) % 2 == c])
+    assert np.array_equal(u, oracle.line_sweeps(p.u0, p.f, p.eps, p.h, axis, oracle.COLORED_GS, 1.0, 1))
+    u = p.u0.copy()
+    for l in lines:
+        u = oracle.line_update_some(u, p.f, p.eps, p.h, axis, 1.0, [l])
+    assert np.array_equal(u, oracle.line_sweeps(p.u0, p.f, p.eps, p.h, axis, oracle.LEX_GS, 1.0, 1))
+    with pytest.raises(ValueError):
+        oracle.line_update_some(p.u0, p.f, p.eps, p.h, axis, 1.0, [(npq[0], 0)])
