@@ -66,6 +66,8 @@ def _load():
     lib.bso_line_jacobi_eps_tangent.restype = I
     lib.bso_cube_sweeps.argtypes = [I, I, I, P, D, I, I, I, I, D, I, P, P]
     lib.bso_cube_sweeps.restype = I
+    lib.bso_exchange_ghosts.argtypes = [I, P, P, I, P]
+    lib.bso_exchange_ghosts.restype = I
     lib.bso_set_threads.argtypes = [I]
     lib.bso_set_threads.restype = None
     lib.bso_get_threads.argtypes = []
@@ -215,4 +217,33 @@ def line_jacobi_eps_tangent(u0, f, eps, h, axis, omega, K, gK):
                                          float(omega), int(K), _p(u0), _p(f), _p(gK), _p(out))
     if rc:
         raise ValueError("bso_line_jacobi_eps_tangent failed")
+    return out
+
+
+def exchange_ghosts(us, links):
+    """Ghost exchange between adjacent patches: copies of the padded arrays
+    us[p] in which, for every link (a, axis, b) (patch b on a's high side
+    along axis, equal extents along the other axes), a's high ghost layer
+    holds b's first interior layer and b's low ghost layer a's last one."""
+    lib = _load()
+    out = [np.array(u, dtype=np.float64, order="C", copy=True) for u in us]
+    dims = np.ascontiguousarray([_dims_of(u) for u in out], dtype=np.int32).reshape(-1)
+    ptrs = (ctypes.c_void_p * len(out))(*[u.ctypes.data for u in out])
+    lk = np.ascontiguousarray(np.asarray(links, dtype=np.int32).reshape(-1, 3))
+    rc = lib.bso_exchange_ghosts(len(out), _p(dims), ptrs, lk.shape[0], _p(lk))
+    if rc:
+        raise ValueError("bso_exchange_ghosts: bad link (%d)" % rc)
+    return out
+
+
+def patchset_sweeps(us, fs, eps, h, links, kind, arg, scheme, omega, nsweeps):
+    """nsweeps smoothing steps of a patch set with adjacency: in every step
+    each patch takes one sweep of `kind` ('line' along axis arg, 'plane' with
+    normal arg, 'cube' with block arg) of `scheme` from its own ghosts, then
+    the ghosts are exchanged (section 2).  eps and h are per patch."""
+    fn = {"line": line_sweeps, "plane": plane_sweeps, "cube": cube_sweeps}[kind]
+    out = [np.array(u, copy=True) for u in us]
+    for _ in range(nsweeps):
+        out = [fn(out[p], fs[p], eps[p], h[p], arg, scheme, omega, 1) for p in range(len(out))]
+        out = exchange_ghosts(out, links)
     return out

@@ -913,3 +913,49 @@ int bso_line_jacobi_eps_tangent(int nx, int ny, int nz, const double eps[3], dou
     for (int b = 0; b < 3; ++b) free(t[b]);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Ghost exchange between adjacent patches (section 2: the ghost cells that   */
+/* patches share are updated Jacobi-fashion once a full smoothing step is     */
+/* done; section 1.1: such interior ghosts carry the values of the            */
+/* neighbouring patch).  A link (a, axis, b) says that patch b lies on patch  */
+/* a's high side along `axis`, face to face: both have the same extents along */
+/* the two other axes.  The exchange copies b's first interior layer along    */
+/* `axis` into a's ghost layer at index n_a, and a's last interior layer into */
+/* b's ghost layer at index -1.  Every copy reads interior cells and writes   */
+/* ghost cells, so the copies can run in any order.                          */
+/* ------------------------------------------------------------------------- */
+int bso_exchange_ghosts(int npatch, const int *dims, double *const *us, int nlinks, const int *links)
+{
+    for (int t = 0; t < nlinks; ++t) {
+        int a = links[3 * t], axis = links[3 * t + 1], b = links[3 * t + 2];
+        if (a < 0 || a >= npatch || b < 0 || b >= npatch || a == b || axis < 0 || axis > 2) return 1;
+        for (int o = 0; o < 3; ++o)
+            if (o != axis && dims[3 * a + o] != dims[3 * b + o]) return 2;
+    }
+    for (int t = 0; t < nlinks; ++t) {
+        int a = links[3 * t], axis = links[3 * t + 1], b = links[3 * t + 2];
+        const double eps1[3] = {1.0, 1.0, 1.0};
+        grid_t ga = mkgrid(dims[3 * a], dims[3 * a + 1], dims[3 * a + 2], eps1, 1.0);
+        grid_t gb = mkgrid(dims[3 * b], dims[3 * b + 1], dims[3 * b + 2], eps1, 1.0);
+        int na = dim_of(&ga, axis);
+        /* the two tangential axes, lower first */
+        int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+        int m1 = dim_of(&ga, t1), m2 = dim_of(&ga, t2);
+        for (int q = 0; q < m2; ++q)
+            for (int p = 0; p < m1; ++p) {
+                int ia[3], ib[3];
+                ia[t1] = ib[t1] = p;
+                ia[t2] = ib[t2] = q;
+                /* a's ghost at n_a <- b's cell 0 */
+                ia[axis] = na;
+                ib[axis] = 0;
+                us[a][uidx(&ga, ia[0], ia[1], ia[2])] = us[b][uidx(&gb, ib[0], ib[1], ib[2])];
+                /* b's ghost at -1 <- a's cell n_a - 1 */
+                ia[axis] = na - 1;
+                ib[axis] = -1;
+                us[b][uidx(&gb, ib[0], ib[1], ib[2])] = us[a][uidx(&ga, ia[0], ia[1], ia[2])];
+            }
+    }
+    return 0;
+}

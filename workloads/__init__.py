@@ -158,3 +158,80 @@ def small_patch(nx, ny, nz, seed, eps=None, ghosts="uniform", u0="uniform", f="u
     if eps is None:
         eps = (1.0, 3.0, 7.0)
     return make_patch(nx, ny, nz, eps, 1.0 / max(nx, ny, nz), seed, f=f, u0=u0, ghosts=ghosts)
+
+
+# --- patch sets with adjacency (ghost exchange between patches) ----------------
+
+@dataclass
+class LinkedSet:
+    """Patches that tile a box face to face.  links: (a, axis, b) with b on a's
+    high side along axis; offsets: (x0, y0, z0) of each patch in the box."""
+    dims: list
+    eps: list
+    h: list
+    u0: list
+    f: list
+    links: list
+    offsets: list
+
+    @property
+    def npatch(self):
+        return len(self.dims)
+
+    def cells(self) -> int:
+        return int(sum(nx * ny * nz for nx, ny, nz in self.dims))
+
+
+def split_patch(patch: Patch, cuts) -> LinkedSet:
+    """Cut one patch into a grid of sub-patches at the cell positions
+    cuts = (xcuts, ycuts, zcuts) (interior boundaries along each axis).  Each
+    sub-patch's u holds the global array's values on its interior and face
+    ghosts (so the ghosts are already consistent), f its slice of f."""
+    nx, ny, nz = patch.dims
+    edges = [[0] + sorted(c) + [n] for c, n in zip(cuts, (nx, ny, nz))]
+    counts = [len(e) - 1 for e in edges]
+    index = {}
+    dims, us, fs, offs = [], [], [], []
+    for c in range(counts[2]):
+        for b in range(counts[1]):
+            for a in range(counts[0]):
+                x0, x1 = edges[0][a], edges[0][a + 1]
+                y0, y1 = edges[1][b], edges[1][b + 1]
+                z0, z1 = edges[2][c], edges[2][c + 1]
+                index[(a, b, c)] = len(dims)
+                dims.append((x1 - x0, y1 - y0, z1 - z0))
+                us.append(np.ascontiguousarray(patch.u0[z0:z1 + 2, y0:y1 + 2, x0:x1 + 2]))
+                fs.append(np.ascontiguousarray(patch.f[z0:z1, y0:y1, x0:x1]))
+                offs.append((x0, y0, z0))
+    links = []
+    for (a, b, c), p in index.items():
+        for axis, nb in ((0, (a + 1, b, c)), (1, (a, b + 1, c)), (2, (a, b, c + 1))):
+            if nb in index:
+                links.append((p, axis, index[nb]))
+    n = len(dims)
+    return LinkedSet(dims=dims, eps=[patch.eps] * n, h=[patch.h] * n, u0=us, f=fs, links=links, offsets=offs)
+
+
+def c4_adjacent_patchset(grid=(14, 14, 15), seed=4, edges=EDGE_CHOICES) -> LinkedSet:
+    """An adjacent version of the uneven AMR set: a grid of patches that tile a
+    box face to face (14 x 14 x 15 = 2940 patches by default), the edge of
+    every slab of patches drawn from `edges` (so faces always match), eps =
+    10^U[0,2] per axis and patch, h = 1/64, u, f and the box's outer ghosts ~
+    U[-1,1]; the ghosts between patches start from the neighbours' values."""
+    rng = rng_for(seed)
+    ex = [int(v) for v in rng.choice(np.asarray(edges), size=grid[0])]
+    ey = [int(v) for v in rng.choice(np.asarray(edges), size=grid[1])]
+    ez = [int(v) for v in rng.choice(np.asarray(edges), size=grid[2])]
+    X, Y, Z = sum(ex), sum(ey), sum(ez)
+    npatch = grid[0] * grid[1] * grid[2]
+    eps = 10.0 ** rng.uniform(0.0, 2.0, size=(npatch, 3))
+    f = rng.uniform(-1.0, 1.0, size=(Z, Y, X))
+    u = np.empty((Z + 2, Y + 2, X + 2))
+    u[1:-1, 1:-1, 1:-1] = rng.uniform(-1.0, 1.0, size=(Z, Y, X))
+    gm = ghost_mask(X, Y, Z)
+    u[gm] = rng.uniform(-1.0, 1.0, size=int(gm.sum()))
+    whole = Patch(u0=u, f=f, eps=(1.0, 1.0, 1.0), h=1.0 / 64)
+    cuts = [list(np.cumsum(e)[:-1]) for e in (ex, ey, ez)]
+    s = split_patch(whole, cuts)
+    s.eps = [tuple(float(v) for v in e) for e in eps]
+    return s
