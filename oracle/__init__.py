@@ -50,6 +50,14 @@ def _load():
     D, I, P = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
     lib.bso_residual.argtypes = [I, I, I, P, D, P, P, P]
     lib.bso_residual.restype = D
+    lib.bso_residual_bc.argtypes = [I, I, I, P, D, P, P, P, I]
+    lib.bso_residual_bc.restype = D
+    lib.bso_line_sweeps_bc.argtypes = [I, I, I, P, D, I, I, D, I, I, P, P, I]
+    lib.bso_line_sweeps_bc.restype = I
+    lib.bso_plane_sweeps_bc.argtypes = [I, I, I, P, D, I, I, D, I, P, P, I]
+    lib.bso_plane_sweeps_bc.restype = I
+    lib.bso_cube_sweeps_bc.argtypes = [I, I, I, P, D, I, I, I, I, D, I, P, P, I]
+    lib.bso_cube_sweeps_bc.restype = I
     lib.bso_tridiag_solve.argtypes = [I, D, D, P, P]
     lib.bso_tridiag_solve.restype = None
     lib.bso_line_sweeps.argtypes = [I, I, I, P, D, I, I, D, I, I, P, P]
@@ -68,6 +76,10 @@ def _load():
     lib.bso_cube_sweeps.restype = I
     lib.bso_exchange_ghosts.argtypes = [I, P, P, I, P]
     lib.bso_exchange_ghosts.restype = I
+    lib.bso_restrict.argtypes = [I, I, I, P, D, P]
+    lib.bso_restrict.restype = I
+    lib.bso_prolong_add_bc.argtypes = [I, I, I, P, P, I]
+    lib.bso_prolong_add_bc.restype = I
     lib.bso_set_threads.argtypes = [I]
     lib.bso_set_threads.restype = None
     lib.bso_get_threads.argtypes = []
@@ -105,13 +117,21 @@ def get_threads() -> int:
     return int(_load().bso_get_threads())
 
 
-def residual(u, f, eps, h, want_r=True):
+# Boundary reading: bc is a 6-bit mask of faces with extrapolated Dirichlet
+# conditions (bit 2a: low face of axis a, bit 2a+1: high face), where the
+# ghost takes -(the adjacent interior value) and folds into the operator
+# (section 1.1: boundary conditions extrapolated into the ghost layer); other
+# faces read their ghosts as data.  bc = 0 everywhere by default.
+BC_ALL = 63
+
+
+def residual(u, f, eps, h, want_r=True, bc=0):
     """(r, sum r^2): r = h^2 f - A_eps u over interior cells (eq. stencil3d7)."""
     lib = _load()
     nx, ny, nz = _check(u, f)
     e = _eps(eps)
     r = np.empty((nz, ny, nx)) if want_r else None
-    s = lib.bso_residual(nx, ny, nz, _p(e), float(h), _p(u), _p(f), _p(r))
+    s = lib.bso_residual_bc(nx, ny, nz, _p(e), float(h), _p(u), _p(f), _p(r), int(bc))
     return r, s
 
 
@@ -124,31 +144,31 @@ def tridiag_solve(off, diag, rhs):
     return x
 
 
-def line_sweeps(u, f, eps, h, axis, scheme, omega, nsweeps, lex_form=0):
+def line_sweeps(u, f, eps, h, axis, scheme, omega, nsweeps, lex_form=0, bc=0):
     """Return u after nsweeps line-block sweeps (u is not modified)."""
     lib = _load()
     nx, ny, nz = _check(u, f)
     out = u.copy()
-    rc = lib.bso_line_sweeps(nx, ny, nz, _p(_eps(eps)), float(h), int(axis), int(scheme),
-                             float(omega), int(nsweeps), int(lex_form), _p(out), _p(f))
+    rc = lib.bso_line_sweeps_bc(nx, ny, nz, _p(_eps(eps)), float(h), int(axis), int(scheme),
+                                float(omega), int(nsweeps), int(lex_form), _p(out), _p(f), int(bc))
     if rc:
         raise ValueError("bso_line_sweeps failed (%d)" % rc)
     return out
 
 
-def plane_sweeps(u, f, eps, h, normal, scheme, omega, nsweeps):
+def plane_sweeps(u, f, eps, h, normal, scheme, omega, nsweeps, bc=0):
     """Return u after nsweeps plane-block sweeps (u is not modified)."""
     lib = _load()
     nx, ny, nz = _check(u, f)
     out = u.copy()
-    rc = lib.bso_plane_sweeps(nx, ny, nz, _p(_eps(eps)), float(h), int(normal), int(scheme),
-                              float(omega), int(nsweeps), _p(out), _p(f))
+    rc = lib.bso_plane_sweeps_bc(nx, ny, nz, _p(_eps(eps)), float(h), int(normal), int(scheme),
+                                 float(omega), int(nsweeps), _p(out), _p(f), int(bc))
     if rc:
         raise ValueError("bso_plane_sweeps failed (%d)" % rc)
     return out
 
 
-def cube_sweeps(u, f, eps, h, block, scheme, omega, nsweeps):
+def cube_sweeps(u, f, eps, h, block, scheme, omega, nsweeps, bc=0):
     """Return u after nsweeps sweeps over geometric blocks of block = (bx, by, bz)
     cells (shorter last blocks where an edge does not divide the patch; each
     block solved exactly).  u is not modified."""
@@ -156,8 +176,8 @@ def cube_sweeps(u, f, eps, h, block, scheme, omega, nsweeps):
     nx, ny, nz = _check(u, f)
     bx, by, bz = (int(b) for b in block)
     out = u.copy()
-    rc = lib.bso_cube_sweeps(nx, ny, nz, _p(_eps(eps)), float(h), bx, by, bz, int(scheme),
-                             float(omega), int(nsweeps), _p(out), _p(f))
+    rc = lib.bso_cube_sweeps_bc(nx, ny, nz, _p(_eps(eps)), float(h), bx, by, bz, int(scheme),
+                                float(omega), int(nsweeps), _p(out), _p(f), int(bc))
     if rc:
         raise ValueError("bso_cube_sweeps failed (%d)" % rc)
     return out
@@ -247,3 +267,68 @@ def patchset_sweeps(us, fs, eps, h, links, kind, arg, scheme, omega, nsweeps):
         out = [fn(out[p], fs[p], eps[p], h[p], arg, scheme, omega, 1) for p in range(len(out))]
         out = exchange_ghosts(out, links)
     return out
+
+
+# --- multigrid with the block smoothers (section 1: line and plane smoothers are
+# components of robust geometric multigrid; section 5: multilevel use) ---------
+
+def restrict(r, scale=1.0):
+    """Cell-centred restriction: mean of each 2x2x2 group of fine values (f
+    layout, even dims), times scale."""
+    lib = _load()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    nz, ny, nx = r.shape
+    out = np.empty((nz // 2, ny // 2, nx // 2))
+    if lib.bso_restrict(nx, ny, nz, _p(r), float(scale), _p(out)):
+        raise ValueError("restrict: fine dims must be even and >= 2")
+    return out
+
+
+def prolong_add(uc, uf, bc=0):
+    """uf (padded, fine) + trilinear interpolation of the coarse padded uc
+    (coarse ghosts are read at the edges, or extrapolated across the faces in
+    bc); returns a new array."""
+    lib = _load()
+    out = np.array(uf, dtype=np.float64, copy=True)
+    nx, ny, nz = _dims_of(out)
+    uc = np.ascontiguousarray(uc, dtype=np.float64)
+    assert uc.shape == (nz // 2 + 2, ny // 2 + 2, nx // 2 + 2)
+    if lib.bso_prolong_add_bc(nx, ny, nz, _p(uc), _p(out), int(bc)):
+        raise ValueError("prolong_add: fine dims must be even and >= 2")
+    return out
+
+
+def mg_levels(dims, max_levels=32):
+    """Levels of the factor-2 hierarchy: halve while every edge is even and >= 2."""
+    n = 1
+    d = list(dims)
+    while n < max_levels and all(v % 2 == 0 and v >= 2 for v in d):
+        d = [v // 2 for v in d]
+        n += 1
+    return n
+
+
+def vcycle(u, f, eps, h, kind, arg, scheme, omega, nu1, nu2, ncoarse, levels=None, bc=0, coarse_bc=None):
+    """One V(nu1, nu2) cycle for A u = h^2 f on one patch: nu1 smoothing sweeps
+    of `kind` ('line' along axis arg, 'plane' with normal arg) and `scheme`;
+    the defect d = h^2 f - A u restricted to f_c = R(d / h^2) on the grid of
+    cell width 2h (so that the coarse equation is A e_c = (2h)^2 f_c with zero
+    ghosts and the same eps); the cycle applied to e_c = 0 there; u += P e_c;
+    nu2 sweeps.  On the coarsest level: ncoarse sweeps.  bc is this level's
+    boundary reading; the coarse levels take coarse_bc (default: bc), whose
+    ghosts carry the error's homogeneous condition.  Returns the new u."""
+    fn = {"line": line_sweeps, "plane": plane_sweeps}[kind]
+    nx, ny, nz = _dims_of(u)
+    if coarse_bc is None:
+        coarse_bc = bc
+    if levels is None:
+        levels = mg_levels((nx, ny, nz))
+    if levels <= 1:
+        return fn(u, f, eps, h, arg, scheme, omega, ncoarse, bc=bc)
+    u = fn(u, f, eps, h, arg, scheme, omega, nu1, bc=bc)
+    d, _ = residual(u, f, eps, h, bc=bc)
+    fc = restrict(d, 1.0 / (h * h))
+    ec = vcycle(np.zeros((nz // 2 + 2, ny // 2 + 2, nx // 2 + 2)), fc, eps, 2.0 * h, kind, arg, scheme, omega,
+                nu1, nu2, ncoarse, levels - 1, bc=coarse_bc, coarse_bc=coarse_bc)
+    u = prolong_add(ec, u, bc=coarse_bc)
+    return fn(u, f, eps, h, arg, scheme, omega, nu2, bc=bc)

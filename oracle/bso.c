@@ -59,6 +59,7 @@ typedef struct {
     int nx, ny, nz;
     double ex, ey, ez, h2;
     ptrdiff_t sx, sy;   /* u strides in y and z (padded) */
+    int bc;             /* extrapolated-Dirichlet faces: bit 2a low, bit 2a+1 high face of axis a */
 } grid_t;
 
 static grid_t mkgrid(int nx, int ny, int nz, const double eps[3], double h)
@@ -69,6 +70,7 @@ static grid_t mkgrid(int nx, int ny, int nz, const double eps[3], double h)
     g.h2 = h * h;
     g.sx = nx + 2;
     g.sy = (ptrdiff_t)(nx + 2) * (ny + 2);
+    g.bc = 0;
     return g;
 }
 
@@ -86,14 +88,52 @@ static int dim_of(const grid_t *g, int a) { return a == 0 ? g->nx : (a == 1 ? g-
 static double eps_of(const grid_t *g, int a) { return a == 0 ? g->ex : (a == 1 ? g->ey : g->ez); }
 static ptrdiff_t ustride_of(const grid_t *g, int a) { return a == 0 ? 1 : (a == 1 ? g->sx : g->sy); }
 
+/* Boundary reading (section 1.1: boundary conditions are extrapolated into the
+ * ghost layer).  By default the ghosts are data (zero Dirichlet = a zero ghost
+ * layer).  A face whose bit is set in bc instead takes the value that puts
+ * zero on the face between the boundary cell and its ghost, ghost = -(the
+ * adjacent interior value), so the stencil's ghost term folds into the
+ * operator: the boundary cell's diagonal gains eps_a and the ghost is never
+ * read.  Neighbour of cell c (index t along axis a, n_a cells) on side dir. */
+static inline double nbr(const grid_t *g, const double *u, ptrdiff_t c, int a, int t, int dir)
+{
+    ptrdiff_t st = a == 0 ? 1 : (a == 1 ? g->sx : g->sy);
+    int n = a == 0 ? g->nx : (a == 1 ? g->ny : g->nz);
+    if (dir < 0 && t == 0 && (g->bc >> (2 * a) & 1)) return -u[c];
+    if (dir > 0 && t == n - 1 && (g->bc >> (2 * a + 1) & 1)) return -u[c];
+    return dir < 0 ? u[c - st] : u[c + st];
+}
+
 /* Residual of one interior cell: h^2 f - (A u) (eq. stencil3d7 with axis weights). */
 static inline double cell_res(const grid_t *g, const double *u, const double *f, int i, int j, int k)
 {
     ptrdiff_t c = uidx(g, i, j, k);
+    if (g->bc) {
+        double ax = g->ex * (2.0 * u[c] - nbr(g, u, c, 0, i, -1) - nbr(g, u, c, 0, i, 1));
+        double ay = g->ey * (2.0 * u[c] - nbr(g, u, c, 1, j, -1) - nbr(g, u, c, 1, j, 1));
+        double az = g->ez * (2.0 * u[c] - nbr(g, u, c, 2, k, -1) - nbr(g, u, c, 2, k, 1));
+        return g->h2 * f[fidx(g, i, j, k)] - (ax + ay + az);
+    }
     double ax = g->ex * (2.0 * u[c] - u[c - 1] - u[c + 1]);
     double ay = g->ey * (2.0 * u[c] - u[c - g->sx] - u[c + g->sx]);
     double az = g->ez * (2.0 * u[c] - u[c - g->sy] - u[c + g->sy]);
     return g->h2 * f[fidx(g, i, j, k)] - (ax + ay + az);
+}
+
+/* Diagonal of the operator at cell (i,j,k): sum_a eps_a (2 + the number of
+ * extrapolated faces of axis a that the cell touches). */
+static double diag_at(const grid_t *g, int i, int j, int k)
+{
+    const int t[3] = {i, j, k}, n[3] = {g->nx, g->ny, g->nz};
+    const double e[3] = {g->ex, g->ey, g->ez};
+    double d = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double m = 2.0;
+        if (t[a] == 0 && (g->bc >> (2 * a) & 1)) m += 1.0;
+        if (t[a] == n[a] - 1 && (g->bc >> (2 * a + 1) & 1)) m += 1.0;
+        d += e[a] * m;
+    }
+    return d;
 }
 
 static int g_threads = 0;
@@ -116,10 +156,11 @@ int bso_get_threads(void)
 
 /* r (unpadded, may be NULL) = h^2 f - A u; returns sum of r^2 over interior
  * cells, accumulated in long double in k,j,i order. */
-double bso_residual(int nx, int ny, int nz, const double eps[3], double h,
-                    const double *u, const double *f, double *r)
+double bso_residual_bc(int nx, int ny, int nz, const double eps[3], double h,
+                       const double *u, const double *f, double *r, int bc)
 {
     grid_t g = mkgrid(nx, ny, nz, eps, h);
+    g.bc = bc;
     long double *part = (long double *)calloc((size_t)nz, sizeof(long double));
 #ifdef _OPENMP
 #pragma omp parallel for num_threads(NT) schedule(static)
@@ -140,6 +181,12 @@ double bso_residual(int nx, int ny, int nz, const double eps[3], double h,
     return (double)tot;
 }
 
+double bso_residual(int nx, int ny, int nz, const double eps[3], double h,
+                    const double *u, const double *f, double *r)
+{
+    return bso_residual_bc(nx, ny, nz, eps, h, u, f, r, 0);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Tridiagonal solve (textbook Thomas algorithm, Conte & de Boor form).       */
 /* Solves tridiag(off, diag, off) x = rhs for a symmetric Toeplitz system,    */
@@ -157,6 +204,22 @@ static void thomas(int n, double off, double diag, const double *rhs, double *x,
         x[i] = (rhs[i] - off * x[i - 1]) / denom;
     }
     /* back substitution */
+    for (int i = n - 2; i >= 0; --i)
+        x[i] = x[i] - cp[i] * x[i + 1];
+}
+
+/* The same for tridiag(off, diag[t], off) with a diagonal that varies along the
+ * line (extrapolated boundary faces). */
+static void thomas_v(int n, double off, const double *diag, const double *rhs, double *x, double *cp)
+{
+    double denom = diag[0];
+    cp[0] = off / denom;
+    x[0] = rhs[0] / denom;
+    for (int i = 1; i < n; ++i) {
+        denom = diag[i] - off * cp[i - 1];
+        cp[i] = off / denom;
+        x[i] = (rhs[i] - off * x[i - 1]) / denom;
+    }
     for (int i = n - 2; i >= 0; --i)
         x[i] = x[i] - cp[i] * x[i + 1];
 }
@@ -191,7 +254,7 @@ static void free_dims(const grid_t *g, int axis, int *np, int *nq)
 /* One block update of line (p,q): residual from usrc, exact tridiagonal
  * solve, udst = usrc + omega*du on the line's cells.  All residuals are formed
  * before any value is written, so usrc == udst (in place) is allowed.
- * buf must hold 2n doubles. */
+ * buf must hold 3n doubles. */
 static void line_update(const grid_t *g, int axis, int p, int q, const double *usrc,
                         double *udst, const double *f, double omega, double *buf)
 {
@@ -204,7 +267,16 @@ static void line_update(const grid_t *g, int axis, int p, int q, const double *u
         line_cell(axis, p, q, t, &i, &j, &k);
         r[t] = cell_res(g, usrc, f, i, j, k);
     }
-    thomas(n, -ea, d, r, r, cp);
+    if (g->bc) {
+        double *dg = buf + 2 * (size_t)n;
+        for (int t = 0; t < n; ++t) {
+            line_cell(axis, p, q, t, &i, &j, &k);
+            dg[t] = diag_at(g, i, j, k);
+        }
+        thomas_v(n, -ea, dg, r, r, cp);
+    } else {
+        thomas(n, -ea, d, r, r, cp);
+    }
     for (int t = 0; t < n; ++t) {
         line_cell(axis, p, q, t, &i, &j, &k);
         ptrdiff_t c = uidx(g, i, j, k);
@@ -225,12 +297,13 @@ static void copy_padded(const grid_t *g, const double *src, double *dst)
  *               lie on the previous anti-diagonal, so processing diagonals in
  *               order gives bit-identical results, in parallel.
  * Returns 0 on success, nonzero on bad arguments. */
-int bso_line_sweeps(int nx, int ny, int nz, const double eps[3], double h, int axis,
-                    int scheme, double omega, int nsweeps, int lex_form,
-                    double *u, const double *f)
+int bso_line_sweeps_bc(int nx, int ny, int nz, const double eps[3], double h, int axis,
+                       int scheme, double omega, int nsweeps, int lex_form,
+                       double *u, const double *f, int bc)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || axis < 0 || axis > 2 || nsweeps < 0) return 1;
+    if (nx < 1 || ny < 1 || nz < 1 || axis < 0 || axis > 2 || nsweeps < 0 || bc < 0 || bc > 63) return 1;
     grid_t g = mkgrid(nx, ny, nz, eps, h);
+    g.bc = bc;
     int n = dim_of(&g, axis), np, nq;
     free_dims(&g, axis, &np, &nq);
     size_t tot = (size_t)(nz + 2) * (size_t)g.sy;
@@ -245,7 +318,7 @@ int bso_line_sweeps(int nx, int ny, int nz, const double eps[3], double h, int a
 #pragma omp parallel num_threads(NT)
 #endif
             {
-                double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+                double *buf = (double *)malloc(sizeof(double) * 3 * (size_t)n);
 #ifdef _OPENMP
 #pragma omp for collapse(2) schedule(static)
 #endif
@@ -258,7 +331,7 @@ int bso_line_sweeps(int nx, int ny, int nz, const double eps[3], double h, int a
             copy_padded(&g, v, t);
         } else if (scheme == BSO_LEX_GS) {
             if (lex_form == 0) {
-                double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+                double *buf = (double *)malloc(sizeof(double) * 3 * (size_t)n);
                 for (int q = 0; q < nq; ++q)
                     for (int p = 0; p < np; ++p)
                         line_update(&g, axis, p, q, u, u, f, omega, buf);
@@ -268,7 +341,7 @@ int bso_line_sweeps(int nx, int ny, int nz, const double eps[3], double h, int a
 #pragma omp parallel num_threads(NT)
 #endif
                 {
-                    double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+                    double *buf = (double *)malloc(sizeof(double) * 3 * (size_t)n);
                     for (int dg = 0; dg <= (np - 1) + (nq - 1); ++dg) {
                         int qlo = dg - (np - 1) > 0 ? dg - (np - 1) : 0;
                         int qhi = dg < nq - 1 ? dg : nq - 1;
@@ -288,7 +361,7 @@ int bso_line_sweeps(int nx, int ny, int nz, const double eps[3], double h, int a
 #pragma omp parallel num_threads(NT)
 #endif
                 {
-                    double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+                    double *buf = (double *)malloc(sizeof(double) * 3 * (size_t)n);
 #ifdef _OPENMP
 #pragma omp for collapse(2) schedule(static)
 #endif
@@ -306,6 +379,13 @@ int bso_line_sweeps(int nx, int ny, int nz, const double eps[3], double h, int a
     }
     free(v);
     return 0;
+}
+
+int bso_line_sweeps(int nx, int ny, int nz, const double eps[3], double h, int axis,
+                    int scheme, double omega, int nsweeps, int lex_form,
+                    double *u, const double *f)
+{
+    return bso_line_sweeps_bc(nx, ny, nz, eps, h, axis, scheme, omega, nsweeps, lex_form, u, f, 0);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -344,6 +424,43 @@ static sine_basis_t make_basis(int na, double ea)
     return B;
 }
 
+/* Orthonormal eigenbasis of tridiag(-1, 2, -1) on n cells whose low / high end
+ * is an extrapolated face (diagonal 3 there), and its eigenvalues times ea.
+ * The eigenvectors are sines sampled at the cell centres:
+ *   neither end: sin(theta (i+1)),      theta = (p+1) pi / (n+1)    (DST-I)
+ *   both ends:   sin(theta (i+1/2)),    theta = (p+1) pi / n        (DST-II)
+ *   low end:     sin(theta (i+1/2)),    theta = (p+1) pi / (n+1/2)
+ *   high end:    sin(theta (n-i-1/2)),  the mirror image,
+ * with eigenvalue 4 sin^2(theta/2) (the extrapolated ghost -v_0 and the zero
+ * ghost v_n are what these sines take one cell beyond each end).  Sine
+ * arguments are reduced in integers; columns are normalised by their sums of
+ * squares. */
+static sine_basis_t make_basis_bc(int na, double ea, int lo, int hi)
+{
+    if (!lo && !hi) return make_basis(na, ea);
+    sine_basis_t B;
+    B.na = na; B.nb = 0;
+    B.S = (double *)malloc(sizeof(double) * (size_t)na * na);
+    B.sigma = (double *)malloc(sizeof(double) * (size_t)na);
+    /* theta (i + 1/2) = pi m / den with the integer m below */
+    long den = (lo && hi) ? 2L * na : 2L * na + 1;
+    for (int p = 0; p < na; ++p) {
+        long double ss = 0.0L;
+        for (int i = 0; i < na; ++i) {
+            long ii = (lo ? i : na - 1 - i);
+            long m = ((long)(p + 1) * (2 * ii + 1)) % (2 * den);
+            double v = sin(M_PI * (double)m / (double)den);
+            B.S[(size_t)i * na + p] = v;
+            ss += (long double)v * v;
+        }
+        double sc = (double)(1.0L / sqrtl(ss));
+        for (int i = 0; i < na; ++i) B.S[(size_t)i * na + p] *= sc;
+        double s = sin(M_PI * (double)(p + 1) / (double)den);
+        B.sigma[p] = 4.0 * ea * s * s;
+    }
+    return B;
+}
+
 static void free_basis(sine_basis_t *B) { free(B->S); free(B->sigma); }
 
 static void plane_axes(int normal, int *a, int *b)
@@ -360,7 +477,7 @@ static void plane_cell(int normal, int s, int ia, int ib, int *i, int *j, int *k
     else { *i = ia; *j = ib; *k = s; }
 }
 
-/* buf must hold 3*na*nb + nb doubles. */
+/* buf must hold 3*na*nb + 2*nb doubles. */
 static void plane_update(const grid_t *g, int normal, int s, const sine_basis_t *B,
                          const double *usrc, double *udst, const double *f, double omega,
                          double *buf)
@@ -387,10 +504,28 @@ static void plane_update(const grid_t *g, int normal, int s, const sine_basis_t 
                 acc += B->S[(size_t)ia * na + p] * r[(size_t)ia * nb + ib];
             rh[(size_t)p * nb + ib] = acc;
         }
-    /* one tridiagonal solve along b per mode */
-    for (int p = 0; p < na; ++p)
-        thomas(nb, -eb, B->sigma[p] + 2.0 * eb + 2.0 * ec, rh + (size_t)p * nb,
-               rh + (size_t)p * nb, cp);
+    /* one tridiagonal solve along b per mode (with extrapolated faces, the
+     * ends along b and the planes at extrapolated faces of c have their
+     * diagonal raised by the folded ghost terms) */
+    if (g->bc) {
+        double *dg = cp + nb;
+        int sc = s;
+        double cdiag = ec * (2.0 + ((sc == 0 && (g->bc >> (2 * normal) & 1)) ? 1.0 : 0.0) +
+                             ((sc == dim_of(g, normal) - 1 && (g->bc >> (2 * normal + 1) & 1)) ? 1.0 : 0.0));
+        for (int p = 0; p < na; ++p) {
+            for (int ib = 0; ib < nb; ++ib) {
+                double m = 2.0;
+                if (ib == 0 && (g->bc >> (2 * b) & 1)) m += 1.0;
+                if (ib == nb - 1 && (g->bc >> (2 * b + 1) & 1)) m += 1.0;
+                dg[ib] = B->sigma[p] + eb * m + cdiag;
+            }
+            thomas_v(nb, -eb, dg, rh + (size_t)p * nb, rh + (size_t)p * nb, cp);
+        }
+    } else {
+        for (int p = 0; p < na; ++p)
+            thomas(nb, -eb, B->sigma[p] + 2.0 * eb + 2.0 * ec, rh + (size_t)p * nb,
+                   rh + (size_t)p * nb, cp);
+    }
     /* inverse transform: w[ia][ib] = sum_p S[ia][p] rh[p][ib] */
     for (int ia = 0; ia < na; ++ia)
         for (int ib = 0; ib < nb; ++ib) {
@@ -409,17 +544,18 @@ static void plane_update(const grid_t *g, int normal, int s, const sine_basis_t 
 
 /* Plane sweeps (normal axis 0/1/2).  scheme as for lines; lexicographic GS
  * visits planes s = 0..n_c-1 in order. */
-int bso_plane_sweeps(int nx, int ny, int nz, const double eps[3], double h, int normal,
-                     int scheme, double omega, int nsweeps, double *u, const double *f)
+int bso_plane_sweeps_bc(int nx, int ny, int nz, const double eps[3], double h, int normal,
+                        int scheme, double omega, int nsweeps, double *u, const double *f, int bc)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || normal < 0 || normal > 2 || nsweeps < 0) return 1;
+    if (nx < 1 || ny < 1 || nz < 1 || normal < 0 || normal > 2 || nsweeps < 0 || bc < 0 || bc > 63) return 1;
     grid_t g = mkgrid(nx, ny, nz, eps, h);
+    g.bc = bc;
     int a, b;
     plane_axes(normal, &a, &b);
     int na = dim_of(&g, a), nb = dim_of(&g, b), nc = dim_of(&g, normal);
-    sine_basis_t B = make_basis(na, eps_of(&g, a));
+    sine_basis_t B = make_basis_bc(na, eps_of(&g, a), bc >> (2 * a) & 1, bc >> (2 * a + 1) & 1);
     size_t tot = (size_t)(nz + 2) * (size_t)g.sy;
-    size_t bufn = 3 * (size_t)na * nb + (size_t)nb;
+    size_t bufn = 3 * (size_t)na * nb + 2 * (size_t)nb;
     double *v = NULL;
     if (scheme == BSO_JACOBI) {
         v = (double *)malloc(tot * sizeof(double));
@@ -472,6 +608,12 @@ int bso_plane_sweeps(int nx, int ny, int nz, const double eps[3], double h, int 
     return 0;
 }
 
+int bso_plane_sweeps(int nx, int ny, int nz, const double eps[3], double h, int normal,
+                     int scheme, double omega, int nsweeps, double *u, const double *f)
+{
+    return bso_plane_sweeps_bc(nx, ny, nz, eps, h, normal, scheme, omega, nsweeps, u, f, 0);
+}
+
 /* One Jacobi plane update restricted to a list of planes, reading usrc and
  * writing udst (padded).  Used to check single planes of a large sweep. */
 int bso_plane_update_some(int nx, int ny, int nz, const double eps[3], double h, int normal,
@@ -484,7 +626,7 @@ int bso_plane_update_some(int nx, int ny, int nz, const double eps[3], double h,
     plane_axes(normal, &a, &b);
     int na = dim_of(&g, a), nb = dim_of(&g, b), nc = dim_of(&g, normal);
     sine_basis_t B = make_basis(na, eps_of(&g, a));
-    size_t bufn = 3 * (size_t)na * nb + (size_t)nb;
+    size_t bufn = 3 * (size_t)na * nb + 2 * (size_t)nb;
     int bad = 0;
 #ifdef _OPENMP
 #pragma omp parallel num_threads(NT)
@@ -513,7 +655,7 @@ int bso_line_update_some(int nx, int ny, int nz, const double eps[3], double h, 
     grid_t g = mkgrid(nx, ny, nz, eps, h);
     int n = dim_of(&g, axis), np, nq, bad = 0;
     free_dims(&g, axis, &np, &nq);
-    double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    double *buf = (double *)malloc(sizeof(double) * 3 * (size_t)n);
     for (int t = 0; t < nlines; ++t) {
         int p = pq[2 * t], q = pq[2 * t + 1];
         if (p < 0 || p >= np || q < 0 || q >= nq) { bad = 1; continue; }
@@ -591,7 +733,7 @@ static int cube_update(const grid_t *g, int bx, int by, int bz, int bi, int bj, 
             for (int ci = 0; ci < ni; ++ci) {
                 int c = (ck * nj + cj) * ni + ci;
                 r[c] = cell_res(g, usrc, f, i0 + ci, j0 + cj, k0 + ck);
-                A[(size_t)c * nb + c] = d;
+                A[(size_t)c * nb + c] = g->bc ? diag_at(g, i0 + ci, j0 + cj, k0 + ck) : d;
                 if (ci > 0) A[(size_t)c * nb + c - 1] = -g->ex;
                 if (ci + 1 < ni) A[(size_t)c * nb + c + 1] = -g->ex;
                 if (cj > 0) A[(size_t)c * nb + c - ni] = -g->ey;
@@ -611,12 +753,13 @@ static int cube_update(const grid_t *g, int bx, int by, int bz, int bi, int bj, 
 
 /* Cube-block sweeps.  scheme: 0 Jacobi, 1 lexicographic GS, 2 coloured GS.
  * Returns 0 on success, nonzero on bad arguments. */
-int bso_cube_sweeps(int nx, int ny, int nz, const double eps[3], double h, int bx, int by, int bz,
-                    int scheme, double omega, int nsweeps, double *u, const double *f)
+int bso_cube_sweeps_bc(int nx, int ny, int nz, const double eps[3], double h, int bx, int by, int bz,
+                       int scheme, double omega, int nsweeps, double *u, const double *f, int bc)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || bx < 1 || by < 1 || bz < 1 || nsweeps < 0) return 1;
+    if (nx < 1 || ny < 1 || nz < 1 || bx < 1 || by < 1 || bz < 1 || nsweeps < 0 || bc < 0 || bc > 63) return 1;
     if (scheme < BSO_JACOBI || scheme > BSO_COLORED_GS) return 2;
     grid_t g = mkgrid(nx, ny, nz, eps, h);
+    g.bc = bc;
     if (bx > nx) bx = nx;
     if (by > ny) by = ny;
     if (bz > nz) bz = nz;
@@ -664,6 +807,12 @@ int bso_cube_sweeps(int nx, int ny, int nz, const double eps[3], double h, int b
     return bad ? 3 : 0;
 }
 
+int bso_cube_sweeps(int nx, int ny, int nz, const double eps[3], double h, int bx, int by, int bz,
+                    int scheme, double omega, int nsweeps, double *u, const double *f)
+{
+    return bso_cube_sweeps_bc(nx, ny, nz, eps, h, bx, by, bz, scheme, omega, nsweeps, u, f, 0);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Adjoint of K damped Jacobi line sweeps (reverse mode, every state stored). */
 /*                                                                            */
@@ -694,7 +843,7 @@ static void apply_minv_lines(const grid_t *g, int axis, const double *in, double
 #pragma omp parallel num_threads(NT)
 #endif
     {
-        double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+        double *buf = (double *)malloc(sizeof(double) * 3 * (size_t)n);
         int i, j, k;
 #ifdef _OPENMP
 #pragma omp for collapse(2) schedule(static)
@@ -958,4 +1107,77 @@ int bso_exchange_ghosts(int npatch, const int *dims, double *const *us, int nlin
             }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Multigrid transfers on cell-centred grids (the line and plane smoothers    */
+/* are components of geometric multigrid: section 1 and the future work of   */
+/* section 5).  A coarse cell (I,J,K) covers the fine cells (2I+a, 2J+b,      */
+/* 2K+c), a,b,c in {0,1}; fine dims are even.                                */
+/*   restriction: the mean of the eight fine values, times `scale`;           */
+/*   prolongation: trilinear interpolation between coarse cell centres: along */
+/*   each axis a fine cell takes 3/4 of its parent and 1/4 of the parent's    */
+/*   neighbour on the fine cell's side (a coarse ghost at the edge), so the   */
+/*   eight weights are products of 3/4 and 1/4.                               */
+/* ------------------------------------------------------------------------- */
+int bso_restrict(int nx, int ny, int nz, const double *rfine, double scale, double *fcoarse)
+{
+    if (nx < 2 || ny < 2 || nz < 2 || (nx | ny | nz) & 1) return 1;
+    int mx = nx / 2, my = ny / 2, mz = nz / 2;
+    for (int K = 0; K < mz; ++K)
+        for (int J = 0; J < my; ++J)
+            for (int I = 0; I < mx; ++I) {
+                double s = 0.0;
+                for (int c = 0; c < 2; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a)
+                            s += rfine[((size_t)(2 * K + c) * ny + (2 * J + b)) * nx + (2 * I + a)];
+                fcoarse[((size_t)K * my + J) * mx + I] = scale * (s / 8.0);
+            }
+    return 0;
+}
+
+/* Coarse value at (I,J,K), any index one cell outside: read as stored, except
+ * across a face whose bit is set in bc, where the value is the extrapolated
+ * one, -(the reflected interior value) (per axis: an edge or corner ghost
+ * flips sign once per extrapolated axis it lies beyond). */
+static double coarse_at(const grid_t *gc, const double *uc, int I, int J, int K, int bc)
+{
+    int t[3] = {I, J, K};
+    const int n[3] = {gc->nx, gc->ny, gc->nz};
+    double sg = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        if (t[a] < 0 && (bc >> (2 * a) & 1)) { t[a] = 0; sg = -sg; }
+        if (t[a] >= n[a] && (bc >> (2 * a + 1) & 1)) { t[a] = n[a] - 1; sg = -sg; }
+    }
+    return sg * uc[uidx(gc, t[0], t[1], t[2])];
+}
+
+int bso_prolong_add_bc(int nx, int ny, int nz, const double *ucoarse, double *ufine, int bc)
+{
+    if (nx < 2 || ny < 2 || nz < 2 || (nx | ny | nz) & 1 || bc < 0 || bc > 63) return 1;
+    const double eps1[3] = {1.0, 1.0, 1.0};
+    grid_t gf = mkgrid(nx, ny, nz, eps1, 1.0);
+    grid_t gc = mkgrid(nx / 2, ny / 2, nz / 2, eps1, 1.0);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int I = i / 2, J = j / 2, K = k / 2;
+                /* the neighbour coarse cell on the fine cell's side */
+                int di = (i & 1) ? 1 : -1, dj = (j & 1) ? 1 : -1, dk = (k & 1) ? 1 : -1;
+                double v = 0.0;
+                for (int c = 0; c < 2; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a) {
+                            double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (c ? 0.25 : 0.75);
+                            v += w * coarse_at(&gc, ucoarse, I + a * di, J + b * dj, K + c * dk, bc);
+                        }
+                ufine[uidx(&gf, i, j, k)] += v;
+            }
+    return 0;
+}
+
+int bso_prolong_add(int nx, int ny, int nz, const double *ucoarse, double *ufine)
+{
+    return bso_prolong_add_bc(nx, ny, nz, ucoarse, ufine, 0);
 }

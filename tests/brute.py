@@ -17,8 +17,10 @@ def interior_index(nx, ny, nz):
     return idx
 
 
-def assemble(nx, ny, nz, eps):
-    """Dense A_int (m x m) for interior cells, C order [k][j][i]."""
+def assemble(nx, ny, nz, eps, bc=0):
+    """Dense A_int (m x m) for interior cells, C order [k][j][i].  bc: faces
+    with an extrapolated ghost (-(the boundary cell's value); bit 2a low, bit
+    2a+1 high face of axis a), whose stencil term lands on the diagonal."""
     m = nx * ny * nz
     A = np.zeros((m, m))
     idx = interior_index(nx, ny, nz)
@@ -28,25 +30,36 @@ def assemble(nx, ny, nz, eps):
             for i in range(nx):
                 c = idx[k, j, i]
                 A[c, c] = 2 * (ex + ey + ez)
-                for (di, dj, dk, e) in ((1, 0, 0, ex), (-1, 0, 0, ex), (0, 1, 0, ey), (0, -1, 0, ey),
-                                        (0, 0, 1, ez), (0, 0, -1, ez)):
+                for (ax, di, dj, dk, e) in ((0, 1, 0, 0, ex), (0, -1, 0, 0, ex), (1, 0, 1, 0, ey), (1, 0, -1, 0, ey),
+                                            (2, 0, 0, 1, ez), (2, 0, 0, -1, ez)):
                     ii, jj, kk = i + di, j + dj, k + dk
                     if 0 <= ii < nx and 0 <= jj < ny and 0 <= kk < nz:
                         A[c, idx[kk, jj, ii]] = -e
+                    else:
+                        side = 0 if (di + dj + dk) < 0 else 1
+                        if bc >> (2 * ax + side) & 1:
+                            A[c, c] += e      # ghost = -u_c: -e * (-u_c)
     return A
 
 
-def ghost_rhs(upad, eps):
-    """B g: the ghost terms of the stencil moved to the right-hand side."""
+def ghost_rhs(upad, eps, bc=0):
+    """B g: the ghost terms of the stencil moved to the right-hand side (faces
+    in bc carry none: their ghost is part of the operator)."""
     nz, ny, nx = (s - 2 for s in upad.shape)
     ex, ey, ez = eps
     g = np.zeros((nz, ny, nx))
-    g[:, :, 0] += ex * upad[1:-1, 1:-1, 0]
-    g[:, :, -1] += ex * upad[1:-1, 1:-1, -1]
-    g[:, 0, :] += ey * upad[1:-1, 0, 1:-1]
-    g[:, -1, :] += ey * upad[1:-1, -1, 1:-1]
-    g[0, :, :] += ez * upad[0, 1:-1, 1:-1]
-    g[-1, :, :] += ez * upad[-1, 1:-1, 1:-1]
+    if not bc & 1:
+        g[:, :, 0] += ex * upad[1:-1, 1:-1, 0]
+    if not bc & 2:
+        g[:, :, -1] += ex * upad[1:-1, 1:-1, -1]
+    if not bc & 4:
+        g[:, 0, :] += ey * upad[1:-1, 0, 1:-1]
+    if not bc & 8:
+        g[:, -1, :] += ey * upad[1:-1, -1, 1:-1]
+    if not bc & 16:
+        g[0, :, :] += ez * upad[0, 1:-1, 1:-1]
+    if not bc & 32:
+        g[-1, :, :] += ez * upad[-1, 1:-1, 1:-1]
     return g.reshape(-1)
 
 
@@ -106,12 +119,12 @@ def splitting(A, bid, order, colour, scheme, omega):
     return D / omega + L
 
 
-def sweeps(upad, f, eps, h, kind, axis, scheme, omega, nsweeps):
+def sweeps(upad, f, eps, h, kind, axis, scheme, omega, nsweeps, bc=0):
     nz, ny, nx = f.shape
-    A = assemble(nx, ny, nz, eps)
+    A = assemble(nx, ny, nz, eps, bc)
     bid, order, colour = block_ids(nx, ny, nz, kind, axis)
     M = splitting(A, bid, order, colour, scheme, omega)
-    b = h * h * f.reshape(-1) + ghost_rhs(upad, eps)
+    b = h * h * f.reshape(-1) + ghost_rhs(upad, eps, bc)
     x = upad[1:-1, 1:-1, 1:-1].reshape(-1).copy()
     for _ in range(nsweeps):
         r = b - A @ x
