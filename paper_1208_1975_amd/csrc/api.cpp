@@ -305,15 +305,16 @@ bs_status bs_residual(const bs_patchset *ps, const double *u, const double *f, d
 }
 
 // Host-side test hook (not part of the public header): the line table that
-// bs_create_patchset would build for one line, copied to out[cap].  Returns
-// the number of doubles (or -1); info = {Lr, P, Llast}.
-int bsi_line_table(int n, double eps_a, double d, int preq, double *out, int cap, int *info)
+// bs_create_patchset would build for one line (end diagonals raised by dlo /
+// dhi for extrapolated faces), copied to out[cap].  Returns the number of
+// doubles (or -1); info = {Lr, P, Llast}.
+int bsi_line_table(int n, double eps_a, double d, int preq, double dlo, double dhi, double *out, int cap, int *info)
 {
     int Lr, P, Ll;
     if (!line_split(n, preq, Lr, P, Ll)) return -1;
     std::vector<double> t;
     try {
-        t = build_line_table(n, eps_a, d, preq);
+        t = build_line_table(n, eps_a, d, preq, dlo, dhi);
     } catch (...) {
         return -1;
     }

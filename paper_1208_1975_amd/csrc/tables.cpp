@@ -79,13 +79,22 @@ bool line_split(int n, int preq, int &Lr, int &P, int &Llast)
     return true;
 }
 
-std::vector<double> build_line_table(int n, double eps_a, double d, int preq)
+std::vector<double> build_line_table(int n, double eps_a, double d, int preq, double dlo, double dhi)
 {
     int Lr, P, Llast;
     if (!line_split(n, preq, Lr, P, Llast)) throw std::runtime_error("line split");
     const ld e = eps_a, dd = d;
     std::vector<double> out(static_cast<size_t>(line_table_size(Lr, P)), 0.0);
-    const std::vector<ld> m = pivots(Lr, e, dd);
+    std::vector<ld> m = pivots(Lr, e, dd);
+    if (P == 1 && (dlo != 0.0 || dhi != 0.0)) {
+        // one chunk: the exact LU factors of the line's own matrix, whose end
+        // diagonals carry the extrapolated faces (no interface coupling)
+        std::vector<ld> dg(n, dd);
+        dg[0] += dlo;
+        dg[n - 1] += dhi;
+        m[0] = dg[0];
+        for (int t = 1; t < n; ++t) m[t] = dg[t] - e * e / m[t - 1];
+    }
     out[0] = 0.0;
     for (int t = 1; t < Lr; ++t) out[t] = static_cast<double>(e / m[t - 1]);
     for (int t = 0; t < Lr; ++t) out[Lr + t] = static_cast<double>(1.0L / m[t]);
@@ -135,6 +144,26 @@ std::vector<double> build_line_table(int n, double eps_a, double d, int preq)
             S[static_cast<size_t>(rb) * N + (2 * p + 2)] -= ew[len - 1];
         }
     }
+    // Extrapolated ends (P > 1): the line matrix is the Toeplitz one plus dlo
+    // at its first and dhi at its last diagonal entry.  Chunk 0 then solves
+    // T x = r - dlo x_0 e_0 (+ the coupling to chunk 1), i.e. it takes the
+    // spike ev with the coefficient beta_prev = -(dlo / eps_a) alpha_0, as if
+    // a previous chunk ended in that value; likewise the last chunk takes ew
+    // with alpha_next = -(dhi / eps_a) beta_{P-1}.  The interface rows gain
+    // those terms, and the rows of the inverse that give beta_prev for chunk
+    // 0 and alpha_next for the last chunk are the scaled rows of alpha_0 and
+    // beta_{P-1}: an exact reformulation, with kernels unchanged.
+    if (P > 1 && dlo != 0.0) {
+        const ld c = static_cast<ld>(dlo) / e;
+        S[0 * static_cast<size_t>(N) + 0] += c * evF[0];
+        S[1 * static_cast<size_t>(N) + 0] += c * evF[Lr - 1];
+    }
+    if (P > 1 && dhi != 0.0) {
+        const ld c = static_cast<ld>(dhi) / e;
+        const int ra = 2 * (P - 1), rb = ra + 1;
+        S[static_cast<size_t>(ra) * N + rb] += c * ewT[0];
+        S[static_cast<size_t>(rb) * N + rb] += c * ewT[Llast - 1];
+    }
     invert(S, N);
     const size_t kb = 6 * static_cast<size_t>(Lr), ka = kb + 2 * static_cast<size_t>(P) * P;
     for (int p = 0; p < P; ++p)
@@ -142,6 +171,13 @@ std::vector<double> build_line_table(int n, double eps_a, double d, int preq)
             if (p > 0) out[kb + static_cast<size_t>(p) * N + jj] = static_cast<double>(S[static_cast<size_t>(2 * p - 1) * N + jj]);
             if (p < P - 1) out[ka + static_cast<size_t>(p) * N + jj] = static_cast<double>(S[static_cast<size_t>(2 * p + 2) * N + jj]);
         }
+    if (P > 1 && dlo != 0.0)
+        for (int jj = 0; jj < N; ++jj)
+            out[kb + jj] = static_cast<double>(-(static_cast<ld>(dlo) / e) * S[jj]);
+    if (P > 1 && dhi != 0.0)
+        for (int jj = 0; jj < N; ++jj)
+            out[ka + static_cast<size_t>(P - 1) * N + jj] =
+                static_cast<double>(-(static_cast<ld>(dhi) / e) * S[static_cast<size_t>(2 * P - 1) * N + jj]);
     return out;
 }
 

@@ -11,8 +11,10 @@ namespace bs {
 // last chunk length Llast.  False if Lr would exceed kMaxChunkLen.
 bool line_split(int n, int preq, int &Lr, int &P, int &Llast);
 
-// Line table (layout in bs_internal.h) for tridiag(-eps_a, d, -eps_a) of order n.
-std::vector<double> build_line_table(int n, double eps_a, double d, int preq);
+// Line table (layout in bs_internal.h) for tridiag(-eps_a, d, -eps_a) of order n
+// with dlo / dhi added to its first / last diagonal entry (extrapolated faces
+// at the line's ends; zero for ghosts read as data).
+std::vector<double> build_line_table(int n, double eps_a, double d, int preq, double dlo = 0.0, double dhi = 0.0);
 
 // Orthonormal DST-I basis of order n, row-major n x n (symmetric, its own
 // inverse): S[i][p] = sqrt(2/(n+1)) sin(pi (i+1)(p+1) / (n+1)).

@@ -128,17 +128,17 @@ def test_layout_plan_offsets():
         bsmod.bs_layout_plan([(3, 0, 3)])
 
 
-def line_table(n, e, d, preq):
+def line_table(n, e, d, preq, dlo=0.0, dhi=0.0):
     L = _lib()
     f = L.bsi_line_table
-    f.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
-                  ctypes.c_void_p]
+    f.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     f.restype = ctypes.c_int
     info = (ctypes.c_int * 3)()
-    size = f(n, e, d, preq, None, 0, info)
+    size = f(n, e, d, preq, dlo, dhi, None, 0, info)
     assert size > 0
     out = np.zeros(size)
-    assert f(n, e, d, preq, out.ctypes.data_as(ctypes.c_void_p), size, info) == size
+    assert f(n, e, d, preq, dlo, dhi, out.ctypes.data_as(ctypes.c_void_p), size, info) == size
     return out, tuple(info)
 
 
@@ -173,10 +173,15 @@ def partitioned_solve(tab, info, e, r):
 @pytest.mark.parametrize("n,preq", [(1, 1), (2, 2), (7, 4), (32, 1), (33, 4), (64, 16), (100, 8), (256, 8),
                                     (256, 16), (255, 16), (512, 16), (17, 16)])
 @pytest.mark.parametrize("eps", [(1.0, 1.0, 100.0), (3.0, 1.0, 1.0), (1.0, 100.0, 100.0)])
-def test_line_table_solves_exactly(n, preq, eps):
+@pytest.mark.parametrize("ends", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_line_table_solves_exactly(n, preq, eps, ends):
+    """The chunked solve from the library's tables equals a banded LAPACK solve
+    of the line matrix, also with extrapolated faces at either end (diagonal
+    raised by eps_a there, folded into the interface system)."""
     d = 2 * sum(eps)
     e = eps[2]
-    tab, info = line_table(n, e, d, preq)
+    dlo, dhi = ends[0] * e, ends[1] * e
+    tab, info = line_table(n, e, d, preq, dlo, dhi)
     Lr, P, Ll = info
     assert Lr <= 64 and (P - 1) * Lr + Ll == n and 1 <= Ll <= Lr and P <= preq
     rng = np.random.default_rng(n + preq)
@@ -184,6 +189,8 @@ def test_line_table_solves_exactly(n, preq, eps):
     ab = np.zeros((3, n))
     ab[0, 1:] = -e
     ab[1, :] = d
+    ab[1, 0] += dlo
+    ab[1, -1] += dhi
     ab[2, :-1] = -e
     ref = scipy.linalg.solve_banded((1, 1), ab, r)
     got = partitioned_solve(tab, info, e, r)
