@@ -72,6 +72,8 @@ def _load():
     lib.bso_line_jacobi_adjoint.restype = I
     lib.bso_line_jacobi_eps_tangent.argtypes = [I, I, I, P, D, I, D, I, P, P, P, P]
     lib.bso_line_jacobi_eps_tangent.restype = I
+    lib.bso_block_adjoint.argtypes = [I, I, I, P, D, I, I, I, D, I, P, P, P, P, P, P]
+    lib.bso_block_adjoint.restype = I
     lib.bso_cube_sweeps.argtypes = [I, I, I, P, D, I, I, I, I, D, I, P, P]
     lib.bso_cube_sweeps.restype = I
     lib.bso_exchange_ghosts.argtypes = [I, P, P, I, P]
@@ -224,6 +226,25 @@ def line_jacobi_adjoint(u0, f, eps, h, axis, omega, K, gK):
                                      int(K), _p(u0), _p(f), _p(gK), _p(g_u0), _p(g_f), _p(g_eps))
     if rc:
         raise ValueError("bso_line_jacobi_adjoint failed")
+    return g_u0, g_f, g_eps
+
+
+def block_adjoint(u0, f, eps, h, kind, axis, scheme, omega, K, gK):
+    """Reverse-mode gradients of K sweeps of line ('line', along axis) or plane
+    ('plane', normal axis) blocks under JACOBI or COLORED_GS, every state
+    stored.  Returns (g_u0 padded incl. face-ghost gradients, g_f, g_eps[3])."""
+    lib = _load()
+    nx, ny, nz = _check(u0, f)
+    gK = np.ascontiguousarray(gK, dtype=np.float64)
+    assert gK.shape == u0.shape
+    k = {"line": 0, "plane": 1}[kind]
+    g_u0 = np.zeros_like(u0)
+    g_f = np.zeros_like(f)
+    g_eps = np.zeros(3)
+    rc = lib.bso_block_adjoint(nx, ny, nz, _p(_eps(eps)), float(h), k, int(axis), int(scheme), float(omega),
+                               int(K), _p(u0), _p(f), _p(gK), _p(g_u0), _p(g_f), _p(g_eps))
+    if rc:
+        raise ValueError("bso_block_adjoint failed")
     return g_u0, g_f, g_eps
 
 

@@ -1064,6 +1064,193 @@ int bso_line_jacobi_eps_tangent(int nx, int ny, int nz, const double eps[3], dou
 }
 
 /* ------------------------------------------------------------------------- */
+/* Reverse mode for line or plane blocks under damped block Jacobi or         */
+/* two-colour block GS.  A sweep is a sequence of half-steps                  */
+/*   x <- x + omega P M^{-1} r(x),                                            */
+/* P the projection onto the blocks updated by the half-step (all blocks for  */
+/* Jacobi; colour 0, then colour 1 for GS).  M is block diagonal and P picks  */
+/* whole blocks, so P M^{-1} = M^{-1} P, and with M, A symmetric the adjoint   */
+/* of one half-step, for gbar = dL/dx after it, is the Jacobi one with        */
+/*   lambda = M^{-1} P gbar,                                                  */
+/*   w      = P M^{-1} r(x)        (x the state before the half-step),        */
+/* and the half-steps are reversed (colour 1 before colour 0).  dM/deps_b is  */
+/* the 1D operator tridiag(-1,2,-1) inside the block along an axis the block  */
+/* spans, 2 I along the others.  Every state is stored (no checkpoints).      */
+/* ------------------------------------------------------------------------- */
+
+/* Is (i,j,k) in a block of colour `colour` (-1: every block)? */
+static int in_colour(int kind, int axis, int colour, int i, int j, int k)
+{
+    if (colour < 0) return 1;
+    if (kind == 1) return ((axis == 0 ? i : (axis == 1 ? j : k)) & 1) == colour;
+    int pq = axis == 0 ? j + k : (axis == 1 ? i + k : i + j);
+    return (pq & 1) == colour;
+}
+
+/* M^{-1} applied to every plane normal to `normal` (zero ghosts within a
+ * plane): sine transform along the lower in-plane axis a, one tridiagonal
+ * solve per mode along b, inverse transform.  out may alias in. */
+static void apply_minv_planes(const grid_t *g, int normal, const double *in, double *out)
+{
+    int a, b;
+    plane_axes(normal, &a, &b);
+    int na = dim_of(g, a), nb = dim_of(g, b), ns = dim_of(g, normal);
+    double eb = eps_of(g, b), ec = eps_of(g, normal);
+    sine_basis_t B = make_basis(na, eps_of(g, a));
+    double *r = (double *)malloc(sizeof(double) * (size_t)na * nb);
+    double *rh = (double *)malloc(sizeof(double) * (size_t)na * nb);
+    double *cp = (double *)malloc(sizeof(double) * (size_t)nb);
+    int i, j, k;
+    for (int sidx = 0; sidx < ns; ++sidx) {
+        for (int ia = 0; ia < na; ++ia)
+            for (int ib = 0; ib < nb; ++ib) {
+                plane_cell(normal, sidx, ia, ib, &i, &j, &k);
+                r[(size_t)ia * nb + ib] = in[uidx(g, i, j, k)];
+            }
+        for (int p = 0; p < na; ++p)
+            for (int ib = 0; ib < nb; ++ib) {
+                double acc = 0.0;
+                for (int ia = 0; ia < na; ++ia) acc += B.S[(size_t)ia * na + p] * r[(size_t)ia * nb + ib];
+                rh[(size_t)p * nb + ib] = acc;
+            }
+        for (int p = 0; p < na; ++p)
+            thomas(nb, -eb, B.sigma[p] + 2.0 * eb + 2.0 * ec, rh + (size_t)p * nb, rh + (size_t)p * nb, cp);
+        for (int ia = 0; ia < na; ++ia)
+            for (int ib = 0; ib < nb; ++ib) {
+                double acc = 0.0;
+                for (int p = 0; p < na; ++p) acc += B.S[(size_t)ia * na + p] * rh[(size_t)p * nb + ib];
+                plane_cell(normal, sidx, ia, ib, &i, &j, &k);
+                out[uidx(g, i, j, k)] = acc;
+            }
+    }
+    free(r); free(rh); free(cp); free_basis(&B);
+}
+
+static void apply_minv_blocks(const grid_t *g, int kind, int axis, const double *in, double *out)
+{
+    if (kind == 0) apply_minv_lines(g, axis, in, out);
+    else apply_minv_planes(g, axis, in, out);
+}
+
+/* (dM/deps_b) w at interior cell (i,j,k) for blocks of `kind` along / normal
+ * to `axis`: the block spans axis b for lines along b and for planes whose
+ * normal is not b. */
+static double dm_apply_blocks(const grid_t *g, int kind, int axis, int b, const double *w, int i, int j, int k)
+{
+    ptrdiff_t c = uidx(g, i, j, k);
+    int spans = kind == 0 ? b == axis : b != axis;
+    if (!spans) return 2.0 * w[c];
+    int t = b == 0 ? i : (b == 1 ? j : k);
+    int n = dim_of(g, b);
+    ptrdiff_t s = ustride_of(g, b);
+    double lo = t > 0 ? w[c - s] : 0.0, hi = t < n - 1 ? w[c + s] : 0.0;
+    return 2.0 * w[c] - lo - hi;
+}
+
+/* kind 0: lines along axis, 1: planes normal to axis; scheme BSO_JACOBI or
+ * BSO_COLORED_GS.  Outputs as bso_line_jacobi_adjoint. */
+int bso_block_adjoint(int nx, int ny, int nz, const double eps[3], double h, int kind, int axis, int scheme,
+                      double omega, int K, const double *u0, const double *f, const double *gK, double *g_u0,
+                      double *g_f, double g_eps[3])
+{
+    if (nx < 1 || ny < 1 || nz < 1 || axis < 0 || axis > 2 || K < 0 || (kind != 0 && kind != 1)) return 1;
+    if (scheme != BSO_JACOBI && scheme != BSO_COLORED_GS) return 1;
+    grid_t g = mkgrid(nx, ny, nz, eps, h);
+    size_t tot = (size_t)(nz + 2) * (size_t)g.sy;
+    int H = scheme == BSO_JACOBI ? 1 : 2;
+    int S = K * H;
+    double *states = (double *)malloc(sizeof(double) * tot * (size_t)(S + 1));
+    double *ws = (double *)calloc(tot * (size_t)(S > 0 ? S : 1), sizeof(double));
+    memcpy(states, u0, tot * sizeof(double));
+    /* forward: every half-step's state and its w = P M^{-1} r(x) */
+    for (int st = 0; st < S; ++st) {
+        int colour = H == 1 ? -1 : st % 2;
+        const double *x = states + (size_t)st * tot;
+        double *xn = states + (size_t)(st + 1) * tot;
+        double *w = ws + (size_t)st * tot;
+        memcpy(xn, x, tot * sizeof(double));
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) w[uidx(&g, i, j, kk)] = cell_res(&g, x, f, i, j, kk);
+        apply_minv_blocks(&g, kind, axis, w, w);
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    ptrdiff_t c = uidx(&g, i, j, kk);
+                    if (!in_colour(kind, axis, colour, i, j, kk)) w[c] = 0.0;
+                    xn[c] = x[c] + omega * w[c];
+                }
+    }
+    double *gb = (double *)calloc(tot, sizeof(double));
+    double *lam = (double *)calloc(tot, sizeof(double));
+    double *alam = (double *)calloc(tot, sizeof(double));
+    double *gghost = (double *)calloc(tot, sizeof(double));
+    long double geps[3] = {0.0L, 0.0L, 0.0L};
+    for (int kk = 0; kk < nz; ++kk)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) gb[uidx(&g, i, j, kk)] = gK[uidx(&g, i, j, kk)];
+    if (g_f) memset(g_f, 0, sizeof(double) * (size_t)nx * ny * nz);
+    double ev[3] = {g.ex, g.ey, g.ez};
+    for (int st = S - 1; st >= 0; --st) {
+        int colour = H == 1 ? -1 : st % 2;
+        const double *U = states + (size_t)st * tot;
+        const double *W = ws + (size_t)st * tot;
+        /* lambda = M^{-1} P gbar */
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    ptrdiff_t c = uidx(&g, i, j, kk);
+                    lam[c] = in_colour(kind, axis, colour, i, j, kk) ? gb[c] : 0.0;
+                }
+        apply_minv_blocks(&g, kind, axis, lam, lam);
+        for (int b = 0; b < 3; ++b) {
+            long double sacc = 0.0L;
+            for (int kk = 0; kk < nz; ++kk)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        ptrdiff_t c = uidx(&g, i, j, kk);
+                        double t = d_axis(&g, U, c, b) + dm_apply_blocks(&g, kind, axis, b, W, i, j, kk);
+                        sacc += (long double)lam[c] * (long double)t;
+                    }
+            geps[b] += -(long double)omega * sacc;
+        }
+        if (g_f)
+            for (int kk = 0; kk < nz; ++kk)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) g_f[fidx(&g, i, j, kk)] += omega * g.h2 * lam[uidx(&g, i, j, kk)];
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    ptrdiff_t c = uidx(&g, i, j, kk);
+                    double l = omega * lam[c];
+                    if (i == 0) gghost[c - 1] += ev[0] * l;
+                    if (i == nx - 1) gghost[c + 1] += ev[0] * l;
+                    if (j == 0) gghost[c - g.sx] += ev[1] * l;
+                    if (j == ny - 1) gghost[c + g.sx] += ev[1] * l;
+                    if (kk == 0) gghost[c - g.sy] += ev[2] * l;
+                    if (kk == nz - 1) gghost[c + g.sy] += ev[2] * l;
+                }
+        apply_a_int(&g, lam, alam);
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    ptrdiff_t c = uidx(&g, i, j, kk);
+                    gb[c] = gb[c] - omega * alam[c];
+                }
+    }
+    if (g_u0) {
+        for (size_t t = 0; t < tot; ++t) g_u0[t] = gghost[t];
+        for (int kk = 0; kk < nz; ++kk)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) g_u0[uidx(&g, i, j, kk)] = gb[uidx(&g, i, j, kk)];
+    }
+    if (g_eps)
+        for (int b = 0; b < 3; ++b) g_eps[b] = (double)geps[b];
+    free(states); free(ws); free(gb); free(lam); free(alam); free(gghost);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Ghost exchange between adjacent patches (section 2: the ghost cells that   */
 /* patches share are updated Jacobi-fashion once a full smoothing step is     */
 /* done; section 1.1: such interior ghosts carry the values of the            */
