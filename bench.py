@@ -406,6 +406,11 @@ def forms():
     del u, f
     torch.cuda.empty_cache()
 
+    out["c4_adjacent_2940_xline_chaotic_exchange"] = exchange_form()
+    torch.cuda.empty_cache()
+    out["mg_vcycle_256_zline"] = mg_form()
+    torch.cuda.empty_cache()
+
     # geometric cube blocks (the paper's own block kind) on the block-size
     # study's 64 patches of 64^3, eps = 1: 3 sweeps per block size and scheme
     out["cube_blocks_64x64cube"] = cube_forms()
@@ -434,6 +439,74 @@ def forms():
                                  "workspace_MiB": round(nbytes / 2 ** 20, 1)}
     ps.close()
     return out
+
+
+def exchange_form():
+    """The adjacent version of the uneven AMR set (2940 patches tiling a box face
+    to face): 20 x-line chaotic GS sweeps in one graph launch with the ghost
+    exchange after every sweep, against the same sweeps without links, and the
+    exchange alone (its share of the smoothing step)."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import c4_adjacent_patchset
+
+    s = c4_adjacent_patchset()
+    ps = bs.PatchSet(s.dims, s.eps, s.h)
+    u0, f = ps.pack_u(s.u0), ps.pack_f(s.f)
+    u = u0.clone()
+    cells = s.cells()
+    ps.autotune_line(0, "chaotic", u, f)
+    ps.line_relax(0, "chaotic", 1.0, 20, u, f)                          # capture
+    ms_plain = ev_ms(lambda: ps.line_relax(0, "chaotic", 1.0, 20, u, f), reps=3)
+    ps.set_links(s.links)
+    u.copy_(u0)
+    ps.line_relax(0, "chaotic", 1.0, 20, u, f)                          # capture with the exchange
+    ms_x = ev_ms(lambda: ps.line_relax(0, "chaotic", 1.0, 20, u, f), reps=3)
+    ps.exchange_ghosts(u)
+    ms_e = ev_ms(lambda: [ps.exchange_ghosts(u) for _ in range(20)], reps=3)
+    ghost_cells = 2 * sum(s.dims[a][(ax + 1) % 3] * s.dims[a][(ax + 2) % 3] for a, ax, _ in s.links)
+    res = {"patches": s.npatch, "links": len(s.links), "cells": cells, "exchanged_ghost_cells": ghost_cells,
+           "ms_20_sweeps_with_exchange": round(ms_x, 3), "ms_20_sweeps_without": round(ms_plain, 3),
+           "ms_20_exchanges_alone": round(ms_e, 3),
+           "exchange_share_of_step": round((ms_x - ms_plain) / ms_x, 4),
+           "glups_with_exchange": round(cells * 20 / (ms_x * 1e-3) / 1e9, 3),
+           "exchange_GBs": round(16.0 * ghost_cells * 20 / (ms_e * 1e-3) / 1e9, 1)}
+    ps.close()
+    return res
+
+
+def mg_form():
+    """One V(1,1) cycle with z-line two-colour GS smoothing on the 256^3
+    eps (1,1,100) patch with extrapolated faces on every level: time per cycle
+    and the residual reduction per cycle (f = 0, random initial guess)."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import make_patch
+
+    p = make_patch(256, 256, 256, (1.0, 1.0, 100.0), 1.0 / 256, seed=2, f="zero", u0="uniform")
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    ps.set_bc([63])
+    mg = bs.Multigrid(ps, "line", 2, "colored", 1.0, 1, 1, 20, 0, 63)
+    u0, f = ps.pack_u([p.u0]), ps.pack_f([p.f])
+    u = u0.clone()
+    n2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rs = []
+    for _ in range(8):
+        ps.residual(u, f, None, n2)
+        rs.append(math.sqrt(float(n2.item())))
+        mg.vcycle(u, f)
+    ms = ev_ms(lambda: mg.vcycle(u, f), reps=5)
+    # a cycle smooths each level twice (coarsest: 20 sweeps): fine-grid sweep equivalents
+    fine_eq = sum(2.0 / 8 ** l for l in range(mg.levels - 1)) + 20.0 / 8 ** (mg.levels - 1)
+    res = {"levels": mg.levels, "ms_per_cycle": round(ms, 3),
+           "residual_factor_per_cycle": [round(rs[i + 1] / rs[i], 4) for i in range(len(rs) - 1)],
+           "fine_sweep_equivalents_per_cycle": round(fine_eq, 3),
+           "glups_equivalent": round(256 ** 3 * fine_eq / (ms * 1e-3) / 1e9, 2)}
+    mg.close()
+    ps.close()
+    return res
 
 
 def cpu_model():

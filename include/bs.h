@@ -25,7 +25,9 @@
  *
  * Ghosts are inputs that the caller owns and updates between calls (section
  * 2: ghost cells are refreshed after a full smoothing step); every call leaves
- * u's ghost cells bit-unchanged.  Edge and corner ghosts are never read.
+ * u's ghost cells bit-unchanged, except the ghosts of extrapolated faces
+ * (bs_set_bc) and of linked faces (bs_set_links), which the library updates
+ * after every sweep.  Edge and corner ghosts are never read.
  *
  * Pointers named *_host are host memory; every other buffer pointer is device
  * memory on the device that was current at bs_create_patchset.  The caller
@@ -114,6 +116,43 @@ void bs_destroy_patchset(bs_patchset *ps);
  * and that size and every prepared size not yet rebuilt are dropped (they must
  * be prepared again). */
 bs_status bs_set_eps(bs_patchset *ps, const double *eps_host);
+
+/* Boundary condition per face: bc_host[npatch] holds a 6-bit mask per patch,
+ * bit 2a = the low face of axis a (cells at index 0), bit 2a+1 = the high face.
+ * A set bit marks an extrapolated Dirichlet face (section 1.1: boundary
+ * conditions are extrapolated into the ghost layer; the value at the face is
+ * zero): its ghost is the negated adjacent interior value, which folds into
+ * the operator as +eps_a on the diagonal of the cells next to the face and
+ * into every block that contains them.  A clear bit (the default) keeps the
+ * ghosts of that face as caller data.  The ghost cells of an extrapolated face
+ * are the library's: the sweeps overwrite them with the negated adjacent
+ * interior values, and bs_residual ignores them.  Rebuilds the line tables
+ * (raised end diagonals) and drops prepared cube block sizes.  Synchronous.
+ * BS_ERR_INVALID for a mask outside 0..63 or one that marks a linked face
+ * (bs_set_links); on BS_ERR_OOM / BS_ERR_HIP the set keeps its previous
+ * conditions.  Lines and planes (FP64) take any mask; mixed-precision planes
+ * and cube blocks return BS_ERR_UNSUPPORTED on a patch set with any
+ * extrapolated face. */
+bs_status bs_set_bc(bs_patchset *ps, const int32_t *bc_host);
+
+/* Face adjacency (section 2: ghosts are updated Jacobi-fashion after every
+ * smoothing step; section 1.1: the ghosts of faces between patches keep the
+ * patches consistent).  links_host[3*nlinks] holds (a, axis, b): patch b lies
+ * on patch a's high side along `axis`, with equal extents along the other two
+ * axes.  Afterwards every sweep of bs_line_relax, bs_plane_relax and
+ * bs_cube_relax is followed by a ghost update on the new iterate: a's high
+ * ghost layer along `axis` takes b's first interior layer and b's low ghost
+ * layer a's last one (and extrapolated faces take their negated interior
+ * values).  nlinks = 0 removes the links.  Synchronous.  BS_ERR_INVALID for
+ * an index out of range, a == b, unequal extents, a face used by two links,
+ * or a face that is extrapolated; nothing changes on any error. */
+bs_status bs_set_links(bs_patchset *ps, int32_t nlinks, const int32_t *links_host);
+
+/* One ghost update of u (device, u layout) as the sweeps apply it after every
+ * step: the linked faces' ghosts from their neighbours, the extrapolated
+ * faces' ghosts from their own interior.  Edge and corner ghosts are never
+ * touched.  Asynchronous on `stream`. */
+bs_status bs_exchange_ghosts(const bs_patchset *ps, double *u, hipStream_t stream);
 
 /* Layout of an existing patch set (same meaning as bs_layout_plan). */
 bs_status bs_layout(const bs_patchset *ps, int64_t *u_numel, int64_t *f_numel,
@@ -258,6 +297,65 @@ bs_status bs_relax_backward(bs_patchset *ps, int32_t axis, double omega, int32_t
                             const double *grad_uK, double *grad_u0, double *grad_f,
                             double *grad_eps, void *workspace, size_t workspace_bytes,
                             hipStream_t stream);
+
+/* Geometric multigrid with the block smoothers (section 1: line and plane
+ * smoothers are the components of robust geometric multigrid; section 5:
+ * multilevel use).  A cycle object holds the coarse levels of a fine patch
+ * set: every patch is coarsened on its own by factors of two (cell width 2h,
+ * the same eps) while all its edges are even, down to `levels` levels (0: as
+ * many as every patch allows).  One V(nu1, nu2) cycle of bs_vcycle on
+ * A u = h^2 f: nu1 sweeps of the smoother; the defect d = h^2 f - A u
+ * restricted (mean of the 2x2x2 children) to f_c = R(d / h^2); the cycle
+ * applied to the coarse error equation A e = (2h)^2 f_c from e = 0, whose
+ * ghosts are zero, or extrapolated on the faces of coarse_bc (the same mask
+ * for every patch and coarse level; bs_set_bc's meaning); u += trilinear
+ * interpolation of e (across a face of coarse_bc the coarse value is
+ * reflected and negated); nu2 sweeps.  The coarsest level takes ncoarse
+ * sweeps.  Smoother: kind 0 = line blocks along axis `arg`, kind 1 = plane
+ * blocks normal to `arg`, with `scheme` and omega, in FP64.
+ *
+ * bs_mg_create: synchronous; allocates the levels (their patch sets and
+ * three u/f-sized fields each, plus one defect field per level but the
+ * coarsest).  The fine set stays the caller's and must outlive the cycle
+ * object; its dims, eps and faces are copied: after bs_set_eps or bs_set_bc on
+ * it, bs_vcycle returns BS_ERR_INVALID until the object is created again.
+ * BS_ERR_INVALID for bad arguments; BS_ERR_UNSUPPORTED for a fine set with
+ * links. */
+typedef struct bs_mg bs_mg;
+bs_status bs_mg_create(bs_patchset *fine, int32_t kind, int32_t arg, bs_scheme scheme, double omega, int32_t nu1,
+                       int32_t nu2, int32_t ncoarse, int32_t levels, int32_t coarse_bc, bs_mg **out);
+void bs_mg_destroy(bs_mg *mg);
+/* Number of levels of the cycle (the fine level included). */
+bs_status bs_mg_levels(const bs_mg *mg, int32_t *levels);
+/* One V-cycle: u in/out (u layout of the fine set), f (f layout), work (u
+ * layout; the Jacobi smoother's second vector, may be NULL for the
+ * Gauss-Seidel schemes).  Asynchronous on `stream`.  The first cycle with a
+ * given (u, f, work) runs eagerly and builds every table the levels need; the
+ * next one is captured into a HIP graph, which later calls replay. */
+bs_status bs_vcycle(bs_mg *mg, double *u, const double *f, double *work, hipStream_t stream);
+
+/* Adjoint of nsweeps FP64 sweeps of line blocks (kind 0, along `axis`) or
+ * plane blocks (kind 1, normal to `axis`) under BS_JACOBI or BS_COLORED_GS,
+ * for a loss L with dL/du_K = grad_uK: the gradients of the differentiable
+ * smoother beyond Jacobi lines.  A two-colour sweep is two half-steps
+ * u += omega P_c M^{-1} r(u), P_c the projection onto the blocks of colour c
+ * (colour 0 first); M is block diagonal, so P_c M^{-1} = M^{-1} P_c, and each
+ * half-step is undone in reverse order (colour 1, then colour 0) with
+ * lambda = M^{-1} P_c gbar:  dL/df += omega h^2 lambda,  dL/dghost +=
+ * omega eps_a lambda (face ghosts),  dL/deps_b -= omega <lambda, D_b u +
+ * (dM/deps_b) P_c M^{-1} r(u)>,  gbar -= omega A_int lambda.  States are
+ * recomputed from checkpoints taken every ckpt_every sweeps; the workspace
+ * (bs_block_backward_workspace_bytes; 0 on invalid arguments) holds them.
+ * Outputs and their layouts as bs_relax_backward (each may be NULL).
+ * BS_ERR_UNSUPPORTED for BS_CHAOTIC_GS (no unique forward map), for patch sets
+ * with links or extrapolated faces, and for lines or planes the forward calls
+ * refuse. */
+size_t bs_block_backward_workspace_bytes(const bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme,
+                                         int32_t nsweeps, int32_t ckpt_every);
+bs_status bs_block_backward(bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme, double omega,
+                            int32_t nsweeps, int32_t ckpt_every, const double *u0, const double *f,
+                            const double *grad_uK, double *grad_u0, double *grad_f, double *grad_eps,
+                            void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Message for the last non-OK status returned on this host thread ("" if none). */
 const char *bs_last_error(void);

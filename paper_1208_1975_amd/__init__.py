@@ -30,8 +30,9 @@ _STATUS = {1: "BS_ERR_INVALID", 2: "BS_ERR_UNSUPPORTED", 3: "BS_ERR_OOM", 4: "BS
 # Every symbol the public header declares.
 EXPORTS = ("bs_layout_plan", "bs_create_patchset", "bs_destroy_patchset", "bs_set_eps", "bs_layout",
            "bs_residual", "bs_line_relax", "bs_plane_relax", "bs_cube_prepare", "bs_cube_relax",
-           "bs_autotune_line", "bs_line_config",
-           "bs_backward_workspace_bytes", "bs_relax_backward", "bs_last_error")
+           "bs_autotune_line", "bs_line_config", "bs_set_bc", "bs_set_links", "bs_exchange_ghosts",
+           "bs_mg_create", "bs_mg_destroy", "bs_mg_levels", "bs_vcycle", "bs_block_backward_workspace_bytes",
+           "bs_block_backward", "bs_backward_workspace_bytes", "bs_relax_backward", "bs_last_error")
 
 
 class BSError(RuntimeError):
@@ -79,10 +80,23 @@ def lib():
     L.bs_backward_workspace_bytes.argtypes = [vp, i32, i32, i32]
     L.bs_backward_workspace_bytes.restype = sz
     L.bs_relax_backward.argtypes = [vp, i32, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.bs_set_bc.argtypes = [vp, vp]
+    L.bs_set_links.argtypes = [vp, i32, vp]
+    L.bs_exchange_ghosts.argtypes = [vp, vp, vp]
+    L.bs_mg_create.argtypes = [vp, i32, i32, ctypes.c_int, dbl, i32, i32, i32, i32, i32, P(vp)]
+    L.bs_mg_destroy.argtypes = [vp]
+    L.bs_mg_destroy.restype = None
+    L.bs_mg_levels.argtypes = [vp, P(i32)]
+    L.bs_vcycle.argtypes = [vp, vp, vp, vp, vp]
+    L.bs_block_backward_workspace_bytes.argtypes = [vp, i32, i32, ctypes.c_int, i32, i32]
+    L.bs_block_backward_workspace_bytes.restype = sz
+    L.bs_block_backward.argtypes = [vp, i32, i32, ctypes.c_int, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.bs_last_error.argtypes = []
     L.bs_last_error.restype = ctypes.c_char_p
     for name in ("bs_layout_plan", "bs_create_patchset", "bs_set_eps", "bs_layout", "bs_residual",
-                 "bs_line_relax", "bs_plane_relax", "bs_autotune_line", "bs_line_config", "bs_relax_backward"):
+                 "bs_line_relax", "bs_plane_relax", "bs_autotune_line", "bs_line_config", "bs_relax_backward",
+                 "bs_set_bc", "bs_set_links", "bs_exchange_ghosts", "bs_mg_create", "bs_mg_levels", "bs_vcycle",
+                 "bs_block_backward"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -167,6 +181,48 @@ def bs_set_eps(ps, eps):
     _check(lib().bs_set_eps(ps, e))
 
 
+def bs_set_bc(ps, bc):
+    """Per patch the 6-bit mask of extrapolated-Dirichlet faces (bit 2a: low
+    face of axis a, bit 2a+1: high face)."""
+    b = _host_array(ctypes.c_int32, [int(v) for v in bc])
+    _check(lib().bs_set_bc(ps, b))
+
+
+def bs_set_links(ps, links):
+    """Face-adjacent patches [(a, axis, b)]: b lies on a's high side along axis."""
+    flat = [int(v) for t in links for v in t]
+    arr = _host_array(ctypes.c_int32, flat) if flat else None
+    _check(lib().bs_set_links(ps, len(flat) // 3, arr))
+
+
+def bs_exchange_ghosts(ps, u, stream=None):
+    _check(lib().bs_exchange_ghosts(ps, _ptr(u), _stream(stream)))
+
+
+def bs_mg_create(ps, kind, arg, scheme, omega, nu1, nu2, ncoarse, levels=0, coarse_bc=0):
+    """Multigrid cycle object over patch set ps: kind 'line' (axis arg) or
+    'plane' (normal arg) block smoothing."""
+    k = {"line": 0, "plane": 1}[kind] if isinstance(kind, str) else int(kind)
+    out = ctypes.c_void_p()
+    _check(lib().bs_mg_create(ps, k, int(arg), _scheme(scheme), float(omega), int(nu1), int(nu2), int(ncoarse),
+                              int(levels), int(coarse_bc), ctypes.byref(out)))
+    return out
+
+
+def bs_mg_destroy(mg):
+    lib().bs_mg_destroy(mg)
+
+
+def bs_mg_levels(mg):
+    n = ctypes.c_int32()
+    _check(lib().bs_mg_levels(mg, ctypes.byref(n)))
+    return n.value
+
+
+def bs_vcycle(mg, u, f, work=None, stream=None):
+    _check(lib().bs_vcycle(mg, _ptr(u), _ptr(f), _ptr(work), _stream(stream)))
+
+
 def bs_layout(ps, npatch):
     un, fn = ctypes.c_int64(), ctypes.c_int64()
     uo = (ctypes.c_int64 * npatch)()
@@ -223,6 +279,23 @@ def bs_relax_backward(ps, axis, omega, nsweeps, ckpt_every, u0, f, grad_uK, grad
                                    _ptr(workspace), wb, _stream(stream)))
 
 
+def _kind(kind):
+    return {"line": 0, "plane": 1}[kind] if isinstance(kind, str) else int(kind)
+
+
+def bs_block_backward_workspace_bytes(ps, kind, axis, scheme, nsweeps, ckpt_every):
+    return int(lib().bs_block_backward_workspace_bytes(ps, _kind(kind), int(axis), _scheme(scheme), int(nsweeps),
+                                                       int(ckpt_every)))
+
+
+def bs_block_backward(ps, kind, axis, scheme, omega, nsweeps, ckpt_every, u0, f, grad_uK, grad_u0=None,
+                      grad_f=None, grad_eps=None, workspace=None, stream=None):
+    wb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().bs_block_backward(ps, _kind(kind), int(axis), _scheme(scheme), float(omega), int(nsweeps),
+                                   int(ckpt_every), _ptr(u0), _ptr(f), _ptr(grad_uK), _ptr(grad_u0), _ptr(grad_f),
+                                   _ptr(grad_eps), _ptr(workspace), wb, _stream(stream)))
+
+
 def stream_triad(a, b, c, mode=0, stream=None):
     """Device streaming probe c = a + b (float64, n even): the 24 bytes per
     element of a line sweep at the HBM ceiling (mode 1: nontemporal b)."""
@@ -271,6 +344,15 @@ class PatchSet:
         new = [tuple(float(v) for v in t) for t in eps]
         bs_set_eps(self.handle, new)   # raises on failure; the library then keeps its old eps
         self.eps = new
+
+    def set_bc(self, bc):
+        bs_set_bc(self.handle, bc)
+
+    def set_links(self, links):
+        bs_set_links(self.handle, links)
+
+    def exchange_ghosts(self, u, stream=None):
+        bs_exchange_ghosts(self.handle, u, stream)
 
     def empty_u(self):
         return torch.zeros(self.u_numel, dtype=torch.float64, device=self.device)
@@ -344,6 +426,29 @@ class PatchSet:
                                              _ptr(u), _ptr(f), _ptr(work), _stream(stream)))
 
 
+class Multigrid:
+    """Owns a V-cycle object over a PatchSet (which must outlive it)."""
+
+    def __init__(self, ps, kind, arg, scheme, omega, nu1=1, nu2=1, ncoarse=10, levels=0, coarse_bc=0):
+        self.ps = ps
+        self.handle = bs_mg_create(ps.handle, kind, arg, scheme, omega, nu1, nu2, ncoarse, levels, coarse_bc)
+        self.levels = bs_mg_levels(self.handle)
+
+    def vcycle(self, u, f, work=None, stream=None):
+        bs_vcycle(self.handle, u, f, work, stream)
+
+    def close(self):
+        if self.handle is not None:
+            bs_mg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # --- differentiable smoother ---------------------------------------------------
 
 class LineJacobiFn(torch.autograd.Function):
@@ -379,6 +484,46 @@ class LineJacobiFn(torch.autograd.Function):
         bs_relax_backward(ps.handle, axis, omega, K, ckpt, u0.detach(), f.detach(), grad_uK.contiguous(),
                           g_u0, g_f, g_eps, ws)
         return g_f, g_u0, g_eps.view(eps.shape).to(eps.device), None, None, None, None, None
+
+
+class BlockSmoothFn(torch.autograd.Function):
+    """u_K = K sweeps of line blocks (kind 'line', along axis) or plane blocks
+    (kind 'plane', normal to axis) under 'jacobi' or 'colored' GS from (f, u0)
+    with axis weights eps, differentiable in f, u0 (incl. face ghosts) and eps
+    through the library's adjoint, recomputing states from checkpoints taken
+    every `ckpt` sweeps.  Arguments as LineJacobiFn plus kind and scheme."""
+
+    @staticmethod
+    def forward(ctx, f, u0, eps, ps, kind, axis, scheme, omega, K, ckpt):
+        _sync_eps(ps, eps)
+        u = u0.detach().clone()
+        work = torch.empty_like(u)
+        if kind == "line":
+            ps.line_relax(axis, scheme, omega, K, u, f.detach(), work)
+        else:
+            ps.plane_relax(axis, scheme, omega, K, u, f.detach(), work)
+        ctx.save_for_backward(f, u0, eps)
+        ctx.cfg = (ps, kind, int(axis), scheme, float(omega), int(K), int(ckpt))
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_uK):
+        f, u0, eps = ctx.saved_tensors
+        ps, kind, axis, scheme, omega, K, ckpt = ctx.cfg
+        _sync_eps(ps, eps)
+        nbytes = bs_block_backward_workspace_bytes(ps.handle, kind, axis, scheme, K, ckpt)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=u0.device)
+        g_u0 = torch.zeros_like(u0)
+        g_f = torch.zeros_like(f)
+        g_eps = torch.empty(ps.npatch * 3, dtype=torch.float64, device=u0.device)
+        bs_block_backward(ps.handle, kind, axis, scheme, omega, K, ckpt, u0.detach(), f.detach(),
+                          grad_uK.contiguous(), g_u0, g_f, g_eps, ws)
+        return g_f, g_u0, g_eps.view(eps.shape).to(eps.device), None, None, None, None, None, None, None
+
+
+def block_smooth(f, u0, eps, ps, kind="line", axis=2, scheme="jacobi", omega=0.8, K=20, ckpt=5):
+    """Differentiable K-sweep block smoother (see BlockSmoothFn)."""
+    return BlockSmoothFn.apply(f, u0, eps, ps, kind, axis, scheme, omega, K, ckpt)
 
 
 def _sync_eps(ps, eps):

@@ -110,6 +110,7 @@ bs_status build_tables(bs_patchset *ps)
         d.foff = ps->foff[p];
         for (int a = 0; a < 3; ++a) d.eps[a] = ps->eps[3 * p + a];
         d.h2 = ps->h[p] * ps->h[p];
+        d.bc = ps->bc[p];
         const double dd = 2.0 * (d.eps[0] + d.eps[1] + d.eps[2]);
         for (int a = 0; a < 3; ++a) {
             for (int o = 0; o < kNumPOpt; ++o) {
@@ -120,7 +121,10 @@ bs_status build_tables(bs_patchset *ps)
                 if (!line_split(d.n[a], kPOpts[o], Lr, P, Ll)) continue;
                 std::vector<double> t;
                 try {
-                    t = build_line_table(d.n[a], d.eps[a], dd, kPOpts[o]);
+                    // an extrapolated face at a line's end raises that end's diagonal by eps_a
+                    const int bcm = ps->bc[p];
+                    t = build_line_table(d.n[a], d.eps[a], dd, kPOpts[o], ((bcm >> (2 * a)) & 1) ? d.eps[a] : 0.0,
+                                         ((bcm >> (2 * a + 1)) & 1) ? d.eps[a] : 0.0);
                 } catch (const std::exception &ex) {
                     return fail(BS_ERR_INVALID, "line table for patch %d axis %d: %s", p, a, ex.what());
                 }
@@ -204,6 +208,7 @@ bs_status bs_create_patchset(int32_t npatch, const int32_t *dims_host, const dou
     ps->dims.assign(dims_host, dims_host + 3 * static_cast<size_t>(npatch));
     ps->eps.assign(eps_host, eps_host + 3 * static_cast<size_t>(npatch));
     ps->h.assign(h_host, h_host + npatch);
+    ps->bc.assign(npatch, 0);
     for (int p = 0; p < npatch; ++p)
         for (int a = 0; a < 3; ++a) ps->max_n[a] = std::max(ps->max_n[a], ps->dims[3 * p + a]);
     plan_layout(npatch, dims_host, ps->uoff, ps->foff, ps->u_numel, ps->f_numel);
@@ -269,6 +274,33 @@ bs_status bs_set_eps(bs_patchset *ps, const double *eps_host)
         return st;
     }
     return cube_rebuild_all(ps);   // block inverses depend on eps
+}
+
+bs_status bs_set_bc(bs_patchset *ps, const int32_t *bc_host)
+{
+    if (!ps || !bc_host) return fail(BS_ERR_INVALID, "bs_set_bc: null argument");
+    for (int p = 0; p < ps->npatch; ++p)
+        if (bc_host[p] < 0 || bc_host[p] > 63) return fail(BS_ERR_INVALID, "bs_set_bc: bc[%d] is not a 6-bit mask", p);
+    for (size_t t = 0; t < ps->links.size() / 3; ++t) {
+        const int a = ps->links[3 * t], axis = ps->links[3 * t + 1], b = ps->links[3 * t + 2];
+        if (((bc_host[a] >> (2 * axis + 1)) & 1) || ((bc_host[b] >> (2 * axis)) & 1))
+            return fail(BS_ERR_INVALID, "bs_set_bc: link %zu joins a face that would be extrapolated", t);
+    }
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    std::vector<int32_t> nb(bc_host, bc_host + ps->npatch);
+    FaceOpsBuild fb;
+    bs_status st = make_face_ops(ps, nb, ps->links, fb);
+    if (st != BS_OK) return st;   // nothing changed
+    ps->bc.swap(nb);
+    if ((st = build_tables(ps)) != BS_OK) {
+        ps->bc.swap(nb);   // the old tables were kept: the set keeps its old conditions
+        return st;
+    }
+    commit_face_ops(ps, fb);
+    reset_bc_state(ps);
+    ps->cube.clear();   // block inverses depend on the conditions: prepare again
+    return BS_OK;
 }
 
 bs_status bs_layout(const bs_patchset *ps, int64_t *u_numel, int64_t *f_numel, int64_t *u_off_host,

@@ -38,7 +38,7 @@ struct PlaneTabRef {
 
 struct PatchDesc {
     int32_t n[3];          // nx, ny, nz
-    int32_t pad0;
+    int32_t bc;            // extrapolated faces: bit 2a = low face of axis a, bit 2a+1 = high face
     int64_t uoff, foff;    // element offsets of this patch in u and f
     double eps[3];
     double h2;
@@ -175,12 +175,69 @@ struct CubeBatchArgs {
 };
 hipError_t launch_cube_small(const CubeBatchArgs &a, int nchunks, int np, hipStream_t s);
 
+// Ghost updates (k_ghost.hip).  One face operation copies the m1 x m2 cells
+// of a layer: dst[d0 + a*d1 + b*d2] = sign * u[s0 + a*s1 + b*s2] (element
+// offsets into the patch set's u).  Exchange between face-adjacent patches is
+// a copy (sign +1) of the neighbour's first interior layer into a ghost layer;
+// an extrapolated face is its own interior layer negated (sign -1).
+struct FaceOp {
+    int64_t d0, s0;
+    int32_t d1, d2, s1, s2;
+    int32_t m1, m2;
+    double sign;
+};
+// A launch item: cells [first, first + count) of op `op` (in a-fastest order).
+struct FaceItem {
+    int32_t op, first, count, pad;
+};
+constexpr int kFaceItemCells = 2048;
+hipError_t launch_face_ops(double *u, const FaceOp *ops, const FaceItem *items, int nitems, hipStream_t s);
+
+// Lines next to an extrapolated face parallel to them: their block carries the
+// folded ghosts on its whole diagonal, so they are solved one line per thread
+// (Thomas with on-the-fly pivots) instead of by the chunked kernels.  p, q:
+// the line's indices along the two other axes (lower axis first).
+__host__ __device__ inline bool offline_extrap(int bc, int b, int p, int nb, int c, int q, int nc)
+{
+    return (((bc >> (2 * b)) & 1) && p == 0) || (((bc >> (2 * b + 1)) & 1) && p == nb - 1) ||
+           (((bc >> (2 * c)) & 1) && q == 0) || (((bc >> (2 * c + 1)) & 1) && q == nc - 1);
+}
+struct BLineItem {
+    int32_t patch, p, q, colour;
+};
+struct BLineArgs {
+    const double *src;
+    double *dst;
+    const double *f;
+    const PatchDesc *pd;
+    const BLineItem *items;
+    double *scratch;          // 2 * maxlen * nlines doubles: [t][line] pivots and eliminated rhs
+    int32_t axis, nitems, nlines, first;   // items [first, first + nitems) of nlines
+    double omega;
+};
+hipError_t launch_bline(const BLineArgs &a, hipStream_t s);
+
+// Multigrid transfers (k_mg.hip), per patch: pf / pc the fine / coarse
+// descriptors, max_cells the largest coarse (restriction) or fine
+// (prolongation) patch.
+//   restriction:   fc = mean of the 2x2x2 fine values of d / h_fine^2 (f layouts)
+//   prolongation:  uf += trilinear interpolation of uc (u layouts); beyond a
+//                  face in bc the coarse value is the reflected one, negated
+hipError_t launch_restrict(const double *d, double *fc, const PatchDesc *pf, const PatchDesc *pc, int npatch,
+                           int64_t max_cells, hipStream_t s);
+hipError_t launch_prolong_add(const double *uc, double *uf, const PatchDesc *pf, const PatchDesc *pc, int npatch,
+                              int64_t max_cells, int bc, hipStream_t s);
+
 // Adjoint of damped Jacobi line sweeps (k_adjoint.hip).
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s);
 hipError_t launch_adj_init(const double *gK, double *gbar, const PatchDesc *pd, int npatch, hipStream_t s);
+// spans: bit b set when the blocks span axis b (lines along a: 1 << a;
+// planes normal to c: the other two bits), which decides dM/deps_b.
 hipError_t launch_adj_step(const double *lam, const double *U, const double *w, double *gbar, double *gf,
-                           double *acc, const PatchDesc *pd, const ResidTile *tiles, int ntiles, int axis,
+                           double *acc, const PatchDesc *pd, const ResidTile *tiles, int ntiles, int spans,
                            double omega, hipStream_t s);
+// Interior of a u-layout field into f layout (dst[f cell] = src[u cell]).
+hipError_t launch_u_to_f(const double *src, double *dst, const PatchDesc *pd, int npatch, hipStream_t s);
 hipError_t launch_eps_final(const double *acc, const int32_t *first_block, int npatch, double omega, double *out,
                             hipStream_t s);
 

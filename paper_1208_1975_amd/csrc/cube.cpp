@@ -345,6 +345,12 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
 {
     const PatchDesc *pdd = static_cast<const PatchDesc *>(ps->desc_d.p);
     bs_status st;
+    // ghosts of linked faces are exchanged after every sweep (section 2)
+    auto ghosts = [&](double *v) -> bs_status {
+        if (!ghost_active(ps)) return BS_OK;
+        hipError_t e = ghost_update(ps, v, false, stream);
+        return e == hipSuccess ? BS_OK : hip_fail(e, "ghost update");
+    };
     if (scheme == BS_JACOBI) {
         hipError_t e = launch_ghost_copy(u, work, pdd, ps->npatch, stream);
         if (e != hipSuccess) return hip_fail(e, "ghost copy");
@@ -356,15 +362,17 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
                 if (g.nb > kCubeSmallCells &&
                     (st = cube_pass(plan, g, true, 0, g.nblk, src, dst, f, omega, stream)) != BS_OK)
                     return st;
+            if ((st = ghosts(dst)) != BS_OK) return st;
         }
         if (nsweeps & 1) {
             e = launch_interior_copy(work, u, pdd, ps->npatch, stream);
             if (e != hipSuccess) return hip_fail(e, "interior copy");
+            if ((st = ghosts(u)) != BS_OK) return st;
         }
         return BS_OK;
     }
     // coloured (and chaotic) block GS: colour-0 blocks of every group, then colour 1, in place
-    for (int s = 0; s < nsweeps; ++s)
+    for (int s = 0; s < nsweeps; ++s) {
         for (int col = 0; col < 2; ++col) {
             if ((st = small_pass(plan, 1 + col, u, u, f, omega, stream)) != BS_OK) return st;
             for (const CubeGroup &g : plan.groups) {
@@ -373,6 +381,8 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
                 if ((st = cube_pass(plan, g, false, lo, n, u, u, f, omega, stream)) != BS_OK) return st;
             }
         }
+        if ((st = ghosts(u)) != BS_OK) return st;
+    }
     return BS_OK;
 }
 
@@ -416,6 +426,7 @@ bs_status bs_cube_prepare(bs_patchset *ps, int32_t bx, int32_t by, int32_t bz)
 {
     bs_status st = check_block(ps, bx, by, bz, "bs_cube_prepare");
     if (st != BS_OK) return st;
+    if (any_bc(ps)) return fail(BS_ERR_UNSUPPORTED, "bs_cube_prepare: cube blocks with extrapolated faces");
     const auto key = std::make_tuple(int(bx), int(by), int(bz));
     if (ps->cube.count(key)) return BS_OK;
     hipError_t e = hipSetDevice(ps->device);

@@ -1,4 +1,6 @@
-// Adjoint of damped Jacobi line sweeps.  With interior unknowns x, fixed
+// Adjoint of damped Jacobi line or plane sweeps, and of each half-step of
+// two-colour GS (the projection P onto one colour's blocks commutes with M;
+// lambda = M^{-1} P gbar, w = P M^{-1} r).  With interior unknowns x, fixed
 // ghosts g, x^{k+1} = x^k + omega M^{-1} r(x^k), r = h^2 F + B g - A_int x,
 // and symmetric M and A, one reverse step for dL/dx^{k+1} = gbar is
 //   lambda    = M^{-1} gbar                    (line solve, done by k_line)
@@ -6,8 +8,9 @@
 //   dL/dg    += omega B^T lambda               (face ghosts: eps_a lambda of the adjacent cell)
 //   dL/deps_a += -omega <lambda, D_a U^k + (dM/deps_a) w^k>,  w^k = M^{-1} r(x^k)
 //   gbar      <- gbar - omega A_int lambda
-// with D_a U = 2U - U_{-a} - U_{+a} (ghosts included) and, for lines along
-// axis a, dM/deps_a = tridiag(-1, 2, -1) on each line and dM/deps_b = 2 I.
+// with D_a U = 2U - U_{-a} - U_{+a} (ghosts included) and dM/deps_b =
+// tridiag(-1, 2, -1) inside each block along an axis b the blocks span, 2 I
+// along the others.
 #include <algorithm>
 
 #include "bs_internal.h"
@@ -23,7 +26,7 @@ struct AdjArgs {
     double *acc;          // [ntiles][3] per-tile accumulators of <lambda, ...>
     const PatchDesc *pd;
     const ResidTile *tiles;
-    int axis;
+    int spans;            // bit b: the blocks span axis b
     double omega;
 };
 
@@ -49,6 +52,19 @@ __global__ void __launch_bounds__(256) k_adj_init(const double *gK, double *gbar
     }
 }
 
+// Interior of a u-layout field into f layout (blockIdx.y = patch).
+__global__ void __launch_bounds__(256) k_u_to_f(const double *src, double *dst, const PatchDesc *pds)
+{
+    const PatchDesc *pd = pds + blockIdx.y;
+    const int nx = pd->n[0], ny = pd->n[1], nz = pd->n[2];
+    const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2);
+    const int64_t total = (int64_t)nx * ny * nz;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = c % nx, j = (c / nx) % ny, k = c / ((int64_t)nx * ny);
+        dst[pd->foff + c] = src[pd->uoff + (k + 1) * sy + (j + 1) * sx + (i + 1)];
+    }
+}
+
 // One tile of the residual's tiling (tx x ty columns marched along z): the
 // z-neighbours of lambda, U and w stay in registers and the next plane's
 // values are fetched a step ahead; each column's partial sums run in
@@ -64,7 +80,7 @@ __global__ void __launch_bounds__(kAdjThreads) k_adj_step(AdjArgs a)
     const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2), pf = (int64_t)nx * ny;
     const double e0 = pd->eps[0], e1 = pd->eps[1], e2 = pd->eps[2];
     const double om = a.omega, omh2 = a.omega * pd->h2;
-    const int ax = a.axis;
+    const int spans = a.spans;
     int tx = 64;
     while (tx > 1 && (tx >> 1) >= nx) tx >>= 1;
     const int i = t.x0 + (int)(threadIdx.x & (tx - 1));
@@ -87,17 +103,18 @@ __global__ void __launch_bounds__(kAdjThreads) k_adj_step(AdjArgs a)
         const double lp_n = a.lam[cn], up_n = a.U[cn], wp_n = a.w[cn];
         const double lxm = a.lam[c - 1], lxp = a.lam[c + 1], lym = a.lam[c - sx], lyp = a.lam[c + sx];
         const double uxm = a.U[c - 1], uxp = a.U[c + 1], uym = a.U[c - sx], uyp = a.U[c + sx];
-        const int64_t sa = ax == 0 ? 1 : sx;   // the line axis' neighbours (x or y; z from registers)
-        const double wam = a.w[c - sa], wap = a.w[c + sa];
+        // w's neighbours along x and y (z from registers); w is zero outside
+        // the blocks' cells, so a block's edge sees zero beyond it
+        const double wxm = a.w[c - 1], wxp = a.w[c + 1], wym = a.w[c - sx], wyp = a.w[c + sx];
         const double g0 = a.gbar[c];
         const double gf0 = a.gf ? a.gf[fo + (int64_t)k * pf] : 0.0;
         double al = fma(e0, 2.0 * lc - lxm - lxp, 0.0);
         al = fma(e1, 2.0 * lc - lym - lyp, al);
         al = fma(e2, 2.0 * lc - lm - lp, al);
         const double w2 = 2.0 * wc;
-        const double mw0 = ax == 0 ? w2 - wam - wap : w2;
-        const double mw1 = ax == 1 ? w2 - wam - wap : w2;
-        const double mw2 = ax == 2 ? w2 - wm - wp : w2;
+        const double mw0 = (spans & 1) ? w2 - wxm - wxp : w2;
+        const double mw1 = (spans & 2) ? w2 - wym - wyp : w2;
+        const double mw2 = (spans & 4) ? w2 - wm - wp : w2;
         if (valid) {
             p0 += lc * ((2.0 * uc - uxm - uxp) + mw0);
             p1 += lc * ((2.0 * uc - uym - uyp) + mw1);
@@ -161,6 +178,12 @@ hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_u_to_f(const double *src, double *dst, const PatchDesc *pd, int npatch, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_u_to_f, dim3(256, npatch), dim3(256), 0, s, src, dst, pd);
+    return hipGetLastError();
+}
+
 hipError_t launch_adj_init(const double *gK, double *gbar, const PatchDesc *pd, int npatch, hipStream_t s)
 {
     hipLaunchKernelGGL(k_adj_init, dim3(256, npatch), dim3(256), 0, s, gK, gbar, pd);
@@ -168,11 +191,11 @@ hipError_t launch_adj_init(const double *gK, double *gbar, const PatchDesc *pd, 
 }
 
 hipError_t launch_adj_step(const double *lam, const double *U, const double *w, double *gbar, double *gf,
-                           double *acc, const PatchDesc *pd, const ResidTile *tiles, int ntiles, int axis,
+                           double *acc, const PatchDesc *pd, const ResidTile *tiles, int ntiles, int spans,
                            double omega, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    AdjArgs a{lam, U, w, gbar, gf, acc, pd, tiles, axis, omega};
+    AdjArgs a{lam, U, w, gbar, gf, acc, pd, tiles, spans, omega};
     hipLaunchKernelGGL(k_adj_step, dim3(ntiles), dim3(kAdjThreads), 0, s, a);
     return hipGetLastError();
 }

@@ -240,7 +240,9 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
         o = (it.tile / nti) * tyo + lo;
         i = (it.tile % nti) * tx + li;
     }
-    const bool valid = (i < nx) && (o < no) && (p < P);
+    // lines next to an extrapolated face parallel to them are solved by the
+    // boundary-line kernel (their block has a raised diagonal): skipped here
+    const bool valid = (i < nx) && (o < no) && (p < P) && !offline_extrap(pd->bc, 0, i, nx, oaxis, o, no);
     // Inactive lanes and chunks read clamped, in-patch addresses so that every
     // load can be issued without a branch; their results are never stored.
     const int ic = i < nx ? i : nx - 1;
@@ -478,7 +480,8 @@ __device__ __forceinline__ void line_x_item(const LineArgs &a, const float *__re
             k = rho / ny;
             j = rho % ny;
         }
-        const bool in = j < ny && k < nz;
+        // rows next to an extrapolated y or z face belong to the boundary-line kernel
+        const bool in = j < ny && k < nz && !offline_extrap(pd->bc, 1, j, ny, 2, k, nz);
         rowu[threadIdx.x] = in ? pd->uoff + (int64_t)(k + 1) * sy + (int64_t)(j + 1) * sx + 1 : -1;
         rowf[threadIdx.x] = in ? pd->foff + ((int64_t)k * ny + j) * nx : -1;
     }

@@ -212,7 +212,8 @@ __global__ void __launch_bounds__(256) k_line_xr(LineArgs a)
                     k = rho / ny;
                     j = rho - k * ny;
                 }
-                const bool in = row_ok && j < ny && k < nz;
+                // rows next to an extrapolated y or z face: the boundary-line kernel
+                const bool in = row_ok && j < ny && k < nz && !offline_extrap(pd->bc, 1, j, ny, 2, k, nz);
                 const int jc = in ? j : 0, kc = in ? k : 0;
                 // byte offsets of this lane's first cell in u and f
                 const uint32_t cu = 8u * ((uint32_t)(kc + 1) * sy + (uint32_t)(jc + 1) * sx + 1u + (uint32_t)i0);

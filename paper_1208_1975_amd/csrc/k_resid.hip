@@ -1,4 +1,5 @@
-// Residual r = h^2 f - A u (eq. stencil3d7 with axis weights) and its
+// Residual r = h^2 f - A u (eq. stencil3d7 with axis weights; on an
+// extrapolated face the ghost is the negated adjacent cell) and its
 // per-patch 2-norm^2, reduced in a fixed order (bit-reproducible); plus the
 // copies the Jacobi second vector needs.
 #include "bs_internal.h"
@@ -45,6 +46,10 @@ __global__ void __launch_bounds__(kResidThreads) k_residual(ResidArgs a)
     const int ic = i < nx ? i : nx - 1, jc = j < ny ? j : ny - 1;   // in-patch addresses for every lane
     const bool need_l = li == 0, need_r = li == tx - 1 || i >= nx - 1;
     const int64_t xo = need_l ? -1 : 1;                            // the row-end lane's own neighbour
+    const int bc = pd->bc;
+    const bool xlo = (bc & 1) && i == 0, xhi = (bc & 2) && i == nx - 1;
+    const bool ylo = (bc & 4) && j == 0, yhi = (bc & 8) && j == ny - 1;
+    const bool zlo = (bc & 16) != 0, zhi = (bc & 32) != 0;
     const int k0 = t.z0, k1 = t.z1;
     const double *u = a.u + pd->uoff + (int64_t)(jc + 1) * sx + (ic + 1);   // column (i, j), plane index k + 1
     const int64_t fo = pd->foff + (int64_t)jc * nx + ic;                     // f / r column, plane index k
@@ -67,9 +72,14 @@ __global__ void __launch_bounds__(kResidThreads) k_residual(ResidArgs a)
         // before the selects, which the compiler may turn into branches
         double dl = wave_nb<-1>(uc), dr = wave_nb<+1>(uc);
         asm volatile("" : "+v"(dl), "+v"(dr));
-        const double left = need_l ? xa : dl;
-        const double right = need_r ? (need_l ? xb : xa) : dr;
-        const double nb = fma(ex, left + right, fma(ey, ym + yp, ez * (uzm + uzp)));
+        double left = need_l ? xa : dl;
+        double right = need_r ? (need_l ? xb : xa) : dr;
+        // extrapolated faces: the ghost is the negated cell itself
+        left = xlo ? -uc : left;
+        right = xhi ? -uc : right;
+        const double yl = ylo ? -uc : ym, yh = yhi ? -uc : yp;
+        const double zl = (zlo && k == 0) ? -uc : uzm, zh = (zhi && k == nz - 1) ? -uc : uzp;
+        const double nb = fma(ex, left + right, fma(ey, yl + yh, ez * (zl + zh)));
         const double r = fma(-d, uc, fma(h2, fv, nb));
         if (valid) {
             const int64_t c = fo + (int64_t)k * pf;

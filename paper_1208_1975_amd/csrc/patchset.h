@@ -116,7 +116,13 @@ struct bs_patchset {
     int mixed_dlayout = 0;
     int chaotic_chunk = 0;   // tiles per even/odd chunk of the chaotic dispatch order (0: default)
     std::map<std::vector<int>, int> chaotic_chunks;   // per line configuration: tiles per chunk
-    std::vector<int64_t> basis_off, lam_off;   // [3 * npatch] each, offsets in doubles
+    // [3 * npatch] each, offsets in doubles: the basis read by the forward
+    // transforms (V^T), by the inverse ones (V; the same entries for the
+    // symmetric DST-I basis), the inverse eigenvalue grid of the interior
+    // planes, and of the first / last plane along the normal when that face
+    // is extrapolated (-1 otherwise)
+    std::vector<int64_t> basis_off, basis_inv_off, lam_off, lam_lo_off, lam_hi_off;
+    std::vector<int8_t> basis_kind;   // [3 * npatch]: 0 DST-I, 1 both ends raised, 2 one end raised
     // cached work lists and tuned configurations
     std::map<bs::WorkKey, std::unique_ptr<bs::WorkList>> lists;
     std::map<std::pair<int, int>, bs::LineCfg> line_cfg;   // (axis, colour_mode) -> cfg
@@ -124,7 +130,20 @@ struct bs_patchset {
     std::map<std::tuple<int, int, int>, std::unique_ptr<bs::CubePlan>> cube;
     // captured sweep sequences, replayed with one graph launch
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    // boundary conditions and adjacency: per patch the mask of extrapolated
+    // faces, the links (a, axis, b) between face-adjacent patches, the face
+    // operations of one ghost update (extrapolated faces first) and, per line
+    // axis, the lines next to extrapolated faces parallel to them
+    std::vector<int32_t> bc;
+    std::vector<int32_t> links;
+    bs::DevBuf face_ops_d, face_items_d;
+    int nfill_items = 0, nface_items = 0;
+    bool bline_ready[3] = {false, false, false};
+    bs::DevBuf bline_d[3];
+    int bline_count[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // colour 0 items, then colour 1
+    bs::DevBuf bline_scratch;
     hipStream_t capture_stream = nullptr;
+    uint64_t gen = 0;   // bumped whenever device tables or captured graphs are replaced
     bool use_graphs = true;
     ~bs_patchset();
 };

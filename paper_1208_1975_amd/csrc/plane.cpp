@@ -29,33 +29,65 @@ uint16_t bf16_bits(double v)
     return static_cast<uint16_t>(u >> 16);
 }
 
-// Bases S_x, S_y, S_z of every patch and the inverse eigenvalue grid of every
+// Bases of every patch and axis and the inverse eigenvalue grid of every
 // (patch, normal):  normal z: [q_y][p_x] = 1/(sigma_y,q + sigma_x,p + 2 eps_z);
-// normal y: [q_z][p_x]; normal x: [q_z][q_y].  FP32 copies share the offsets.
+// normal y: [q_z][p_x]; normal x: [q_z][q_y].  An axis with extrapolated faces
+// takes the eigenbasis of its raised line block (stored as V^T for the forward
+// and V for the inverse transforms), and a plane next to an extrapolated face
+// normal to the planes adds eps_c per such face to its grid.  FP32 copies
+// share the offsets.
 bs_status build_plane_tables(bs_patchset *ps)
 {
     std::vector<double> tab;
-    ps->basis_off.assign(3 * static_cast<size_t>(ps->npatch), -1);
-    ps->lam_off.assign(3 * static_cast<size_t>(ps->npatch), -1);
+    const size_t n3 = 3 * static_cast<size_t>(ps->npatch);
+    ps->basis_off.assign(n3, -1);
+    ps->basis_inv_off.assign(n3, -1);
+    ps->basis_kind.assign(n3, 0);
+    ps->lam_off.assign(n3, -1);
+    ps->lam_lo_off.assign(n3, -1);
+    ps->lam_hi_off.assign(n3, -1);
     for (int p = 0; p < ps->npatch; ++p) {
         const int n[3] = {ps->dims[3 * p], ps->dims[3 * p + 1], ps->dims[3 * p + 2]};
         const double *e = &ps->eps[3 * static_cast<size_t>(p)];
+        const int bcm = ps->bc[p];
         std::vector<long double> sg[3];
         for (int a = 0; a < 3; ++a) {
-            ps->basis_off[3 * p + a] = static_cast<int64_t>(tab.size());
-            const std::vector<double> S = sine_basis(n[a]);
-            tab.insert(tab.end(), S.begin(), S.end());
+            const int lo = (bcm >> (2 * a)) & 1, hi = (bcm >> (2 * a + 1)) & 1;
+            const std::vector<double> V = bc_sine_basis(n[a], lo, hi);
+            ps->basis_kind[3 * p + a] = static_cast<int8_t>(lo && hi ? 1 : (lo || hi ? 2 : 0));
+            ps->basis_inv_off[3 * p + a] = static_cast<int64_t>(tab.size());
+            tab.insert(tab.end(), V.begin(), V.end());
             while (tab.size() % 8) tab.push_back(0.0);   // 16-byte aligned BF16 copies
-            sg[a] = sine_eigenvalues(n[a], e[a]);
+            if (lo || hi) {
+                ps->basis_off[3 * p + a] = static_cast<int64_t>(tab.size());
+                for (int i = 0; i < n[a]; ++i)
+                    for (int k = 0; k < n[a]; ++k) tab.push_back(V[static_cast<size_t>(k) * n[a] + i]);
+                while (tab.size() % 8) tab.push_back(0.0);
+            } else {
+                ps->basis_off[3 * p + a] = ps->basis_inv_off[3 * p + a];   // symmetric
+            }
+            sg[a] = bc_sine_eigenvalues(n[a], e[a], lo, hi);
         }
         for (int c = 0; c < 3; ++c) {
             const int ar = c == 0 ? 2 : (c == 1 ? 2 : 1);   // grid rows (slow index)
             const int ac = c == 0 ? 1 : 0;                   // grid columns
-            ps->lam_off[3 * p + c] = static_cast<int64_t>(tab.size());
-            for (int q = 0; q < n[ar]; ++q)
-                for (int r = 0; r < n[ac]; ++r)
-                    tab.push_back(static_cast<double>(1.0L / (sg[ar][q] + sg[ac][r] + 2.0L * e[c])));
-            while (tab.size() % 8) tab.push_back(0.0);
+            const int lo = (bcm >> (2 * c)) & 1, hi = (bcm >> (2 * c + 1)) & 1;
+            auto grid = [&](long double shift) {
+                const int64_t off = static_cast<int64_t>(tab.size());
+                for (int q = 0; q < n[ar]; ++q)
+                    for (int r = 0; r < n[ac]; ++r)
+                        tab.push_back(static_cast<double>(1.0L / (sg[ar][q] + sg[ac][r] + 2.0L * e[c] + shift)));
+                while (tab.size() % 8) tab.push_back(0.0);
+                return off;
+            };
+            ps->lam_off[3 * p + c] = grid(0.0L);
+            // one plane along the normal takes both shifts
+            if (n[c] == 1 && (lo || hi)) {
+                ps->lam_lo_off[3 * p + c] = grid(static_cast<long double>(e[c]) * (lo + hi));
+            } else {
+                if (lo) ps->lam_lo_off[3 * p + c] = grid(e[c]);
+                if (hi) ps->lam_hi_off[3 * p + c] = grid(e[c]);
+            }
         }
     }
     bs_status st = upload(ps->plane_tab_d, tab.data(), tab.size() * sizeof(double), "plane tables");
@@ -72,6 +104,7 @@ bs_status build_plane_tables(bs_patchset *ps)
         if ((st = dev_alloc(ps->plane_t_d, static_cast<size_t>(ps->f_numel) * 8, "plane scratch")) != BS_OK) return st;
     }
     ps->plane_ready = true;
+    ++ps->gen;
     return BS_OK;
 }
 
@@ -102,6 +135,7 @@ struct Chain {
     Product g[4];
     int64_t u0, u_b, u_m, u_n;   // update mapping of the last product
     int filter_n = 0;            // last product filters columns by colour (normal x)
+    int colour_shift = 0;        // column n of the last product is plane n + colour_shift
     bool empty = false;
 };
 
@@ -109,20 +143,26 @@ struct Chain {
 // of one patch with normal c and the given colour (-1: all).  Fields live in
 // the patch's f layout; the chain alternates between the input field (kIn)
 // and the scratch field (kOut), ending with the update.
-Chain plane_chain_geometry(const bs_patchset *ps, int p, int c, int colour)
+Chain plane_chain_geometry(const bs_patchset *ps, int p, int c, int colour, int k0 = 0, int k1 = -1)
 {
     Chain ch;
     const int nx = ps->dims[3 * p], ny = ps->dims[3 * p + 1], nz = ps->dims[3 * p + 2];
     const int64_t sx = nx + 2, sy = sx * (ny + 2), pl = static_cast<int64_t>(nx) * ny;
     const int64_t uo = ps->uoff[p];
-    const int first = colour < 0 ? 0 : colour, step = colour < 0 ? 1 : 2;
+    // planes [k0, k1) along the normal (all by default)
+    if (k1 < 0) k1 = ps->dims[3 * p + c];
+    const int first = colour < 0 ? k0 : k0 + ((colour - k0) & 1), step = colour < 0 ? 1 : 2;
+    if (first >= k1) {
+        ch.empty = true;
+        return ch;
+    }
     auto prod = [](Operand A, Operand B, Operand C, int M, int N, int K, int batch) {
         Product q;
         q.A = A; q.B = B; q.C = C; q.M = M; q.N = N; q.K = K; q.batch = batch;
         return q;
     };
     if (c == 2) {   // planes k: (ny x nx); x by right product, y by left product
-        const int nb = (nz - first + step - 1) / step;
+        const int nb = (k1 - first + step - 1) / step;
         if (nb <= 0) { ch.empty = true; return ch; }
         const int64_t o = first * pl, sb = step * pl;
         ch.g[0] = prod({kIn, o, nx, sb}, {kSx, 0, nx, 0}, {kOut, o, nx, sb}, ny, nx, nx, nb);
@@ -132,7 +172,7 @@ Chain plane_chain_geometry(const bs_patchset *ps, int p, int c, int colour)
         ch.g[3] = prod({kOut, o, nx, sb}, {kSx, 0, nx, 0}, {kIn, o, nx, sb}, ny, nx, nx, nb);
         ch.u0 = uo + (first + 1) * sy + sx + 1; ch.u_b = step * sy; ch.u_m = sx; ch.u_n = 1;
     } else if (c == 1) {   // planes j: (nz x nx) with row stride nx*ny
-        const int nb = (ny - first + step - 1) / step;
+        const int nb = (k1 - first + step - 1) / step;
         if (nb <= 0) { ch.empty = true; return ch; }
         const int64_t o = static_cast<int64_t>(first) * nx, sb = static_cast<int64_t>(step) * nx;
         ch.g[0] = prod({kIn, o, pl, sb}, {kSx, 0, nx, 0}, {kOut, o, pl, sb}, nz, nx, nx, nb);
@@ -141,41 +181,54 @@ Chain plane_chain_geometry(const bs_patchset *ps, int p, int c, int colour)
         ch.g[2] = prod({kSz, 0, nz, 0}, {kIn, o, pl, sb}, {kOut, o, pl, sb}, nz, nx, nz, nb);
         ch.g[3] = prod({kOut, o, pl, sb}, {kSx, 0, nx, 0}, {kIn, o, pl, sb}, nz, nx, nx, nb);
         ch.u0 = uo + sy + (first + 1) * sx + 1; ch.u_b = step * sx; ch.u_m = sy; ch.u_n = 1;
-    } else {   // planes i: z by left product per j, y by left product per k; colour filters columns
-        ch.g[0] = prod({kSz, 0, nz, 0}, {kIn, 0, pl, nx}, {kOut, 0, pl, nx}, nz, nx, nz, ny);
-        ch.g[1] = prod({kSy, 0, ny, 0}, {kOut, 0, nx, pl}, {kIn, 0, nx, pl}, ny, nx, ny, nz);
+    } else {   // planes i (columns [k0, k1)): z by left product per j, y by left product per k;
+               // colour filters columns
+        const int w = k1 - k0;
+        ch.g[0] = prod({kSz, 0, nz, 0}, {kIn, k0, pl, nx}, {kOut, k0, pl, nx}, nz, w, nz, ny);
+        ch.g[1] = prod({kSy, 0, ny, 0}, {kOut, k0, nx, pl}, {kIn, k0, nx, pl}, ny, w, ny, nz);
         ch.g[1].sc_b = ny; ch.g[1].sc_m = 1; ch.g[1].sc_n = 0;
-        ch.g[2] = prod({kSy, 0, ny, 0}, {kIn, 0, nx, pl}, {kOut, 0, nx, pl}, ny, nx, ny, nz);
-        ch.g[3] = prod({kSz, 0, nz, 0}, {kOut, 0, pl, nx}, {kIn, 0, pl, nx}, nz, nx, nz, ny);
-        ch.u0 = uo + sy + sx + 1; ch.u_b = sx; ch.u_m = sy; ch.u_n = 1;
+        ch.g[2] = prod({kSy, 0, ny, 0}, {kIn, k0, nx, pl}, {kOut, k0, nx, pl}, ny, w, ny, nz);
+        ch.g[3] = prod({kSz, 0, nz, 0}, {kOut, k0, pl, nx}, {kIn, k0, pl, nx}, nz, w, nz, ny);
+        ch.u0 = uo + sy + sx + 1 + k0; ch.u_b = sx; ch.u_m = sy; ch.u_n = 1;
         ch.filter_n = 1;
+        ch.colour_shift = k0;
     }
     return ch;
 }
 
+// inv: the inverse transforms (the last two products) read V, the forward ones
+// V^T (the same entries for the symmetric DST-I basis).
 template <typename T>
-const T *operand_ptr(const bs_patchset *ps, int p, int c, const Operand &o, const T *in, const T *out, const T *tab)
+const T *operand_ptr(const bs_patchset *ps, int p, int c, const Operand &o, const T *in, const T *out, const T *tab,
+                     bool inv = false)
 {
+    const std::vector<int64_t> &bo = inv ? ps->basis_inv_off : ps->basis_off;
     switch (o.buf) {
     case kIn: return in + o.off;
     case kOut: return out + o.off;
-    case kSx: return tab + ps->basis_off[3 * p + 0];
-    case kSy: return tab + ps->basis_off[3 * p + 1];
-    case kSz: return tab + ps->basis_off[3 * p + 2];
+    case kSx: return tab + bo[3 * p + 0];
+    case kSy: return tab + bo[3 * p + 1];
+    case kSz: return tab + bo[3 * p + 2];
     default: return tab + ps->lam_off[3 * p + c];
     }
 }
 
 // FP64 chain for one patch: R (residual, f layout) is consumed as scratch.
-// Every product has a DST-I basis on one side; the basis obeys
-// S[n-1-i][j] = (-1)^j S[i][j], so each product splits into its even and its
-// odd output rows (left products) or columns (right products), each a product
-// over half the contraction with the field folded about its middle
-// (x[k] + x[n-1-k] for even, x[k] - x[n-1-k] for odd outputs): half the flops.
-bs_status chain_f64(bs_patchset *ps, int p, int c, int colour, const double *src, double *dst, double omega,
-                    hipStream_t s)
+// Every product has a sine basis on one side.  The DST-I basis obeys
+// S[n-1-i][j] = (-1)^j S[i][j] and is symmetric, so each product splits into
+// its even and its odd output rows (left products) or columns (right
+// products), each a product over half the contraction with the field folded
+// about its middle (x[k] + x[n-1-k] for even, x[k] - x[n-1-k] for odd
+// outputs): half the flops.  The basis of an axis with both faces
+// extrapolated keeps the mirror property in its rows only, so only the
+// forward transforms fold; an axis with one extrapolated face has no mirror
+// property and its products run unfolded.  Planes next to an extrapolated
+// face normal to them are solved by chains of their own (their eigenvalue
+// grid is shifted).
+bs_status chain_range(bs_patchset *ps, int p, int c, int colour, int k0, int k1, int64_t lam, const double *src,
+                      double *dst, double omega, hipStream_t s)
 {
-    const Chain ch = plane_chain_geometry(ps, p, c, colour);
+    const Chain ch = plane_chain_geometry(ps, p, c, colour, k0, k1);
     if (ch.empty) return BS_OK;
     const double *tab = static_cast<const double *>(ps->plane_tab_d.p);
     double *R = static_cast<double *>(ps->plane_r_d.p) + ps->foff[p];
@@ -183,50 +236,78 @@ bs_status chain_f64(bs_patchset *ps, int p, int c, int colour, const double *src
     for (int q = 0; q < 4; ++q) {
         const Product &pr = ch.g[q];
         const bool right = pr.B.buf == kSx || pr.B.buf == kSy || pr.B.buf == kSz;   // C = A S, else C = S B
-        for (int par = 0; par < 2; ++par) {
+        const int baxis = (right ? pr.B.buf : pr.A.buf) - kSx;
+        const int kind = ps->basis_kind[3 * p + baxis];
+        const bool inv = q >= 2;
+        const bool fold = kind == 0 || (kind == 1 && !inv);
+        for (int par = 0; par < (fold ? 2 : 1); ++par) {
             GemmArgs g{};
-            g.A = operand_ptr<double>(ps, p, c, pr.A, R, T, tab);
+            g.A = operand_ptr<double>(ps, p, c, pr.A, R, T, tab, inv);
             g.lda = pr.A.ld; g.sA = pr.A.sb;
-            g.B = operand_ptr<double>(ps, p, c, pr.B, R, T, tab);
+            g.B = operand_ptr<double>(ps, p, c, pr.B, R, T, tab, inv);
             g.ldb = pr.B.ld; g.sB = pr.B.sb;
-            g.C = const_cast<double *>(operand_ptr<double>(ps, p, c, pr.C, R, T, tab));
+            g.C = const_cast<double *>(operand_ptr<double>(ps, p, c, pr.C, R, T, tab, inv));
             g.ldc = pr.C.ld; g.sC = pr.C.sb;
             g.M = pr.M; g.N = pr.N; g.batch = pr.batch;
             g.Kfull = pr.K;
-            g.K = par == 0 ? (pr.K + 1) / 2 : pr.K / 2;
-            g.fsign = par == 0 ? 1 : -1;
+            g.K = pr.K;
             g.row_s = 1; g.col_s = 1;
-            if (right) {   // columns n = 2n' + par; B' = rows 2n' + par of the (symmetric) basis
-                g.fold = 1;
-                g.b_trans = 1;
-                g.B += static_cast<int64_t>(par) * pr.B.ld;
-                g.ldb = 2 * pr.B.ld;
-                g.N = (pr.N + 1 - par) / 2;
-                g.col_s = 2; g.col_o = par;
-            } else {       // rows m = 2m' + par; A' = rows 2m' + par of the basis
-                g.fold = 2;
-                g.A += static_cast<int64_t>(par) * pr.A.ld;
-                g.lda = 2 * pr.A.ld;
-                g.M = (pr.M + 1 - par) / 2;
-                g.row_s = 2; g.row_o = par;
+            if (right) g.b_trans = 1;   // B(k, n) at n*ldb + k: V^T / V stored row-major
+            if (fold) {
+                g.K = par == 0 ? (pr.K + 1) / 2 : pr.K / 2;
+                g.fsign = par == 0 ? 1 : -1;
+                if (right) {   // columns n = 2n' + par; B' = rows 2n' + par of the stored basis
+                    g.fold = 1;
+                    g.B += static_cast<int64_t>(par) * pr.B.ld;
+                    g.ldb = 2 * pr.B.ld;
+                    g.N = (pr.N + 1 - par) / 2;
+                    g.col_s = 2; g.col_o = par;
+                } else {       // rows m = 2m' + par; A' = rows 2m' + par of the basis
+                    g.fold = 2;
+                    g.A += static_cast<int64_t>(par) * pr.A.ld;
+                    g.lda = 2 * pr.A.ld;
+                    g.M = (pr.M + 1 - par) / 2;
+                    g.row_s = 2; g.row_o = par;
+                }
             }
-            if (g.K <= 0) continue;
+            if (g.K <= 0 || g.M <= 0 || g.N <= 0) continue;
             g.ncolour = -1;
             int epi = kEpiStore;
             if (q == 1) {
                 epi = kEpiScale;
-                g.scale = tab + ps->lam_off[3 * p + c];
+                g.scale = tab + lam;
                 g.sc_b = pr.sc_b; g.sc_m = pr.sc_m; g.sc_n = pr.sc_n;
             } else if (q == 3) {
                 epi = kEpiUpdate;
                 g.usrc = src; g.udst = dst; g.omega = omega;
                 g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
-                if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
+                if (ch.filter_n) { g.ncolour = colour; g.colour_shift = ch.colour_shift; }
             }
             hipError_t e = launch_gemm_f64(g, epi, s);
             if (e != hipSuccess) return hip_fail(e, "plane transform");
         }
     }
+    return BS_OK;
+}
+
+bs_status chain_f64(bs_patchset *ps, int p, int c, int colour, const double *src, double *dst, double omega,
+                    hipStream_t s)
+{
+    const int nc = ps->dims[3 * p + c];
+    const int64_t lo = ps->lam_lo_off[3 * p + c], hi = ps->lam_hi_off[3 * p + c];
+    if (lo < 0 && hi < 0) return chain_range(ps, p, c, colour, 0, nc, ps->lam_off[3 * p + c], src, dst, omega, s);
+    if (nc == 1) return chain_range(ps, p, c, colour, 0, 1, lo, src, dst, omega, s);
+    int k0 = 0, k1 = nc;
+    bs_status st;
+    if (lo >= 0) {
+        if ((st = chain_range(ps, p, c, colour, 0, 1, lo, src, dst, omega, s)) != BS_OK) return st;
+        k0 = 1;
+    }
+    if (hi >= 0) {
+        if ((st = chain_range(ps, p, c, colour, nc - 1, nc, hi, src, dst, omega, s)) != BS_OK) return st;
+        k1 = nc - 1;
+    }
+    if (k1 > k0) return chain_range(ps, p, c, colour, k0, k1, ps->lam_off[3 * p + c], src, dst, omega, s);
     return BS_OK;
 }
 
@@ -264,7 +345,7 @@ bs_status chain_lowp(bs_patchset *ps, int p, int c, int colour, int prec, int la
             if (epi == kEpiUpdate || epi == kEpiUpdateAcc) {
                 g.usrc = src; g.udst = dst; g.omega = omega;
                 g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
-                if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
+                if (ch.filter_n) { g.ncolour = colour; g.colour_shift = ch.colour_shift; }
             }
             if (epi == kEpiD64 || epi == kEpiUpdateAcc) {
                 // D shares the f-layout indexing of the chain's final field (kIn = F1)
@@ -328,7 +409,7 @@ bs_status chain_bf16(bs_patchset *ps, int p, int c, int colour, int last_epi, in
             if (epi == kEpiUpdate || epi == kEpiUpdateAcc) {
                 g.usrc = src; g.udst = dst; g.omega = omega;
                 g.u0 = ch.u0; g.u_b = ch.u_b; g.u_m = ch.u_m; g.u_n = ch.u_n;
-                if (ch.filter_n) { g.ncolour = colour; g.colour_shift = 0; }
+                if (ch.filter_n) { g.ncolour = colour; g.colour_shift = ch.colour_shift; }
             }
             if (epi == kEpiD64 || epi == kEpiUpdateAcc) {
                 g.D = D + (g.C - F1);
@@ -407,6 +488,35 @@ bs_status residual_into_scratch(bs_patchset *ps, const double *u, const double *
 
 }  // namespace
 
+// One FP64 plane half-step for the adjoint's recomputation: dst = src + omega
+// P M^{-1} r(src) on the planes of `colour` (-1: all; dst == src in place).
+bs_status plane_step(bs_patchset *ps, int normal, int colour, const double *src, double *dst, const double *f,
+                     double omega, hipStream_t s)
+{
+    bs_status st;
+    if (!ps->plane_ready && (st = build_plane_tables(ps)) != BS_OK) return st;
+    if ((st = residual_into_scratch(ps, src, f, s, BS_FP64, 0)) != BS_OK) return st;
+    return plane_pass(ps, normal, colour, BS_FP64, 0, src, dst, omega, s);
+}
+
+// out += M^{-1} P rhs on the planes of `colour`, rhs = r(src) = h^2 f - A src
+// (f given) or src's interior (f null); out (u layout) is zero where the
+// result goes, so that it receives M^{-1} P rhs there.
+bs_status plane_solve(bs_patchset *ps, int normal, int colour, const double *src, const double *f, double *out,
+                      hipStream_t s)
+{
+    bs_status st;
+    if (!ps->plane_ready && (st = build_plane_tables(ps)) != BS_OK) return st;
+    if (f) {
+        if ((st = residual_into_scratch(ps, src, f, s, BS_FP64, 0)) != BS_OK) return st;
+    } else {
+        hipError_t e = launch_u_to_f(src, static_cast<double *>(ps->plane_r_d.p),
+                                     static_cast<const PatchDesc *>(ps->desc_d.p), ps->npatch, s);
+        if (e != hipSuccess) return hip_fail(e, "field copy");
+    }
+    return plane_pass(ps, normal, colour, BS_FP64, 0, out, out, 1.0, s);
+}
+
 }  // namespace bs
 
 using namespace bs;
@@ -430,12 +540,20 @@ bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme,
     for (int a = 0; a < 3; ++a)
         if (a != normal_axis && ps->max_n[a] > kMaxPlaneEdge)
             return fail(BS_ERR_UNSUPPORTED, "bs_plane_relax: an in-plane edge exceeds %d", kMaxPlaneEdge);
+    if (any_bc(ps) && prec != BS_FP64)
+        return fail(BS_ERR_UNSUPPORTED, "bs_plane_relax: extrapolated faces with mixed precision");
     if (nsweeps == 0) return BS_OK;
     bs_status st;
     if (!ps->plane_ready && (st = build_plane_tables(ps)) != BS_OK) return st;
     if (prec != BS_FP64 && (st = ensure_mixed_scratch(ps)) != BS_OK) return st;
     const int rf = prec == BS_FP64 ? 0 : refine;
     const PatchDesc *pdd = static_cast<const PatchDesc *>(ps->desc_d.p);
+    // ghosts of linked faces are exchanged after every sweep (section 2)
+    auto ghosts = [&](double *v) -> bs_status {
+        if (!ghost_active(ps)) return BS_OK;
+        hipError_t e = ghost_update(ps, v, false, stream);
+        return e == hipSuccess ? BS_OK : hip_fail(e, "ghost update");
+    };
     if (scheme == BS_JACOBI) {
         hipError_t e = launch_ghost_copy(u, work, pdd, ps->npatch, stream);
         if (e != hipSuccess) return hip_fail(e, "ghost copy");
@@ -444,20 +562,24 @@ bs_status bs_plane_relax(bs_patchset *ps, int32_t normal_axis, bs_scheme scheme,
             double *dst = (sw & 1) ? u : work;
             if ((st = residual_into_scratch(ps, src, f, stream, prec, rf)) != BS_OK) return st;
             if ((st = plane_pass(ps, normal_axis, -1, prec, rf, src, dst, omega, stream)) != BS_OK) return st;
+            if ((st = ghosts(dst)) != BS_OK) return st;
         }
         if (nsweeps & 1) {
             e = launch_interior_copy(work, u, pdd, ps->npatch, stream);
             if (e != hipSuccess) return hip_fail(e, "interior copy");
+            if ((st = ghosts(u)) != BS_OK) return st;
         }
         return BS_OK;
     }
     // Gauss-Seidel: planes of colour 0, then colour 1 (the chaotic scheme runs
     // the same colour-major order), in place
-    for (int sw = 0; sw < nsweeps; ++sw)
+    for (int sw = 0; sw < nsweeps; ++sw) {
         for (int colour = 0; colour < 2; ++colour) {
             if ((st = residual_into_scratch(ps, u, f, stream, prec, rf)) != BS_OK) return st;
             if ((st = plane_pass(ps, normal_axis, colour, prec, rf, u, u, omega, stream)) != BS_OK) return st;
         }
+        if ((st = ghosts(u)) != BS_OK) return st;
+    }
     return BS_OK;
 }
 

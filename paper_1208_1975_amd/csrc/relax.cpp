@@ -179,6 +179,7 @@ int device_cus()
 
 void clear_graphs(bs_patchset *ps)
 {
+    ++ps->gen;   // sequences captured elsewhere (multigrid cycles) hold the same pointers
     for (auto &kv : ps->graphs) (void)hipGraphExecDestroy(kv.second);
     ps->graphs.clear();
 }
@@ -429,6 +430,10 @@ bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const
 {
     const PatchDesc *pdd = static_cast<const PatchDesc *>(ps->desc_d.p);
     bs_status st;
+    // lines next to extrapolated faces parallel to them (their own kernel), and
+    // the ghost update after every sweep (links and extrapolated faces)
+    const bool bl = bline_any(ps, axis);
+    const bool gh = ghost_active(ps);
     auto pass = [&](int cm, int run, const double *src, double *dst) -> bs_status {
         if (!per_patch) return line_pass(ps, axis, c, cm, run, src, dst, f, omega, stream, -1, 0, 0, f32);
         for (int p = 0; p < ps->npatch; ++p) {
@@ -437,6 +442,12 @@ bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const
         }
         return BS_OK;
     };
+    auto ghosts = [&](double *v, bool fill_only) -> bs_status {
+        if (!gh) return BS_OK;
+        hipError_t e = ghost_update(ps, v, fill_only, stream);
+        return e == hipSuccess ? BS_OK : hip_fail(e, "ghost update");
+    };
+    if ((st = ghosts(u, true)) != BS_OK) return st;
     if (scheme == BS_JACOBI) {
         hipError_t e = launch_ghost_copy(u, work, pdd, ps->npatch, stream);
         if (e != hipSuccess) return hip_fail(e, "ghost copy");
@@ -444,17 +455,21 @@ bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const
             const double *src = (s & 1) ? work : u;
             double *dst = (s & 1) ? u : work;
             if ((st = pass(0, 0, src, dst)) != BS_OK) return st;
+            if (bl && (st = bline_pass(ps, axis, -1, src, dst, f, omega, stream)) != BS_OK) return st;
+            if ((st = ghosts(dst, false)) != BS_OK) return st;
         }
         if (nsweeps & 1) {
             e = launch_interior_copy(work, u, pdd, ps->npatch, stream);
             if (e != hipSuccess) return hip_fail(e, "interior copy");
+            if ((st = ghosts(u, false)) != BS_OK) return st;
         }
         return BS_OK;
     }
     const int cm = scheme_mode(axis, scheme);
     if (scheme == BS_CHAOTIC_GS && chaotic_colour_major(ps, axis, c)) {
-        // every tile would run at once: colour-major in two launches (all
-        // colour-0 lines, then all colour-1 lines), the two-colour sweep
+        // every tile would run at once (or boundary lines have their own
+        // kernel): colour-major in two launches (all colour-0 lines, then all
+        // colour-1 lines), the two-colour sweep
         const LineCfg c1 = line_cfg(ps, axis, 1);
         for (int s = 0; s < nsweeps; ++s) {
             for (int run = 0; run < 2; ++run) {
@@ -466,17 +481,22 @@ bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const
                         st = line_pass(ps, axis, c1, 1, run, u, u, f, omega, stream, p, 0, 0, f32);
                 }
                 if (st != BS_OK) return st;
+                if (bl && (st = bline_pass(ps, axis, run, u, u, f, omega, stream)) != BS_OK) return st;
             }
+            if ((st = ghosts(u, false)) != BS_OK) return st;
         }
         return BS_OK;
     }
     for (int s = 0; s < nsweeps; ++s) {
         if (scheme == BS_COLORED_GS) {
             if ((st = pass(cm, 0, u, u)) != BS_OK) return st;
+            if (bl && (st = bline_pass(ps, axis, 0, u, u, f, omega, stream)) != BS_OK) return st;
             if ((st = pass(cm, 1, u, u)) != BS_OK) return st;
+            if (bl && (st = bline_pass(ps, axis, 1, u, u, f, omega, stream)) != BS_OK) return st;
         } else {
             if ((st = pass(cm, 2, u, u)) != BS_OK) return st;
         }
+        if ((st = ghosts(u, false)) != BS_OK) return st;
     }
     return BS_OK;
 }
@@ -507,6 +527,9 @@ int chaotic_chunk_for(bs_patchset *ps, int axis, const LineCfg &c)
 // across tile borders); such sweeps are dispatched colour-major instead.
 bool chaotic_colour_major(bs_patchset *ps, int axis, const LineCfg &c)
 {
+    // lines next to extrapolated faces are solved by their own kernel, which
+    // the in-tile two-colour form cannot interleave with
+    if (bline_any(ps, axis)) return true;
     const int kind = axis == 0 ? 1 : 0;
     int64_t tiles = 0;
     for (int p = 0; p < ps->npatch; ++p) tiles += tiles_of(ps, p, kind, axis, c.tx, 2);
@@ -572,6 +595,17 @@ extern "C" {
 bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double omega, int32_t nsweeps,
                         bs_precision prec, double *u, const double *f, double *work, hipStream_t stream)
 {
+    return line_relax_impl(ps, axis, scheme, omega, nsweeps, prec, u, f, work, stream, true);
+}
+
+}  // extern "C"
+
+namespace bs {
+
+bs_status line_relax_impl(bs_patchset *ps, int32_t axis, bs_scheme scheme, double omega, int32_t nsweeps,
+                          bs_precision prec, double *u, const double *f, double *work, hipStream_t stream,
+                          bool allow_graph)
+{
     bs_status st = check_line_args(axis, scheme, omega, nsweeps, prec, "bs_line_relax");
     if (st != BS_OK) return st;
     if (!ps || !u || !f) return fail(BS_ERR_INVALID, "bs_line_relax: null patch set, u or f");
@@ -582,10 +616,11 @@ bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double 
     const LineCfg c = line_cfg(ps, axis, cm);
     if ((st = check_line_cfg(ps, axis, c)) != BS_OK) return st;
     if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;
+    if (bline_any(ps, axis) && (st = bline_prepare(ps, axis)) != BS_OK) return st;
     hipError_t e = prepare_line_kernels();
     if (e != hipSuccess) return hip_fail(e, "line kernel attributes");
     const int f32 = prec == BS_MIXED_FP32 ? 1 : 0;
-    if (!ps->use_graphs || nsweeps < 2)
+    if (!allow_graph || !ps->use_graphs || nsweeps < 2)
         return enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, stream, false, f32);
 
     // replay a captured graph of the whole sequence (captured on first use)
@@ -620,6 +655,10 @@ bs_status bs_line_relax(bs_patchset *ps, int32_t axis, bs_scheme scheme, double 
     return BS_OK;
 }
 
+}  // namespace bs
+
+extern "C" {
+
 bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, const double *u, const double *f,
                            hipStream_t stream)
 {
@@ -629,6 +668,7 @@ bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, cons
     if ((st = check_line_ps(ps, axis, "bs_autotune_line")) != BS_OK) return st;
     hipError_t e = prepare_line_kernels();
     if (e != hipSuccess) return hip_fail(e, "line kernel attributes");
+    if (bline_any(ps, axis) && (st = bline_prepare(ps, axis)) != BS_OK) return st;
     const int cm = scheme_mode(axis, scheme);
     DevBuf su, sw;
     const size_t bytes = static_cast<size_t>(ps->u_numel) * sizeof(double);
@@ -815,6 +855,7 @@ int bsi_line_relax_per_patch(bs_patchset *ps, int32_t axis, bs_scheme scheme, do
     const LineCfg c = line_cfg(ps, axis, cm);
     if ((st = check_line_cfg(ps, axis, c)) != BS_OK) return st;
     if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;
+    if (bline_any(ps, axis) && (st = bline_prepare(ps, axis)) != BS_OK) return st;
     if (prepare_line_kernels() != hipSuccess) return BS_ERR_HIP;
     return enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, stream, true);
 }

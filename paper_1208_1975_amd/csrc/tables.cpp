@@ -207,4 +207,43 @@ std::vector<long double> sine_eigenvalues(int n, double eps)
     return sg;
 }
 
+std::vector<double> bc_sine_basis(int n, int lo, int hi)
+{
+    if (!lo && !hi) return sine_basis(n);
+    const ld pi = 3.141592653589793238462643383279502884L;
+    // angle = pi * m / den, m reduced in integers modulo 2 den
+    const long den = (lo && hi) ? 2L * n : 2L * n + 1;
+    std::vector<ld> V(static_cast<size_t>(n) * n);
+    for (int k = 0; k < n; ++k) {
+        ld ss = 0.0L;
+        for (int i = 0; i < n; ++i) {
+            long m;
+            if (lo && hi)
+                m = static_cast<long>(k + 1) * (2 * i + 1);
+            else
+                m = 2L * (k + 1) * (hi ? i + 1 : n - i);
+            m %= 2 * den;
+            const ld v = std::sin(pi * static_cast<ld>(m) / static_cast<ld>(den));
+            V[static_cast<size_t>(i) * n + k] = v;
+            ss += v * v;
+        }
+        const ld sc = 1.0L / std::sqrt(ss);
+        for (int i = 0; i < n; ++i) V[static_cast<size_t>(i) * n + k] *= sc;
+    }
+    return std::vector<double>(V.begin(), V.end());
+}
+
+std::vector<long double> bc_sine_eigenvalues(int n, double eps, int lo, int hi)
+{
+    if (!lo && !hi) return sine_eigenvalues(n, eps);
+    const ld pi = 3.141592653589793238462643383279502884L;
+    const ld den = (lo && hi) ? 2.0L * n : 2.0L * n + 1.0L;
+    std::vector<long double> sg(n);
+    for (int k = 0; k < n; ++k) {
+        const ld s = std::sin(pi * (k + 1) / den);
+        sg[k] = 4.0L * eps * s * s;
+    }
+    return sg;
+}
+
 }  // namespace bs

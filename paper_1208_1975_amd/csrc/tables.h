@@ -24,4 +24,13 @@ std::vector<double> sine_basis(int n);
 // sigma_p = 4 eps sin^2((p+1) pi / (2(n+1))).
 std::vector<long double> sine_eigenvalues(int n, double eps);
 
+// Eigenbasis of the line block tridiag(-eps, 2 eps, -eps) of order n whose
+// first (lo) and / or last (hi) diagonal entry is raised by eps (an
+// extrapolated face at that end), row-major V[i][k] with orthonormal columns
+// in the order of bc_sine_eigenvalues.  lo = hi = 0 is sine_basis (DST-I);
+// lo = hi = 1 the DST-II basis sin(pi (k+1)(2i+1) / (2n)); one raised end the
+// sines sin(2 pi (k+1) m / (2n+1)) with m = i+1 (hi) or n-i (lo).
+std::vector<double> bc_sine_basis(int n, int lo, int hi);
+std::vector<long double> bc_sine_eigenvalues(int n, double eps, int lo, int hi);
+
 }  // namespace bs
