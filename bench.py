@@ -465,8 +465,8 @@ def exchange_form():
     ms_x = ev_ms(lambda: ps.line_relax(0, "chaotic", 1.0, 20, u, f), reps=3)
     ps.exchange_ghosts(u)
     ms_e = ev_ms(lambda: [ps.exchange_ghosts(u) for _ in range(20)], reps=3)
-    ghost_cells = 2 * sum(s.dims[a][(ax + 1) % 3] * s.dims[a][(ax + 2) % 3] for a, ax, _ in s.links)
-    res = {"patches": s.npatch, "links": len(s.links), "cells": cells, "exchanged_ghost_cells": ghost_cells,
+    ghost_cells = 2 * sum(int(s.dims[a][(ax + 1) % 3]) * int(s.dims[a][(ax + 2) % 3]) for a, ax, _ in s.links)
+    res = {"patches": int(s.npatch), "links": len(s.links), "cells": int(cells), "exchanged_ghost_cells": ghost_cells,
            "ms_20_sweeps_with_exchange": round(ms_x, 3), "ms_20_sweeps_without": round(ms_plain, 3),
            "ms_20_exchanges_alone": round(ms_e, 3),
            "exchange_share_of_step": round((ms_x - ms_plain) / ms_x, 4),
@@ -500,7 +500,7 @@ def mg_form():
     ms = ev_ms(lambda: mg.vcycle(u, f), reps=5)
     # a cycle smooths each level twice (coarsest: 20 sweeps): fine-grid sweep equivalents
     fine_eq = sum(2.0 / 8 ** l for l in range(mg.levels - 1)) + 20.0 / 8 ** (mg.levels - 1)
-    res = {"levels": mg.levels, "ms_per_cycle": round(ms, 3),
+    res = {"levels": int(mg.levels), "ms_per_cycle": round(ms, 3),
            "residual_factor_per_cycle": [round(rs[i + 1] / rs[i], 4) for i in range(len(rs) - 1)],
            "fine_sweep_equivalents_per_cycle": round(fine_eq, 3),
            "glups_equivalent": round(256 ** 3 * fine_eq / (ms * 1e-3) / 1e9, 2)}
