@@ -357,6 +357,21 @@ bs_status bs_block_backward(bs_patchset *ps, int32_t kind, int32_t axis, bs_sche
                             const double *grad_uK, double *grad_u0, double *grad_f, double *grad_eps,
                             void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* bs_residual for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same result and per-patch norms, bit for bit, with the per-tile partial sums
+ * of the norm reduction in a static device array of 65536 doubles (512 KiB)
+ * instead of the patch set's own buffer.  Each GPU holds its own copy of the
+ * array for the life of the process; its address is looked up on the first
+ * call on a device.  Allocates nothing.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (several streams, several host
+ * threads) race.  BS_ERR_UNSUPPORTED for a patch set with more than 65536
+ * residual tiles (a tile covers at most 256 columns by 64 planes of one
+ * patch), BS_ERR_INVALID for the argument errors of bs_residual or when the
+ * current device is not the patch set's. */
+bs_status bs_residual_noalloc(const bs_patchset *ps, const double *u, const double *f, double *r,
+                              double *rnorm2, hipStream_t stream);
+
 /* Message for the last non-OK status returned on this host thread ("" if none). */
 const char *bs_last_error(void);
 

@@ -32,7 +32,8 @@ EXPORTS = ("bs_layout_plan", "bs_create_patchset", "bs_destroy_patchset", "bs_se
            "bs_residual", "bs_line_relax", "bs_plane_relax", "bs_cube_prepare", "bs_cube_relax",
            "bs_autotune_line", "bs_line_config", "bs_set_bc", "bs_set_links", "bs_exchange_ghosts",
            "bs_mg_create", "bs_mg_destroy", "bs_mg_levels", "bs_vcycle", "bs_block_backward_workspace_bytes",
-           "bs_block_backward", "bs_backward_workspace_bytes", "bs_relax_backward", "bs_last_error")
+           "bs_block_backward", "bs_backward_workspace_bytes", "bs_relax_backward", "bs_residual_noalloc",
+           "bs_last_error")
 
 
 class BSError(RuntimeError):
