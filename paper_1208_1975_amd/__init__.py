@@ -72,6 +72,8 @@ def lib():
     L.bsi_set_line_cfg.restype = ctypes.c_int
     L.bsi_set_xline_cfg.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.bsi_set_xline_cfg.restype = ctypes.c_int
+    L.bsi_set_xz_cfg.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.bsi_set_xz_cfg.restype = ctypes.c_int
     L.bsi_set_graphs.argtypes = [vp, ctypes.c_int]
     L.bsi_set_graphs.restype = ctypes.c_int
     L.bsi_line_relax_per_patch.argtypes = [vp, i32, ctypes.c_int, dbl, i32, vp, vp, vp, vp]
@@ -261,8 +263,8 @@ def bs_autotune_line(ps, axis, scheme, u, f, stream=None):
 
 def bs_line_config(ps, axis, scheme):
     """dict(chunks, chunk_len, tile, grid, tuned, form) of the launch configuration
-    in use (form 1, register x-lines: chunks = wavefronts per workgroup,
-    chunk_len = cells per lane)."""
+    in use (forms 1 and 2, register x-lines: chunks = wavefronts per workgroup,
+    chunk_len = cells per lane; form 2, marched along z: tile = planes per item)."""
     out = (ctypes.c_int32 * 6)()
     _check(lib().bs_line_config(ps, int(axis), _scheme(scheme), out))
     return dict(zip(("chunks", "chunk_len", "tile", "grid", "tuned", "form"), list(out)))
@@ -418,6 +420,11 @@ class PatchSet:
         """Register x-line kernel (x-lines of up to 64 cells across the lanes of
         a 16-lane row) with `waves` wavefronts per workgroup."""
         _check(lib().bsi_set_xline_cfg(self.handle, _scheme(scheme), int(waves), int(grid)))
+
+    def set_xz_config(self, scheme, waves=4, planes=0, grid=0):
+        """z-marching x-line kernel (x-lines of up to 64 cells, items of rows by
+        `planes` planes marched along z; 0 = the default) for Jacobi or chaotic GS."""
+        _check(lib().bsi_set_xz_cfg(self.handle, _scheme(scheme), int(waves), int(planes), int(grid)))
 
     def set_graphs(self, enable):
         _check(lib().bsi_set_graphs(self.handle, 1 if enable else 0))

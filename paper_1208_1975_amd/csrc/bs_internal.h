@@ -97,6 +97,12 @@ struct ResidArgs {
 hipError_t launch_line_strided(const LineArgs &a, int grid, int Lmax, int nwaves, size_t lds, hipStream_t s);
 hipError_t launch_line_x(const LineArgs &a, int grid, int Lmax, int nwaves, size_t lds, hipStream_t s);
 hipError_t launch_line_xr(const LineArgs &a, int grid, int nwaves, hipStream_t s);
+// x-lines of up to 64 cells marched along z: items of rows x planes (a.tx =
+// planes per item); colour_mode 0 (Jacobi) or 2 (chaotic GS).
+hipError_t launch_line_xz(const LineArgs &a, int grid, int nwaves, hipStream_t s);
+int line_xz_occupancy(int nwaves, int cm, int f32);
+// Rows of one z-marching x-line item.
+__host__ __device__ inline int xz_item_rows(int nx, int nwaves) { return nwaves * 4 * (16 / ((nx + 3) >> 2)); }
 hipError_t prepare_line_kernels();
 // Workgroups per compute unit that a line-kernel configuration can hold at once.
 int line_occupancy(int axis, int Lmax, int nwaves, size_t lds, int colour_mode, int f32);

@@ -59,7 +59,9 @@ struct LineCfg {
     int tx = 64;      // strided kernel: lanes along x per row
     int grid = 0;     // persistent grid size (0: one workgroup per work item)
     int form = 0;     // 0: a line's chunks on the wavefronts of a workgroup;
-                      // 1: x-lines across the lanes of a 16-lane row (nx <= 64)
+                      // 1: x-lines across the lanes of a 16-lane row (nx <= 64);
+                      // 2: the same lines marched along z (nx <= 64; Jacobi, chaotic GS)
+    int zc = 0;       // form 2: planes per work item
     int tuned = 0;    // 1: chosen by bs_autotune_line
 };
 

@@ -30,10 +30,15 @@ int lmax_for(int Lr)
     return 64;
 }
 
-// Tiles of one patch for a line kernel.
-int tiles_of(const bs_patchset *ps, int p, int kind, int axis, int tx, int colour_mode)
+// Tiles of one patch for a line kernel (kind 0 strided y/z lines, 1 x-line
+// row blocks, 2 z-marching x-line items: tx = planes per item, nw = waves).
+int tiles_of(const bs_patchset *ps, int p, int kind, int axis, int tx, int colour_mode, int nw = 0)
 {
     const int nx = ps->dims[3 * p], ny = ps->dims[3 * p + 1], nz = ps->dims[3 * p + 2];
+    if (kind == 2) {
+        const int R = xz_item_rows(nx, nw);
+        return ((ny + R - 1) / R) * ((nz + tx - 1) / tx);
+    }
     if (kind == 1) {
         const int64_t rows = static_cast<int64_t>(colour_mode == 1 ? (ny + 1) / 2 : ny) * nz;
         return static_cast<int>((rows + 63) / 64);
@@ -187,7 +192,7 @@ void clear_graphs(bs_patchset *ps)
 bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, int colour_mode, WorkList **out,
                        int chunk)
 {
-    if (colour_mode != 2) chunk = 0;
+    if (colour_mode != 2 || kind == 2) chunk = 0;
     if (colour_mode == 2 && chunk <= 0) chunk = ps->npatch == 1 ? 64 : 512;
     const WorkKey key{kind, axis, popt, tx, colour_mode, chunk};
     auto itr = ps->lists.find(key);
@@ -206,15 +211,17 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
     auto wl = std::make_unique<WorkList>();
     std::vector<WorkItem> all, plain;
     std::vector<WorkItem> runs[2];
-    const int ncol = colour_mode ? 2 : 1;
+    // z-marching x-line items: one run in every colour mode (chaotic GS orders
+    // its lines inside each item)
+    const int ncol = (colour_mode && kind != 2) ? 2 : 1;
     for (int c = 0; c < ncol; ++c) {
         std::vector<WorkItem> &run = runs[c];
         wl->pfirst[c].assign(ps->npatch, 0);
         wl->pcount[c].assign(ps->npatch, 0);
         for (int p : order) {
-            const int nt = tiles_of(ps, p, kind, axis, tx, colour_mode);
+            const int nt = tiles_of(ps, p, kind, axis, tx, colour_mode, popt);
             wl->pfirst[c][p] = static_cast<int>(run.size());
-            if (colour_mode == 2) {
+            if (colour_mode == 2 && kind != 2) {
                 // in-tile two-colour: all tiles, tile rows of parity c in run c
                 // (x lines: a tile is a block of rows, alternate tiles)
                 const int nti = kind == 1 ? 1 : tiles_per_row(ps, p, tx);
@@ -228,7 +235,7 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
         wl->pp_off[c] = static_cast<int>(plain.size());
         plain.insert(plain.end(), run.begin(), run.end());
     }
-    if (colour_mode == 2) {
+    if (colour_mode == 2 && kind != 2) {
         // one launch runs both groups: local even-then-odd chunks per XCD
         const std::vector<WorkItem> d = chaotic_order(ps, runs, order, wl->pfirst, wl->pcount, axis, chunk);
         wl->count[0] = static_cast<int>(d.size());
@@ -256,6 +263,20 @@ bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, in
     *out = wl.get();
     ps->lists.emplace(key, std::move(wl));
     return BS_OK;
+}
+
+// Planes per z-marching x-line item: whole patches along z unless the set
+// would have fewer than eight items per compute unit, then halved (down to 4).
+int xz_planes(const bs_patchset *ps, int nwaves)
+{
+    int zc = ps->max_n[2];
+    auto items = [&](int z) {
+        int64_t n = 0;
+        for (int p = 0; p < ps->npatch; ++p) n += tiles_of(ps, p, 2, 0, z, 0, nwaves);
+        return n;
+    };
+    while (zc > 4 && items(zc) < 8 * static_cast<int64_t>(device_cus())) zc = (zc + 1) / 2;
+    return std::max(zc, 1);
 }
 
 LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode)
@@ -295,7 +316,7 @@ LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode)
 
 size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c)
 {
-    if (c.form == 1) return 0;
+    if (c.form == 1 || c.form == 2) return 0;
     int tsz = 0, sd = 1;
     for (int p = 0; p < ps->npatch; ++p) {
         const LineTabRef &r = ps->desc[p].line[axis][c.popt];
@@ -320,6 +341,18 @@ bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c)
         if (c.popt != 0 || c.Lmax != 4) return fail(BS_ERR_INVALID, "line config: bad register x-line form");
         if (c.nwaves != 1 && c.nwaves != 2 && c.nwaves != 4)
             return fail(BS_ERR_INVALID, "line config: register x-lines take 1, 2 or 4 wavefronts");
+        if (c.grid < 0) return fail(BS_ERR_INVALID, "line config: negative grid");
+        for (int p = 0; p < ps->npatch; ++p)
+            if (ps->desc[p].line[0][0].off < 0)
+                return fail(BS_ERR_UNSUPPORTED, "line config: patch %d has no x-line factor table", p);
+        return BS_OK;
+    }
+    if (c.form == 2) {
+        if (axis != 0 || ps->max_n[0] > kXregMaxN)
+            return fail(BS_ERR_UNSUPPORTED, "line config: z-marching x-lines need axis 0 and nx <= %d", kXregMaxN);
+        if (c.popt != 0 || c.Lmax != 4) return fail(BS_ERR_INVALID, "line config: bad z-marching x-line form");
+        if (c.nwaves < 1 || c.nwaves > 4) return fail(BS_ERR_INVALID, "line config: z-marching x-lines take 1 to 4 wavefronts");
+        if (c.zc < 1) return fail(BS_ERR_INVALID, "line config: z-marching x-lines need planes per item >= 1");
         if (c.grid < 0) return fail(BS_ERR_INVALID, "line config: negative grid");
         for (int p = 0; p < ps->npatch; ++p)
             if (ps->desc[p].line[0][0].off < 0)
@@ -351,10 +384,12 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
                     double *dst, const double *f, double omega, hipStream_t stream, int patch, int rhs_mode,
                     int out_mode, int f32)
 {
-    const int kind = axis == 0 ? 1 : 0;
+    const int kind = axis == 0 ? (c.form == 2 ? 2 : 1) : 0;
+    if (kind == 2 && colour_mode == 1)
+        return fail(BS_ERR_INVALID, "line pass: z-marching x-lines run Jacobi or chaotic GS only");
     WorkList *wl = nullptr;
-    bs_status st = get_worklist(ps, kind, axis, c.popt, c.tx, colour_mode, &wl,
-                                colour_mode == 2 ? chaotic_chunk_for(ps, axis, c) : 0);
+    bs_status st = get_worklist(ps, kind, axis, kind == 2 ? c.nwaves : c.popt, kind == 2 ? c.zc : c.tx, colour_mode,
+                                &wl, (colour_mode == 2 && kind != 2) ? chaotic_chunk_for(ps, axis, c) : 0);
     if (st != BS_OK) return st;
     LineArgs a{};
     a.src = src;
@@ -370,7 +405,7 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
                                          kMallBytes) ? 1 : 0;
     a.axis = axis;
     a.popt = c.popt;
-    a.tx = c.tx;
+    a.tx = kind == 2 ? c.zc : c.tx;
     a.colour_mode = colour_mode;
     a.rhs_mode = rhs_mode;
     a.out_mode = out_mode;
@@ -382,12 +417,17 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
         a.items = base + first;
         a.nitems = count;
         const int grid = c.grid > 0 ? std::min(count, c.grid) : count;
-        hipError_t e = c.form == 1  ? launch_line_xr(a, grid, c.nwaves, stream)
+        hipError_t e = c.form == 2  ? launch_line_xz(a, grid, c.nwaves, stream)
+                       : c.form == 1  ? launch_line_xr(a, grid, c.nwaves, stream)
                        : axis == 0  ? launch_line_x(a, grid, c.Lmax, c.nwaves, lds, stream)
                                     : launch_line_strided(a, grid, c.Lmax, c.nwaves, lds, stream);
         return e == hipSuccess ? BS_OK : hip_fail(e, "line sweep kernel");
     };
     if (colour_mode == 2) run = 2;   // in-tile two-colour: both tile-row groups in one pass
+    if (kind == 2) {                 // one run in every mode
+        if (patch >= 0) return launch(wl->pp_off[0] + wl->pfirst[0][patch], wl->pcount[0][patch]);
+        return launch(0, wl->count[0]);
+    }
     if (patch >= 0) {
         const int runs = colour_mode ? (run == 2 ? 2 : 1) : 1;
         for (int k = 0; k < runs; ++k) {
@@ -530,6 +570,7 @@ bool chaotic_colour_major(bs_patchset *ps, int axis, const LineCfg &c)
     // lines next to extrapolated faces are solved by their own kernel, which
     // the in-tile two-colour form cannot interleave with
     if (bline_any(ps, axis)) return true;
+    if (c.form == 2) return false;   // z-marching items order their own lines
     const int kind = axis == 0 ? 1 : 0;
     int64_t tiles = 0;
     for (int p = 0; p < ps->npatch; ++p) tiles += tiles_of(ps, p, kind, axis, c.tx, 2);
@@ -546,6 +587,7 @@ bs_status prepare_lists(bs_patchset *ps, int axis, const LineCfg &c, int colour_
         if (st != BS_OK) return st;
         return get_worklist(ps, axis == 0 ? 1 : 0, axis, c1.popt, c1.tx, 1, &wl);
     }
+    if (c.form == 2) return get_worklist(ps, 2, axis, c.nwaves, c.zc, colour_mode, &wl, 0);
     return get_worklist(ps, axis == 0 ? 1 : 0, axis, c.popt, c.tx, colour_mode, &wl,
                         colour_mode == 2 ? chaotic_chunk_for(ps, axis, c) : 0);
 }
@@ -703,6 +745,24 @@ bs_status bs_autotune_line(bs_patchset *ps, int32_t axis, bs_scheme scheme, cons
             }
         }
     }
+    if (axis == 0 && ps->max_n[0] <= kXregMaxN && cm != 1) {
+        // x-lines marched along z (Jacobi and chaotic GS)
+        for (int nw : {2, 4}) {
+            const int zc0 = xz_planes(ps, nw);
+            for (int zc : {zc0, std::max(1, zc0 / 4)}) {
+                LineCfg c;
+                c.form = 2;
+                c.popt = 0;
+                c.Lmax = 4;
+                c.nwaves = nw;
+                c.zc = zc;
+                c.tx = 64;
+                c.grid = 0;
+                if (check_line_cfg(ps, axis, c) == BS_OK) cands.push_back(c);
+                if (zc0 <= 4) break;
+            }
+        }
+    }
     if (axis == 0 && ps->max_n[0] <= kXregMaxN) {
         for (int nw : {1, 2, 4}) {
             LineCfg c;
@@ -765,9 +825,9 @@ bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, 
     auto itr = ps->line_cfg.find(std::make_pair(static_cast<int>(axis), cm));
     const bool set = itr != ps->line_cfg.end();
     const LineCfg c = set ? itr->second : default_line_cfg(ps, axis, cm);
-    cfg_host[0] = c.form == 1 ? c.nwaves : kPOpts[c.popt];
+    cfg_host[0] = c.form != 0 ? c.nwaves : kPOpts[c.popt];
     cfg_host[1] = c.Lmax;
-    cfg_host[2] = c.tx;
+    cfg_host[2] = c.form == 2 ? c.zc : c.tx;
     cfg_host[3] = c.grid;
     cfg_host[4] = c.tuned;
     cfg_host[5] = c.form;
@@ -814,6 +874,28 @@ int bsi_set_xline_cfg(bs_patchset *ps, int scheme, int nwaves, int grid)
     c.popt = 0;
     c.Lmax = 4;
     c.nwaves = nwaves;
+    c.tx = 64;
+    c.grid = grid;
+    bs_status st = check_line_cfg(ps, 0, c);
+    if (st != BS_OK) return st;
+    ps->line_cfg[std::make_pair(0, colour_mode)] = c;
+    clear_graphs(ps);
+    return BS_OK;
+}
+
+// Select the z-marching x-line kernel for `scheme` (Jacobi or chaotic GS):
+// nwaves wavefronts per workgroup, zc planes per item (0: the default),
+// persistent grid size (0: one workgroup per item).
+int bsi_set_xz_cfg(bs_patchset *ps, int scheme, int nwaves, int zc, int grid)
+{
+    if (!ps || (scheme != BS_JACOBI && scheme != BS_CHAOTIC_GS) || zc < 0) return BS_ERR_INVALID;
+    const int colour_mode = scheme_mode(0, static_cast<bs_scheme>(scheme));
+    LineCfg c;
+    c.form = 2;
+    c.popt = 0;
+    c.Lmax = 4;
+    c.nwaves = nwaves;
+    c.zc = zc > 0 ? zc : (nwaves >= 1 && nwaves <= 4 ? xz_planes(ps, nwaves) : 1);
     c.tx = 64;
     c.grid = grid;
     bs_status st = check_line_cfg(ps, 0, c);
