@@ -130,9 +130,10 @@ bs_status bs_set_eps(bs_patchset *ps, const double *eps_host);
  * (raised end diagonals) and drops prepared cube block sizes.  Synchronous.
  * BS_ERR_INVALID for a mask outside 0..63 or one that marks a linked face
  * (bs_set_links); on BS_ERR_OOM / BS_ERR_HIP the set keeps its previous
- * conditions.  Lines and planes (FP64) take any mask; mixed-precision planes
- * and cube blocks return BS_ERR_UNSUPPORTED on a patch set with any
- * extrapolated face. */
+ * conditions.  Lines, planes (FP64) and cube blocks take any mask (a cube
+ * block touching an extrapolated face gets its own inverse); mixed-precision
+ * planes return BS_ERR_UNSUPPORTED on a patch set with any extrapolated
+ * face. */
 bs_status bs_set_bc(bs_patchset *ps, const int32_t *bc_host);
 
 /* Face adjacency (section 2: ghosts are updated Jacobi-fashion after every

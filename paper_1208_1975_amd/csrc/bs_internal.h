@@ -221,7 +221,9 @@ struct BLineArgs {
     int32_t axis, nitems, nlines, first;   // items [first, first + nitems) of nlines
     double omega;
 };
-hipError_t launch_bline(const BLineArgs &a, hipStream_t s);
+// Two launches: the lines' residuals one cell per thread, then the solves one
+// line per thread (maxlen: the longest line of the set along the axis).
+hipError_t launch_bline(const BLineArgs &a, int maxlen, hipStream_t s);
 
 // Multigrid transfers (k_mg.hip), per patch: pf / pc the fine / coarse
 // descriptors, max_cells the largest coarse (restriction) or fine

@@ -24,6 +24,7 @@
 #include "patchset.h"
 #include "plane.h"
 #include "relax.h"
+#include "tables.h"
 
 namespace bs {
 
@@ -32,38 +33,34 @@ namespace {
 constexpr int kCubeMaxCells = 512;                      // cells per block (8^3, the paper's largest)
 constexpr int64_t kCubeMaxInvBytes = int64_t(1) << 30;  // all inverses of one block size
 
-// Orthonormal DST-I basis S[i][p] = sqrt(2/(n+1)) sin((i+1)(p+1) pi/(n+1)) of
-// tridiag(-1, 2, -1) (n x n) and its eigenvalues 4 sin^2((p+1) pi/(2(n+1))).
-// The sine argument is reduced modulo 2(n+1) in integers first.
-void dst1(int n, std::vector<double> &S, std::vector<double> &sig)
+// Orthonormal eigenbasis V[i][p] of the 1D block operator tridiag(-1, 2, -1)
+// of order n, with its first / last diagonal entry raised by one where the
+// block touches an extrapolated face at that end (lo / hi), and its
+// eigenvalues: the DST-I basis with neither, DST-II with both, the one-sided
+// sine basis with one (closed forms in tables.cpp).
+void block_basis(int n, int lo, int hi, std::vector<double> &V, std::vector<double> &sig)
 {
-    S.assign(size_t(n) * n, 0.0);
-    sig.assign(n, 0.0);
-    const double sc = std::sqrt(2.0 / (n + 1)), pi = std::acos(-1.0);
-    for (int i = 0; i < n; ++i)
-        for (int p = 0; p < n; ++p) {
-            const int m = ((i + 1) * (p + 1)) % (2 * (n + 1));
-            S[size_t(i) * n + p] = sc * std::sin(pi * m / (n + 1));
-        }
-    for (int p = 0; p < n; ++p) {
-        const double t = std::sin((p + 1) * pi / (2.0 * (n + 1)));
-        sig[p] = 4.0 * t * t;
-    }
+    V = bc_sine_basis(n, lo, hi);
+    const std::vector<long double> s = bc_sine_eigenvalues(n, 1.0, lo, hi);
+    sig.assign(s.begin(), s.end());
 }
 
 // Dense inverse of the block matrix of an ni x nj x nk block,
 //   A_b = ex (I (x) I (x) T_ni) + ey (I (x) T_nj (x) I) + ez (T_nk (x) I (x) I),
-// (the stencil restricted to the block; T_n = tridiag(-1, 2, -1)), from its
-// eigen-decomposition: A_b^{-1} = S diag(1/lambda) S with S = S_k (x) S_j (x) S_i
-// symmetric and lambda_pqr = ex sig_p + ey sig_q + ez sig_r.  Column c' is
-// S (lambda^{-1} .* S e_c'), S e_c' being the product of one row of each basis;
-// the outer S is applied one axis at a time.  Cells are numbered x fastest.
-void block_inverse(int ni, int nj, int nk, double ex, double ey, double ez, double *out)
+// (the stencil restricted to the block; T_n = tridiag(-1, 2, -1), with an end
+// diagonal raised by one where the block touches an extrapolated face: bits of
+// `raise`, 2a low / 2a+1 high end of axis a), from its eigen-decomposition:
+// A_b^{-1} = S diag(1/lambda) S^T with S = S_k (x) S_j (x) S_i orthonormal and
+// lambda_pqr = ex sig_p + ey sig_q + ez sig_r.  Column c' is
+// S (lambda^{-1} .* S^T e_c'), S^T e_c' being the product of one row of each
+// basis; the outer S is applied one axis at a time.  Cells are numbered x
+// fastest.
+void block_inverse(int ni, int nj, int nk, double ex, double ey, double ez, int raise, double *out)
 {
     std::vector<double> Si, Sj, Sk, si, sj, sk;
-    dst1(ni, Si, si);
-    dst1(nj, Sj, sj);
-    dst1(nk, Sk, sk);
+    block_basis(ni, raise & 1, (raise >> 1) & 1, Si, si);
+    block_basis(nj, (raise >> 2) & 1, (raise >> 3) & 1, Sj, sj);
+    block_basis(nk, (raise >> 4) & 1, (raise >> 5) & 1, Sk, sk);
     const int nb = ni * nj * nk;
     std::vector<double> w(nb), t1(nb), t2(nb);
     for (int ck2 = 0; ck2 < nk; ++ck2)
@@ -114,12 +111,13 @@ struct HostImage {
 
 bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &plan)
 {
-    // classes of patches with equal dims, eps and h share inverses and offsets
-    using ClassKey = std::tuple<int, int, int, double, double, double, double>;
+    // classes of patches with equal dims, eps, h and extrapolated faces share
+    // inverses and offsets
+    using ClassKey = std::tuple<int, int, int, double, double, double, double, int>;
     std::vector<std::pair<ClassKey, std::vector<int>>> classes;
     for (int p = 0; p < ps->npatch; ++p) {
         const ClassKey k{ps->dims[3 * p], ps->dims[3 * p + 1], ps->dims[3 * p + 2], ps->eps[3 * p],
-                         ps->eps[3 * p + 1], ps->eps[3 * p + 2], ps->h[p]};
+                         ps->eps[3 * p + 1], ps->eps[3 * p + 2], ps->h[p], ps->bc[p]};
         auto it = std::find_if(classes.begin(), classes.end(), [&](const auto &c) { return c.first == k; });
         if (it == classes.end()) classes.push_back({k, {p}});
         else it->second.push_back(p);
@@ -131,18 +129,33 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
         const int nx = std::get<0>(cl.first), ny = std::get<1>(cl.first), nz = std::get<2>(cl.first);
         const double ex = std::get<3>(cl.first), ey = std::get<4>(cl.first), ez = std::get<5>(cl.first);
         const double h = std::get<6>(cl.first);
+        const int bcm = std::get<7>(cl.first);
         const int cb[3] = {std::min(bx, nx), std::min(by, ny), std::min(bz, nz)};
         const int n[3] = {nx, ny, nz};
         const int64_t SY = nx + 2, SZ = int64_t(nx + 2) * (ny + 2);
-        // per axis: the full edge and, if the axis is not a multiple of it, the remainder
-        std::vector<int> ext[3];
-        for (int a = 0; a < 3; ++a) {
-            if (n[a] / cb[a] > 0) ext[a].push_back(cb[a]);
-            if (n[a] % cb[a]) ext[a].push_back(n[a] % cb[a]);
-        }
-        for (int sx : ext[0])
-            for (int sy : ext[1])
-                for (int sz : ext[2]) {
+        // per axis, the blocks' origins grouped by (edge, touches an
+        // extrapolated low face, touches an extrapolated high face): the full
+        // edge and, if the axis is not a multiple of it, the remainder
+        struct Seg {
+            int size, lo, hi;
+            std::vector<int> origins;
+        };
+        std::vector<Seg> segs[3];
+        for (int a = 0; a < 3; ++a)
+            for (int o = 0; o < n[a]; o += cb[a]) {
+                const int size = std::min(cb[a], n[a] - o);
+                const int lo = (o == 0 && ((bcm >> (2 * a)) & 1)) ? 1 : 0;
+                const int hi = (o + size == n[a] && ((bcm >> (2 * a + 1)) & 1)) ? 1 : 0;
+                auto it = std::find_if(segs[a].begin(), segs[a].end(),
+                                       [&](const Seg &sg) { return sg.size == size && sg.lo == lo && sg.hi == hi; });
+                if (it == segs[a].end()) segs[a].push_back(Seg{size, lo, hi, {o}});
+                else it->origins.push_back(o);
+            }
+        for (const Seg &gx : segs[0])
+            for (const Seg &gy : segs[1])
+                for (const Seg &gz : segs[2]) {
+                    const int sx = gx.size, sy = gy.size, sz = gz.size;
+                    const int raise = gx.lo | (gx.hi << 1) | (gy.lo << 2) | (gy.hi << 3) | (gz.lo << 4) | (gz.hi << 5);
                     const int nb = sx * sy * sz;
                     inv_bytes += int64_t(nb) * nb * 8;
                     if (inv_bytes > kCubeMaxInvBytes)
@@ -158,7 +171,7 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
                     g.sy = SY;
                     g.sz = SZ;
                     std::vector<double> inv(size_t(nb) * nb);
-                    block_inverse(sx, sy, sz, ex, ey, ez, inv.data());
+                    block_inverse(sx, sy, sz, ex, ey, ez, raise, inv.data());
                     g.o_ainv = img.put(inv.data(), inv.size() * 8);
                     std::vector<int32_t> uo(nb), fo(nb);
                     for (int ck = 0; ck < sz; ++ck)
@@ -170,17 +183,7 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
                             }
                     g.o_uoff = img.put(uo.data(), uo.size() * 4);
                     g.o_foff = img.put(fo.data(), fo.size() * 4);
-                    // this shape's blocks: origin index i0 = bi * cb runs over the
-                    // full blocks if the edge is the full one, else the last block
-                    auto origins = [&](int a, int s) {
-                        std::vector<int> o;
-                        if (s == cb[a] && n[a] / cb[a] > 0)
-                            for (int t = 0; t < n[a] / cb[a]; ++t) o.push_back(t * cb[a]);
-                        else
-                            o.push_back(n[a] - n[a] % cb[a]);
-                        return o;
-                    };
-                    const std::vector<int> oi = origins(0, sx), oj = origins(1, sy), ok = origins(2, sz);
+                    const std::vector<int> &oi = gx.origins, &oj = gy.origins, &ok = gz.origins;
                     // Block lists in dispatch order: x fastest, then y within a band of
                     // G block rows, then z, then the next band, so that a run of 64
                     // blocks (one workgroup of the fused kernel) is a slab one block
@@ -351,6 +354,12 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
         hipError_t e = ghost_update(ps, v, false, stream);
         return e == hipSuccess ? BS_OK : hip_fail(e, "ghost update");
     };
+    // extrapolated faces: their ghosts hold the negated adjacent values before
+    // the first sweep (each is read only by its own cell's block)
+    if (ghost_active(ps)) {
+        hipError_t e = ghost_update(ps, u, true, stream);
+        if (e != hipSuccess) return hip_fail(e, "ghost update");
+    }
     if (scheme == BS_JACOBI) {
         hipError_t e = launch_ghost_copy(u, work, pdd, ps->npatch, stream);
         if (e != hipSuccess) return hip_fail(e, "ghost copy");
@@ -426,7 +435,6 @@ bs_status bs_cube_prepare(bs_patchset *ps, int32_t bx, int32_t by, int32_t bz)
 {
     bs_status st = check_block(ps, bx, by, bz, "bs_cube_prepare");
     if (st != BS_OK) return st;
-    if (any_bc(ps)) return fail(BS_ERR_UNSUPPORTED, "bs_cube_prepare: cube blocks with extrapolated faces");
     const auto key = std::make_tuple(int(bx), int(by), int(bz));
     if (ps->cube.count(key)) return BS_OK;
     hipError_t e = hipSetDevice(ps->device);

@@ -160,6 +160,7 @@ bs_status bline_prepare(bs_patchset *ps, int axis)
     ps->bline_d[axis].swap(d);
     ps->bline_count[axis][0] = static_cast<int>(col[0].size());
     ps->bline_count[axis][1] = static_cast<int>(col[1].size());
+    ps->bline_maxlen[axis] = maxlen;
     ps->bline_ready[axis] = true;
     return BS_OK;
 }
@@ -181,7 +182,7 @@ bs_status bline_pass(bs_patchset *ps, int axis, int colour, const double *src, d
     a.first = colour == 1 ? n0 : 0;
     a.nitems = colour < 0 ? n0 + n1 : (colour == 0 ? n0 : n1);
     a.omega = omega;
-    hipError_t e = launch_bline(a, s);
+    hipError_t e = launch_bline(a, ps->bline_maxlen[axis], s);
     return e == hipSuccess ? BS_OK : hip_fail(e, "boundary line kernel");
 }
 

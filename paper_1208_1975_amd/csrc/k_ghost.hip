@@ -33,15 +33,79 @@ hipError_t launch_face_ops(double *u, const FaceOp *ops, const FaceItem *items, 
     return hipGetLastError();
 }
 
-// One thread per line.  The line's residual r = h^2 f - A u is formed from the
-// source with every extrapolated neighbour taken as the negated cell itself;
-// the line block tridiag(-eps_a, d_t, -eps_a) has d_t = 2(eps_x + eps_y +
-// eps_z) plus eps_b for every extrapolated face next to the line (its whole
-// length) and eps_a at an extrapolated end.  Thomas algorithm: the forward
-// elimination stores the reciprocal pivots and the eliminated right-hand side
-// in the scratch ([t][line], coalesced across the threads), the back
-// substitution reads them and writes dst = src + omega du.  In place (src ==
-// dst) every cell of the line is read before it is written.
+// Geometry of boundary line `line` along axis ax: first cell in u and f, the
+// strides along the line, its length, and the diagonal shift from the
+// extrapolated faces parallel to it.
+struct BLineGeo {
+    int64_t u0, f0, sa, fa, ub, uc;
+    int na;
+    double shift;
+    bool xb_lo, xb_hi, xc_lo, xc_hi, lo_a, hi_a;
+};
+
+__device__ __forceinline__ BLineGeo bline_geo(const PatchDesc *pd, const BLineItem &it, int ax)
+{
+    BLineGeo g;
+    const int b = ax == 0 ? 1 : 0, c = ax == 2 ? 1 : 2;   // the other axes, lower first
+    const int n[3] = {pd->n[0], pd->n[1], pd->n[2]};
+    const int64_t us[3] = {1, n[0] + 2, (int64_t)(n[0] + 2) * (n[1] + 2)};
+    const int64_t fs[3] = {1, n[0], (int64_t)n[0] * n[1]};
+    const int bc = pd->bc;
+    g.xb_lo = ((bc >> (2 * b)) & 1) && it.p == 0;
+    g.xb_hi = ((bc >> (2 * b + 1)) & 1) && it.p == n[b] - 1;
+    g.xc_lo = ((bc >> (2 * c)) & 1) && it.q == 0;
+    g.xc_hi = ((bc >> (2 * c + 1)) & 1) && it.q == n[c] - 1;
+    g.lo_a = (bc >> (2 * ax)) & 1;
+    g.hi_a = (bc >> (2 * ax + 1)) & 1;
+    g.shift = (g.xb_lo ? pd->eps[b] : 0.0) + (g.xb_hi ? pd->eps[b] : 0.0) + (g.xc_lo ? pd->eps[c] : 0.0) +
+              (g.xc_hi ? pd->eps[c] : 0.0);
+    g.u0 = pd->uoff + us[0] + us[1] + us[2] + (int64_t)it.p * us[b] + (int64_t)it.q * us[c];
+    g.f0 = pd->foff + (int64_t)it.p * fs[b] + (int64_t)it.q * fs[c];
+    g.sa = us[ax];
+    g.fa = fs[ax];
+    g.ub = us[b];
+    g.uc = us[c];
+    g.na = n[ax];
+    return g;
+}
+
+// Residuals of the boundary lines, one thread per cell (thread i: cell
+// t = i / nitems of line first + i % nitems), into scratch row 2t + 1: the
+// line's residual r = h^2 f - A u from the source, with every extrapolated
+// neighbour taken as the negated cell itself.
+__global__ void __launch_bounds__(256) k_bline_resid(BLineArgs a, int maxlen)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)a.nitems * maxlen) return;
+    const int l = (int)(i % a.nitems), t = (int)(i / a.nitems);
+    const int line = a.first + l;
+    const BLineItem it = a.items[line];
+    const PatchDesc *pd = a.pd + it.patch;
+    const int ax = a.axis;
+    const BLineGeo g = bline_geo(pd, it, ax);
+    if (t >= g.na) return;
+    const double *src = a.src;
+    const int b = ax == 0 ? 1 : 0, c = ax == 2 ? 1 : 2;
+    const double ea = pd->eps[ax], eb = pd->eps[b], ec = pd->eps[c];
+    const double d = 2.0 * (pd->eps[0] + pd->eps[1] + pd->eps[2]);
+    const int64_t cu = g.u0 + (int64_t)t * g.sa;
+    const double uc = src[cu];
+    const double lo = (t == 0 && g.lo_a) ? -uc : src[cu - g.sa];
+    const double hi = (t == g.na - 1 && g.hi_a) ? -uc : src[cu + g.sa];
+    const double bl = g.xb_lo ? -uc : src[cu - g.ub], bh = g.xb_hi ? -uc : src[cu + g.ub];
+    const double cl = g.xc_lo ? -uc : src[cu - g.uc], ch = g.xc_hi ? -uc : src[cu + g.uc];
+    const double nb = fma(ea, lo + hi, fma(eb, bl + bh, ec * (cl + ch)));
+    a.scratch[(int64_t)(2 * t + 1) * a.nlines + line] = fma(-d, uc, fma(pd->h2, a.f[g.f0 + (int64_t)t * g.fa], nb));
+}
+
+// One thread per line: the Thomas algorithm on the line block
+// tridiag(-eps_a, d_t, -eps_a), d_t = 2(eps_x + eps_y + eps_z) plus eps_b for
+// every extrapolated face next to the line (its whole length) and eps_a at an
+// extrapolated end, with pivots formed on the fly.  The forward elimination
+// overwrites the residual (row 2t + 1) with the eliminated right-hand side
+// and stores the reciprocal pivot in row 2t; the back substitution writes
+// dst = src + omega du.  In place (src == dst) every cell of the line is read
+// before it is written.
 __global__ void __launch_bounds__(256) k_bline(BLineArgs a)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -50,71 +114,39 @@ __global__ void __launch_bounds__(256) k_bline(BLineArgs a)
     const BLineItem it = a.items[line];
     const PatchDesc *pd = a.pd + it.patch;
     const int ax = a.axis;
-    const int b = ax == 0 ? 1 : 0, c = ax == 2 ? 1 : 2;   // the other axes, lower first
-    const int n[3] = {pd->n[0], pd->n[1], pd->n[2]};
-    const int64_t us[3] = {1, n[0] + 2, (int64_t)(n[0] + 2) * (n[1] + 2)};
-    const int64_t fs[3] = {1, n[0], (int64_t)n[0] * n[1]};
-    const int bc = pd->bc;
-    const double e[3] = {pd->eps[0], pd->eps[1], pd->eps[2]};
-    const double ea = e[ax];
-    const double d = 2.0 * (e[0] + e[1] + e[2]);
-    double shift = 0.0;
-    if (((bc >> (2 * b)) & 1) && it.p == 0) shift += e[b];
-    if (((bc >> (2 * b + 1)) & 1) && it.p == n[b] - 1) shift += e[b];
-    if (((bc >> (2 * c)) & 1) && it.q == 0) shift += e[c];
-    if (((bc >> (2 * c + 1)) & 1) && it.q == n[c] - 1) shift += e[c];
-    const bool lo_a = (bc >> (2 * ax)) & 1, hi_a = (bc >> (2 * ax + 1)) & 1;
-    // the line's first cell in u and f
-    const int64_t u0 = pd->uoff + us[0] + us[1] + us[2] + (int64_t)it.p * us[b] + (int64_t)it.q * us[c];
-    const int64_t f0 = pd->foff + (int64_t)it.p * fs[b] + (int64_t)it.q * fs[c];
-    const int64_t sa = us[ax], fa = fs[ax];
-    // off-line neighbours: +-1 along b and c, extrapolated ones replaced by -u
-    const bool xb_lo = ((bc >> (2 * b)) & 1) && it.p == 0, xb_hi = ((bc >> (2 * b + 1)) & 1) && it.p == n[b] - 1;
-    const bool xc_lo = ((bc >> (2 * c)) & 1) && it.q == 0, xc_hi = ((bc >> (2 * c + 1)) & 1) && it.q == n[c] - 1;
-    const int na = n[ax];
-    const double *src = a.src;
-    const double h2 = pd->h2;
-    // scratch row 2t: reciprocal pivot of cell t, row 2t + 1: eliminated rhs
-    double uprev = 0.0, ucur = src[u0], mprev = 1.0, zprev = 0.0;
+    const BLineGeo g = bline_geo(pd, it, ax);
+    const double ea = pd->eps[ax];
+    const double dd = 2.0 * (pd->eps[0] + pd->eps[1] + pd->eps[2]) + g.shift;
+    const int na = g.na;
+    double *sc = a.scratch + line;
+    const int64_t L = a.nlines;
+    double mprev = 1.0, zprev = 0.0;
     for (int t = 0; t < na; ++t) {
-        const int64_t cu = u0 + (int64_t)t * sa;
-        const double unext = t + 1 < na ? src[cu + sa] : 0.0;
-        const double lo = t == 0 ? (lo_a ? -ucur : src[cu - sa]) : uprev;
-        const double hi = t == na - 1 ? (hi_a ? -ucur : src[cu + sa]) : unext;
-        const double bl = xb_lo ? -ucur : src[cu - us[b]], bh = xb_hi ? -ucur : src[cu + us[b]];
-        const double cl = xc_lo ? -ucur : src[cu - us[c]], ch = xc_hi ? -ucur : src[cu + us[c]];
-        const double nb = ea * (lo + hi) + e[b] * (bl + bh) + e[c] * (cl + ch);
-        const double r = fma(-d, ucur, fma(h2, a.f[f0 + (int64_t)t * fa], nb));
-        const double dt = d + shift + (t == 0 && lo_a ? ea : 0.0) + (t == na - 1 && hi_a ? ea : 0.0);
-        double m, z;
-        if (t == 0) {
-            m = dt;
-            z = r;
-        } else {
-            const double g = ea / mprev;
-            m = dt - ea * g;
-            z = fma(g, zprev, r);
-        }
-        a.scratch[(int64_t)(2 * t) * a.nlines + line] = 1.0 / m;
-        a.scratch[(int64_t)(2 * t + 1) * a.nlines + line] = z;
+        const double r = sc[(int64_t)(2 * t + 1) * L];
+        const double dt = dd + (t == 0 && g.lo_a ? ea : 0.0) + (t == na - 1 && g.hi_a ? ea : 0.0);
+        const double gm = t == 0 ? 0.0 : ea / mprev;
+        const double m = fma(-ea, gm, dt);
+        const double z = fma(gm, zprev, r);
+        sc[(int64_t)(2 * t) * L] = 1.0 / m;
+        sc[(int64_t)(2 * t + 1) * L] = z;
         mprev = m;
         zprev = z;
-        uprev = ucur;
-        ucur = unext;
     }
     double du = 0.0;
     for (int t = na - 1; t >= 0; --t) {
-        const double q = a.scratch[(int64_t)(2 * t) * a.nlines + line];
-        const double z = a.scratch[(int64_t)(2 * t + 1) * a.nlines + line];
+        const double q = sc[(int64_t)(2 * t) * L];
+        const double z = sc[(int64_t)(2 * t + 1) * L];
         du = (t == na - 1 ? z : fma(ea, du, z)) * q;
-        const int64_t cu = u0 + (int64_t)t * sa;
-        a.dst[cu] = fma(a.omega, du, src[cu]);
+        const int64_t cu = g.u0 + (int64_t)t * g.sa;
+        a.dst[cu] = fma(a.omega, du, a.src[cu]);
     }
 }
 
-hipError_t launch_bline(const BLineArgs &a, hipStream_t s)
+hipError_t launch_bline(const BLineArgs &a, int maxlen, hipStream_t s)
 {
     if (a.nitems <= 0) return hipSuccess;
+    const int64_t cells = (int64_t)a.nitems * maxlen;
+    hipLaunchKernelGGL(k_bline_resid, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, a, maxlen);
     hipLaunchKernelGGL(k_bline, dim3((a.nitems + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }

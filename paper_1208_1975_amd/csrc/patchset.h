@@ -143,6 +143,7 @@ struct bs_patchset {
     bool bline_ready[3] = {false, false, false};
     bs::DevBuf bline_d[3];
     int bline_count[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // colour 0 items, then colour 1
+    int bline_maxlen[3] = {0, 0, 0};                     // longest such line per axis
     bs::DevBuf bline_scratch;
     hipStream_t capture_stream = nullptr;
     uint64_t gen = 0;   // bumped whenever device tables or captured graphs are replaced

@@ -273,9 +273,6 @@ def test_bc_and_links_errors():
     ps.set_links([])
     ps.set_bc([63] * ls.npatch)
     u, f, w = ps.pack_u(ls.u0), ps.pack_f(ls.f), ps.empty_u()
-    with pytest.raises(bs.BSError) as ei:
-        ps.cube_prepare((2, 2, 2))
-    assert ei.value.status == bs.BS_ERR_UNSUPPORTED
     ws = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(bs.BSError) as ei:
         bs.bs_relax_backward(ps.handle, 2, 0.8, 2, 1, u, f, u, None, None, None, ws)
@@ -324,3 +321,30 @@ def test_plane_bc_fixed_point_and_mixed_refused():
         ps.plane_relax(2, "jacobi", 1.0, 1, ps.pack_u([p.u0]), ps.pack_f([f]), ps.empty_u(), prec="fp32")
     assert ei.value.status == bs.BS_ERR_UNSUPPORTED
     ps.close()
+
+
+CUBE_CASES = [((9, 7, 6), (4, 4, 4)), ((8, 8, 8), (2, 2, 2)), ((10, 6, 7), (3, 5, 2)), ((12, 12, 10), (8, 8, 4)),
+              ((5, 9, 11), (8, 8, 8)), ((16, 4, 9), (4, 2, 2))]
+
+
+@pytest.mark.parametrize("dims,block", CUBE_CASES)
+@pytest.mark.parametrize("bc", [63, 3, 1 | 8 | 32, 2 | 4 | 16, 48])
+def test_cube_bc_parity(dims, block, bc):
+    """Cube blocks with extrapolated faces: the blocks touching such a face get
+    the inverse of their raised block matrix (one-sided or DST-II factors
+    along the touching axes); fused (<= 64 cells) and two-kernel forms."""
+    p = small_patch(*dims, seed=61, eps=(1.0, 3.0, 7.0))
+    for scheme in ("jacobi", "colored", "chaotic"):
+        omega = 0.8 if scheme == "jacobi" else 1.0
+        for nsweeps in (1, 2):
+            log("cube bc=%d %s %s %s %d" % (bc, dims, block, scheme, nsweeps))
+            ps, u, f, w = _single(p, bc)
+            ps.cube_prepare(block)
+            ps.cube_relax(block, scheme, omega, nsweeps, u, f, w)
+            torch.cuda.synchronize()
+            got = ps.view_u(u, 0).cpu().numpy()
+            ref = oracle.cube_sweeps(p.u0, p.f, p.eps, p.h, block, OSCH[scheme], omega, nsweeps, bc=bc)
+            err = relerr(got[1:-1, 1:-1, 1:-1], ref[1:-1, 1:-1, 1:-1])
+            assert err < TOL, (scheme, nsweeps, err)
+            _check_ghosts(got, p.u0, bc)
+            ps.close()
