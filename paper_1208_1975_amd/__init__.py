@@ -74,6 +74,10 @@ def lib():
     L.bsi_set_xline_cfg.restype = ctypes.c_int
     L.bsi_set_xz_cfg.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.bsi_set_xz_cfg.restype = ctypes.c_int
+    L.bsi_set_pair.argtypes = [vp, ctypes.c_int]
+    L.bsi_set_pair.restype = ctypes.c_int
+    L.bsi_set_chaotic_chunk.argtypes = [vp, ctypes.c_int]
+    L.bsi_set_chaotic_chunk.restype = ctypes.c_int
     L.bsi_set_graphs.argtypes = [vp, ctypes.c_int]
     L.bsi_set_graphs.restype = ctypes.c_int
     L.bsi_line_relax_per_patch.argtypes = [vp, i32, ctypes.c_int, dbl, i32, vp, vp, vp, vp]
@@ -425,6 +429,15 @@ class PatchSet:
         """z-marching x-line kernel (x-lines of up to 64 cells, items of rows by
         `planes` planes marched along z; 0 = the default) for Jacobi or chaotic GS."""
         _check(lib().bsi_set_xz_cfg(self.handle, _scheme(scheme), int(waves), int(planes), int(grid)))
+
+    def set_pair(self, enable):
+        """Chaotic GS on y/z lines with omega 1: two x-cells per lane (True, the
+        default) or one line per lane with the in-tile correction solve."""
+        _check(lib().bsi_set_pair(self.handle, 1 if enable else 0))
+
+    def set_chaotic_chunk(self, tiles):
+        """Tiles per even/odd chunk of the one-launch chaotic order (0: default)."""
+        _check(lib().bsi_set_chaotic_chunk(self.handle, int(tiles)))
 
     def set_graphs(self, enable):
         _check(lib().bsi_set_graphs(self.handle, 1 if enable else 0))

@@ -100,6 +100,11 @@ hipError_t launch_line_xr(const LineArgs &a, int grid, int nwaves, hipStream_t s
 // x-lines of up to 64 cells marched along z: items of rows x planes (a.tx =
 // planes per item); colour_mode 0 (Jacobi) or 2 (chaotic GS).
 hipError_t launch_line_xz(const LineArgs &a, int grid, int nwaves, hipStream_t s);
+// Chaotic GS on y/z lines with omega = 1, two x-cells per lane (colour-0 lines,
+// then colour-1 lines, one solve each); items of 128 x-cells by one row.
+hipError_t launch_line_pair(const LineArgs &a, int grid, int Lmax, int nwaves, hipStream_t s);
+hipError_t prepare_pair_kernels();
+size_t pair_lds_bytes(int Lmax, int nwaves);
 int line_xz_occupancy(int nwaves, int cm, int f32);
 // Rows of one z-marching x-line item.
 __host__ __device__ inline int xz_item_rows(int nx, int nwaves) { return nwaves * 4 * (16 / ((nx + 3) >> 2)); }

@@ -148,5 +148,6 @@ struct bs_patchset {
     hipStream_t capture_stream = nullptr;
     uint64_t gen = 0;   // bumped whenever device tables or captured graphs are replaced
     bool use_graphs = true;
+    bool use_pair = true;   // chaotic y/z lines with omega 1: the two-cells-per-lane kernel
     ~bs_patchset();
 };

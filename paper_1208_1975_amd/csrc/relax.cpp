@@ -39,6 +39,7 @@ int tiles_of(const bs_patchset *ps, int p, int kind, int axis, int tx, int colou
         const int R = xz_item_rows(nx, nw);
         return ((ny + R - 1) / R) * ((nz + tx - 1) / tx);
     }
+    if (kind == 3) return ((nx + 127) / 128) * (axis == 2 ? ny : nz);   // 128 x-cells by one row
     if (kind == 1) {
         const int64_t rows = static_cast<int64_t>(colour_mode == 1 ? (ny + 1) / 2 : ny) * nz;
         return static_cast<int>((rows + 63) / 64);
@@ -380,16 +381,24 @@ bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c)
 // colour_mode 1 with run = 0 / 1 = that colour only, run = 2 = both colours in
 // one launch, colour 0 dispatched first (chaotic).  patch >= 0 restricts the
 // pass to one patch's items (one launch per patch and run).
+bool pair_for(const bs_patchset *ps, int axis, const LineCfg &c, double omega, int f32)
+{
+    return axis != 0 && ps->use_pair && omega == 1.0 && !f32 && c.form == 0 && c.Lmax <= 16 && !bline_any(ps, axis);
+}
+
 bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
                     double *dst, const double *f, double omega, hipStream_t stream, int patch, int rhs_mode,
                     int out_mode, int f32)
 {
-    const int kind = axis == 0 ? (c.form == 2 ? 2 : 1) : 0;
+    // chaotic GS on y/z lines with omega = 1: two cells per lane (kind 3)
+    const bool pair = colour_mode == 2 && !rhs_mode && !out_mode && pair_for(ps, axis, c, omega, f32);
+    const int kind = pair ? 3 : (axis == 0 ? (c.form == 2 ? 2 : 1) : 0);
     if (kind == 2 && colour_mode == 1)
         return fail(BS_ERR_INVALID, "line pass: z-marching x-lines run Jacobi or chaotic GS only");
     WorkList *wl = nullptr;
-    bs_status st = get_worklist(ps, kind, axis, kind == 2 ? c.nwaves : c.popt, kind == 2 ? c.zc : c.tx, colour_mode,
-                                &wl, (colour_mode == 2 && kind != 2) ? chaotic_chunk_for(ps, axis, c) : 0);
+    bs_status st = get_worklist(ps, kind, axis, kind == 2 ? c.nwaves : c.popt,
+                                kind == 2 ? c.zc : (kind == 3 ? 128 : c.tx), colour_mode, &wl,
+                                (colour_mode == 2 && kind != 2) ? chaotic_chunk_for(ps, axis, c) : 0);
     if (st != BS_OK) return st;
     LineArgs a{};
     a.src = src;
@@ -417,7 +426,8 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
         a.items = base + first;
         a.nitems = count;
         const int grid = c.grid > 0 ? std::min(count, c.grid) : count;
-        hipError_t e = c.form == 2  ? launch_line_xz(a, grid, c.nwaves, stream)
+        hipError_t e = pair         ? launch_line_pair(a, grid, c.Lmax, c.nwaves, stream)
+                       : c.form == 2  ? launch_line_xz(a, grid, c.nwaves, stream)
                        : c.form == 1  ? launch_line_xr(a, grid, c.nwaves, stream)
                        : axis == 0  ? launch_line_x(a, grid, c.Lmax, c.nwaves, lds, stream)
                                     : launch_line_strided(a, grid, c.Lmax, c.nwaves, lds, stream);
@@ -662,6 +672,11 @@ bs_status line_relax_impl(bs_patchset *ps, int32_t axis, bs_scheme scheme, doubl
     hipError_t e = prepare_line_kernels();
     if (e != hipSuccess) return hip_fail(e, "line kernel attributes");
     const int f32 = prec == BS_MIXED_FP32 ? 1 : 0;
+    if (cm == 2 && !chaotic_colour_major(ps, axis, c) && pair_for(ps, axis, c, omega, f32)) {
+        WorkList *wl;
+        if ((st = get_worklist(ps, 3, axis, c.popt, 128, 2, &wl, chaotic_chunk_for(ps, axis, c))) != BS_OK) return st;
+        if ((e = prepare_pair_kernels()) != hipSuccess) return hip_fail(e, "line kernel attributes");
+    }
     if (!allow_graph || !ps->use_graphs || nsweeps < 2)
         return enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, stream, false, f32);
 
@@ -916,6 +931,16 @@ int bsi_set_chaotic_chunk(bs_patchset *ps, int tiles)
     return BS_OK;
 }
 
+// Enable (1) or disable (0) the two-cells-per-lane chaotic kernel for y/z
+// lines with omega 1 (disabled: the one-line-per-lane in-tile two-colour form).
+int bsi_set_pair(bs_patchset *ps, int enable)
+{
+    if (!ps) return BS_ERR_INVALID;
+    ps->use_pair = enable != 0;
+    clear_graphs(ps);
+    return BS_OK;
+}
+
 // Enable (1) or disable (0) graph capture of sweep sequences.
 int bsi_set_graphs(bs_patchset *ps, int enable)
 {
@@ -939,6 +964,7 @@ int bsi_line_relax_per_patch(bs_patchset *ps, int32_t axis, bs_scheme scheme, do
     if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;
     if (bline_any(ps, axis) && (st = bline_prepare(ps, axis)) != BS_OK) return st;
     if (prepare_line_kernels() != hipSuccess) return BS_ERR_HIP;
+    if (prepare_pair_kernels() != hipSuccess) return BS_ERR_HIP;
     return enqueue_line_sweeps(ps, axis, scheme, c, omega, nsweeps, u, f, work, stream, true);
 }
 
