@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--profile-c4", action="store_true",
                     help="fixed batched sequence for rocprofv3 (3000 AMR patches: 1 GiB copy, 3 x-line chaotic GS sweeps)")
     ap.add_argument("--profile-planes", action="store_true",
-                    help="fixed plane-sweep sequence for rocprofv3 (512^3: FP64, FP32, BF16 refine 1; 2 sweeps each)")
+                    help="fixed plane-sweep sequence for rocprofv3 (512^3: FP64, FP32, BF16 refine 1 and 2; 2 sweeps each)")
     ap.add_argument("--cubes", action="store_true",
                     help="only the cube-block timings (64 patches of 64^3), printed as JSON")
     ap.add_argument("--profile-cubes", action="store_true",
@@ -112,7 +112,7 @@ def profile_c4_run():
 
 def profile_planes_run():
     """Fixed plane-sweep sequence for kernel traces: 512^3 xy-plane Jacobi,
-    two sweeps in each precision."""
+    two sweeps each in FP64, FP32 (refine 0) and BF16 (refine 1 and 2)."""
     import torch
 
     import paper_1208_1975_amd as bs
@@ -124,7 +124,7 @@ def profile_planes_run():
     f = ps.pack_f([p.f])
     u0 = ps.pack_u([p.u0])
     w = ps.empty_u()
-    for prec, refine in (("fp64", 0), ("fp32", 0), ("bf16", 1)):
+    for prec, refine in (("fp64", 0), ("fp32", 0), ("bf16", 1), ("bf16", 2)):
         u = u0.clone()
         ps.plane_relax(2, "jacobi", 1.0, 2, u, f, w, prec=prec, refine=refine)
         torch.cuda.synchronize()
@@ -159,17 +159,19 @@ def profile_cubes_run():
 def measured_traffic():
     """HBM bytes per launch of the z-line sweep kernel from the committed
     counter summary (FETCH_SIZE / WRITE_SIZE, scaled by a copy of known size),
-    used only while the kernel source is the one the counters were taken on."""
+    used only while the kernel sources are the ones the counters were taken on
+    (SHA-256 of the listed files, concatenated in order)."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    src = os.path.join(here, "paper_1208_1975_amd", "csrc", "k_line.hip")
     prof = os.path.join(here, "profiles", "zline_256cube_hbm_counters.md")
     try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
         for ln in open(prof):
             if ln.startswith("traffic-json: "):
                 t = json.loads(ln[len("traffic-json: "):])
-                return t if t.get("source_sha256") == sha else None
+                h = hashlib.sha256()
+                for rel in t.get("sources", []):
+                    h.update(open(os.path.join(here, rel), "rb").read())
+                return t if t.get("sources") and t.get("source_sha256") == h.hexdigest() else None
     except OSError:
         return None
     return None

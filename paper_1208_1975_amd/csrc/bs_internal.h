@@ -90,6 +90,7 @@ struct ResidArgs {
     const ResidTile *tiles;
     float *e32;                   // optional FP32 copy of r (f layout), may be null
     unsigned short *e16;          // optional BF16 copy of r (bit patterns), may be null
+    float *r32;                   // optional FP32 r (f layout; the BF16 plane defect's input), may be null
 };
 
 // Host launchers (defined in the .hip files).

@@ -44,11 +44,14 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) double As[2][BK][BM + 2];
     __shared__ __attribute__((aligned(16))) double Bs[2][BK][BN + 2];
-    const int b = blockIdx.z;
-    // tiles of one product map XCD-contiguously, column tiles of a row tile
-    // together: the workgroups that read the same rows of A share an L2
-    const int tile = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const int m0 = (tile / gridDim.x) * BM, n0 = (tile % gridDim.x) * BN;
+    // tiles numbered n fastest, then m, then the batch, each XCD taking a
+    // contiguous range: the column tiles that read the same rows of A run
+    // together on one XCD and share its L2
+    const int nt = (g.N + BN - 1) / BN, mt = (g.M + BM - 1) / BM;
+    const int t = xcd_block(blockIdx.x, gridDim.x);
+    const int tn = t % nt, tr = t / nt;
+    const int b = tr / mt;
+    const int m0 = (tr - b * mt) * BM, n0 = tn * BN;
     const double *A = g.A + (int64_t)b * g.sA;
     const double *B = g.B + (int64_t)b * g.sB;
     const int tid = threadIdx.x;
@@ -223,7 +226,7 @@ __global__ void __launch_bounds__(kThreads) k_gemm_f64(GemmArgs g)
 template <int BT, int FOLD, bool VEC>
 static hipError_t launch_f64_v(const GemmArgs &g, int epi, hipStream_t s)
 {
-    const dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
+    const dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM) * g.batch));
     switch (epi) {
     case kEpiStore: hipLaunchKernelGGL((k_gemm_f64<kEpiStore, BT, FOLD, VEC>), grid, dim3(kThreads), 0, s, g); break;
     case kEpiScale: hipLaunchKernelGGL((k_gemm_f64<kEpiScale, BT, FOLD, VEC>), grid, dim3(kThreads), 0, s, g); break;

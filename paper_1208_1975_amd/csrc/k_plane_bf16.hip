@@ -16,6 +16,12 @@
 // transposed) or as [k][n] (a field), which is transposed on its way into
 // LDS.  The store epilogues can write C^T, so that the next product finds its
 // field operand k-contiguous.
+//
+// The tiles of a launch are numbered n fastest, then m, then the batch, and
+// each XCD takes a contiguous range of that numbering (xcd_block), so the
+// column tiles that share one A row block run together on one XCD and read it
+// once into that XCD's L2 (in the hardware's own order each of them sat on a
+// different XCD and fetched the block again from memory).
 #include <cstdint>
 
 #include "bs_internal.h"
@@ -50,8 +56,11 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
 {
     __shared__ __attribute__((aligned(16))) u16 As[2][TM * PK];
     __shared__ __attribute__((aligned(16))) u16 Bs[2][TN * PK];
-    const int b = blockIdx.z;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int nt = (g.N + TN - 1) / TN, mt = (g.M + TM - 1) / TM;
+    const int t = xcd_block(blockIdx.x, gridDim.x);
+    const int tn = t % nt, tr = t / nt;
+    const int b = tr / mt;
+    const int m0 = (tr - b * mt) * TM, n0 = tn * TN;
     const u16 *A = g.A + (int64_t)b * g.sA;
     const u16 *B = g.B + (int64_t)b * g.sB;
     const int tid = threadIdx.x;
@@ -190,17 +199,19 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
             }
         return;
     }
-    // The four outputs of a lane in one 16 x 16 block at a time: every value
-    // they read (scale, D, u) is loaded before any of their stores, so those
-    // loads are in flight together instead of one round trip per element.
+    // The outputs of a lane in JG 16 x 16 blocks at a time (a whole block row
+    // for the epilogues that read FP64 memory): every value they read (scale,
+    // D, u) is loaded before any of their stores, so those loads are in flight
+    // together instead of one round trip per element or per block.
+    constexpr int JG = (EPI == kEpiD64 || EPI == kEpiUpdate || EPI == kEpiUpdateAcc) ? 4 : 1;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int jh = 0; jh < 4; ++jh) {
-            double in1[1][4], in2[1][4];
-            bool ok[1][4];
+        for (int jh = 0; jh < 4; jh += JG) {
+            double in1[JG][4], in2[JG][4];
+            bool ok[JG][4];
 #pragma unroll
-            for (int jj = 0; jj < 1; ++jj)
+            for (int jj = 0; jj < JG; ++jj)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = m0 + wm * 64 + i * 16 + 4 * lk + r;
@@ -215,12 +226,12 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
                     in2[jj][r] = 0.0;
                     if (EPI == kEpiScale)
                         in1[jj][r] = g.scale[(int64_t)b * g.sc_b + (int64_t)rr * g.sc_m + (int64_t)cc * g.sc_n];
-                    if (EPI == kEpiUpdateAcc || (EPI == kEpiD64 && g.accumulate)) in1[jj][r] = g.D[ci];
+                    if (EPI == kEpiUpdateAcc || (EPI == kEpiD64 && g.accumulate)) in1[jj][r] = (double)g.D[ci];
                     if (EPI == kEpiUpdate || EPI == kEpiUpdateAcc)
                         in2[jj][r] = g.usrc[g.u0 + (int64_t)b * g.u_b + (int64_t)rr * g.u_m + (int64_t)cc * g.u_n];
                 }
 #pragma unroll
-            for (int jj = 0; jj < 1; ++jj)
+            for (int jj = 0; jj < JG; ++jj)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     if (!ok[jj][r]) continue;
@@ -233,7 +244,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
                     } else if (EPI == kEpiScale) {
                         g.C[ci] = to_bf16(v * static_cast<float>(in1[jj][r]));
                     } else if (EPI == kEpiD64) {
-                        g.D[ci] = g.accumulate ? in1[jj][r] + (double)v : (double)v;
+                        g.D[ci] = g.accumulate ? (float)(in1[jj][r] + (double)v) : v;
                     } else {
                         const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
                         const double du = EPI == kEpiUpdateAcc ? in1[jj][r] + (double)v : (double)v;
@@ -246,7 +257,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
 template <int BT, bool VEC>
 static hipError_t launch_bf16_v(const GemmBf16Args &g, int epi, hipStream_t s)
 {
-    const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, g.batch);
+    const dim3 grid((unsigned)(((g.N + TN - 1) / TN) * ((g.M + TM - 1) / TM) * g.batch));
     switch (epi) {
     case kEpiStore: hipLaunchKernelGGL((k_gemm_bf16<kEpiStore, BT, VEC>), grid, dim3(256), 0, s, g); break;
     case kEpiScale: hipLaunchKernelGGL((k_gemm_bf16<kEpiScale, BT, VEC>), grid, dim3(256), 0, s, g); break;

@@ -33,8 +33,14 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
 {
     __shared__ __attribute__((aligned(16))) float As[2][BK][BM + 4];
     __shared__ __attribute__((aligned(16))) float Bs[2][BK][BN + 4];
-    const int b = blockIdx.z;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    // tiles numbered n fastest, then m, then the batch, each XCD taking a
+    // contiguous range: the column tiles that read the same rows of A share
+    // one XCD's L2
+    const int nt = (g.N + BN - 1) / BN, mt = (g.M + BM - 1) / BM;
+    const int t = xcd_block(blockIdx.x, gridDim.x);
+    const int tn = t % nt, tr = t / nt;
+    const int b = tr / mt;
+    const int m0 = (tr - b * mt) * BM, n0 = tn * BN;
     const float *A = g.A + (int64_t)b * g.sA;
     const float *B = g.B + (int64_t)b * g.sB;
     const int tid = threadIdx.x;
@@ -177,41 +183,68 @@ __device__ __forceinline__ void put_lowp(unsigned short *E, int64_t c, double v)
 }
 
 // E = low-precision (R - M_P D) on every cell of one patch (D may be null:
-// E = R), M_P the plane block with normal c: d D - eps_a (in-plane neighbours
-// along a) - eps_b (along b), zero beyond the plane's edges.  T: float, or
-// unsigned short holding BF16 (rounded from FP64 directly).
-template <typename T>
-__global__ void __launch_bounds__(256) k_plane_defect(const double *R, const double *D, T *E, int nx, int ny,
-                                                      int nz, int normal, double ex, double ey, double ez)
+// E = R), M_P the plane block with normal NORMAL: d D - eps_a (in-plane
+// neighbours along a) - eps_b (along b), zero beyond the plane's edges,
+// formed in FP64 from R and D stored as S (double, or float for the BF16
+// chain).  T: float, or unsigned short holding BF16 (rounded from FP64
+// directly).  One thread per cell; the neighbour loads are unconditional
+// (clamped addresses, zero weights beyond the plane's edges), so they are all
+// in flight together.
+template <typename S, typename T, int NORMAL>
+__global__ void __launch_bounds__(256) k_plane_defect(const S *R, const S *D, T *E, int nx, int ny, int nz,
+                                                      double ex, double ey, double ez, double rnx, double rny)
 {
     const int n = nx * ny * nz;   // < 2^31: patches are below 4 GiB
-    const double d = 2.0 * (ex + ey + ez);
-    const double rnx = 1.0 / nx, rny = 1.0 / ny;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-        double v = R[c];
-        if (D) {
-            const int jk = div_rd(c, nx, rnx);
-            const int i = c - jk * nx;
-            const int k = div_rd(jk, ny, rny);
-            const int j = jk - k * ny;
-            double md = d * D[c];
-            if (normal != 0) {
-                if (i > 0) md -= ex * D[c - 1];
-                if (i < nx - 1) md -= ex * D[c + 1];
-            }
-            if (normal != 1) {
-                if (j > 0) md -= ey * D[c - nx];
-                if (j < ny - 1) md -= ey * D[c + nx];
-            }
-            if (normal != 2) {
-                const int64_t pl = (int64_t)nx * ny;
-                if (k > 0) md -= ez * D[c - pl];
-                if (k < nz - 1) md -= ez * D[c + pl];
-            }
-            v -= md;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= n) return;
+    double v = (double)R[c];
+    if (D) {
+        const int jk = div_rd(c, nx, rnx);
+        const int i = c - jk * nx;
+        const int k = div_rd(jk, ny, rny);
+        const int j = jk - k * ny;
+        const int64_t pl = (int64_t)nx * ny;
+        double md = 2.0 * (ex + ey + ez) * (double)D[c];
+        if (NORMAL != 0) {
+            const double a = (double)D[i > 0 ? c - 1 : c], b = (double)D[i < nx - 1 ? c + 1 : c];
+            md -= (i > 0 ? ex : 0.0) * a + (i < nx - 1 ? ex : 0.0) * b;
         }
-        put_lowp(E, c, v);
+        if (NORMAL != 1) {
+            const double a = (double)D[j > 0 ? c - nx : c], b = (double)D[j < ny - 1 ? c + nx : c];
+            md -= (j > 0 ? ey : 0.0) * a + (j < ny - 1 ? ey : 0.0) * b;
+        }
+        if (NORMAL != 2) {
+            const double a = (double)D[k > 0 ? c - pl : c], b = (double)D[k < nz - 1 ? c + pl : c];
+            md -= (k > 0 ? ez : 0.0) * a + (k < nz - 1 ? ez : 0.0) * b;
+        }
+        v -= md;
     }
+    put_lowp(E, c, v);
+}
+
+template <typename S, typename T>
+static hipError_t launch_defect(const S *R, const S *D, T *E, int nx, int ny, int nz, int normal, const double eps[3],
+                                hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    const double rnx = 1.0 / nx, rny = 1.0 / ny;
+    switch (normal) {
+    case 0:
+        hipLaunchKernelGGL((k_plane_defect<S, T, 0>), grid, dim3(256), 0, s, R, D, E, nx, ny, nz, eps[0], eps[1],
+                           eps[2], rnx, rny);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_plane_defect<S, T, 1>), grid, dim3(256), 0, s, R, D, E, nx, ny, nz, eps[0], eps[1],
+                           eps[2], rnx, rny);
+        break;
+    default:
+        hipLaunchKernelGGL((k_plane_defect<S, T, 2>), grid, dim3(256), 0, s, R, D, E, nx, ny, nz, eps[0], eps[1],
+                           eps[2], rnx, rny);
+        break;
+    }
+    return hipGetLastError();
 }
 
 template <bool VEC>
@@ -232,7 +265,7 @@ hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStrea
 {
     if (prec != 1) return hipErrorInvalidValue;
     if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
-    const dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
+    const dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM) * g.batch));
     const bool vec = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0) &&
                      g.lda % 4 == 0 && g.ldb % 4 == 0 && g.sA % 4 == 0 && g.sB % 4 == 0 && g.K % 4 == 0 &&
                      g.N % 4 == 0;
@@ -242,21 +275,13 @@ hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStrea
 hipError_t launch_plane_defect(const double *R, const double *D, float *E, int nx, int ny, int nz, int normal,
                                const double eps[3], hipStream_t s)
 {
-    const int64_t n = (int64_t)nx * ny * nz;
-    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_plane_defect<float>, dim3(blocks), dim3(256), 0, s, R, D, E, nx, ny, nz, normal, eps[0],
-                       eps[1], eps[2]);
-    return hipGetLastError();
+    return launch_defect(R, D, E, nx, ny, nz, normal, eps, s);
 }
 
-hipError_t launch_plane_defect_bf16(const double *R, const double *D, unsigned short *E, int nx, int ny, int nz,
+hipError_t launch_plane_defect_bf16(const float *R, const float *D, unsigned short *E, int nx, int ny, int nz,
                                     int normal, const double eps[3], hipStream_t s)
 {
-    const int64_t n = (int64_t)nx * ny * nz;
-    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_plane_defect<unsigned short>, dim3(blocks), dim3(256), 0, s, R, D, E, nx, ny, nz, normal,
-                       eps[0], eps[1], eps[2]);
-    return hipGetLastError();
+    return launch_defect(R, D, E, nx, ny, nz, normal, eps, s);
 }
 
 }  // namespace bs

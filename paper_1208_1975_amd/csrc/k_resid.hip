@@ -85,6 +85,7 @@ __global__ void __launch_bounds__(kResidThreads) k_residual(ResidArgs a)
             const int64_t c = fo + (int64_t)k * pf;
             if (a.r) a.r[c] = r;
             if (a.e32) a.e32[c] = (float)r;
+            if (a.r32) a.r32[c] = (float)r;
             if (a.e16) a.e16[c] = __builtin_bit_cast(unsigned short, static_cast<__bf16>(r));
             acc = fma(r, r, acc);
         }

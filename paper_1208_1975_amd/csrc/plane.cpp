@@ -370,7 +370,7 @@ bs_status chain_bf16(bs_patchset *ps, int p, int c, int colour, int last_epi, in
     const float *tab32 = static_cast<const float *>(ps->plane_tab32_d.p);
     uint16_t *F1 = static_cast<uint16_t *>(ps->plane_f1_d.p) + ps->foff[p];
     uint16_t *F2 = static_cast<uint16_t *>(ps->plane_f2_d.p) + ps->foff[p];
-    double *D = static_cast<double *>(ps->plane_t_d.p) + ps->foff[p];
+    float *D = static_cast<float *>(ps->plane_t_d.p) + ps->foff[p];   // FP32 correction
     // Planes with x in-plane (normals y and z): the first two products store
     // their result transposed in a compact per-plane layout (plane b at
     // b*M*N, element (m, n) at n*M + m), so the second and third products
@@ -438,12 +438,16 @@ bs_status plane_pass(bs_patchset *ps, int c, int colour, int prec, int refine, c
         const double *R = static_cast<const double *>(ps->plane_r_d.p) + ps->foff[p];
         double *D = static_cast<double *>(ps->plane_t_d.p) + ps->foff[p];
         float *F1 = static_cast<float *>(ps->plane_f1_d.p) + ps->foff[p];
+        // the BF16 chain keeps R and D in FP32 (their rounding, 2^-24
+        // relative, is far below the BF16 solve's error after two defect steps)
+        const float *R32 = static_cast<const float *>(ps->plane_r_d.p) + ps->foff[p];
+        const float *D32 = static_cast<const float *>(ps->plane_t_d.p) + ps->foff[p];
         const double *eps = &ps->eps[3 * static_cast<size_t>(p)];
         const bool b16 = prec == BS_MIXED_BF16;
         uint16_t *E16 = static_cast<uint16_t *>(ps->plane_f1_d.p) + ps->foff[p];
-        auto defect = [&](const double *Dp) {
-            return b16 ? launch_plane_defect_bf16(R, Dp, E16, nx, ny, nz, c, eps, s)
-                       : launch_plane_defect(R, Dp, F1, nx, ny, nz, c, eps, s);
+        auto defect = [&]() {
+            return b16 ? launch_plane_defect_bf16(R32, D32, E16, nx, ny, nz, c, eps, s)
+                       : launch_plane_defect(R, D, F1, nx, ny, nz, c, eps, s);
         };
         auto chain = [&](int epi, int acc) {
             return b16 ? chain_bf16(ps, p, c, colour, epi, acc, src, dst, omega, s)
@@ -457,7 +461,7 @@ bs_status plane_pass(bs_patchset *ps, int c, int colour, int prec, int refine, c
         }
         if ((st = chain(kEpiD64, 0)) != BS_OK) return st;
         for (int j = 0; j < refine; ++j) {
-            hipError_t e = defect(D);
+            hipError_t e = defect();
             if (e != hipSuccess) return hip_fail(e, "plane defect");
             // the last defect step updates u straight from its product
             if ((st = chain(j + 1 < refine ? kEpiD64 : kEpiUpdateAcc, 1)) != BS_OK) return st;
@@ -466,16 +470,18 @@ bs_status plane_pass(bs_patchset *ps, int c, int colour, int prec, int refine, c
     return BS_OK;
 }
 
-// R = residual (f layout) for the FP64 chain and for refined mixed solves;
-// the mixed solves also get E = low-precision R in F1 (R itself is skipped
-// when nothing reads it).
+// R = residual (f layout) for the FP64 chain and for refined mixed solves
+// (FP32 for the BF16 chain); the mixed solves also get E = low-precision R in
+// F1 (R itself is skipped when nothing reads it).
 bs_status residual_into_scratch(bs_patchset *ps, const double *u, const double *f, hipStream_t s, int prec,
                                 int refine)
 {
     ResidArgs a{};
     a.u = u;
     a.f = f;
-    a.r = (prec == BS_FP64 || refine > 0) ? static_cast<double *>(ps->plane_r_d.p) : nullptr;
+    a.r = (prec == BS_FP64 || (prec == BS_MIXED_FP32 && refine > 0)) ? static_cast<double *>(ps->plane_r_d.p)
+                                                                       : nullptr;
+    if (prec == BS_MIXED_BF16 && refine > 0) a.r32 = static_cast<float *>(ps->plane_r_d.p);
     if (prec == BS_MIXED_FP32) a.e32 = static_cast<float *>(ps->plane_f1_d.p);
     if (prec == BS_MIXED_BF16) a.e16 = static_cast<uint16_t *>(ps->plane_f1_d.p);
     a.partial = nullptr;

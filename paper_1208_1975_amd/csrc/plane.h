@@ -78,9 +78,10 @@ hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStrea
 // The same product with BF16 operands in memory (unsigned short bit patterns)
 // and FP32 accumulation.  A is [m][k] (k contiguous, leading dimension lda);
 // B is [n][k] with leading dimension ldb when b_trans != 0, else [k][n].
-// Store / scale epilogues write BF16 C; kEpiD64 and kEpiUpdate as above;
-// kEpiUpdateAcc: udst[u] = usrc[u] + omega (D + C) (the last defect step of a
-// refined solve applied straight to u; D with C's indexing).
+// Store / scale epilogues write BF16 C; kEpiD64 and kEpiUpdate as above, with
+// the correction D held in FP32; kEpiUpdateAcc: udst[u] = usrc[u] +
+// omega (D + C) in FP64 (the last defect step of a refined solve applied
+// straight to u; D with C's indexing).
 struct GemmBf16Args {
     const unsigned short *A;
     int64_t lda, sA;
@@ -91,7 +92,7 @@ struct GemmBf16Args {
     int M, N, K, batch;
     const float *scale;
     int64_t sc_b, sc_m, sc_n;
-    double *D;
+    float *D;
     int accumulate;
     const double *usrc;
     double *udst;
@@ -104,8 +105,9 @@ struct GemmBf16Args {
 hipError_t launch_gemm_bf16(const GemmBf16Args &g, int b_trans, int epi, hipStream_t s);
 hipError_t launch_plane_defect(const double *R, const double *D, float *E, int nx, int ny, int nz, int normal,
                                const double eps[3], hipStream_t s);
-// The same defect rounded to BF16 (bit patterns).
-hipError_t launch_plane_defect_bf16(const double *R, const double *D, unsigned short *E, int nx, int ny, int nz,
+// The same defect from FP32 R and D (formed in FP64), rounded to BF16 (bit
+// patterns).
+hipError_t launch_plane_defect_bf16(const float *R, const float *D, unsigned short *E, int nx, int ny, int nz,
                                     int normal, const double eps[3], hipStream_t s);
 
 }  // namespace bs
