@@ -182,44 +182,116 @@ __device__ __forceinline__ void put_lowp(unsigned short *E, int64_t c, double v)
     E[c] = __builtin_bit_cast(unsigned short, static_cast<__bf16>(v));
 }
 
+// V consecutive values of a row from p (V = 1, or 4 from a 4-element-aligned
+// p: one 16-byte load of floats, two of doubles).
+template <int V, typename S>
+__device__ __forceinline__ void ld_row(const S *p, double (&o)[V])
+{
+    if constexpr (V == 1) {
+        o[0] = (double)p[0];
+    } else if constexpr (sizeof(S) == 4) {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+    } else {
+        const double2 q0 = *reinterpret_cast<const double2 *>(p), q1 = *reinterpret_cast<const double2 *>(p + 2);
+        o[0] = q0.x; o[1] = q0.y; o[2] = q1.x; o[3] = q1.y;
+    }
+}
+
 // E = low-precision (R - M_P D) on every cell of one patch (D may be null:
 // E = R), M_P the plane block with normal NORMAL: d D - eps_a (in-plane
 // neighbours along a) - eps_b (along b), zero beyond the plane's edges,
 // formed in FP64 from R and D stored as S (double, or float for the BF16
 // chain).  T: float, or unsigned short holding BF16 (rounded from FP64
-// directly).  One thread per cell; the neighbour loads are unconditional
+// directly).  A thread takes V consecutive cells of one x-row (V = 4 when
+// the rows are multiples of four cells and the fields 16-byte aligned, so
+// every load is one vector load); the neighbour loads are unconditional
 // (clamped addresses, zero weights beyond the plane's edges), so they are all
 // in flight together.
-template <typename S, typename T, int NORMAL>
+template <typename S, typename T, int NORMAL, int V>
 __global__ void __launch_bounds__(256) k_plane_defect(const S *R, const S *D, T *E, int nx, int ny, int nz,
                                                       double ex, double ey, double ez, double rnx, double rny)
 {
     const int n = nx * ny * nz;   // < 2^31: patches are below 4 GiB
-    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int c = (blockIdx.x * 256 + threadIdx.x) * V;
     if (c >= n) return;
-    double v = (double)R[c];
+    double v[V];
+    ld_row<V>(R + c, v);
     if (D) {
         const int jk = div_rd(c, nx, rnx);
         const int i = c - jk * nx;
         const int k = div_rd(jk, ny, rny);
         const int j = jk - k * ny;
         const int64_t pl = (int64_t)nx * ny;
-        double md = 2.0 * (ex + ey + ez) * (double)D[c];
+        double dc[V], md[V];
+        ld_row<V>(D + c, dc);
+        const double d = 2.0 * (ex + ey + ez);
+#pragma unroll
+        for (int e = 0; e < V; ++e) md[e] = d * dc[e];
         if (NORMAL != 0) {
-            const double a = (double)D[i > 0 ? c - 1 : c], b = (double)D[i < nx - 1 ? c + 1 : c];
-            md -= (i > 0 ? ex : 0.0) * a + (i < nx - 1 ? ex : 0.0) * b;
+            const double l = (double)D[i > 0 ? c - 1 : c], r = (double)D[i + V < nx ? c + V : c];
+            const double wl = i > 0 ? ex : 0.0, wr = i + V < nx ? ex : 0.0;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const double xl = e == 0 ? wl * l : ex * dc[e > 0 ? e - 1 : 0];
+                const double xr = e == V - 1 ? wr * r : ex * dc[e < V - 1 ? e + 1 : 0];
+                md[e] -= xl + xr;
+            }
         }
         if (NORMAL != 1) {
-            const double a = (double)D[j > 0 ? c - nx : c], b = (double)D[j < ny - 1 ? c + nx : c];
-            md -= (j > 0 ? ey : 0.0) * a + (j < ny - 1 ? ey : 0.0) * b;
+            double a[V], b[V];
+            ld_row<V>(D + (j > 0 ? c - nx : c), a);
+            ld_row<V>(D + (j < ny - 1 ? c + nx : c), b);
+            const double wa = j > 0 ? ey : 0.0, wb = j < ny - 1 ? ey : 0.0;
+#pragma unroll
+            for (int e = 0; e < V; ++e) md[e] -= wa * a[e] + wb * b[e];
         }
         if (NORMAL != 2) {
-            const double a = (double)D[k > 0 ? c - pl : c], b = (double)D[k < nz - 1 ? c + pl : c];
-            md -= (k > 0 ? ez : 0.0) * a + (k < nz - 1 ? ez : 0.0) * b;
+            double a[V], b[V];
+            ld_row<V>(D + (k > 0 ? c - pl : c), a);
+            ld_row<V>(D + (k < nz - 1 ? c + pl : c), b);
+            const double wa = k > 0 ? ez : 0.0, wb = k < nz - 1 ? ez : 0.0;
+#pragma unroll
+            for (int e = 0; e < V; ++e) md[e] -= wa * a[e] + wb * b[e];
         }
-        v -= md;
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] -= md[e];
     }
-    put_lowp(E, c, v);
+    if constexpr (V == 4 && sizeof(T) == 2) {   // four BF16 values: one 8-byte store
+        uint2 w;
+        w.x = __builtin_bit_cast(unsigned short, static_cast<__bf16>(v[0])) |
+              ((uint32_t)__builtin_bit_cast(unsigned short, static_cast<__bf16>(v[1])) << 16);
+        w.y = __builtin_bit_cast(unsigned short, static_cast<__bf16>(v[2])) |
+              ((uint32_t)__builtin_bit_cast(unsigned short, static_cast<__bf16>(v[3])) << 16);
+        *reinterpret_cast<uint2 *>(E + c) = w;
+    } else if constexpr (V == 4) {             // four floats: one 16-byte store
+        *reinterpret_cast<float4 *>(E + c) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    } else {
+        put_lowp(E, c, v[0]);
+    }
+}
+
+template <typename S, typename T, int V>
+static void launch_defect_v(const S *R, const S *D, T *E, int nx, int ny, int nz, int normal, const double eps[3],
+                            hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const dim3 grid((unsigned)((n / V + 255) / 256));
+    const double rnx = 1.0 / nx, rny = 1.0 / ny;
+    switch (normal) {
+    case 0:
+        hipLaunchKernelGGL((k_plane_defect<S, T, 0, V>), grid, dim3(256), 0, s, R, D, E, nx, ny, nz, eps[0],
+                           eps[1], eps[2], rnx, rny);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_plane_defect<S, T, 1, V>), grid, dim3(256), 0, s, R, D, E, nx, ny, nz, eps[0],
+                           eps[1], eps[2], rnx, rny);
+        break;
+    default:
+        hipLaunchKernelGGL((k_plane_defect<S, T, 2, V>), grid, dim3(256), 0, s, R, D, E, nx, ny, nz, eps[0],
+                           eps[1], eps[2], rnx, rny);
+        break;
+    }
 }
 
 template <typename S, typename T>
@@ -228,22 +300,13 @@ static hipError_t launch_defect(const S *R, const S *D, T *E, int nx, int ny, in
 {
     const int64_t n = (int64_t)nx * ny * nz;
     if (n <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((n + 255) / 256));
-    const double rnx = 1.0 / nx, rny = 1.0 / ny;
-    switch (normal) {
-    case 0:
-        hipLaunchKernelGGL((k_plane_defect<S, T, 0>), grid, dim3(256), 0, s, R, D, E, nx, ny, nz, eps[0], eps[1],
-                           eps[2], rnx, rny);
-        break;
-    case 1:
-        hipLaunchKernelGGL((k_plane_defect<S, T, 1>), grid, dim3(256), 0, s, R, D, E, nx, ny, nz, eps[0], eps[1],
-                           eps[2], rnx, rny);
-        break;
-    default:
-        hipLaunchKernelGGL((k_plane_defect<S, T, 2>), grid, dim3(256), 0, s, R, D, E, nx, ny, nz, eps[0], eps[1],
-                           eps[2], rnx, rny);
-        break;
-    }
+    const bool vec = nx % 4 == 0 && reinterpret_cast<uintptr_t>(R) % (4 * sizeof(S)) == 0 &&
+                     reinterpret_cast<uintptr_t>(D) % (4 * sizeof(S)) == 0 &&
+                     reinterpret_cast<uintptr_t>(E) % (4 * sizeof(T)) == 0;
+    if (vec)
+        launch_defect_v<S, T, 4>(R, D, E, nx, ny, nz, normal, eps, s);
+    else
+        launch_defect_v<S, T, 1>(R, D, E, nx, ny, nz, normal, eps, s);
     return hipGetLastError();
 }
 
