@@ -23,6 +23,7 @@
 // once into that XCD's L2 (in the hardware's own order each of them sat on a
 // different XCD and fetched the block again from memory).
 #include <cstdint>
+#include <type_traits>
 
 #include "bs_internal.h"
 #include "plane.h"
@@ -46,16 +47,36 @@ __device__ __forceinline__ u16 to_bf16(float v)
 
 }  // namespace
 
-// Operand chunks are loaded branch-free into registers (clamped, in-range
-// addresses) and completed in stash (zeroed outside the operands), so the
-// next step's loads stay in flight while the matrix cores work on the current
-// one.  VEC: every row 16-byte aligned and every row length a multiple of 8,
-// so a chunk is one 16-byte load.
-template <int EPI, int BT, bool VEC>
+// Two ways to feed the matrix cores.
+//
+// Register staging (any shapes): operand chunks are loaded branch-free into
+// registers (clamped, in-range addresses) and completed in stash (zeroed
+// outside the operands), so the next step's loads stay in flight while the
+// matrix cores work on the current one.  VEC: every row 16-byte aligned and
+// every row length a multiple of 8, so a chunk is one 16-byte load.
+//
+// Direct staging (ASYNC; B given [n][k], 16-byte aligned rows, K a multiple
+// of TK): global_load_lds writes each lane's 16 bytes straight into LDS, so
+// the operand tiles of the next NS - 1 steps are in flight at once without
+// holding registers.  A wave's load fills 1 KiB of LDS, lane l at byte 16 l:
+// 16 rows of TK = 32 BF16 (64 bytes) with no padding; lane l takes row l / 4
+// and slot l % 4, which holds the row's k-chunk (l % 4) ^ ((row / 2) % 4).
+// That swizzle puts the 16-byte slots that one 8-lane phase of the MFMA
+// operand reads (rows r..r+7, one chunk) and of the writes (two rows, four
+// chunks each) in different bank groups.  Each step waits for its own tile
+// (s_waitcnt vmcnt) and a workgroup barrier, then issues the tile NS - 1
+// steps ahead into the buffer that every wave finished reading in the
+// previous step.
+constexpr int NS = 3;   // LDS stages of direct staging
+
+template <int EPI, int BT, bool VEC, bool ASYNC>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
 {
-    __shared__ __attribute__((aligned(16))) u16 As[2][TM * PK];
-    __shared__ __attribute__((aligned(16))) u16 Bs[2][TN * PK];
+    // register staging's double buffer (a single row when direct staging
+    // uses its own stage arrays)
+    constexpr int NBUF = ASYNC ? 1 : 2;
+    __shared__ __attribute__((aligned(16))) u16 As[NBUF][ASYNC ? 8 : TM * PK];
+    __shared__ __attribute__((aligned(16))) u16 Bs[NBUF][ASYNC ? 8 : TN * PK];
     const int nt = (g.N + TN - 1) / TN, mt = (g.M + TM - 1) / TM;
     const int t = xcd_block(blockIdx.x, gridDim.x);
     const int tn = t % nt, tr = t / nt;
@@ -141,26 +162,124 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
     };
 
     const int nk = (g.K + TK - 1) / TK;
-    fetch(0);
-    stash(0, 0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) fetch((kt + 1) * TK);
-        bf16x8 af[4], bfr[4];
+    if constexpr (!ASYNC) {
+        fetch(0);
+        stash(0, 0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < nk) fetch((kt + 1) * TK);
+            bf16x8 af[4], bfr[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            af[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][(wm * 64 + i * 16 + l16) * PK + 8 * lk]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][(wn * 64 + j * 16 + l16) * PK + 8 * lk]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][(wm * 64 + i * 16 + l16) * PK + 8 * lk]);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-        if (kt + 1 < nk) stash(cur ^ 1, (kt + 1) * TK);
-        __syncthreads();
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][(wn * 64 + j * 16 + l16) * PK + 8 * lk]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+            if (kt + 1 < nk) stash(cur ^ 1, (kt + 1) * TK);
+            __syncthreads();
+        }
+    } else {
+        // one named LDS array per stage and operand: the compiler then sees
+        // that an operand read and the loads still in flight into the other
+        // stages touch different objects, and adds no wait of its own
+        __shared__ __attribute__((aligned(16))) u16 A0[TM * TK], A1[TM * TK], A2[TM * TK];
+        __shared__ __attribute__((aligned(16))) u16 B0[TN * TK], B1[TN * TK], B2[TN * TK];
+        static_assert(NS == 3, "three named stages");
+        typedef __attribute__((address_space(3))) void lds_t;
+        typedef const __attribute__((address_space(1))) void glb_t;
+        auto abuf = [&](auto S) -> u16 * {
+            if constexpr (decltype(S)::value == 0) return A0;
+            else if constexpr (decltype(S)::value == 1) return A1;
+            else return A2;
+        };
+        auto bbuf = [&](auto S) -> u16 * {
+            if constexpr (decltype(S)::value == 0) return B0;
+            else if constexpr (decltype(S)::value == 1) return B1;
+            else return B2;
+        };
+        // this lane's rows and k-chunk in the wave's two 16-row loads of A and
+        // of B (wave w fills rows 32 w .. 32 w + 31 of both tiles)
+        const int rr = 32 * w + (lane >> 2);                 // + 16 h
+        const int ka = ((lane & 3) ^ ((rr >> 1) & 3)) * 8;   // rr + 16 takes the same chunk
+        const u16 *ga[2], *gb[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gm = m0 + rr + 16 * h, gn = n0 + rr + 16 * h;
+            ga[h] = A + (int64_t)(gm < g.M ? gm : g.M - 1) * g.lda + ka;
+            gb[h] = B + (int64_t)(gn < g.N ? gn : g.N - 1) * g.ldb + ka;
+        }
+        auto issue = [&](auto S, int kt) {
+            const int k0 = kt * TK;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                __builtin_amdgcn_global_load_lds((glb_t *)(ga[h] + k0), (lds_t *)(abuf(S) + (32 * w + 16 * h) * TK),
+                                                 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((glb_t *)(gb[h] + k0), (lds_t *)(bbuf(S) + (32 * w + 16 * h) * TK),
+                                                 16, 0, 0);
+            }
+        };
+        // operand reads: row l16 of a 16-row block (a multiple of 16 from the
+        // tile's start), k-chunk lk, at its swizzled slot
+        const int sw = (lk ^ ((l16 >> 1) & 3)) * 8;
+        // FULL: a step of the steady state (the next step's tile in flight and
+        // the one after issued here), with no conditions, so that the loop
+        // body has no branches for the compiler's wait analysis to merge
+        auto step = [&](auto S, auto FULL, int kt) {
+            constexpr int st = decltype(S)::value;
+            constexpr bool full = decltype(FULL)::value;
+            // this step's tile has landed (loads complete in order; the next
+            // step's four loads may stay in flight), this wave's operand
+            // reads of the previous step have returned (lgkmcnt(0)), and after
+            // the barrier every wave's have: the previous step's buffer is
+            // refilled next
+            if (full || kt + 1 < nk)
+                __builtin_amdgcn_s_waitcnt(0x74);   // vmcnt(4) lgkmcnt(0)
+            else
+                __builtin_amdgcn_s_waitcnt(0x70);   // vmcnt(0) lgkmcnt(0)
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            const u16 *As_ = abuf(S), *Bs_ = bbuf(S);
+            bf16x8 af[4], bfr[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&As_[(wm * 64 + i * 16 + l16) * TK + sw]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs_[(wn * 64 + j * 16 + l16) * TK + sw]);
+            // the tile two steps ahead, into the buffer all waves finished with
+            // (issued after this step's operand reads)
+            if (full || kt + 2 < nk) issue(std::integral_constant<int, (st + 2) % 3>{}, kt + 2);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        };
+        using C0 = std::integral_constant<int, 0>;
+        using C1 = std::integral_constant<int, 1>;
+        using C2 = std::integral_constant<int, 2>;
+        using Full = std::true_type;
+        using Tail = std::false_type;
+        issue(C0{}, 0);   // nk >= 2 (launch condition)
+        issue(C1{}, 1);
+        int kt = 0;
+        for (; kt + 3 <= nk - 2; kt += 3) {   // steps kt .. kt + 2 all issue the tile two ahead
+            step(C0{}, Full{}, kt);
+            step(C1{}, Full{}, kt + 1);
+            step(C2{}, Full{}, kt + 2);
+        }
+        // at most four steps remain (kt a multiple of three: stages 0, 1, 2, 0)
+        if (kt < nk) step(C0{}, Tail{}, kt);
+        if (kt + 1 < nk) step(C1{}, Tail{}, kt + 1);
+        if (kt + 2 < nk) step(C2{}, Tail{}, kt + 2);
+        if (kt + 3 < nk) step(C0{}, Tail{}, kt + 3);
     }
 
     // register r of a lane holds row 4*(lane/16) + r, column lane%16 of its
@@ -268,20 +387,25 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
         }
 }
 
-template <int BT, bool VEC>
+template <int BT, bool VEC, bool ASYNC>
 static hipError_t launch_bf16_v(const GemmBf16Args &g, int epi, hipStream_t s)
 {
     const dim3 grid((unsigned)(((g.N + TN - 1) / TN) * ((g.M + TM - 1) / TM) * g.batch));
     switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL((k_gemm_bf16<kEpiStore, BT, VEC>), grid, dim3(256), 0, s, g); break;
-    case kEpiScale: hipLaunchKernelGGL((k_gemm_bf16<kEpiScale, BT, VEC>), grid, dim3(256), 0, s, g); break;
-    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdate, BT, VEC>), grid, dim3(256), 0, s, g); break;
-    case kEpiD64: hipLaunchKernelGGL((k_gemm_bf16<kEpiD64, BT, VEC>), grid, dim3(256), 0, s, g); break;
-    case kEpiUpdateAcc: hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdateAcc, BT, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiStore: hipLaunchKernelGGL((k_gemm_bf16<kEpiStore, BT, VEC, ASYNC>), grid, dim3(256), 0, s, g); break;
+    case kEpiScale: hipLaunchKernelGGL((k_gemm_bf16<kEpiScale, BT, VEC, ASYNC>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdate, BT, VEC, ASYNC>), grid, dim3(256), 0, s, g); break;
+    case kEpiD64: hipLaunchKernelGGL((k_gemm_bf16<kEpiD64, BT, VEC, ASYNC>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdateAcc:
+        hipLaunchKernelGGL((k_gemm_bf16<kEpiUpdateAcc, BT, VEC, ASYNC>), grid, dim3(256), 0, s, g);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
+
+// Direct staging on (1) or off (0), -1: whenever the shapes allow it.
+static int g_bf16_async = -1;
 
 template <int BT>
 static hipError_t launch_bf16_t(const GemmBf16Args &g, int epi, hipStream_t s)
@@ -291,8 +415,14 @@ static hipError_t launch_bf16_t(const GemmBf16Args &g, int epi, hipStream_t s)
     const bool vec = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0) &&
                      g.lda % 8 == 0 && g.ldb % 8 == 0 && g.sA % 8 == 0 && g.sB % 8 == 0 && g.K % 8 == 0 &&
                      (BT || g.N % 8 == 0);
-    return vec ? launch_bf16_v<BT, true>(g, epi, s) : launch_bf16_v<BT, false>(g, epi, s);
+    if constexpr (BT == 1) {
+        if (vec && g.K % TK == 0 && g.K >= 2 * TK && g_bf16_async != 0)
+            return launch_bf16_v<1, true, true>(g, epi, s);
+    }
+    return vec ? launch_bf16_v<BT, true, false>(g, epi, s) : launch_bf16_v<BT, false, false>(g, epi, s);
 }
+
+void set_bf16_async(int mode) { g_bf16_async = mode; }
 
 hipError_t launch_gemm_bf16(const GemmBf16Args &g, int b_trans, int epi, hipStream_t s)
 {

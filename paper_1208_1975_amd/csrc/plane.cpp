@@ -641,6 +641,15 @@ int bsi_gemm_bf16(const uint16_t *A, int64_t lda, int64_t sA, const uint16_t *B,
     return launch_gemm_bf16(g, b_trans, epi, s) == hipSuccess ? BS_OK : BS_ERR_HIP;
 }
 
+// Operand staging of the BF16 products (process-wide): -1 default, 0 through
+// registers, 1 direct to LDS where the shapes allow it.
+int bsi_set_bf16_async(int mode)
+{
+    if (mode < -1 || mode > 1) return BS_ERR_INVALID;
+    set_bf16_async(mode);
+    return BS_OK;
+}
+
 // Register-to-row mapping used by the mixed products of this patch set.
 int bsi_set_mixed_dlayout(bs_patchset *ps, int dlayout)
 {

@@ -103,6 +103,9 @@ struct GemmBf16Args {
 };
 
 hipError_t launch_gemm_bf16(const GemmBf16Args &g, int b_trans, int epi, hipStream_t s);
+// Operand staging of the BF16 products: 1 direct to LDS where the shapes allow
+// it, 0 always through registers, -1 (default) as 1.
+void set_bf16_async(int mode);
 hipError_t launch_plane_defect(const double *R, const double *D, float *E, int nx, int ny, int nz, int normal,
                                const double eps[3], hipStream_t s);
 // The same defect from FP32 R and D (formed in FP64), rounded to BF16 (bit

@@ -196,3 +196,34 @@ def test_bf16_gemm_output_layout_probe():
         tC = torch.zeros((M, N), dtype=torch.bfloat16, device="cuda")
         gemm_bf16(tA, K, 0, tB, N, 0, bt, tC, N, 0, M, N, K, 1)
         assert np.array_equal(tC.float().cpu().numpy(), A), bt
+
+
+def _set_bf16_async(mode):
+    L = bs.lib()
+    L.bsi_set_bf16_async.argtypes = [ctypes.c_int]
+    L.bsi_set_bf16_async.restype = ctypes.c_int
+    assert L.bsi_set_bf16_async(mode) == 0
+
+
+@pytest.mark.parametrize("K", [64, 96, 128, 160, 192, 224, 512])
+@pytest.mark.parametrize("M,N,batch", [(200, 136, 2), (128, 128, 1), (17, 300, 3)])
+def test_bf16_direct_staging_matches_register_staging(M, N, K, batch):
+    """B given [n][k] with K a multiple of 32: the products that stage their
+    operand tiles straight into LDS (three stages, swizzled slots) give the
+    bit pattern of the register-staged ones (same products in the same order),
+    for every count of K steps (2 to 16: every tail of the three-stage loop)
+    and for row counts that are not multiples of the 128-row tile."""
+    need_gpu()
+    tA, tB, A, B = _bf16_case(M, N, K, batch, M + 7 * N + K)
+    tBt = tB.transpose(1, 2).contiguous()      # [n][k]
+    out = {}
+    try:
+        for mode in (0, 1):
+            _set_bf16_async(mode)
+            tC = torch.zeros((batch, M, N), dtype=torch.bfloat16, device="cuda")
+            gemm_bf16(tA, K, M * K, tBt, K, N * K, 1, tC, N, M * N, M, N, K, batch)
+            out[mode] = tC
+    finally:
+        _set_bf16_async(-1)
+    assert torch.equal(out[0], out[1])
+    _bf16_check(out[1], A @ B, K, A, B)
