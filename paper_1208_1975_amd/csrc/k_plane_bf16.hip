@@ -70,7 +70,7 @@ __device__ __forceinline__ u16 to_bf16(float v)
 constexpr int NS = 3;   // LDS stages of direct staging
 
 template <int EPI, int BT, bool VEC, bool ASYNC>
-__global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_gemm_bf16(GemmBf16Args g)
 {
     // register staging's double buffer (a single row when direct staging
     // uses its own stage arrays)
@@ -336,12 +336,13 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
     // instead of one round trip per element or per block.  (The D epilogue
     // keeps one block at a time: a block row there cost a wave per SIMD of
     // occupancy and ran slower, 765 against 630 us per 512^3 product.)
-    constexpr int JG = (EPI == kEpiUpdate || EPI == kEpiUpdateAcc) ? 4 : 1;
+    constexpr int JG = (EPI == kEpiUpdate || EPI == kEpiUpdateAcc) ? 4 : (EPI == kEpiD64 ? 2 : 1);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int jh = 0; jh < 4; jh += JG) {
-            double in1[JG][4], in2[JG][4];
+            float in1[JG][4];   // scale factor or FP32 D
+            double in2[JG][4];
             bool ok[JG][4];
 #pragma unroll
             for (int jj = 0; jj < JG; ++jj)
@@ -355,11 +356,11 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
                     ok[jj][r] = o;
                     const int rr = o ? row : 0, cc = o ? col : 0;   // in-range addresses for every lane
                     const int64_t ci = (int64_t)b * g.sC + (int64_t)rr * g.ldc + cc;
-                    in1[jj][r] = 0.0;
+                    in1[jj][r] = 0.0f;
                     in2[jj][r] = 0.0;
                     if (EPI == kEpiScale)
                         in1[jj][r] = g.scale[(int64_t)b * g.sc_b + (int64_t)rr * g.sc_m + (int64_t)cc * g.sc_n];
-                    if (EPI == kEpiUpdateAcc || (EPI == kEpiD64 && g.accumulate)) in1[jj][r] = (double)g.D[ci];
+                    if (EPI == kEpiUpdateAcc || (EPI == kEpiD64 && g.accumulate)) in1[jj][r] = g.D[ci];
                     if (EPI == kEpiUpdate || EPI == kEpiUpdateAcc)
                         in2[jj][r] = g.usrc[g.u0 + (int64_t)b * g.u_b + (int64_t)rr * g.u_m + (int64_t)cc * g.u_n];
                 }
@@ -375,12 +376,12 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmBf16Args g)
                     if (EPI == kEpiStore) {
                         g.C[ci] = to_bf16(v);
                     } else if (EPI == kEpiScale) {
-                        g.C[ci] = to_bf16(v * static_cast<float>(in1[jj][r]));
+                        g.C[ci] = to_bf16(v * in1[jj][r]);
                     } else if (EPI == kEpiD64) {
-                        g.D[ci] = g.accumulate ? (float)(in1[jj][r] + (double)v) : v;
+                        g.D[ci] = g.accumulate ? (float)((double)in1[jj][r] + (double)v) : v;
                     } else {
                         const int64_t u = g.u0 + (int64_t)b * g.u_b + (int64_t)row * g.u_m + (int64_t)col * g.u_n;
-                        const double du = EPI == kEpiUpdateAcc ? in1[jj][r] + (double)v : (double)v;
+                        const double du = EPI == kEpiUpdateAcc ? (double)in1[jj][r] + (double)v : (double)v;
                         g.udst[u] = fma(g.omega, du, in2[jj][r]);
                     }
                 }
