@@ -186,6 +186,13 @@ struct CubeBatchArgs {
     double omega;
 };
 hipError_t launch_cube_small(const CubeBatchArgs &a, int nchunks, int np, hipStream_t s);
+//   launch_cube_big: blocks of 65..256 cells, fused likewise: one workgroup of
+//   512 threads per chunk of at most 32 consecutive blocks; np = 128 or 256
+//   (nb rounded up); the stored inverse must be symmetric.  Larger blocks
+//   take launch_cube_resid and the FP64 product with the gather epilogue.
+constexpr int kCubeBigChunk = 32;
+constexpr int kCubeFusedCells = 256;
+hipError_t launch_cube_big(const CubeBatchArgs &a, int nchunks, int np, hipStream_t s);
 
 // Ghost updates (k_ghost.hip).  One face operation copies the m1 x m2 cells
 // of a layer: dst[d0 + a*d1 + b*d2] = sign * u[s0 + a*s1 + b*s2] (element

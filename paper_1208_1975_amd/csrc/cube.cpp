@@ -5,8 +5,13 @@
 //   step 1  R[block][cell] = h^2 f - A u          (k_cube_resid)
 //   step 2  DU = R Ainv^T                          (FP64 matrix cores)
 //   step 3  u' = u + omega DU                      (the product's epilogue)
-// or, for blocks of up to 64 cells, all three in one kernel (k_cube_small),
-// one launch per operand size for every patch class and shape of the set.
+// for blocks of more than 256 cells, or all three in one kernel, one launch
+// per operand size for every patch class and shape of the set: k_cube_small
+// for blocks of up to 64 cells (inverse in LDS), k_cube_big for 65 to 256
+// (residuals in LDS, inverse read from memory).  For 512-cell blocks the
+// fused form measured slower than the two kernels (0.58 against 0.52 ms per
+// sweep of 64 x 64^3): its 32 x 512 FP64 accumulators per workgroup leave one
+// workgroup per compute unit, with nothing to hide its loads behind.
 // The blocks of a patch of equal shape share one inverse (constant
 // coefficients), so step 2 is one dense product per shape: the blocks are the
 // rows, which is what makes it a matrix-core contraction rather than the
@@ -217,18 +222,18 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
                     emit(1);
                     g.o_ubase = img.put(ub.data(), ub.size() * 8);
                     g.o_fbase = img.put(fb.data(), fb.size() * 8);
-                    if (nb > kCubeSmallCells) rmax = std::max(rmax, int64_t(g.nblk) * nb);
+                    if (nb > kCubeFusedCells) rmax = std::max(rmax, int64_t(g.nblk) * nb);
                     plan.groups.push_back(g);
                 }
     }
     bs_status st = upload(plan.buf, img.bytes.data(), img.bytes.size(), "cube tables");
     if (st != BS_OK) return st;
-    // blocks of up to 64 cells: every group in one launch per operand size
+    // every group in one launch per operand size and list (chunks of 64
+    // blocks for the small-block kernel, 32 for the large-block one)
     const char *base = static_cast<const char *>(plan.buf.p);
     std::vector<CubeGroupDev> gd;
-    std::vector<CubeChunk> lists[3][3];
+    std::vector<CubeChunk> lists[5][3];
     for (const CubeGroup &g : plan.groups) {
-        if (g.nb > kCubeSmallCells) continue;
         const int gi = int(gd.size());
         CubeGroupDev d{};
         d.ainv = reinterpret_cast<const double *>(base + g.o_ainv);
@@ -246,16 +251,18 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
         d.ez = g.ez;
         d.h2 = g.h2;
         gd.push_back(d);
-        const int npc = g.nb <= 16 ? 0 : (g.nb <= 32 ? 1 : 2);
+        if (g.nb > kCubeFusedCells) continue;   // residual matrix and product (cube_pass)
+        const int npc = g.nb <= 16 ? 0 : g.nb <= 32 ? 1 : g.nb <= 64 ? 2 : g.nb <= 128 ? 3 : 4;
+        const int per = npc < 3 ? 64 : kCubeBigChunk;
         auto cut = [&](std::vector<CubeChunk> &v, int lo, int hi) {
-            for (int b = lo; b < hi; b += 64) v.push_back(CubeChunk{gi, b, std::min(b + 64, hi), 0});
+            for (int b = lo; b < hi; b += per) v.push_back(CubeChunk{gi, b, std::min(b + per, hi), 0});
         };
         cut(lists[npc][0], 0, g.nblk);        // Jacobi: the colour-free list
         cut(lists[npc][1], 0, g.ncol0);       // colour 0 of the colour-major list
         cut(lists[npc][2], g.ncol0, g.nblk);  // colour 1
     }
     std::vector<CubeChunk> all;
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < 5; ++p)
         for (int k = 0; k < 3; ++k) {
             plan.chunk_off[p][k] = int(all.size());
             plan.chunk_cnt[p][k] = int(lists[p][k].size());
@@ -272,7 +279,7 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
     return BS_OK;
 }
 
-// Steps 1-3 for blocks [lo, lo + n) of a group of blocks over 64 cells:
+// Steps 1-3 for blocks [lo, lo + n) of a group of blocks over 256 cells:
 // src -> dst, in two kernels.
 bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, bool jacobi, int lo, int n, const double *src,
                     double *dst, const double *f, double omega, hipStream_t stream)
@@ -322,12 +329,13 @@ bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, bool jacobi, int l
     return BS_OK;
 }
 
-// Blocks of up to 64 cells of every group, list k (0 Jacobi, 1 colour 0,
-// 2 colour 1): one fused launch per operand size.
+// Blocks of every group, list k (0 Jacobi, 1 colour 0, 2 colour 1): one
+// fused launch per operand size (big: the sizes over 64 cells, else those up
+// to 64).
 bs_status small_pass(const CubePlan &plan, int k, const double *src, double *dst, const double *f, double omega,
-                     hipStream_t stream)
+                     hipStream_t stream, bool big = false)
 {
-    for (int p = 0; p < 3; ++p) {
+    for (int p = big ? 3 : 0; p < (big ? 5 : 3); ++p) {
         if (!plan.chunk_cnt[p][k]) continue;
         CubeBatchArgs a{};
         a.u = src;
@@ -337,7 +345,8 @@ bs_status small_pass(const CubePlan &plan, int k, const double *src, double *dst
         a.chunks = static_cast<const CubeChunk *>(plan.chunks.p) + plan.chunk_off[p][k];
         a.list = k == 0 ? 1 : 0;
         a.omega = omega;
-        hipError_t e = launch_cube_small(a, plan.chunk_cnt[p][k], 16 << p, stream);
+        hipError_t e = p < 3 ? launch_cube_small(a, plan.chunk_cnt[p][k], 16 << p, stream)
+                             : launch_cube_big(a, plan.chunk_cnt[p][k], 16 << p, stream);
         if (e != hipSuccess) return hip_fail(e, "cube blocks (fused)");
     }
     return BS_OK;
@@ -367,8 +376,9 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
             const double *src = (s & 1) ? work : u;
             double *dst = (s & 1) ? u : work;
             if ((st = small_pass(plan, 0, src, dst, f, omega, stream)) != BS_OK) return st;
+            if ((st = small_pass(plan, 0, src, dst, f, omega, stream, true)) != BS_OK) return st;
             for (const CubeGroup &g : plan.groups)
-                if (g.nb > kCubeSmallCells &&
+                if (g.nb > kCubeFusedCells &&
                     (st = cube_pass(plan, g, true, 0, g.nblk, src, dst, f, omega, stream)) != BS_OK)
                     return st;
             if ((st = ghosts(dst)) != BS_OK) return st;
@@ -384,8 +394,9 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
     for (int s = 0; s < nsweeps; ++s) {
         for (int col = 0; col < 2; ++col) {
             if ((st = small_pass(plan, 1 + col, u, u, f, omega, stream)) != BS_OK) return st;
+            if ((st = small_pass(plan, 1 + col, u, u, f, omega, stream, true)) != BS_OK) return st;
             for (const CubeGroup &g : plan.groups) {
-                if (g.nb <= kCubeSmallCells) continue;
+                if (g.nb <= kCubeFusedCells) continue;
                 const int lo = col ? g.ncol0 : 0, n = col ? g.nblk - g.ncol0 : g.ncol0;
                 if ((st = cube_pass(plan, g, false, lo, n, u, u, f, omega, stream)) != BS_OK) return st;
             }

@@ -1,11 +1,14 @@
 // Geometric cube blocks (section 2; the block Jacobi algorithm on GPUs).
 //
-// Large blocks (more than 64 cells): step 1, the residual of every cell of a
-// run of equally shaped blocks, is gathered into a block-major matrix
+// Blocks of more than 256 cells: step 1, the residual of every cell of a run
+// of equally shaped blocks, is gathered into a block-major matrix
 // R[block][cell] (cells of a block numbered x fastest); step 2, the product
 // with the precomputed block inverse, is the FP64 matrix-core product
 // R Ainv^T, whose epilogue applies step 3 (the update) through the same
 // offset tables.
+//
+// Blocks of 65 to 256 cells: all three steps in one kernel, the residuals
+// formed into LDS and the inverse read from memory (k_cube_big).
 //
 // Small blocks (up to 64 cells): all three steps in one kernel.  The inverse
 // (at most 64 x 64) sits in LDS and each wavefront forms its blocks'
@@ -167,6 +170,152 @@ __global__ void __launch_bounds__(256) k_cube_small(CubeBatchArgs ba_)
         for (int j = 0; j < NP / 16; ++j)
             if (ok && j * 16 + l16 < nb) a.dst[base + So[0][j * 16 + l16]] = fma(a.omega, acc[j][r], accu[j][r]);
     }
+}
+
+// Fused large blocks (65 to 256 cells): NP = nb rounded up to 128 or 256.  A
+// workgroup of eight wavefronts owns 32 consecutive blocks of one group's
+// list and all NP columns of their product with the inverse, so each residual
+// is formed once: wavefront w computes the 32 x (NP / 8) result columns
+// [w NP / 8, (w + 1) NP / 8) as two row blocks of v_mfma_f64_16x16x4.  The
+// contraction runs over the cells 16 at a time: the 512 threads form the 32
+// blocks' residuals of those 16 cells (one each, into LDS in the operand
+// layout), and every wavefront reads its slice of the inverse straight from
+// memory (the block matrix is symmetric, so row k of the stored inverse is
+// its column k: 16 consecutive columns are one 128-byte run; all workgroups
+// share it through L2).  The next step's residual inputs and inverse slice are
+// loaded while the current step's products run.  Epilogue: dst = u + omega du
+// through the offset tables, as the small-block kernel.
+template <int NP>
+__global__ void __launch_bounds__(512) k_cube_big(CubeBatchArgs ba_)
+{
+    constexpr int NW = NP / 8;      // result columns per wavefront
+    constexpr int JB = NW / 16;     // 16-column blocks per wavefront
+    constexpr int BK = 16;          // cells per step: one residual per thread
+    constexpr int KS = BK / 4;      // matrix-core steps per step
+    __shared__ double As[2][BK][33];   // [buffer][cell of the step][block]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const CubeChunk ch = ba_.chunks[xcd_block(blockIdx.x, gridDim.x)];
+    const CubeGroupDev &g = ba_.groups[ch.group];
+    const double *u = ba_.u, *f = ba_.f;
+    const int nb = g.nb, b0 = ch.first, bend = ch.end;
+    const int64_t sy = g.sy, sz = g.sz;
+    const double ex = g.ex, ey = g.ey, ez = g.ez, h2 = g.h2;
+    const int64_t *ubase = g.ubase[ba_.list], *fbase = g.fbase[ba_.list];
+    const double *ainv = g.ainv;
+
+    // residual role: block rb (0..31), cell BK kt + rc of the step
+    const int rb = tid / BK, rc = tid % BK;
+    const bool rbok = b0 + rb < bend;
+    const int64_t rub = ubase[rbok ? b0 + rb : b0], rfb = fbase[rbok ? b0 + rb : b0];
+    const int nk = (nb + BK - 1) / BK;
+    double v[8];
+    auto rload = [&](int kt) {
+        const int c = BK * kt + rc;
+        const int cc = c < nb ? c : nb - 1;   // in-range offsets for every lane
+        const int64_t iu = rub + g.uoff[cc];
+        v[0] = u[iu];
+        v[1] = u[iu - 1];
+        v[2] = u[iu + 1];
+        v[3] = u[iu - sy];
+        v[4] = u[iu + sy];
+        v[5] = u[iu - sz];
+        v[6] = u[iu + sz];
+        v[7] = f[rfb + g.foff[cc]];
+    };
+    auto rstore = [&](int kt, int buf) {
+        const int c = BK * kt + rc;
+        const double uc = v[0];
+        const double ax = ex * (2.0 * uc - v[1] - v[2]);
+        const double ay = ey * (2.0 * uc - v[3] - v[4]);
+        const double az = ez * (2.0 * uc - v[5] - v[6]);
+        As[buf][rc][rb] = (rbok && c < nb) ? h2 * v[7] - (ax + ay + az) : 0.0;
+    };
+    // inverse slice of a step: lane (l16, lk) holds Ainv[k][n] for k = BK kt +
+    // 4 s + lk, n = w NW + 16 j + l16 (zero outside nb x nb)
+    double bq[KS][JB];
+    auto bload = [&](int kt, double (&o)[KS][JB]) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = BK * kt + 4 * s + lk;
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                const int n = w * NW + 16 * j + l16;
+                const double x = ainv[(int64_t)(k < nb ? k : nb - 1) * nb + (n < nb ? n : nb - 1)];
+                o[s][j] = (k < nb && n < nb) ? x : 0.0;
+            }
+        }
+    };
+    dbl4 acc[2][JB];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < JB; ++j) acc[r][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    rload(0);
+    bload(0, bq);
+    rstore(0, 0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        double bn[KS][JB];
+        const bool more = kt + 1 < nk;
+        if (more) {   // the next step's inputs, in flight during this step's products
+            rload(kt + 1);
+            bload(kt + 1, bn);
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const double a0 = As[cur][4 * s + lk][l16], a1 = As[cur][4 * s + lk][16 + l16];
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bq[s][j], acc[0][j], 0, 0, 0);
+                acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bq[s][j], acc[1][j], 0, 0, 0);
+            }
+        }
+        if (more) {
+            rstore(kt + 1, cur ^ 1);
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int j = 0; j < JB; ++j) bq[s][j] = bn[s][j];
+        }
+        __syncthreads();
+    }
+
+    // result register r of a lane: block 16 hb + 4 r + l/16, cell column
+    // w NW + 16 j + l/16 ... l%16: column n = w NW + 16 j + l16
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * hb + 4 * r + lk;
+            const bool ok = b0 + m < bend;
+            const int64_t base = ubase[ok ? b0 + m : b0];
+            double uo[JB];
+            int64_t at[JB];
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {   // all the centre values first, then the stores
+                const int n = w * NW + 16 * j + l16;
+                at[j] = base + g.uoff[n < nb ? n : nb - 1];
+                uo[j] = u[at[j]];
+            }
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                const int n = w * NW + 16 * j + l16;
+                if (ok && n < nb) ba_.dst[at[j]] = fma(ba_.omega, acc[hb][j][r], uo[j]);
+            }
+        }
+}
+
+hipError_t launch_cube_big(const CubeBatchArgs &a, int nchunks, int np, hipStream_t s)
+{
+    if (nchunks <= 0) return hipSuccess;
+    const dim3 grid(nchunks);
+    if (np == 128) hipLaunchKernelGGL(k_cube_big<128>, grid, dim3(512), 0, s, a);
+    else if (np == 256) hipLaunchKernelGGL(k_cube_big<256>, grid, dim3(512), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_cube_small(const CubeBatchArgs &a, int nchunks, int np, hipStream_t s)

@@ -82,10 +82,11 @@ struct CubePlan {
     DevBuf buf;    // tables and inverses
     DevBuf rbuf;   // block-major residual scratch (largest group of blocks over 64 cells)
     int64_t inv_bytes = 0;
-    // blocks of up to 64 cells: device group descriptors and chunk lists, per
-    // operand size (16, 32, 64) and list (Jacobi, colour 0, colour 1)
+    // device group descriptors and chunk lists, per operand size (16, 32, 64:
+    // the small-block kernel; 128, 256: the fused large-block kernel) and list
+    // (Jacobi, colour 0, colour 1)
     DevBuf gdesc, chunks;
-    int chunk_off[3][3] = {}, chunk_cnt[3][3] = {};
+    int chunk_off[5][3] = {}, chunk_cnt[5][3] = {};
 };
 
 bs_status fail(bs_status st, const char *fmt, ...);
