@@ -191,7 +191,6 @@ hipError_t launch_cube_small(const CubeBatchArgs &a, int nchunks, int np, hipStr
 //   (nb rounded up); the stored inverse must be symmetric.  Larger blocks
 //   take launch_cube_resid and the FP64 product with the gather epilogue.
 constexpr int kCubeBigChunk = 32;
-constexpr int kCubeFusedCells = 256;
 hipError_t launch_cube_big(const CubeBatchArgs &a, int nchunks, int np, hipStream_t s);
 
 // Ghost updates (k_ghost.hip).  One face operation copies the m1 x m2 cells

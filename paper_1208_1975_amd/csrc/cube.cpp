@@ -12,6 +12,7 @@
 // fused form measured slower than the two kernels (0.58 against 0.52 ms per
 // sweep of 64 x 64^3): its 32 x 512 FP64 accumulators per workgroup leave one
 // workgroup per compute unit, with nothing to hide its loads behind.
+// fused_max (a test hook) can lower the size limit of the fused kernels.
 // The blocks of a patch of equal shape share one inverse (constant
 // coefficients), so step 2 is one dense product per shape: the blocks are the
 // rows, which is what makes it a matrix-core contraction rather than the
@@ -222,7 +223,7 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
                     emit(1);
                     g.o_ubase = img.put(ub.data(), ub.size() * 8);
                     g.o_fbase = img.put(fb.data(), fb.size() * 8);
-                    if (nb > kCubeFusedCells) rmax = std::max(rmax, int64_t(g.nblk) * nb);
+                    if (nb > ps->cube_fused_max) rmax = std::max(rmax, int64_t(g.nblk) * nb);
                     plan.groups.push_back(g);
                 }
     }
@@ -251,7 +252,7 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
         d.ez = g.ez;
         d.h2 = g.h2;
         gd.push_back(d);
-        if (g.nb > kCubeFusedCells) continue;   // residual matrix and product (cube_pass)
+        if (g.nb > ps->cube_fused_max) continue;   // residual matrix and product (cube_pass)
         const int npc = g.nb <= 16 ? 0 : g.nb <= 32 ? 1 : g.nb <= 64 ? 2 : g.nb <= 128 ? 3 : 4;
         const int per = npc < 3 ? 64 : kCubeBigChunk;
         auto cut = [&](std::vector<CubeChunk> &v, int lo, int hi) {
@@ -273,13 +274,14 @@ bs_status build_plan(const bs_patchset *ps, int bx, int by, int bz, CubePlan &pl
     if ((st = upload(plan.chunks, all.data(), all.size() * sizeof(CubeChunk), "cube chunk lists")) != BS_OK)
         return st;
     plan.inv_bytes = inv_bytes;
+    plan.fused_max = ps->cube_fused_max;
     if (plan.rbuf.bytes < size_t(rmax) * 8 &&
         (st = dev_alloc(plan.rbuf, size_t(rmax) * 8, "cube residual scratch")) != BS_OK)
         return st;
     return BS_OK;
 }
 
-// Steps 1-3 for blocks [lo, lo + n) of a group of blocks over 256 cells:
+// Steps 1-3 for blocks [lo, lo + n) of a group of blocks over fused_max cells:
 // src -> dst, in two kernels.
 bs_status cube_pass(const CubePlan &plan, const CubeGroup &g, bool jacobi, int lo, int n, const double *src,
                     double *dst, const double *f, double omega, hipStream_t stream)
@@ -378,7 +380,7 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
             if ((st = small_pass(plan, 0, src, dst, f, omega, stream)) != BS_OK) return st;
             if ((st = small_pass(plan, 0, src, dst, f, omega, stream, true)) != BS_OK) return st;
             for (const CubeGroup &g : plan.groups)
-                if (g.nb > kCubeFusedCells &&
+                if (g.nb > plan.fused_max &&
                     (st = cube_pass(plan, g, true, 0, g.nblk, src, dst, f, omega, stream)) != BS_OK)
                     return st;
             if ((st = ghosts(dst)) != BS_OK) return st;
@@ -396,7 +398,7 @@ bs_status enqueue_cube_sweeps(bs_patchset *ps, const CubePlan &plan, bs_scheme s
             if ((st = small_pass(plan, 1 + col, u, u, f, omega, stream)) != BS_OK) return st;
             if ((st = small_pass(plan, 1 + col, u, u, f, omega, stream, true)) != BS_OK) return st;
             for (const CubeGroup &g : plan.groups) {
-                if (g.nb <= kCubeFusedCells) continue;
+                if (g.nb <= plan.fused_max) continue;
                 const int lo = col ? g.ncol0 : 0, n = col ? g.nblk - g.ncol0 : g.ncol0;
                 if ((st = cube_pass(plan, g, false, lo, n, u, u, f, omega, stream)) != BS_OK) return st;
             }
@@ -508,6 +510,17 @@ bs_status bs_cube_relax(bs_patchset *ps, int32_t bx, int32_t by, int32_t bz, bs_
         itr = ps->graphs.emplace(key, exec).first;
     }
     if ((e = hipGraphLaunch(itr->second, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return BS_OK;
+}
+
+// Largest cube block (cells, 64..256) on the fused kernels; larger blocks take
+// the residual matrix and a separate product.  Drops the prepared sizes.
+int bsi_set_cube_fused_max(bs_patchset *ps, int cells)
+{
+    if (!ps || cells < 64 || cells > 256) return BS_ERR_INVALID;
+    ps->cube_fused_max = cells;
+    clear_graphs(ps);
+    ps->cube.clear();
     return BS_OK;
 }
 

@@ -174,9 +174,13 @@ __global__ void __launch_bounds__(256) k_cube_small(CubeBatchArgs ba_)
 
 // Fused large blocks (65 to 256 cells): NP = nb rounded up to 128 or 256.  A
 // workgroup of eight wavefronts owns 32 consecutive blocks of one group's
-// list and all NP columns of their product with the inverse, so each residual
-// is formed once: wavefront w computes the 32 x (NP / 8) result columns
-// [w NP / 8, (w + 1) NP / 8) as two row blocks of v_mfma_f64_16x16x4.  The
+// list and all NP columns of their product with the inverse, so each
+// residual is formed once and every cell of its blocks is read before any is
+// written (in place, Gauss-Seidel); wavefront w computes 32 x (NP / 8) result
+// columns as two row blocks of v_mfma_f64_16x16x4.  (Splitting the columns of
+// a chunk over two workgroups, as 512-cell blocks would need for two
+// workgroups per compute unit, lets one workgroup write cells of a block that
+// the other still reads in place.)  The
 // contraction runs over the cells 16 at a time: the 512 threads form the 32
 // blocks' residuals of those 16 cells (one each, into LDS in the operand
 // layout), and every wavefront reads its slice of the inverse straight from
@@ -284,7 +288,7 @@ __global__ void __launch_bounds__(512) k_cube_big(CubeBatchArgs ba_)
     }
 
     // result register r of a lane: block 16 hb + 4 r + l/16, cell column
-    // w NW + 16 j + l/16 ... l%16: column n = w NW + 16 j + l16
+    // column n = w NW + 16 j + l16
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb)
 #pragma unroll

@@ -87,6 +87,7 @@ struct CubePlan {
     // (Jacobi, colour 0, colour 1)
     DevBuf gdesc, chunks;
     int chunk_off[5][3] = {}, chunk_cnt[5][3] = {};
+    int fused_max = 256;   // largest block (cells) on the fused kernels; larger: two kernels
 };
 
 bs_status fail(bs_status st, const char *fmt, ...);
@@ -150,5 +151,6 @@ struct bs_patchset {
     uint64_t gen = 0;   // bumped whenever device tables or captured graphs are replaced
     bool use_graphs = true;
     bool use_pair = true;   // chaotic y/z lines with omega 1: the two-cells-per-lane kernel
+    int cube_fused_max = 256;   // cube blocks up to this many cells on the fused kernels (at most 256)
     ~bs_patchset();
 };

@@ -266,3 +266,37 @@ def test_set_eps_after_a_captured_sequence():
         ref = oracle.cube_sweeps(p.u0, p.f, new_eps, p.h, block, oracle.JACOBI, 0.8, 2)
         log("cubes eps change after capture %s" % (block,))
         assert relerr(ps.view_u(u, 0).cpu().numpy(), ref) < TOL, block
+
+
+@pytest.mark.parametrize("block", [(8, 4, 4), (8, 8, 4), (7, 6, 5)])
+def test_fused_large_blocks_equal_two_kernel_form_on_many_workgroups(block):
+    """Blocks of 65-256 cells run fused (residuals of 32 blocks in LDS, the
+    product, the update in one kernel).  On 32 patches of 64^3 thousands of
+    workgroups run at different times, so an in-place pass that wrote cells
+    of a block another workgroup still reads would show here (small patches
+    run every workgroup at once and hide it): the fused sweeps must equal the
+    residual-matrix + product form to rounding, in place and into a second
+    vector."""
+    import ctypes
+    L = bs.lib()
+    L.bsi_set_cube_fused_max.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.bsi_set_cube_fused_max.restype = ctypes.c_int
+    s = uniform_patchset(npatch=32)
+    ps = bs.PatchSet([tuple(d) for d in s.dims], [tuple(e) for e in s.eps], list(s.h))
+    u0, f, w = ps.pack_u(s.u0), ps.pack_f(s.f), ps.empty_u()
+    try:
+        for scheme, omega in (("jacobi", 0.8), ("chaotic", 1.0)):
+            res = {}
+            for fmax in (64, 256):
+                assert L.bsi_set_cube_fused_max(ps.handle, fmax) == 0
+                ps.cube_prepare(block)
+                u = u0.clone()
+                ps.cube_relax(block, scheme, omega, 2, u, f, w)
+                torch.cuda.synchronize()
+                res[fmax] = u
+            d = float((res[64] - res[256]).abs().max() / res[64].abs().max())
+            log("cube %s %s: fused vs two kernels %.3e" % (block, scheme, d))
+            assert d < 1e-13, (block, scheme, d)
+    finally:
+        L.bsi_set_cube_fused_max(ps.handle, 256)
+        ps.close()
