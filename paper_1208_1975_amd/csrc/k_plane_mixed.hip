@@ -25,10 +25,17 @@ constexpr int BM = 64, BN = 64, BK = 32;
 // accumulation.  A 64 x 64 block of C per workgroup (four wavefronts, 32 x 32
 // each); K advances BK at a time through two LDS buffers, the next tile
 // fetched into registers while the current one feeds the matrix cores.
+// BT: B given [n][k] (transposed on its way into LDS).  FOLD 1 / 2: the
+// contraction runs over A's rows / B's k-rows folded about the middle of a
+// length-Kfull axis, x'[k] = x[k] + fsign x[Kfull-1-k] (x[k] alone where
+// k = Kfull-1-k): with the other operand the even or odd half of a DST-I
+// basis (S[n-1-i][j] = (-1)^j S[i][j]), one half of the product at half the
+// flops; its rows or columns are the logical rows / columns m row_s + row_o /
+// n col_s + col_o of C.
 // The fetch is branch-free (clamped in-range addresses, zeroing deferred to
 // the LDS store), so those loads stay in flight during the products; VEC:
 // aligned rows whose lengths are multiples of 4, one 16-byte load per quad.
-template <int EPI, bool VEC>
+template <int EPI, bool VEC, int BT, int FOLD>
 __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
 {
     __shared__ __attribute__((aligned(16))) float As[2][BK][BM + 4];
@@ -73,19 +80,55 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
 
+    const int Kf = g.Kfull;
+    const float fs = (float)g.fsign;
+    // the mirrored entries Kf-1-k of k = c0 .. c0+3 (in that order) of a row
+    // (FOLD 1) -- one 16-byte load of the quad Kf-4-c0 .. Kf-1-c0, reversed,
+    // when aligned -- and the folding of a loaded quad
+    auto ldm4 = [&](const float *row, int c0) -> float4 {
+        if constexpr (VEC) {
+            const int b = Kf - 4 - c0;
+            const float4 v = *reinterpret_cast<const float4 *>(row + (b >= 0 ? b : 0));
+            return float4{v.w, v.z, v.y, v.x};
+        } else {
+            float4 v;
+            v.x = row[Kf - 1 - c0 >= 0 ? Kf - 1 - c0 : 0];
+            v.y = row[Kf - 2 - c0 >= 0 ? Kf - 2 - c0 : 0];
+            v.z = row[Kf - 3 - c0 >= 0 ? Kf - 3 - c0 : 0];
+            v.w = row[Kf - 4 - c0 >= 0 ? Kf - 4 - c0 : 0];
+            return v;
+        }
+    };
+    auto fold4 = [&](float4 v, float4 m, int c0) -> float4 {   // entries k = c0 .. c0+3
+        v.x = (c0 < g.K && Kf - 1 - c0 != c0) ? fmaf(fs, m.x, v.x) : v.x;
+        v.y = (c0 + 1 < g.K && Kf - 2 - c0 != c0 + 1) ? fmaf(fs, m.y, v.y) : v.y;
+        v.z = (c0 + 2 < g.K && Kf - 3 - c0 != c0 + 2) ? fmaf(fs, m.z, v.z) : v.z;
+        v.w = (c0 + 3 < g.K && Kf - 4 - c0 != c0 + 3) ? fmaf(fs, m.w, v.w) : v.w;
+        return v;
+    };
+
     // A tile BM x BK: quad c -> row c / 8, k offset (c % 8) * 4; B tile BK x BN:
-    // quad c -> k row c / 16, n offset (c % 16) * 4 (two quads a thread)
-    float4 ra[2], rb[2];
+    // quad c -> k row c / 16, n offset (c % 16) * 4, or (BT) n row c / 8, k
+    // offset (c % 8) * 4 (two quads a thread)
+    float4 ra[2], rb[2], rm[2];   // rm: the mirrored quad (A for FOLD 1, B for FOLD 2)
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int c = tid + 256 * q;
             const int r = c >> 3, kc = (c & 7) * 4;
             const int gr = m0 + r;
-            ra[q] = ld4(A + (int64_t)(gr < g.M ? gr : g.M - 1) * g.lda, k0 + kc, g.K);
-            const int kr = c >> 4, nc = (c & 15) * 4;
-            const int gk = k0 + kr;
-            rb[q] = ld4(B + (int64_t)(gk < g.K ? gk : g.K - 1) * g.ldb, n0 + nc, g.N);
+            const float *arow = A + (int64_t)(gr < g.M ? gr : g.M - 1) * g.lda;
+            ra[q] = ld4(arow, k0 + kc, g.K);
+            if constexpr (FOLD == 1) rm[q] = ldm4(arow, k0 + kc);
+            if constexpr (BT) {
+                const int gn = n0 + r;
+                rb[q] = ld4(B + (int64_t)(gn < g.N ? gn : g.N - 1) * g.ldb, k0 + kc, g.K);
+            } else {
+                const int kr = c >> 4, nc = (c & 15) * 4;
+                const int gk = k0 + kr, gkc = gk < g.K ? gk : g.K - 1;
+                rb[q] = ld4(B + (int64_t)gkc * g.ldb, n0 + nc, g.N);
+                if constexpr (FOLD == 2) rm[q] = ld4(B + (int64_t)(Kf - 1 - gkc) * g.ldb, n0 + nc, g.N);
+            }
         }
     };
     auto stash = [&](int buf, int k0) {
@@ -93,13 +136,32 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
         for (int q = 0; q < 2; ++q) {
             const int c = tid + 256 * q;
             const int r = c >> 3, kc = (c & 7) * 4;
-            const float4 a4 = keep4(ra[q], k0 + kc, g.K, m0 + r < g.M);
+            float4 a4 = ra[q];
+            if constexpr (FOLD == 1) a4 = fold4(a4, rm[q], k0 + kc);
+            a4 = keep4(a4, k0 + kc, g.K, m0 + r < g.M);
             As[buf][kc][r] = a4.x;
             As[buf][kc + 1][r] = a4.y;
             As[buf][kc + 2][r] = a4.z;
             As[buf][kc + 3][r] = a4.w;
-            const int kr = c >> 4, nc = (c & 15) * 4;
-            *reinterpret_cast<float4 *>(&Bs[buf][kr][nc]) = keep4(rb[q], n0 + nc, g.N, k0 + kr < g.K);
+            if constexpr (BT) {
+                const float4 b4 = keep4(rb[q], k0 + kc, g.K, n0 + r < g.N);
+                Bs[buf][kc][r] = b4.x;
+                Bs[buf][kc + 1][r] = b4.y;
+                Bs[buf][kc + 2][r] = b4.z;
+                Bs[buf][kc + 3][r] = b4.w;
+            } else {
+                const int kr = c >> 4, nc = (c & 15) * 4;
+                const int gk = k0 + kr;
+                float4 b4 = rb[q];
+                if constexpr (FOLD == 2) {
+                    const bool use = gk < g.K && Kf - 1 - gk != gk;
+                    b4.x = use ? fmaf(fs, rm[q].x, b4.x) : b4.x;
+                    b4.y = use ? fmaf(fs, rm[q].y, b4.y) : b4.y;
+                    b4.z = use ? fmaf(fs, rm[q].z, b4.z) : b4.z;
+                    b4.w = use ? fmaf(fs, rm[q].w, b4.w) : b4.w;
+                }
+                *reinterpret_cast<float4 *>(&Bs[buf][kr][nc]) = keep4(b4, n0 + nc, g.N, gk < g.K);
+            }
         }
     };
 
@@ -139,9 +201,10 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
             bool ok[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 32 + i * 16 + (g.dlayout ? r * 4 + lk : lk * 4 + r);
-                const int col = n0 + wn * 32 + j * 16 + l16;
-                bool o = row < g.M && col < g.N;
+                const int pm = m0 + wm * 32 + i * 16 + (g.dlayout ? r * 4 + lk : lk * 4 + r);
+                const int pn = n0 + wn * 32 + j * 16 + l16;
+                const int row = pm * g.row_s + g.row_o, col = pn * g.col_s + g.col_o;   // logical
+                bool o = pm < g.M && pn < g.N;
                 if (EPI == kEpiUpdate || EPI == kEpiUpdateAcc)
                     o = o && !(g.ncolour >= 0 && ((col + g.colour_shift) & 1) != g.ncolour);
                 ok[r] = o;
@@ -157,8 +220,8 @@ __global__ void __launch_bounds__(256) k_gemm_mixed(GemmMixedArgs g)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 if (!ok[r]) continue;
-                const int row = m0 + wm * 32 + i * 16 + (g.dlayout ? r * 4 + lk : lk * 4 + r);
-                const int col = n0 + wn * 32 + j * 16 + l16;
+                const int row = (m0 + wm * 32 + i * 16 + (g.dlayout ? r * 4 + lk : lk * 4 + r)) * g.row_s + g.row_o;
+                const int col = (n0 + wn * 32 + j * 16 + l16) * g.col_s + g.col_o;
                 const float v = acc[i][j][r];
                 const int64_t ci = (int64_t)b * g.sC + (int64_t)row * g.ldc + col;
                 if (EPI == kEpiStore) {
@@ -310,28 +373,46 @@ static hipError_t launch_defect(const S *R, const S *D, T *E, int nx, int ny, in
     return hipGetLastError();
 }
 
-template <bool VEC>
-static hipError_t launch_mixed_v(const GemmMixedArgs &g, int epi, dim3 grid, hipStream_t s)
+template <bool VEC, int BT, int FOLD>
+static hipError_t launch_mixed_f(const GemmMixedArgs &g, int epi, dim3 grid, hipStream_t s)
 {
     switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL((k_gemm_mixed<kEpiStore, VEC>), grid, dim3(256), 0, s, g); break;
-    case kEpiScale: hipLaunchKernelGGL((k_gemm_mixed<kEpiScale, VEC>), grid, dim3(256), 0, s, g); break;
-    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdate, VEC>), grid, dim3(256), 0, s, g); break;
-    case kEpiD64: hipLaunchKernelGGL((k_gemm_mixed<kEpiD64, VEC>), grid, dim3(256), 0, s, g); break;
-    case kEpiUpdateAcc: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdateAcc, VEC>), grid, dim3(256), 0, s, g); break;
+    case kEpiStore: hipLaunchKernelGGL((k_gemm_mixed<kEpiStore, VEC, BT, FOLD>), grid, dim3(256), 0, s, g); break;
+    case kEpiScale: hipLaunchKernelGGL((k_gemm_mixed<kEpiScale, VEC, BT, FOLD>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdate: hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdate, VEC, BT, FOLD>), grid, dim3(256), 0, s, g); break;
+    case kEpiD64: hipLaunchKernelGGL((k_gemm_mixed<kEpiD64, VEC, BT, FOLD>), grid, dim3(256), 0, s, g); break;
+    case kEpiUpdateAcc:
+        hipLaunchKernelGGL((k_gemm_mixed<kEpiUpdateAcc, VEC, BT, FOLD>), grid, dim3(256), 0, s, g);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStream_t s)
+template <bool VEC>
+static hipError_t launch_mixed_v(const GemmMixedArgs &g, int epi, dim3 grid, hipStream_t s)
+{
+    if (g.b_trans && g.fold == 1) return launch_mixed_f<VEC, 1, 1>(g, epi, grid, s);
+    if (!g.b_trans && g.fold == 2) return launch_mixed_f<VEC, 0, 2>(g, epi, grid, s);
+    if (!g.b_trans && g.fold == 0) return launch_mixed_f<VEC, 0, 0>(g, epi, grid, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_mixed(const GemmMixedArgs &g0, int prec, int epi, hipStream_t s)
 {
     if (prec != 1) return hipErrorInvalidValue;
-    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
+    if (g0.M <= 0 || g0.N <= 0 || g0.K <= 0 || g0.batch <= 0) return hipSuccess;
+    GemmMixedArgs g = g0;
+    if (g.row_s == 0) { g.row_s = 1; g.row_o = 0; }
+    if (g.col_s == 0) { g.col_s = 1; g.col_o = 0; }
+    if (g.fold == 0) { g.Kfull = g.K; g.fsign = 1; }
     const dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM) * g.batch));
+    // 16-byte quads: aligned bases and strides, row lengths (K for A and for B
+    // given [n][k], N for B given [k][n]) multiples of 4, and for A's mirrored
+    // quads an axis length Kfull that is one too
     const bool vec = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0) &&
                      g.lda % 4 == 0 && g.ldb % 4 == 0 && g.sA % 4 == 0 && g.sB % 4 == 0 && g.K % 4 == 0 &&
-                     g.N % 4 == 0;
+                     (g.b_trans || g.N % 4 == 0) && (g.fold != 1 || g.Kfull % 4 == 0);
     return vec ? launch_mixed_v<true>(g, epi, grid, s) : launch_mixed_v<false>(g, epi, grid, s);
 }
 

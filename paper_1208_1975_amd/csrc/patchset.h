@@ -151,6 +151,7 @@ struct bs_patchset {
     uint64_t gen = 0;   // bumped whenever device tables or captured graphs are replaced
     bool use_graphs = true;
     bool use_pair = true;   // chaotic y/z lines with omega 1: the two-cells-per-lane kernel
+    bool plane_lr = true;   // FP32 plane chain, normals y, z: the left (non-x) products first and last
     int cube_fused_max = 256;   // cube blocks up to this many cells on the fused kernels (at most 256)
     ~bs_patchset();
 };

@@ -50,9 +50,12 @@ struct GemmArgs {
 hipError_t launch_gemm_f64(const GemmArgs &g, int epi, hipStream_t s);
 
 // The same product with float operands and FP32 accumulation (prec 1: FP32
-// products, prec 2: BF16 products); kEpiD64 stores (or adds, accumulate != 0)
-// the result into the FP64 array D with C's indexing.  dlayout selects the
-// register-to-row mapping of the 16x16 result block (0: 4*(lane/16)+r).
+// products); kEpiD64 stores (or adds, accumulate != 0) the result into the
+// FP64 array D with C's indexing.  dlayout selects the register-to-row
+// mapping of the 16x16 result block (0: 4*(lane/16)+r).  b_trans, fold,
+// Kfull, fsign and row_s / row_o / col_s / col_o as in GemmArgs (the even /
+// odd halves of a DST-I product), with these combinations: b_trans 0 and
+// fold 0 or 2, b_trans 1 and fold 1.
 struct GemmMixedArgs {
     const float *A;
     int64_t lda, sA;
@@ -71,6 +74,8 @@ struct GemmMixedArgs {
     double omega;
     int ncolour, colour_shift;
     int dlayout;
+    int b_trans, fold, Kfull, fsign;
+    int row_s, row_o, col_s, col_o;
 };
 
 hipError_t launch_gemm_mixed(const GemmMixedArgs &g, int prec, int epi, hipStream_t s);
