@@ -76,6 +76,8 @@ def lib():
     L.bsi_set_xz_cfg.restype = ctypes.c_int
     L.bsi_set_pair.argtypes = [vp, ctypes.c_int]
     L.bsi_set_pair.restype = ctypes.c_int
+    L.bsi_set_line_direct.argtypes = [vp, ctypes.c_int]
+    L.bsi_set_line_direct.restype = ctypes.c_int
     L.bsi_set_chaotic_chunk.argtypes = [vp, ctypes.c_int]
     L.bsi_set_chaotic_chunk.restype = ctypes.c_int
     L.bsi_set_graphs.argtypes = [vp, ctypes.c_int]
@@ -434,6 +436,11 @@ class PatchSet:
         """Chaotic GS on y/z lines with omega 1: two x-cells per lane (True, the
         default) or one line per lane with the in-tile correction solve."""
         _check(lib().bsi_set_pair(self.handle, 1 if enable else 0))
+
+    def set_line_direct(self, enable):
+        """Jacobi on y/z lines: the direct form M^{-1}(omega b + (1 - omega) M u)
+        (True, the default) or u + omega M^{-1} r with u kept for the update."""
+        _check(lib().bsi_set_line_direct(self.handle, 1 if enable else 0))
 
     def set_chaotic_chunk(self, tiles):
         """Tiles per even/odd chunk of the one-launch chaotic order (0: default)."""

@@ -91,6 +91,8 @@ bs_status bs_block_backward(bs_patchset *ps, int32_t kind, int32_t axis, bs_sche
         if ((st = check_line_ps_ext(ps, axis, fn)) != BS_OK) return st;
         cj = line_cfg(ps, axis, 0);
         cc = line_cfg(ps, axis, 1);
+        // most line passes here are block solves, not direct-form sweeps
+        if (cj.deflt) cj = default_line_cfg(ps, axis, 0, false);
         if ((st = check_line_cfg(ps, axis, cj)) != BS_OK) return st;
         if ((st = check_line_cfg(ps, axis, cc)) != BS_OK) return st;
         if ((st = prepare_lists(ps, axis, cj, 0)) != BS_OK) return st;

@@ -70,6 +70,7 @@ struct LineArgs {
     const float *tab32;     // FP32 copy of tab (same offsets)
     int32_t f32;            // 1: block solve in FP32 (residual and update stay FP64)
     int32_t f_stream;       // 1: colour mode 0 reads f with nontemporal loads (data beyond the Infinity Cache)
+    int32_t direct;         // 1: colour mode 0 on y/z lines in the direct form dst = M^{-1}(omega b + (1 - omega) M src)
 };
 constexpr int64_t kMallBytes = 256ll << 20;   // MI355X Infinity Cache
 

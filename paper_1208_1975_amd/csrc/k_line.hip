@@ -47,16 +47,29 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
 // item per workgroup when the grid covers the list, a persistent grid otherwise.
 // LDS: the chunk values of u (L per lane, each lane reads back only its own)
 // followed by two buffers of chunk ends.  CM: the kernel mode (0 all lines,
-// 1 one colour per launch, 2 in-tile two-colour), a.colour_mode == CM.  F32:
-// the block solve in FP32 (residual and update stay FP64).
+// 1 one colour per launch, 2 in-tile two-colour; 3 = 0 with f read
+// nontemporally; 4 and 5 = 0 and 3 in the direct form below).  F32: the block
+// solve in FP32 (residual and update stay FP64).
+//
+// Direct form of damped block Jacobi (modes 4, 5): with the line block M and
+// b = h^2 f plus the off-line neighbour and line-end ghost terms, the update
+// u + omega M^{-1}(b - M u) equals M^{-1}(omega b + (1 - omega) M u).  The
+// kernel forms that right-hand side while loading (M u needs only the line's
+// own cells, already loaded for the residual) and stores the solve's result
+// as it is, so u never waits for the update: no LDS for it, and half the
+// registers per cell of the long-chunk form that reads u again.  A line end
+// at an extrapolated face (ghost = -u_0, folded into M's diagonal) takes the
+// ghost's coefficient omega eps_a - eps_a instead of omega eps_a.
+// The direct form with 32-cell chunks is held to 128 VGPRs (four waves per
+// SIMD: two 8-wave workgroups per CU, one loading while the other solves).
 template <int L, int MAXT, int CM, bool F32>
-__global__ void __launch_bounds__(MAXT) k_line_strided(LineArgs a, const double *__restrict__ tabs,
-                                                      const float *__restrict__ tabs32)
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((CM >= 4 && L == 32) ? 4 : 1)))
+k_line_strided(LineArgs a, const double *__restrict__ tabs, const float *__restrict__ tabs32)
 {
     extern __shared__ double smem[];
     const int nw = blockDim.x >> 6;
     double *ucs = smem;
-    double *endb = smem + (L <= 16 ? L * 64 * nw : 0);   // u is held in LDS only for chunks <= 16
+    double *endb = smem + (L <= 16 && CM < 4 ? L * 64 * nw : 0);   // u is held in LDS only for chunks <= 16
     int buf = 0;
     for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
         const WorkItem it = a.items[i];
@@ -79,7 +92,9 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
     // chunks of up to 16 cells keep u in LDS for the update (16 waves x 64
     // lanes x 16 doubles = 128 KiB); longer chunks read it again from memory
     // (the kernel places the LDS buffers by the same rule)
-    constexpr bool kUcLds = L <= 16;
+    constexpr bool kDirect = CM >= 4;
+    constexpr bool kUcLds = L <= 16 && !kDirect;
+    constexpr bool kNtF = CM == 3 || CM == 5;
     const PatchDesc *pd = a.pd + it.patch;
     const int axis = a.axis;          // 1 or 2
     const int oaxis = 3 - axis;       // the other free axis
@@ -149,7 +164,16 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
     double r[L];
     const double ulo = ldb(ub, cu - Sa8);
     const double uhi = ldb(ub, cu + (uint32_t)Lp * Sa8);
-    if (a.rhs_mode) {
+    // direct form: the residual's coefficients scaled by omega, (1 - omega) M u
+    // added; in-line neighbours weigh (omega - 1) eps_a, a line-end ghost
+    // omega eps_a (minus eps_a at an extrapolated end)
+    const double om = a.omega;
+    const double cx = kDirect ? om * ex : ex, co = kDirect ? om * eo : eo, ch2 = kDirect ? om * h2 : h2;
+    const double cd = kDirect ? (1.0 - om) * d : -d;
+    const double cn = kDirect ? (om - 1.0) * ea : ea;
+    const double clo = (kDirect && t0 == 0) ? fma(om, ea, ((pd->bc >> (2 * axis)) & 1) ? -ea : 0.0) : cn;
+    const double chi = (kDirect && pc == P - 1) ? fma(om, ea, ((pd->bc >> (2 * axis + 1)) & 1) ? -ea : 0.0) : cn;
+    if (!kDirect && a.rhs_mode) {
 #pragma unroll
         for (int t = 0; t < L; ++t) {
             r[t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
@@ -159,6 +183,8 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
         // r = h^2 f + eps_o (o-neighbours) + eps_x (x-neighbours) + eps_a
         // (line neighbours) - d u, finished cell by cell as soon as the next
         // centre value has arrived, so only B + 1 centre values stay live
+        // (the direct form's right-hand side the same way, with its own
+        // coefficients)
         double uprev = ulo, ucur = 0.0, rpend = 0.0;
 #pragma unroll
         for (int tb = 0; tb < L; tb += B) {
@@ -173,7 +199,7 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
                 // f with a nontemporal load (measured 117 -> 102 us per 256^3
                 // sweep; data that fits the cache, and the in-place schemes,
                 // are slower with it)
-                if constexpr (CM == 3)
+                if constexpr (kNtF)
                     fb[k] = __builtin_nontemporal_load(reinterpret_cast<const double *>(fbase + (cf + tt * Fa8)));
                 else
                     fb[k] = ldb(fbase, cf + tt * Fa8);
@@ -189,10 +215,15 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
                 const double left = lane_shift<-1>(ub4[k]);
                 const double right = lane_shift<+1>(ub4[k]);
                 const double xs = (need_l ? xa[k] : left) + (need_r ? (need_l ? 0.0 : xa[k]) : right);
-                const double rt = fma(-d, ub4[k], fma(ex, xs, fma(h2, fb[k], eo * (om[k] + op[k]))));
+                const double rt = fma(cd, ub4[k], fma(cx, xs, fma(ch2, fb[k], co * (om[k] + op[k]))));
                 // cell t-1 is complete now that u_t is known (beyond Lp the
                 // upper neighbour is the chunk's far neighbour uhi)
-                if (t > 0) r[t - 1] = fma(ea, uprev + (t < Lp ? ub4[k] : uhi), rpend);
+                if (t > 0) {
+                    if constexpr (kDirect)
+                        r[t - 1] = fma(t == 1 ? clo : cn, uprev, fma(t < Lp ? cn : chi, t < Lp ? ub4[k] : uhi, rpend));
+                    else
+                        r[t - 1] = fma(ea, uprev + (t < Lp ? ub4[k] : uhi), rpend);
+                }
                 uprev = ucur;
                 ucur = ub4[k];
                 rpend = rt;
@@ -201,7 +232,10 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
             // keep the next batch's loads below this point (bounded registers)
             asm volatile("" ::: "memory");
         }
-        r[L - 1] = fma(ea, uprev + uhi, rpend);
+        if constexpr (kDirect)
+            r[L - 1] = fma(cn, uprev, fma(chi, uhi, rpend));
+        else
+            r[L - 1] = fma(ea, uprev + uhi, rpend);
         if (__builtin_amdgcn_ballot_w64(both) != 0) {
 #pragma unroll
             for (int tb = 0; tb < L; tb += B) {
@@ -211,7 +245,7 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
                     xb[k] = ldb(ub, cu + (uint32_t)((tb + k) < Lp ? (tb + k) : Lp - 1) * Sa8 + 8u);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int k = 0; k < B; ++k) r[tb + k] = fma(ex, both ? xb[k] : 0.0, r[tb + k]);
+                for (int k = 0; k < B; ++k) r[tb + k] = fma(cx, both ? xb[k] : 0.0, r[tb + k]);
             }
         }
     }
@@ -224,7 +258,7 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
     ends[(p * 64 + lane) * 2 + 1] = yl;
     __syncthreads();   // every chunk's ends are in LDS; all reads of the tile's lines precede any write
     double uo[kUcLds ? 1 : L];
-    if (!kUcLds && !a.out_mode) {
+    if (!kUcLds && !kDirect && !a.out_mode) {
 #pragma unroll
         for (int t = 0; t < L; ++t) uo[kUcLds ? 0 : t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
     }
@@ -232,7 +266,6 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
     interface_terms_k<T>(as_const(tab), ends, Lr, P, pc, lane, bprev, anext);
     const __attribute__((address_space(4))) T *ev = as_const(tab) + (pc == P - 1 ? 4 * Lr : 2 * Lr);
     const __attribute__((address_space(4))) T *ew = ev + Lr;
-    const double om = a.omega;
     char *db = reinterpret_cast<char *>(a.dst + pd->uoff);
     if (CM == 2) {
         // In-tile two-colour (chaotic GS): the solve above is exact for the
@@ -292,7 +325,8 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
             if (t < Lp) {
                 const double du = static_cast<double>(fma(anext, ew[t], fma(bprev, ev[t], rs[t])));
                 *reinterpret_cast<double *>(db + (cu + (uint32_t)t * Sa8)) =
-                    a.out_mode ? du : fma(om, du, kUcLds ? ucs[t * nthr + threadIdx.x] : uo[kUcLds ? 0 : t]);
+                    (kDirect || a.out_mode) ? du
+                                            : fma(om, du, kUcLds ? ucs[t * nthr + threadIdx.x] : uo[kUcLds ? 0 : t]);
             }
         }
     }
@@ -505,10 +539,20 @@ static void launch_strided_p(const LineArgs &a, int grid, int nwaves, size_t lds
     const dim3 g(grid), b(64 * nwaves);
     switch (a.colour_mode) {
     case 0:
-        if (a.f_stream)
+        if constexpr (!F32) {
+            if (a.direct) {
+                if (a.f_stream)
+                    hipLaunchKernelGGL((k_line_strided<L, MAXT, 5, false>), g, b, lds, s, a, a.tab, a.tab32);
+                else
+                    hipLaunchKernelGGL((k_line_strided<L, MAXT, 4, false>), g, b, lds, s, a, a.tab, a.tab32);
+                break;
+            }
+        }
+        if (a.f_stream) {
             hipLaunchKernelGGL((k_line_strided<L, MAXT, 3, F32>), g, b, lds, s, a, a.tab, a.tab32);
-        else
+        } else {
             hipLaunchKernelGGL((k_line_strided<L, MAXT, 0, F32>), g, b, lds, s, a, a.tab, a.tab32);
+        }
         break;
     case 1: hipLaunchKernelGGL((k_line_strided<L, MAXT, 1, F32>), g, b, lds, s, a, a.tab, a.tab32); break;
     default: hipLaunchKernelGGL((k_line_strided<L, MAXT, 2, F32>), g, b, lds, s, a, a.tab, a.tab32); break;

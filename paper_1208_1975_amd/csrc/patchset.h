@@ -63,6 +63,7 @@ struct LineCfg {
                       // 2: the same lines marched along z (nx <= 64; Jacobi, chaotic GS)
     int zc = 0;       // form 2: planes per work item
     int tuned = 0;    // 1: chosen by bs_autotune_line
+    int deflt = 0;    // 1: the library's default (not set by a caller or the autotuner)
 };
 
 // Geometric cube blocks of one block size: one group per (class of patches
@@ -151,6 +152,7 @@ struct bs_patchset {
     uint64_t gen = 0;   // bumped whenever device tables or captured graphs are replaced
     bool use_graphs = true;
     bool use_pair = true;   // chaotic y/z lines with omega 1: the two-cells-per-lane kernel
+    bool line_direct = true;   // Jacobi on y/z lines in the direct form (no copy of u kept for the update)
     bool plane_lr = true;   // FP32 plane chain, normals y, z: the left (non-x) products first and last
     int cube_fused_max = 256;   // cube blocks up to this many cells on the fused kernels (at most 256)
     ~bs_patchset();

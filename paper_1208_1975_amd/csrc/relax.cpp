@@ -280,15 +280,20 @@ int xz_planes(const bs_patchset *ps, int nwaves)
     return std::max(zc, 1);
 }
 
-LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode)
+LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode, bool direct)
 {
     LineCfg c;
+    c.deflt = 1;
     const int nmax = ps->max_n[axis];
     // the fewest chunks whose length stays <= 16 (about 126 VGPRs at 1024
-    // threads); longer lines take 32-cell chunks
+    // threads); longer lines take 32-cell chunks.  FP64 Jacobi in the direct
+    // form on lines of 129..256 cells takes four chunks of up to 64 cells
+    // (two 4-wave workgroups per CU; 256^3 z-lines: 97 us per sweep against
+    // 102 us with eight chunks of 32 and 104 us with sixteen of 16)
+    const bool wide = axis != 0 && colour_mode == 0 && direct && ps->line_direct && nmax > 128 && nmax <= 256;
     for (int o = 0; o < kNumPOpt; ++o) {
         const int Lr = (nmax + kPOpts[o] - 1) / kPOpts[o];
-        if (Lr <= 16 || o == kNumPOpt - 1) {
+        if (Lr <= (wide ? 64 : 16) || o == kNumPOpt - 1) {
             c.popt = o;
             break;
         }
@@ -419,7 +424,9 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
     a.rhs_mode = rhs_mode;
     a.out_mode = out_mode;
     a.omega = omega;
-    const size_t lds = line_lds_bytes(ps, axis, c);
+    a.direct = (kind == 0 && c.form == 0 && colour_mode == 0 && !rhs_mode && !out_mode && !f32 && ps->line_direct) ? 1 : 0;
+    // the direct form keeps no chunk values of u: the two buffers of chunk ends only
+    const size_t lds = a.direct ? 4 * 64 * static_cast<size_t>(c.nwaves) * sizeof(double) : line_lds_bytes(ps, axis, c);
     const WorkItem *base = static_cast<const WorkItem *>(wl->buf.p);
     auto launch = [&](int first, int count) -> bs_status {
         if (count <= 0) return BS_OK;
@@ -665,13 +672,15 @@ bs_status line_relax_impl(bs_patchset *ps, int32_t axis, bs_scheme scheme, doubl
     if ((st = check_line_ps(ps, axis, "bs_line_relax")) != BS_OK) return st;
     if (nsweeps == 0) return BS_OK;
     const int cm = scheme_mode(axis, scheme);
-    const LineCfg c = line_cfg(ps, axis, cm);
+    const int f32 = prec == BS_MIXED_FP32 ? 1 : 0;
+    // the default configuration is chosen for FP64; an FP32 solve takes its own
+    LineCfg c = line_cfg(ps, axis, cm);
+    if (f32 && c.deflt) c = default_line_cfg(ps, axis, cm, false);
     if ((st = check_line_cfg(ps, axis, c)) != BS_OK) return st;
     if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;
     if (bline_any(ps, axis) && (st = bline_prepare(ps, axis)) != BS_OK) return st;
     hipError_t e = prepare_line_kernels();
     if (e != hipSuccess) return hip_fail(e, "line kernel attributes");
-    const int f32 = prec == BS_MIXED_FP32 ? 1 : 0;
     if (cm == 2 && !chaotic_colour_major(ps, axis, c) && pair_for(ps, axis, c, omega, f32)) {
         WorkList *wl;
         if ((st = get_worklist(ps, 3, axis, c.popt, 128, 2, &wl, chaotic_chunk_for(ps, axis, c))) != BS_OK) return st;
@@ -937,6 +946,24 @@ int bsi_set_pair(bs_patchset *ps, int enable)
 {
     if (!ps) return BS_ERR_INVALID;
     ps->use_pair = enable != 0;
+    clear_graphs(ps);
+    return BS_OK;
+}
+
+// Enable (1, the default) or disable (0) the direct form of Jacobi on y/z lines
+// (dst = M^{-1}(omega b + (1 - omega) M src)); disabled, the kernel keeps u for
+// the update dst = src + omega M^{-1} r.
+int bsi_set_line_direct(bs_patchset *ps, int enable)
+{
+    if (!ps) return BS_ERR_INVALID;
+    ps->line_direct = enable != 0;
+    // default configurations depend on the form: chosen again on next use
+    for (auto it = ps->line_cfg.begin(); it != ps->line_cfg.end();) {
+        if (it->second.deflt)
+            it = ps->line_cfg.erase(it);
+        else
+            ++it;
+    }
     clear_graphs(ps);
     return BS_OK;
 }

@@ -8,7 +8,9 @@ namespace bs {
 int scheme_mode(int axis, bs_scheme scheme);
 bs_status get_worklist(bs_patchset *ps, int kind, int axis, int popt, int tx, int colour_mode, WorkList **out,
                        int chunk = 0);
-LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode);
+// direct: the configuration for sweeps that may run in the direct Jacobi form
+// (FP64, no solve-only or field right-hand-side modes)
+LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode, bool direct = true);
 bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c);
 size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c);
 // rhs_mode 0: right-hand side = residual of src; 1: = src itself.

@@ -122,6 +122,37 @@ def test_line_bc_large_and_fp32(axis):
         ps.close()
 
 
+@pytest.mark.parametrize("axis", [1, 2])
+def test_jacobi_direct_and_update_forms(axis):
+    """Jacobi on y/z lines in the direct form M^{-1}(omega b + (1 - omega) M u)
+    (the FP64 default) and in the update form u + omega M^{-1} r: both match
+    the oracle to 1e-12 for every chunk count, lines of 129..256 cells (four
+    chunks by default) included, with Dirichlet, extrapolated line-end and
+    all-extrapolated faces, omega below, at and above 1."""
+    dims = (40, 150, 24) if axis == 1 else (37, 21, 201)
+    p = small_patch(*dims, seed=13 + axis, eps=(1.0, 3.0, 40.0))
+    ps0, _, _, _ = _single(p, 0)
+    assert ps0.line_config(axis, "jacobi")["chunks"] == 4
+    ps0.close()
+    for bc in (0, 3 << (2 * axis), 63):
+        for omega in (0.8, 1.0, 1.3):
+            ref = oracle.line_sweeps(p.u0, p.f, p.eps, p.h, axis, oracle.JACOBI, omega, 3, bc=bc)
+            for direct in (True, False):
+                for chunks in (0, 4, 8, 16):
+                    log("jacobi forms axis %d bc=%d omega %.1f direct=%s chunks=%d" % (axis, bc, omega, direct, chunks))
+                    ps, u, f, w = _single(p, bc)
+                    ps.set_line_direct(direct)
+                    if chunks:
+                        ps.set_line_config(axis, "jacobi", chunks, 64)
+                    ps.line_relax(axis, "jacobi", omega, 3, u, f, w)
+                    torch.cuda.synchronize()
+                    got = ps.view_u(u, 0).cpu().numpy()
+                    err = relerr(got[1:-1, 1:-1, 1:-1], ref[1:-1, 1:-1, 1:-1])
+                    assert err < TOL, (bc, omega, direct, chunks, err)
+                    _check_ghosts(got, p.u0, bc)
+                    ps.close()
+
+
 def test_line_bc_fixed_point():
     """The exact discrete solution with extrapolated faces is a fixed point."""
     p = small_patch(24, 20, 18, seed=9, eps=(1.0, 1.0, 50.0))
