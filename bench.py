@@ -434,9 +434,19 @@ def forms():
     bwd = lambda: bs.bs_relax_backward(ps.handle, 2, 0.8, 20, 5, u0, f, g, gu0, gf, geps, ws)
     bwd()
     ms_b = ev_ms(bwd, reps=5)
+    # the autograd form: the forward keeps its checkpoints, the backward starts from them
+    fwd_c = lambda: (u.copy_(u0), bs.bs_block_forward_ckpt(ps.handle, "line", 2, "jacobi", 0.8, 20, 5, u, f, ws))
+    fwd_c()
+    ms_fc = ev_ms(fwd_c, reps=5)
+    bwd_c = lambda: bs.bs_block_backward_ckpt(ps.handle, "line", 2, "jacobi", 0.8, 20, 5, f, g, gu0, gf, geps, ws)
+    bwd_c()
+    ms_bc = ev_ms(bwd_c, reps=5)
     cells = 128 ** 3
     out["c5_adjoint_128_K20"] = {"forward_ms": round(ms_f, 3), "backward_ms": round(ms_b, 3),
                                  "backward_over_forward": round(ms_b / ms_f, 2),
+                                 "forward_keeping_checkpoints_ms": round(ms_fc, 3),
+                                 "backward_from_checkpoints_ms": round(ms_bc, 3),
+                                 "backward_from_checkpoints_over_forward": round(ms_bc / ms_f, 2),
                                  "forward_glups": round(cells * 20 / (ms_f * 1e-3) / 1e9, 3),
                                  "workspace_MiB": round(nbytes / 2 ** 20, 1)}
     ps.close()

@@ -358,6 +358,26 @@ bs_status bs_block_backward(bs_patchset *ps, int32_t kind, int32_t axis, bs_sche
                             const double *grad_uK, double *grad_u0, double *grad_f, double *grad_eps,
                             void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* The same adjoint split at its checkpoints, so that the backward does not
+ * run the forward sweeps again (section 2's sweeps; the checkpointing is
+ * the differentiable smoother's).  bs_block_forward_ckpt: u in = u0 (u
+ * layout, ghosts included), out = u_K after the nsweeps sweeps
+ * bs_block_backward differentiates (the ghosts unchanged); it leaves the
+ * states at sweeps 0, c, 2c, ... (c = ckpt_every) in `workspace`
+ * (bs_block_backward_workspace_bytes bytes, the same arguments).
+ * bs_block_backward_ckpt: bs_block_backward from those checkpoints; it
+ * takes no u0.  Between the two calls the workspace, f, the patch set's
+ * eps and the arguments must stay the same; the backward leaves the
+ * checkpoints as they are, so it may run again for another grad_uK.  Errors
+ * as bs_block_backward; both are asynchronous on `stream`. */
+bs_status bs_block_forward_ckpt(bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme, double omega,
+                                int32_t nsweeps, int32_t ckpt_every, double *u, const double *f, void *workspace,
+                                size_t workspace_bytes, hipStream_t stream);
+bs_status bs_block_backward_ckpt(bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme, double omega,
+                                 int32_t nsweeps, int32_t ckpt_every, const double *f, const double *grad_uK,
+                                 double *grad_u0, double *grad_f, double *grad_eps, void *workspace,
+                                 size_t workspace_bytes, hipStream_t stream);
+
 /* bs_residual for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation): the
  * same result and per-patch norms, bit for bit, with the per-tile partial sums

@@ -32,8 +32,8 @@ EXPORTS = ("bs_layout_plan", "bs_create_patchset", "bs_destroy_patchset", "bs_se
            "bs_residual", "bs_line_relax", "bs_plane_relax", "bs_cube_prepare", "bs_cube_relax",
            "bs_autotune_line", "bs_line_config", "bs_set_bc", "bs_set_links", "bs_exchange_ghosts",
            "bs_mg_create", "bs_mg_destroy", "bs_mg_levels", "bs_vcycle", "bs_block_backward_workspace_bytes",
-           "bs_block_backward", "bs_backward_workspace_bytes", "bs_relax_backward", "bs_residual_noalloc",
-           "bs_last_error")
+           "bs_block_backward", "bs_block_forward_ckpt", "bs_block_backward_ckpt", "bs_backward_workspace_bytes",
+           "bs_relax_backward", "bs_residual_noalloc", "bs_last_error")
 
 
 class BSError(RuntimeError):
@@ -100,12 +100,14 @@ def lib():
     L.bs_block_backward_workspace_bytes.argtypes = [vp, i32, i32, ctypes.c_int, i32, i32]
     L.bs_block_backward_workspace_bytes.restype = sz
     L.bs_block_backward.argtypes = [vp, i32, i32, ctypes.c_int, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.bs_block_forward_ckpt.argtypes = [vp, i32, i32, ctypes.c_int, dbl, i32, i32, vp, vp, vp, sz, vp]
+    L.bs_block_backward_ckpt.argtypes = [vp, i32, i32, ctypes.c_int, dbl, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     L.bs_last_error.argtypes = []
     L.bs_last_error.restype = ctypes.c_char_p
     for name in ("bs_layout_plan", "bs_create_patchset", "bs_set_eps", "bs_layout", "bs_residual",
                  "bs_line_relax", "bs_plane_relax", "bs_autotune_line", "bs_line_config", "bs_relax_backward",
                  "bs_set_bc", "bs_set_links", "bs_exchange_ghosts", "bs_mg_create", "bs_mg_levels", "bs_vcycle",
-                 "bs_block_backward"):
+                 "bs_block_backward", "bs_block_forward_ckpt", "bs_block_backward_ckpt"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -305,6 +307,23 @@ def bs_block_backward(ps, kind, axis, scheme, omega, nsweeps, ckpt_every, u0, f,
                                    _ptr(grad_eps), _ptr(workspace), wb, _stream(stream)))
 
 
+def bs_block_forward_ckpt(ps, kind, axis, scheme, omega, nsweeps, ckpt_every, u, f, workspace, stream=None):
+    """u (in: u0, out: u_K) after the sweeps bs_block_backward differentiates,
+    with the checkpoints left in `workspace` for bs_block_backward_ckpt."""
+    wb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().bs_block_forward_ckpt(ps, _kind(kind), int(axis), _scheme(scheme), float(omega), int(nsweeps),
+                                       int(ckpt_every), _ptr(u), _ptr(f), _ptr(workspace), wb, _stream(stream)))
+
+
+def bs_block_backward_ckpt(ps, kind, axis, scheme, omega, nsweeps, ckpt_every, f, grad_uK, grad_u0=None,
+                           grad_f=None, grad_eps=None, workspace=None, stream=None):
+    """bs_block_backward from the checkpoints bs_block_forward_ckpt left in `workspace`."""
+    wb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().bs_block_backward_ckpt(ps, _kind(kind), int(axis), _scheme(scheme), float(omega), int(nsweeps),
+                                        int(ckpt_every), _ptr(f), _ptr(grad_uK), _ptr(grad_u0), _ptr(grad_f),
+                                        _ptr(grad_eps), _ptr(workspace), wb, _stream(stream)))
+
+
 def stream_triad(a, b, c, mode=0, stream=None):
     """Device streaming probe c = a + b (float64, n even): the 24 bytes per
     element of a line sweep at the HBM ceiling (mode 1: nontemporal b)."""
@@ -493,9 +512,13 @@ class LineJacobiFn(torch.autograd.Function):
     def forward(ctx, f, u0, eps, ps, axis, omega, K, ckpt):
         _sync_eps(ps, eps)
         u = u0.detach().clone()
-        work = torch.empty_like(u)
-        ps.line_relax(axis, "jacobi", omega, K, u, f.detach(), work)
+        # the forward keeps its checkpoints for the backward (workspace held
+        # until then)
+        nbytes = bs_backward_workspace_bytes(ps.handle, axis, K, ckpt)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=u0.device)
+        bs_block_forward_ckpt(ps.handle, "line", axis, "jacobi", omega, K, ckpt, u, f.detach(), ws)
         ctx.save_for_backward(f, u0, eps)
+        ctx.ws = ws
         ctx.cfg = (ps, int(axis), float(omega), int(K), int(ckpt))
         return u
 
@@ -504,13 +527,12 @@ class LineJacobiFn(torch.autograd.Function):
         f, u0, eps = ctx.saved_tensors
         ps, axis, omega, K, ckpt = ctx.cfg
         _sync_eps(ps, eps)
-        nbytes = bs_backward_workspace_bytes(ps.handle, axis, K, ckpt)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=u0.device)
         g_u0 = torch.zeros_like(u0)     # alignment gaps between patches stay 0
         g_f = torch.zeros_like(f)
         g_eps = torch.empty(ps.npatch * 3, dtype=torch.float64, device=u0.device)
-        bs_relax_backward(ps.handle, axis, omega, K, ckpt, u0.detach(), f.detach(), grad_uK.contiguous(),
-                          g_u0, g_f, g_eps, ws)
+        bs_block_backward_ckpt(ps.handle, "line", axis, "jacobi", omega, K, ckpt, f.detach(), grad_uK.contiguous(),
+                               g_u0, g_f, g_eps, ctx.ws)
+        ctx.ws = None
         return g_f, g_u0, g_eps.view(eps.shape).to(eps.device), None, None, None, None, None
 
 
@@ -525,12 +547,12 @@ class BlockSmoothFn(torch.autograd.Function):
     def forward(ctx, f, u0, eps, ps, kind, axis, scheme, omega, K, ckpt):
         _sync_eps(ps, eps)
         u = u0.detach().clone()
-        work = torch.empty_like(u)
-        if kind == "line":
-            ps.line_relax(axis, scheme, omega, K, u, f.detach(), work)
-        else:
-            ps.plane_relax(axis, scheme, omega, K, u, f.detach(), work)
+        # the forward keeps its checkpoints for the backward
+        nbytes = bs_block_backward_workspace_bytes(ps.handle, kind, axis, scheme, K, ckpt)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=u0.device)
+        bs_block_forward_ckpt(ps.handle, kind, axis, scheme, omega, K, ckpt, u, f.detach(), ws)
         ctx.save_for_backward(f, u0, eps)
+        ctx.ws = ws
         ctx.cfg = (ps, kind, int(axis), scheme, float(omega), int(K), int(ckpt))
         return u
 
@@ -539,13 +561,12 @@ class BlockSmoothFn(torch.autograd.Function):
         f, u0, eps = ctx.saved_tensors
         ps, kind, axis, scheme, omega, K, ckpt = ctx.cfg
         _sync_eps(ps, eps)
-        nbytes = bs_block_backward_workspace_bytes(ps.handle, kind, axis, scheme, K, ckpt)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=u0.device)
         g_u0 = torch.zeros_like(u0)
         g_f = torch.zeros_like(f)
         g_eps = torch.empty(ps.npatch * 3, dtype=torch.float64, device=u0.device)
-        bs_block_backward(ps.handle, kind, axis, scheme, omega, K, ckpt, u0.detach(), f.detach(),
-                          grad_uK.contiguous(), g_u0, g_f, g_eps, ws)
+        bs_block_backward_ckpt(ps.handle, kind, axis, scheme, omega, K, ckpt, f.detach(), grad_uK.contiguous(),
+                               g_u0, g_f, g_eps, ctx.ws)
+        ctx.ws = None
         return g_f, g_u0, g_eps.view(eps.shape).to(eps.device), None, None, None, None, None, None, None
 
 

@@ -1,5 +1,7 @@
 // Backward of K damped Jacobi or two-colour GS sweeps of line or plane blocks
-// with checkpointing: states at sweeps 0, c, 2c, ... are kept; each segment
+// with checkpointing: states at sweeps 0, c, 2c, ... are kept (taken here, or
+// left in the workspace by a forward call that keeps them, so that the
+// backward need not run the forward again); each segment
 // is recomputed forward and then walked in reverse, one half-step at a time
 // (a Jacobi sweep is one half-step over all blocks, a two-colour sweep colour
 // 0 then colour 1, undone colour 1 first), with the adjoint step of
@@ -49,43 +51,39 @@ bs_status check_backward(const bs_patchset *ps, int32_t kind, int32_t axis, bs_s
     return BS_OK;
 }
 
+// What one call of block_adjoint does.
+enum class AdjMode {
+    full,       // forward to the checkpoints, then the reverse pass
+    forward,    // only the forward: u0 -> u_K, checkpoints left in the workspace
+    reverse     // only the reverse pass, from checkpoints a forward call left
+};
+
 }  // namespace
 
 }  // namespace bs
 
 using namespace bs;
 
-extern "C" {
+namespace {
 
-size_t bs_block_backward_workspace_bytes(const bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme,
-                                         int32_t nsweeps, int32_t ckpt_every)
+// u: u0 (full mode), u0 in / u_K out (forward mode), unused (reverse mode).
+bs_status block_adjoint(AdjMode mode, const char *fn, bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme,
+                        double omega, int32_t nsweeps, int32_t ckpt_every, double *u, const double *f,
+                        const double *grad_uK, double *grad_u0, double *grad_f, double *grad_eps, void *workspace,
+                        size_t workspace_bytes, hipStream_t stream)
 {
-    if (!ps || (kind != 0 && kind != 1) || axis < 0 || axis > 2 || nsweeps < 0 || ckpt_every < 1) return 0;
-    if (scheme != BS_JACOBI && scheme != BS_COLORED_GS) return 0;
-    return plan_backward(ps, nsweeps, ckpt_every, scheme == BS_COLORED_GS).total;
-}
-
-size_t bs_backward_workspace_bytes(const bs_patchset *ps, int32_t axis, int32_t nsweeps, int32_t ckpt_every)
-{
-    return bs_block_backward_workspace_bytes(ps, 0, axis, BS_JACOBI, nsweeps, ckpt_every);
-}
-
-bs_status bs_block_backward(bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme, double omega,
-                            int32_t nsweeps, int32_t ckpt_every, const double *u0, const double *f,
-                            const double *grad_uK, double *grad_u0, double *grad_f, double *grad_eps,
-                            void *workspace, size_t workspace_bytes, hipStream_t stream)
-{
-    const char *fn = "bs_block_backward";
     bs_status st = check_backward(ps, kind, axis, scheme, nsweeps, ckpt_every, fn);
     if (st != BS_OK) return st;
     if (!(omega > 0.0 && omega < 2.0)) return fail(BS_ERR_INVALID, "%s: omega must be in (0, 2)", fn);
-    if (!u0 || !f || !grad_uK) return fail(BS_ERR_INVALID, "%s: null argument", fn);
+    if (!f || (mode != AdjMode::reverse && !u) || (mode != AdjMode::forward && !grad_uK))
+        return fail(BS_ERR_INVALID, "%s: null argument", fn);
     if (!workspace) return fail(BS_ERR_INVALID, "%s: null workspace", fn);
     if (ghost_active(ps)) return fail(BS_ERR_UNSUPPORTED, "%s: patch sets with links or extrapolated faces", fn);
     const bool gs = scheme == BS_COLORED_GS;
     const BackwardPlan bp = plan_backward(ps, nsweeps, ckpt_every, gs);
     if (workspace_bytes < bp.total)
         return fail(BS_ERR_INVALID, "%s: workspace of %zu bytes, needs %zu", fn, workspace_bytes, bp.total);
+    const double *u0 = u;
     LineCfg cj, cc;
     if (kind == 0) {
         if ((st = check_line_ps_ext(ps, axis, fn)) != BS_OK) return st;
@@ -166,21 +164,34 @@ bs_status bs_block_backward(bs_patchset *ps, int32_t kind, int32_t axis, bs_sche
                    "adjoint step");
     };
 
-    // every state buffer carries u0's ghosts; checkpoint 0 is u0
-    for (double *bf : ckpt)
-        if ((st = chk(launch_ghost_copy(u0, bf, pdd, ps->npatch, stream), "ghost copy")) != BS_OK) return st;
-    for (double *bf : seg)
-        if ((st = chk(launch_ghost_copy(u0, bf, pdd, ps->npatch, stream), "ghost copy")) != BS_OK) return st;
-    if (mid && (st = chk(launch_ghost_copy(u0, mid, pdd, ps->npatch, stream), "ghost copy")) != BS_OK) return st;
-    if ((st = chk(launch_interior_copy(u0, ckpt[0], pdd, ps->npatch, stream), "copy")) != BS_OK) return st;
-    // forward: checkpoints at sweeps c, 2c, ...
-    for (int s = 0; s + 1 < bp.ncp; ++s) {
-        const double *src = ckpt[s];
-        for (int j = 1; j <= ckpt_every; ++j) {
-            double *dst = j == ckpt_every ? ckpt[s + 1] : seg[j - 1];
+    if (mode != AdjMode::reverse) {
+        // every state buffer carries u0's ghosts; checkpoint 0 is u0
+        for (double *bf : ckpt)
+            if ((st = chk(launch_ghost_copy(u0, bf, pdd, ps->npatch, stream), "ghost copy")) != BS_OK) return st;
+        for (double *bf : seg)
+            if ((st = chk(launch_ghost_copy(u0, bf, pdd, ps->npatch, stream), "ghost copy")) != BS_OK) return st;
+        if (mid && (st = chk(launch_ghost_copy(u0, mid, pdd, ps->npatch, stream), "ghost copy")) != BS_OK) return st;
+        if ((st = chk(launch_interior_copy(u0, ckpt[0], pdd, ps->npatch, stream), "copy")) != BS_OK) return st;
+        // forward: checkpoints at sweeps c, 2c, ...
+        for (int s = 0; s + 1 < bp.ncp; ++s) {
+            const double *src = ckpt[s];
+            for (int j = 1; j <= ckpt_every; ++j) {
+                double *dst = j == ckpt_every ? ckpt[s + 1] : seg[j - 1];
+                if ((st = sweep(src, dst)) != BS_OK) return st;
+                src = dst;
+            }
+        }
+    }
+    if (mode == AdjMode::forward) {
+        // the sweeps after the last checkpoint, the last one into u
+        const int rest = nsweeps - (bp.ncp - 1) * ckpt_every;
+        const double *src = ckpt[bp.ncp - 1];
+        for (int j = 1; j <= rest; ++j) {
+            double *dst = j == rest ? u : seg[j - 1];
             if ((st = sweep(src, dst)) != BS_OK) return st;
             src = dst;
         }
+        return BS_OK;
     }
     // adjoint state (lambda and w start at zero, ghosts included)
     if ((st = chk(launch_fill(lam, ps->u_numel, 0.0, stream), "fill")) != BS_OK) return st;
@@ -209,6 +220,51 @@ bs_status bs_block_backward(bs_patchset *ps, int32_t kind, int32_t axis, bs_sche
     if (grad_eps && (st = chk(launch_eps_final(acc, pfirst, ps->npatch, omega, grad_eps, stream), "eps reduce")) != BS_OK)
         return st;
     return BS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t bs_block_backward_workspace_bytes(const bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme,
+                                         int32_t nsweeps, int32_t ckpt_every)
+{
+    if (!ps || (kind != 0 && kind != 1) || axis < 0 || axis > 2 || nsweeps < 0 || ckpt_every < 1) return 0;
+    if (scheme != BS_JACOBI && scheme != BS_COLORED_GS) return 0;
+    return plan_backward(ps, nsweeps, ckpt_every, scheme == BS_COLORED_GS).total;
+}
+
+size_t bs_backward_workspace_bytes(const bs_patchset *ps, int32_t axis, int32_t nsweeps, int32_t ckpt_every)
+{
+    return bs_block_backward_workspace_bytes(ps, 0, axis, BS_JACOBI, nsweeps, ckpt_every);
+}
+
+bs_status bs_block_backward(bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme, double omega,
+                            int32_t nsweeps, int32_t ckpt_every, const double *u0, const double *f,
+                            const double *grad_uK, double *grad_u0, double *grad_f, double *grad_eps,
+                            void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    return block_adjoint(AdjMode::full, "bs_block_backward", ps, kind, axis, scheme, omega, nsweeps, ckpt_every,
+                         const_cast<double *>(u0), f, grad_uK, grad_u0, grad_f, grad_eps, workspace, workspace_bytes,
+                         stream);
+}
+
+bs_status bs_block_forward_ckpt(bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme, double omega,
+                                int32_t nsweeps, int32_t ckpt_every, double *u, const double *f, void *workspace,
+                                size_t workspace_bytes, hipStream_t stream)
+{
+    return block_adjoint(AdjMode::forward, "bs_block_forward_ckpt", ps, kind, axis, scheme, omega, nsweeps,
+                         ckpt_every, u, f, nullptr, nullptr, nullptr, nullptr, workspace, workspace_bytes, stream);
+}
+
+bs_status bs_block_backward_ckpt(bs_patchset *ps, int32_t kind, int32_t axis, bs_scheme scheme, double omega,
+                                 int32_t nsweeps, int32_t ckpt_every, const double *f, const double *grad_uK,
+                                 double *grad_u0, double *grad_f, double *grad_eps, void *workspace,
+                                 size_t workspace_bytes, hipStream_t stream)
+{
+    return block_adjoint(AdjMode::reverse, "bs_block_backward_ckpt", ps, kind, axis, scheme, omega, nsweeps,
+                         ckpt_every, nullptr, f, grad_uK, grad_u0, grad_f, grad_eps, workspace, workspace_bytes,
+                         stream);
 }
 
 bs_status bs_relax_backward(bs_patchset *ps, int32_t axis, double omega, int32_t nsweeps, int32_t ckpt_every,

@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "bs_internal.h"
+#include "line_dev.h"
 
 namespace bs {
 
@@ -67,9 +68,12 @@ __global__ void __launch_bounds__(256) k_u_to_f(const double *src, double *dst, 
 
 // One tile of the residual's tiling (tx x ty columns marched along z): the
 // z-neighbours of lambda, U and w stay in registers and the next plane's
-// values are fetched a step ahead; each column's partial sums run in
-// increasing z and the tile's sums reduce in a fixed tree, so the epsilon
-// gradient is bit-reproducible.
+// values are fetched a step ahead; the x-neighbours come from the adjacent
+// lanes (DPP) except at a row's ends, which load theirs; w's neighbours are
+// read only along the axes the blocks span (SP, the spans mask).  Each
+// column's partial sums run in increasing z and the tile's sums reduce in a
+// fixed tree, so the epsilon gradient is bit-reproducible.
+template <int SP>
 __global__ void __launch_bounds__(kAdjThreads) k_adj_step(AdjArgs a)
 {
     __shared__ double red[3][kAdjThreads];
@@ -80,55 +84,81 @@ __global__ void __launch_bounds__(kAdjThreads) k_adj_step(AdjArgs a)
     const int64_t sx = nx + 2, sy = sx * (int64_t)(ny + 2), pf = (int64_t)nx * ny;
     const double e0 = pd->eps[0], e1 = pd->eps[1], e2 = pd->eps[2];
     const double om = a.omega, omh2 = a.omega * pd->h2;
-    const int spans = a.spans;
     int tx = 64;
     while (tx > 1 && (tx >> 1) >= nx) tx >>= 1;
-    const int i = t.x0 + (int)(threadIdx.x & (tx - 1));
+    const int li = (int)(threadIdx.x & (tx - 1));
+    const int i = t.x0 + li;
     const int j = t.y0 + (int)(threadIdx.x / tx);
     const bool valid = i < nx && j < ny;
     const int ic = i < nx ? i : nx - 1, jc = j < ny ? j : ny - 1;   // in-patch addresses for every lane
+    // row ends take their x-neighbours from memory (both sides when tx = 1)
+    const bool need_l = li == 0, need_r = li == tx - 1 || i >= nx - 1;
+    const int64_t xo = need_l ? -1 : 1;
+    const bool two = tx == 1;
     const int k0 = t.z0, k1 = t.z1;
     const int64_t col = pd->uoff + (int64_t)(jc + 1) * sx + (ic + 1);   // column (i, j); plane index k + 1
     const int64_t fo = pd->foff + (int64_t)jc * nx + ic;
-    double lm = a.lam[col + (int64_t)k0 * sy], lc = a.lam[col + (int64_t)(k0 + 1) * sy];
-    double um = a.U[col + (int64_t)k0 * sy], uc = a.U[col + (int64_t)(k0 + 1) * sy];
-    double wm = a.w[col + (int64_t)k0 * sy], wc = a.w[col + (int64_t)(k0 + 1) * sy];
-    double lp = a.lam[col + (int64_t)(k0 + 2) * sy], up = a.U[col + (int64_t)(k0 + 2) * sy];
-    double wp = a.w[col + (int64_t)(k0 + 2) * sy];
+    const double *Lc = a.lam + col, *Uc = a.U + col, *Wc = a.w + col;
+    double lm = Lc[(int64_t)k0 * sy], lc = Lc[(int64_t)(k0 + 1) * sy], lp = Lc[(int64_t)(k0 + 2) * sy];
+    double um = Uc[(int64_t)k0 * sy], uc = Uc[(int64_t)(k0 + 1) * sy], up = Uc[(int64_t)(k0 + 2) * sy];
+    double wm = Wc[(int64_t)k0 * sy], wc = Wc[(int64_t)(k0 + 1) * sy], wp = Wc[(int64_t)(k0 + 2) * sy];
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
     for (int k = k0; k < k1; ++k) {
-        const int64_t c = col + (int64_t)(k + 1) * sy;
+        const int64_t c = (int64_t)(k + 1) * sy;
         // the next step's plane (clamped inside the patch on the last step)
-        const int64_t cn = col + (int64_t)((k + 1 < nz ? k + 1 : nz - 1) + 2) * sy;
-        const double lp_n = a.lam[cn], up_n = a.U[cn], wp_n = a.w[cn];
-        const double lxm = a.lam[c - 1], lxp = a.lam[c + 1], lym = a.lam[c - sx], lyp = a.lam[c + sx];
-        const double uxm = a.U[c - 1], uxp = a.U[c + 1], uym = a.U[c - sx], uyp = a.U[c + sx];
+        const int64_t cn = (int64_t)((k + 1 < nz ? k + 1 : nz - 1) + 2) * sy;
+        const double lp_n = Lc[cn], up_n = Uc[cn], wp_n = Wc[cn];
+        const double lym = Lc[c - sx], lyp = Lc[c + sx], uym = Uc[c - sx], uyp = Uc[c + sx];
+        const double lxa = Lc[c + xo], uxa = Uc[c + xo];
+        const double lxb = two ? Lc[c + 1] : 0.0, uxb = two ? Uc[c + 1] : 0.0;
         // w's neighbours along x and y (z from registers); w is zero outside
         // the blocks' cells, so a block's edge sees zero beyond it
-        const double wxm = a.w[c - 1], wxp = a.w[c + 1], wym = a.w[c - sx], wyp = a.w[c + sx];
-        const double g0 = a.gbar[c];
+        double wym = 0.0, wyp = 0.0, wxa = 0.0, wxb = 0.0;
+        if constexpr ((SP & 2) != 0) {
+            wym = Wc[c - sx];
+            wyp = Wc[c + sx];
+        }
+        if constexpr ((SP & 1) != 0) {
+            wxa = Wc[c + xo];
+            wxb = two ? Wc[c + 1] : 0.0;
+        }
+        const double g0 = a.gbar[col + c];
         const double gf0 = a.gf ? a.gf[fo + (int64_t)k * pf] : 0.0;
+        // the moves run under full EXEC: the empty asm pins their results
+        // before the selects
+        double ldl = lane_shift<-1>(lc), ldr = lane_shift<+1>(lc);
+        double udl = lane_shift<-1>(uc), udr = lane_shift<+1>(uc);
+        asm volatile("" : "+v"(ldl), "+v"(ldr), "+v"(udl), "+v"(udr));
+        const double lxm = need_l ? lxa : ldl, lxp = need_r ? (need_l ? lxb : lxa) : ldr;
+        const double uxm = need_l ? uxa : udl, uxp = need_r ? (need_l ? uxb : uxa) : udr;
         double al = fma(e0, 2.0 * lc - lxm - lxp, 0.0);
         al = fma(e1, 2.0 * lc - lym - lyp, al);
         al = fma(e2, 2.0 * lc - lm - lp, al);
         const double w2 = 2.0 * wc;
-        const double mw0 = (spans & 1) ? w2 - wxm - wxp : w2;
-        const double mw1 = (spans & 2) ? w2 - wym - wyp : w2;
-        const double mw2 = (spans & 4) ? w2 - wm - wp : w2;
+        double mw0 = w2;
+        if constexpr ((SP & 1) != 0) {
+            double wdl = lane_shift<-1>(wc), wdr = lane_shift<+1>(wc);
+            asm volatile("" : "+v"(wdl), "+v"(wdr));
+            const double wxm = need_l ? wxa : wdl, wxp = need_r ? (need_l ? wxb : wxa) : wdr;
+            mw0 = w2 - wxm - wxp;
+        }
+        const double mw1 = (SP & 2) ? w2 - wym - wyp : w2;
+        const double mw2 = (SP & 4) ? w2 - wm - wp : w2;
         if (valid) {
             p0 += lc * ((2.0 * uc - uxm - uxp) + mw0);
             p1 += lc * ((2.0 * uc - uym - uyp) + mw1);
             p2 += lc * ((2.0 * uc - um - up) + mw2);
-            a.gbar[c] = fma(-om, al, g0);
+            double *gb = a.gbar + col + c;
+            gb[0] = fma(-om, al, g0);
             if (a.gf) a.gf[fo + (int64_t)k * pf] = fma(omh2, lc, gf0);
             // face ghosts: each is next to exactly one interior cell, so no two
             // threads touch the same entry
-            if (i == 0) a.gbar[c - 1] = fma(om * e0, lc, a.gbar[c - 1]);
-            if (i == nx - 1) a.gbar[c + 1] = fma(om * e0, lc, a.gbar[c + 1]);
-            if (j == 0) a.gbar[c - sx] = fma(om * e1, lc, a.gbar[c - sx]);
-            if (j == ny - 1) a.gbar[c + sx] = fma(om * e1, lc, a.gbar[c + sx]);
-            if (k == 0) a.gbar[c - sy] = fma(om * e2, lc, a.gbar[c - sy]);
-            if (k == nz - 1) a.gbar[c + sy] = fma(om * e2, lc, a.gbar[c + sy]);
+            if (i == 0) gb[-1] = fma(om * e0, lc, gb[-1]);
+            if (i == nx - 1) gb[1] = fma(om * e0, lc, gb[1]);
+            if (j == 0) gb[-sx] = fma(om * e1, lc, gb[-sx]);
+            if (j == ny - 1) gb[sx] = fma(om * e1, lc, gb[sx]);
+            if (k == 0) gb[-sy] = fma(om * e2, lc, gb[-sy]);
+            if (k == nz - 1) gb[sy] = fma(om * e2, lc, gb[sy]);
         }
         lm = lc; lc = lp; lp = lp_n;
         um = uc; uc = up; up = up_n;
@@ -196,7 +226,16 @@ hipError_t launch_adj_step(const double *lam, const double *U, const double *w, 
 {
     if (ntiles <= 0) return hipSuccess;
     AdjArgs a{lam, U, w, gbar, gf, acc, pd, tiles, spans, omega};
-    hipLaunchKernelGGL(k_adj_step, dim3(ntiles), dim3(kAdjThreads), 0, s, a);
+    const dim3 g(ntiles), t(kAdjThreads);
+    switch (spans) {
+    case 1: hipLaunchKernelGGL(k_adj_step<1>, g, t, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_adj_step<2>, g, t, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_adj_step<3>, g, t, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_adj_step<4>, g, t, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_adj_step<5>, g, t, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_adj_step<6>, g, t, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

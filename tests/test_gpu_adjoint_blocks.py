@@ -112,3 +112,40 @@ def test_block_backward_refusals():
     assert ei.value.status == bs.BS_ERR_INVALID
     assert bs.bs_block_backward_workspace_bytes(ps.handle, "line", 2, "chaotic", 2, 1) == 0
     ps.close()
+
+
+@pytest.mark.parametrize("kind,axis,scheme,omega", [("line", 2, "jacobi", 0.8), ("line", 1, "colored", 1.0),
+                                                    ("line", 0, "jacobi", 1.1), ("plane", 2, "jacobi", 1.0),
+                                                    ("plane", 0, "colored", 1.2)])
+@pytest.mark.parametrize("K,ckpt", [(7, 3), (4, 5), (1, 1)])
+def test_forward_checkpoints_then_backward(kind, axis, scheme, omega, K, ckpt):
+    """bs_block_forward_ckpt + bs_block_backward_ckpt: the forward's u_K is
+    the smoother's (the same sweeps as line_relax / plane_relax, to rounding
+    order), and the backward from its checkpoints gives bit for bit the
+    gradients of bs_block_backward, twice in a row (the checkpoints stay)."""
+    p = small_patch(19, 13, 22, seed=17 + axis, eps=(1.0, 4.0, 9.0))
+    gK = np.random.default_rng(8).uniform(-1, 1, p.u0.shape)
+    log("forward ckpt %s %d %s %.1f K %d ckpt %d" % (kind, axis, scheme, omega, K, ckpt))
+    ref = _grads(p, kind, axis, scheme, omega, K, ckpt, gK)
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    u0, f, g = ps.pack_u([p.u0]), ps.pack_f([p.f]), ps.pack_u([gK])
+    nbytes = bs.bs_block_backward_workspace_bytes(ps.handle, kind, axis, scheme, K, ckpt)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    u = u0.clone()
+    bs.bs_block_forward_ckpt(ps.handle, kind, axis, scheme, omega, K, ckpt, u, f, ws)
+    uref, w = u0.clone(), ps.empty_u()
+    if kind == "line":
+        ps.line_relax(axis, scheme, omega, K, uref, f, w)
+    else:
+        ps.plane_relax(axis, scheme, omega, K, uref, f, w)
+    torch.cuda.synchronize()
+    assert relerr(ps.view_u(u, 0).cpu().numpy(), ps.view_u(uref, 0).cpu().numpy()) < 1e-13
+    for rep in range(2):
+        gu0, gf = torch.zeros_like(u0), torch.zeros_like(f)
+        geps = torch.zeros(3, dtype=torch.float64, device="cuda")
+        bs.bs_block_backward_ckpt(ps.handle, kind, axis, scheme, omega, K, ckpt, f, g, gu0, gf, geps, ws)
+        torch.cuda.synchronize()
+        got = (ps.view_u(gu0, 0).cpu().numpy(), ps.view_f(gf, 0).cpu().numpy(), geps.cpu().numpy())
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), rep
+    ps.close()
