@@ -276,9 +276,9 @@ bs_status bs_line_config(const bs_patchset *ps, int32_t axis, bs_scheme scheme, 
 
 /* Device workspace needed by bs_relax_backward for these arguments, or 0 on
  * invalid arguments.  `axis` (0..2) is the line axis bs_relax_backward will
- * get; it is validated so that the query takes the same arguments as the call
- * it sizes.  The size itself (checkpointed states, one recompute segment and
- * the adjoint work fields) does not depend on the axis. */
+ * get: the size (checkpointed states, one recompute segment, the adjoint
+ * work fields, and for y/z lines the recomputed sweeps' corrections w)
+ * depends on it. */
 size_t bs_backward_workspace_bytes(const bs_patchset *ps, int32_t axis, int32_t nsweeps,
                                    int32_t ckpt_every);
 

@@ -19,21 +19,31 @@ namespace {
 
 struct BackwardPlan {
     int ncp = 0, nseg = 0;       // checkpoints, recomputed states per segment
+    int nw = 0;                  // the recomputed sweeps' corrections w (Jacobi on y/z lines)
     int extra = 0;               // lambda, w, gbar, plus the mid-sweep state of two-colour GS
     size_t state_bytes = 0;      // one u-layout buffer, 256-byte aligned
     size_t acc_bytes = 0;
     size_t total = 0;
 };
 
-BackwardPlan plan_backward(const bs_patchset *ps, int K, int c, bool gs)
+// Jacobi on y/z lines recomputes each segment with sweeps that also write
+// their correction w = M^{-1} r(U), so the reverse steps need no w solve but
+// the segment's last.
+bool keeps_w(int kind, int axis, bool gs)
+{
+    return kind == 0 && axis != 0 && !gs;
+}
+
+BackwardPlan plan_backward(const bs_patchset *ps, int K, int c, bool gs, bool keep_w)
 {
     BackwardPlan b;
     b.ncp = K > 0 ? (K + c - 1) / c : 1;
     b.nseg = std::max(0, std::min(c, K) - 1);
+    b.nw = keep_w ? b.nseg : 0;
     b.extra = gs ? 4 : 3;
     b.state_bytes = (static_cast<size_t>(ps->u_numel) * sizeof(double) + 255) / 256 * 256;
     b.acc_bytes = (static_cast<size_t>(ps->nrtiles) * 3 * sizeof(double) + 255) / 256 * 256;
-    b.total = static_cast<size_t>(b.ncp + b.nseg + b.extra) * b.state_bytes + b.acc_bytes;
+    b.total = static_cast<size_t>(b.ncp + b.nseg + b.nw + b.extra) * b.state_bytes + b.acc_bytes;
     return b;
 }
 
@@ -80,7 +90,8 @@ bs_status block_adjoint(AdjMode mode, const char *fn, bs_patchset *ps, int32_t k
     if (!workspace) return fail(BS_ERR_INVALID, "%s: null workspace", fn);
     if (ghost_active(ps)) return fail(BS_ERR_UNSUPPORTED, "%s: patch sets with links or extrapolated faces", fn);
     const bool gs = scheme == BS_COLORED_GS;
-    const BackwardPlan bp = plan_backward(ps, nsweeps, ckpt_every, gs);
+    const bool keep_w = keeps_w(kind, axis, gs);
+    const BackwardPlan bp = plan_backward(ps, nsweeps, ckpt_every, gs, keep_w);
     if (workspace_bytes < bp.total)
         return fail(BS_ERR_INVALID, "%s: workspace of %zu bytes, needs %zu", fn, workspace_bytes, bp.total);
     const double *u0 = u;
@@ -104,9 +115,10 @@ bs_status block_adjoint(AdjMode mode, const char *fn, bs_patchset *ps, int32_t k
 
     // carve the workspace
     char *wsp = static_cast<char *>(workspace);
-    std::vector<double *> ckpt(bp.ncp), seg(bp.nseg);
+    std::vector<double *> ckpt(bp.ncp), seg(bp.nseg), wseg(bp.nw);
     for (int i = 0; i < bp.ncp; ++i, wsp += bp.state_bytes) ckpt[i] = reinterpret_cast<double *>(wsp);
     for (int i = 0; i < bp.nseg; ++i, wsp += bp.state_bytes) seg[i] = reinterpret_cast<double *>(wsp);
+    for (int i = 0; i < bp.nw; ++i, wsp += bp.state_bytes) wseg[i] = reinterpret_cast<double *>(wsp);
     double *lam = reinterpret_cast<double *>(wsp);
     wsp += bp.state_bytes;
     double *w = reinterpret_cast<double *>(wsp);
@@ -149,8 +161,9 @@ bs_status block_adjoint(AdjMode mode, const char *fn, bs_patchset *ps, int32_t k
         return line_pass(ps, axis, cm ? cc : cj, cm, cm ? colour : 0, src, out, f, omega, stream, -1,
                          residual ? 0 : 1, 1);
     };
-    // the reverse of one half-step from state U for colour (-1: all blocks)
-    auto reverse = [&](int colour, const double *U) -> bs_status {
+    // the reverse of one half-step from state U for colour (-1: all blocks);
+    // wk: U's correction w when a recomputing sweep kept it
+    auto reverse = [&](int colour, const double *U, const double *wk) -> bs_status {
         bs_status s2;
         // blocks of the other colour (and every ghost) must read zero in lambda;
         // w only matters on the half-step's blocks (the planes' solve adds into it)
@@ -158,9 +171,12 @@ bs_status block_adjoint(AdjMode mode, const char *fn, bs_patchset *ps, int32_t k
             if ((s2 = chk(launch_fill(lam, ps->u_numel, 0.0, stream), "fill")) != BS_OK) return s2;
             if (kind == 1 && (s2 = chk(launch_fill(w, ps->u_numel, 0.0, stream), "fill")) != BS_OK) return s2;
         }
-        if ((s2 = solve(colour, U, true, w)) != BS_OK) return s2;
+        if (!wk) {
+            if ((s2 = solve(colour, U, true, w)) != BS_OK) return s2;
+            wk = w;
+        }
         if ((s2 = solve(colour, gbar, false, lam)) != BS_OK) return s2;
-        return chk(launch_adj_step(lam, U, w, gbar, grad_f, acc, pdd, tiles, ps->nrtiles, spans, omega, stream),
+        return chk(launch_adj_step(lam, U, wk, gbar, grad_f, acc, pdd, tiles, ps->nrtiles, spans, omega, stream),
                    "adjoint step");
     };
 
@@ -196,25 +212,33 @@ bs_status block_adjoint(AdjMode mode, const char *fn, bs_patchset *ps, int32_t k
     // adjoint state (lambda and w start at zero, ghosts included)
     if ((st = chk(launch_fill(lam, ps->u_numel, 0.0, stream), "fill")) != BS_OK) return st;
     if ((st = chk(launch_fill(w, ps->u_numel, 0.0, stream), "fill")) != BS_OK) return st;
+    for (double *bf : wseg)
+        if ((st = chk(launch_fill(bf, ps->u_numel, 0.0, stream), "fill")) != BS_OK) return st;
     if ((st = chk(launch_fill(acc, static_cast<int64_t>(ps->nrtiles) * 3, 0.0, stream), "fill")) != BS_OK) return st;
     if (grad_f && (st = chk(launch_fill(grad_f, ps->f_numel, 0.0, stream), "fill")) != BS_OK) return st;
     if ((st = chk(launch_adj_init(grad_uK, gbar, pdd, ps->npatch, stream), "adjoint init")) != BS_OK) return st;
     // reverse, one segment at a time
     for (int s = bp.ncp - 1; s >= 0; --s) {
         const int k0 = s * ckpt_every, k1 = std::min(nsweeps, k0 + ckpt_every);
-        for (int j = 1; j < k1 - k0; ++j)
-            if ((st = sweep(j == 1 ? ckpt[s] : seg[j - 2], seg[j - 1])) != BS_OK) return st;
+        for (int j = 1; j < k1 - k0; ++j) {
+            const double *src = j == 1 ? ckpt[s] : seg[j - 2];
+            // state k0 + j, and (keep_w) the correction of state k0 + j - 1
+            st = keep_w ? line_pass(ps, axis, cj, 0, 0, src, seg[j - 1], f, omega, stream, -1, 0, 2, 0, wseg[j - 1])
+                        : sweep(src, seg[j - 1]);
+            if (st != BS_OK) return st;
+        }
         for (int k = k1 - 1; k >= k0; --k) {
             const double *Uk = k == k0 ? ckpt[s] : seg[k - k0 - 1];
             if (!gs) {
-                if ((st = reverse(-1, Uk)) != BS_OK) return st;
+                const double *wk = (keep_w && k < k1 - 1) ? wseg[k - k0] : nullptr;
+                if ((st = reverse(-1, Uk, wk)) != BS_OK) return st;
                 continue;
             }
             // the mid-sweep state, then colour 1 undone before colour 0
             if ((st = chk(launch_interior_copy(Uk, mid, pdd, ps->npatch, stream), "copy")) != BS_OK) return st;
             if ((st = half(0, mid, mid)) != BS_OK) return st;
-            if ((st = reverse(1, mid)) != BS_OK) return st;
-            if ((st = reverse(0, Uk)) != BS_OK) return st;
+            if ((st = reverse(1, mid, nullptr)) != BS_OK) return st;
+            if ((st = reverse(0, Uk, nullptr)) != BS_OK) return st;
         }
     }
     if (grad_eps && (st = chk(launch_eps_final(acc, pfirst, ps->npatch, omega, grad_eps, stream), "eps reduce")) != BS_OK)
@@ -231,7 +255,8 @@ size_t bs_block_backward_workspace_bytes(const bs_patchset *ps, int32_t kind, in
 {
     if (!ps || (kind != 0 && kind != 1) || axis < 0 || axis > 2 || nsweeps < 0 || ckpt_every < 1) return 0;
     if (scheme != BS_JACOBI && scheme != BS_COLORED_GS) return 0;
-    return plan_backward(ps, nsweeps, ckpt_every, scheme == BS_COLORED_GS).total;
+    const bool gs = scheme == BS_COLORED_GS;
+    return plan_backward(ps, nsweeps, ckpt_every, gs, keeps_w(kind, axis, gs)).total;
 }
 
 size_t bs_backward_workspace_bytes(const bs_patchset *ps, int32_t axis, int32_t nsweeps, int32_t ckpt_every)

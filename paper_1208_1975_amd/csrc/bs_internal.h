@@ -65,12 +65,14 @@ struct LineArgs {
     int32_t colour_mode;    // 0: every line; 1: only lines of the item's colour
     int32_t nitems;         // work items; a workgroup takes items blockIdx.x, +gridDim.x, ...
     int32_t rhs_mode;       // 0: right-hand side = residual h^2 f - A src; 1: = src itself (f unused)
-    int32_t out_mode;       // 0: dst = src + omega du; 1: dst = du (the block solve alone)
+    int32_t out_mode;       // 0: dst = src + omega du; 1: dst = du (the block solve alone);
+                            // 2 (y/z lines, colour mode 0): dst = src + omega du and dst2 = du
     double omega;
     const float *tab32;     // FP32 copy of tab (same offsets)
     int32_t f32;            // 1: block solve in FP32 (residual and update stay FP64)
     int32_t f_stream;       // 1: colour mode 0 reads f with nontemporal loads (data beyond the Infinity Cache)
     int32_t direct;         // 1: colour mode 0 on y/z lines in the direct form dst = M^{-1}(omega b + (1 - omega) M src)
+    double *dst2;           // out_mode 2: receives du
 };
 constexpr int64_t kMallBytes = 256ll << 20;   // MI355X Infinity Cache
 

@@ -258,7 +258,7 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
     ends[(p * 64 + lane) * 2 + 1] = yl;
     __syncthreads();   // every chunk's ends are in LDS; all reads of the tile's lines precede any write
     double uo[kUcLds ? 1 : L];
-    if (!kUcLds && !kDirect && !a.out_mode) {
+    if (!kUcLds && !kDirect && a.out_mode != 1) {
 #pragma unroll
         for (int t = 0; t < L; ++t) uo[kUcLds ? 0 : t] = ldb(ub, cu + (uint32_t)(t < Lp ? t : Lp - 1) * Sa8);
     }
@@ -320,13 +320,17 @@ __device__ __forceinline__ void line_strided_item(const LineArgs &a, const doubl
         return;
     }
     if (valid) {
+        // out_mode 2 (update form only): du itself to dst2 as well
+        char *db2 = reinterpret_cast<char *>((a.out_mode == 2 ? a.dst2 : a.dst) + pd->uoff);
 #pragma unroll
         for (int t = 0; t < L; ++t) {
             if (t < Lp) {
                 const double du = static_cast<double>(fma(anext, ew[t], fma(bprev, ev[t], rs[t])));
                 *reinterpret_cast<double *>(db + (cu + (uint32_t)t * Sa8)) =
-                    (kDirect || a.out_mode) ? du
-                                            : fma(om, du, kUcLds ? ucs[t * nthr + threadIdx.x] : uo[kUcLds ? 0 : t]);
+                    (kDirect || a.out_mode == 1)
+                        ? du
+                        : fma(om, du, kUcLds ? ucs[t * nthr + threadIdx.x] : uo[kUcLds ? 0 : t]);
+                if (!kDirect && a.out_mode == 2) *reinterpret_cast<double *>(db2 + (cu + (uint32_t)t * Sa8)) = du;
             }
         }
     }

@@ -393,8 +393,10 @@ bool pair_for(const bs_patchset *ps, int axis, const LineCfg &c, double omega, i
 
 bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
                     double *dst, const double *f, double omega, hipStream_t stream, int patch, int rhs_mode,
-                    int out_mode, int f32)
+                    int out_mode, int f32, double *dst2)
 {
+    if (out_mode == 2 && (axis == 0 || colour_mode != 0 || rhs_mode || f32 || !dst2 || c.form != 0))
+        return fail(BS_ERR_INVALID, "line pass: the two-output mode needs FP64 Jacobi on y/z lines");
     // chaotic GS on y/z lines with omega = 1: two cells per lane (kind 3)
     const bool pair = colour_mode == 2 && !rhs_mode && !out_mode && pair_for(ps, axis, c, omega, f32);
     const int kind = pair ? 3 : (axis == 0 ? (c.form == 2 ? 2 : 1) : 0);
@@ -423,6 +425,7 @@ bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode
     a.colour_mode = colour_mode;
     a.rhs_mode = rhs_mode;
     a.out_mode = out_mode;
+    a.dst2 = dst2;
     a.omega = omega;
     a.direct = (kind == 0 && c.form == 0 && colour_mode == 0 && !rhs_mode && !out_mode && !f32 && ps->line_direct) ? 1 : 0;
     // the direct form keeps no chunk values of u: the two buffers of chunk ends only

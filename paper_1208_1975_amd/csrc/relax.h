@@ -14,11 +14,12 @@ LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode, bool 
 bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c);
 size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c);
 // rhs_mode 0: right-hand side = residual of src; 1: = src itself.
-// out_mode 0: dst = src + omega du; 1: dst = du.
+// out_mode 0: dst = src + omega du; 1: dst = du; 2 (y/z lines, Jacobi, FP64):
+// dst = src + omega du and dst2 = du.
 // f32: block solve in FP32 (residual and update stay FP64).
 bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
                     double *dst, const double *f, double omega, hipStream_t stream, int patch, int rhs_mode,
-                    int out_mode, int f32 = 0);
+                    int out_mode, int f32 = 0, double *dst2 = nullptr);
 const LineCfg &line_cfg(bs_patchset *ps, int axis, int colour_mode);
 bs_status enqueue_line_sweeps(bs_patchset *ps, int axis, bs_scheme scheme, const LineCfg &c, double omega,
                               int nsweeps, double *u, const double *f, double *work, hipStream_t stream,
