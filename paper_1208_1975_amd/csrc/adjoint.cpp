@@ -100,8 +100,9 @@ bs_status block_adjoint(AdjMode mode, const char *fn, bs_patchset *ps, int32_t k
         if ((st = check_line_ps_ext(ps, axis, fn)) != BS_OK) return st;
         cj = line_cfg(ps, axis, 0);
         cc = line_cfg(ps, axis, 1);
-        // most line passes here are block solves, not direct-form sweeps
-        if (cj.deflt) cj = default_line_cfg(ps, axis, 0, false);
+        // most line passes here are block solves, not direct-form sweeps (and
+        // the z-marching x-line form runs plain sweeps only)
+        if (cj.deflt || cj.form == 2) cj = default_line_cfg(ps, axis, 0, false);
         if ((st = check_line_cfg(ps, axis, cj)) != BS_OK) return st;
         if ((st = check_line_cfg(ps, axis, cc)) != BS_OK) return st;
         if ((st = prepare_lists(ps, axis, cj, 0)) != BS_OK) return st;

@@ -26,10 +26,16 @@ def _setup():
 
 
 def test_default_form_for_short_x_lines():
+    """x-lines of up to 64 cells: Jacobi marches one-wavefront items along
+    z, the Gauss-Seidel schemes take the register form; longer lines the
+    chunked kernel."""
     p = small_patch(48, 5, 6, seed=3)
     s = Single(p)
     cfg = s.ps.line_config(0, "jacobi")
-    assert cfg["form"] == 1 and cfg["chunk_len"] == 4, cfg
+    assert cfg["form"] == 2 and cfg["chunks"] == 1 and cfg["chunk_len"] == 4, cfg
+    for scheme in ("colored", "chaotic"):
+        cfg = s.ps.line_config(0, scheme)
+        assert cfg["form"] == 1 and cfg["chunk_len"] == 4, (scheme, cfg)
     q = small_patch(65, 3, 3, seed=3)
     assert Single(q).ps.line_config(0, "jacobi")["form"] == 0   # longer lines: chunked kernel
 
@@ -104,6 +110,7 @@ def test_fp32_register_x_lines():
     p = small_patch(40, 12, 11, seed=5, eps=(1.0, 3.0, 7.0))
     ref = oracle.line_sweeps(p.u0, p.f, p.eps, p.h, 0, oracle.JACOBI, 0.8, 3)
     s = Single(p)
+    s.ps.set_xline_config("jacobi", waves=4)
     assert s.ps.line_config(0, "jacobi")["form"] == 1
     s.line(0, "jacobi", 0.8, 3, prec="fp32")
     err = relerr(s.u_np(), ref)
