@@ -228,7 +228,9 @@ static hipError_t launch_pair_l(const LineArgs &a, int grid, int nwaves, size_t 
     const int t = 64 * nwaves;
     if (t <= 256) return launch_pair_t<L, 256>(a, grid, nwaves, lds, s);
     if (t <= 512) return launch_pair_t<L, 512>(a, grid, nwaves, lds, s);
-    return launch_pair_t<L, 1024>(a, grid, nwaves, lds, s);
+    // 32-cell chunks: at most eight wavefronts (registers and LDS)
+    if constexpr (L <= 16) return launch_pair_t<L, 1024>(a, grid, nwaves, lds, s);
+    return hipErrorInvalidValue;
 }
 
 template <int L, int MAXT>
@@ -249,6 +251,8 @@ hipError_t prepare_pair_kernels()
     if (e == hipSuccess) e = allow_pair_t<16, 256>();
     if (e == hipSuccess) e = allow_pair_t<16, 512>();
     if (e == hipSuccess) e = allow_pair_t<16, 1024>();
+    if (e == hipSuccess) e = allow_pair_t<32, 256>();
+    if (e == hipSuccess) e = allow_pair_t<32, 512>();
     done = e;
     return e;
 }
@@ -265,6 +269,7 @@ hipError_t launch_line_pair(const LineArgs &a, int grid, int Lmax, int nwaves, h
     switch (Lmax) {
     case 8: return launch_pair_l<8>(a, grid, nwaves, lds, s);
     case 16: return launch_pair_l<16>(a, grid, nwaves, lds, s);
+    case 32: return launch_pair_l<32>(a, grid, nwaves, lds, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -286,14 +286,18 @@ LineCfg default_line_cfg(const bs_patchset *ps, int axis, int colour_mode, bool 
     c.deflt = 1;
     const int nmax = ps->max_n[axis];
     // the fewest chunks whose length stays <= 16 (about 126 VGPRs at 1024
-    // threads); longer lines take 32-cell chunks.  FP64 Jacobi in the direct
-    // form on lines of 129..256 cells takes four chunks of up to 64 cells
+    // threads); longer lines take 32-cell chunks.  On lines of 129..256
+    // cells FP64 Jacobi in the direct form takes four chunks of up to 64 cells
     // (two 4-wave workgroups per CU; 256^3 z-lines: 97 us per sweep against
-    // 102 us with eight chunks of 32 and 104 us with sixteen of 16)
-    const bool wide = axis != 0 && colour_mode == 0 && direct && ps->line_direct && nmax > 128 && nmax <= 256;
+    // 102 us with eight chunks of 32 and 104 us with sixteen of 16), and the
+    // two-cells-per-lane chaotic kernel eight of up to 32 (107-109 against
+    // 111-112 us)
+    const bool yz = axis != 0 && direct && nmax > 128 && nmax <= 256;
+    const int lr_cap = (yz && colour_mode == 0 && ps->line_direct) ? 64
+                       : (yz && colour_mode == 2 && ps->use_pair) ? 32 : 16;
     for (int o = 0; o < kNumPOpt; ++o) {
         const int Lr = (nmax + kPOpts[o] - 1) / kPOpts[o];
-        if (Lr <= (wide ? 64 : 16) || o == kNumPOpt - 1) {
+        if (Lr <= lr_cap || o == kNumPOpt - 1) {
             c.popt = o;
             break;
         }
@@ -400,7 +404,8 @@ bs_status check_line_cfg(const bs_patchset *ps, int axis, const LineCfg &c)
 // pass to one patch's items (one launch per patch and run).
 bool pair_for(const bs_patchset *ps, int axis, const LineCfg &c, double omega, int f32)
 {
-    return axis != 0 && ps->use_pair && omega == 1.0 && !f32 && c.form == 0 && c.Lmax <= 16 && !bline_any(ps, axis);
+    return axis != 0 && ps->use_pair && omega == 1.0 && !f32 && c.form == 0 && c.Lmax <= 32 && !bline_any(ps, axis) &&
+           (c.Lmax <= 16 || c.nwaves <= 8) && pair_lds_bytes(c.Lmax, c.nwaves) <= 160 * 1024;
 }
 
 bs_status line_pass(bs_patchset *ps, int axis, const LineCfg &c, int colour_mode, int run, const double *src,
@@ -690,9 +695,11 @@ bs_status line_relax_impl(bs_patchset *ps, int32_t axis, bs_scheme scheme, doubl
     if (nsweeps == 0) return BS_OK;
     const int cm = scheme_mode(axis, scheme);
     const int f32 = prec == BS_MIXED_FP32 ? 1 : 0;
-    // the default configuration is chosen for FP64; an FP32 solve takes its own
+    // the default configuration is chosen for the direct-form Jacobi and the
+    // two-cells-per-lane chaotic kernels; FP32 solves and chaotic GS with
+    // omega != 1 (the update form) take their own
     LineCfg c = line_cfg(ps, axis, cm);
-    if (f32 && c.deflt) c = default_line_cfg(ps, axis, cm, false);
+    if (c.deflt && (f32 || (cm == 2 && omega != 1.0))) c = default_line_cfg(ps, axis, cm, false);
     if ((st = check_line_cfg(ps, axis, c)) != BS_OK) return st;
     if ((st = prepare_lists(ps, axis, c, cm)) != BS_OK) return st;
     if (bline_any(ps, axis) && (st = bline_prepare(ps, axis)) != BS_OK) return st;
@@ -963,6 +970,13 @@ int bsi_set_pair(bs_patchset *ps, int enable)
 {
     if (!ps) return BS_ERR_INVALID;
     ps->use_pair = enable != 0;
+    // default configurations depend on the kernel: chosen again on next use
+    for (auto it = ps->line_cfg.begin(); it != ps->line_cfg.end();) {
+        if (it->second.deflt)
+            it = ps->line_cfg.erase(it);
+        else
+            ++it;
+    }
     clear_graphs(ps);
     return BS_OK;
 }

@@ -56,7 +56,8 @@ def _row_order_reference(p, axis, nsweeps):
 
 
 @pytest.mark.parametrize("dims,axis,chunks", [((100, 8, 37), 2, 4), ((120, 16, 20), 2, 2), ((64, 9, 21), 1, 2),
-                                              ((127, 33, 8), 2, 1), ((7, 40, 12), 1, 4), ((98, 12, 16), 2, 1)])
+                                              ((127, 33, 8), 2, 1), ((7, 40, 12), 1, 4), ((98, 12, 16), 2, 1),
+                                              ((40, 8, 100), 2, 4), ((30, 150, 9), 1, 8)])   # 32-cell chunks
 def test_pair_sequential_tiles_match_line_by_line_order(dims, axis, chunks):
     p = small_patch(*dims, seed=23, eps=(1.0, 2.0, 30.0))
     ps = bs.PatchSet([p.dims], [p.eps], [p.h])
