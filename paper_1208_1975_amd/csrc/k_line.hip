@@ -38,10 +38,19 @@ namespace bs {
 // no trailing barrier.
 // ---------------------------------------------------------------------------
 
-template <int L, int CM, bool F32>
+template <int L, int CM, bool F32, bool UCL>
 __device__ __forceinline__ void line_strided_item(const LineArgs &a, const double *__restrict__ tabs,
                                                   const float *__restrict__ tabs32, const WorkItem it, double *ends,
                                                   double *ends2, double *ucs);
+
+// Whether the update form keeps u in LDS for the update: 64 lanes x L cells
+// per wavefront, at most 128 KiB (16 wavefronts of 16-cell chunks, or 8 of
+// 32); longer chunks on more wavefronts read u again from memory.
+template <int L, int MAXT, int CM>
+constexpr bool uc_in_lds()
+{
+    return CM < 4 && (L <= 16 || (L == 32 && MAXT <= 512));
+}
 
 // A workgroup drains work items blockIdx.x, blockIdx.x + gridDim.x, ...: one
 // item per workgroup when the grid covers the list, a persistent grid otherwise.
@@ -69,31 +78,31 @@ k_line_strided(LineArgs a, const double *__restrict__ tabs, const float *__restr
     extern __shared__ double smem[];
     const int nw = blockDim.x >> 6;
     double *ucs = smem;
-    double *endb = smem + (L <= 16 && CM < 4 ? L * 64 * nw : 0);   // u is held in LDS only for chunks <= 16
+    constexpr bool UCL = uc_in_lds<L, MAXT, CM>();
+    double *endb = smem + (UCL ? L * 64 * nw : 0);
     int buf = 0;
     for (int i = blockIdx.x; i < a.nitems; i += gridDim.x) {
         const WorkItem it = a.items[i];
         if (it.patch < 0) continue;   // padding of the dispatch order
-        line_strided_item<L, CM, F32>(a, tabs, tabs32, it, endb + buf * (2 * 64 * nw),
-                                      endb + (buf ^ 1) * (2 * 64 * nw), ucs);
+        line_strided_item<L, CM, F32, UCL>(a, tabs, tabs32, it, endb + buf * (2 * 64 * nw),
+                                           endb + (buf ^ 1) * (2 * 64 * nw), ucs);
         // one barrier per item alternates the buffers; the in-tile two-colour
         // mode uses both in every item behind two barriers
         if (CM != 2) buf ^= 1;
     }
 }
 
-template <int L, int CM, bool F32>
+template <int L, int CM, bool F32, bool UCL>
 __device__ __forceinline__ void line_strided_item(const LineArgs &a, const double *__restrict__ tabs,
                                                   const float *__restrict__ tabs32, const WorkItem it, double *ends,
                                                   double *ends2, double *ucs)
 {
     using T = typename std::conditional<F32, float, double>::type;
     const int nthr = blockDim.x;
-    // chunks of up to 16 cells keep u in LDS for the update (16 waves x 64
-    // lanes x 16 doubles = 128 KiB); longer chunks read it again from memory
-    // (the kernel places the LDS buffers by the same rule)
+    // the update form keeps u in LDS for the update when it fits (UCL,
+    // uc_in_lds); otherwise it reads u again from memory
     constexpr bool kDirect = CM >= 4;
-    constexpr bool kUcLds = L <= 16 && !kDirect;
+    constexpr bool kUcLds = UCL;
     constexpr bool kNtF = CM == 3 || CM == 5;
     const PatchDesc *pd = a.pd + it.patch;
     const int axis = a.axis;          // 1 or 2

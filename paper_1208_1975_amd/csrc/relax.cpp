@@ -348,8 +348,12 @@ size_t line_lds_bytes(const bs_patchset *ps, int axis, const LineCfg &c)
     // y/z lines: the chunk values of u and two buffers of chunk ends (the
     // table is read through the scalar cache); x lines: table, chunk ends, the
     // tile's rows, row offsets
-    if (axis != 0)
-        return static_cast<size_t>((c.Lmax <= 16 ? c.Lmax : 0) + 4) * 64 * static_cast<size_t>(c.nwaves) * sizeof(double);
+    if (axis != 0) {
+        // the update form's copy of u (16-cell chunks, or 32-cell chunks on at
+        // most eight wavefronts: the kernels' uc_in_lds rule)
+        const bool ucl = c.Lmax <= 16 || (c.Lmax == 32 && c.nwaves <= 8);
+        return static_cast<size_t>((ucl ? c.Lmax : 0) + 4) * 64 * static_cast<size_t>(c.nwaves) * sizeof(double);
+    }
     size_t n = static_cast<size_t>((tsz + 1) & ~1) + 2 * 64 * static_cast<size_t>(c.nwaves);
     n += 64 * static_cast<size_t>(sd) + 128;
     return n * sizeof(double);

@@ -68,6 +68,26 @@ def test_line_parity_small(dims, axis, scheme):
         assert np.array_equal(got[gm], p.u0[gm])   # ghosts bit-unchanged
 
 
+@pytest.mark.parametrize("dims,axis", [((37, 21, 201), 2), ((40, 150, 24), 1)])
+@pytest.mark.parametrize("chunks", [4, 8, 16])
+def test_update_form_chunk_counts(dims, axis, chunks):
+    """The update form (u kept for the update: in LDS for 16-cell chunks and
+    for 32-cell chunks on eight wavefronts, read again for 64-cell chunks) for
+    two-colour GS, Jacobi (direct form off) and FP32 Jacobi on lines of 201
+    and 150 cells."""
+    p = small_patch(*dims, seed=61 + axis, eps=(1.0, 3.0, 40.0))
+    for scheme, omega, prec in (("colored", 1.0, "fp64"), ("colored", 1.3, "fp64"), ("jacobi", 0.8, "fp64"),
+                                ("jacobi", 0.8, "fp32")):
+        log("update form %s axis %d chunks %d %s %.1f %s" % (dims, axis, chunks, scheme, omega, prec))
+        s = Single(p)
+        s.ps.set_line_direct(False)
+        s.ps.set_line_config(axis, scheme, chunks, 64)
+        s.line(axis, scheme, omega, 2, prec=prec)
+        ref = oracle.line_sweeps(p.u0, p.f, p.eps, p.h, axis, ORACLE_SCHEME[scheme], omega, 2)
+        err = relerr(s.u_np(), ref)
+        assert err < (TOL if prec == "fp64" else 2 * omega * 1e-6), (scheme, omega, prec, err)
+
+
 @pytest.mark.parametrize("dims,axis", [((8, 8, 20), 2), ((16, 4, 30), 2), ((64, 1, 40), 2), ((7, 9, 5), 1),
                                        ((3, 11, 2), 1), ((1, 1, 17), 2), ((20, 6, 8), 0), ((9, 4, 16), 0),
                                        ((33, 1, 1), 0), ((256, 3, 5), 0)])
