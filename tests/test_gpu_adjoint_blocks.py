@@ -149,3 +149,42 @@ def test_forward_checkpoints_then_backward(kind, axis, scheme, omega, K, ckpt):
         for a, b in zip(got, ref):
             assert np.array_equal(a, b), rep
     ps.close()
+
+
+@pytest.mark.parametrize("kind,axis,scheme", [("line", 2, "jacobi"), ("line", 1, "colored"), ("plane", 1, "jacobi")])
+def test_forward_checkpoints_patch_set(kind, axis, scheme):
+    """Three patches of different shapes and eps: the checkpoint-split adjoint
+    gives bit for bit the gradients of bs_block_backward on the same set."""
+    ps_ = [small_patch(*d, seed=90 + i, eps=e) for i, (d, e) in
+           enumerate([((12, 9, 30), (1.0, 2.0, 20.0)), ((7, 16, 11), (3.0, 1.0, 5.0)), ((20, 5, 8), (1.0, 1.0, 1.0))])]
+    ps = bs.PatchSet([p.dims for p in ps_], [p.eps for p in ps_], [p.h for p in ps_])
+    u0, f = ps.pack_u([p.u0 for p in ps_]), ps.pack_f([p.f for p in ps_])
+    rng = np.random.default_rng(12)
+    g = ps.pack_u([rng.uniform(-1, 1, p.u0.shape) for p in ps_])
+    K, ckpt, omega = 6, 4, 0.9
+    nbytes = bs.bs_block_backward_workspace_bytes(ps.handle, kind, axis, scheme, K, ckpt)
+    outs = []
+    for split in (False, True):
+        log("forward ckpt patch set %s %d %s split=%s" % (kind, axis, scheme, split))
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        gu0, gf = torch.zeros_like(u0), torch.zeros_like(f)
+        geps = torch.zeros(3 * ps.npatch, dtype=torch.float64, device="cuda")
+        if split:
+            u = u0.clone()
+            bs.bs_block_forward_ckpt(ps.handle, kind, axis, scheme, omega, K, ckpt, u, f, ws)
+            uref, w = u0.clone(), ps.empty_u()
+            if kind == "line":
+                ps.line_relax(axis, scheme, omega, K, uref, f, w)
+            else:
+                ps.plane_relax(axis, scheme, omega, K, uref, f, w)
+            bs.bs_block_backward_ckpt(ps.handle, kind, axis, scheme, omega, K, ckpt, f, g, gu0, gf, geps, ws)
+            torch.cuda.synchronize()
+            for i in range(ps.npatch):
+                assert relerr(ps.view_u(u, i).cpu().numpy(), ps.view_u(uref, i).cpu().numpy()) < 1e-13
+        else:
+            bs.bs_block_backward(ps.handle, kind, axis, scheme, omega, K, ckpt, u0, f, g, gu0, gf, geps, ws)
+            torch.cuda.synchronize()
+        outs.append((gu0.cpu().numpy(), gf.cpu().numpy(), geps.cpu().numpy()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    ps.close()
