@@ -77,7 +77,12 @@ hipError_t launch_cube_resid(const CubeArgs &a, hipStream_t s)
 // product), so the epilogue only stores.
 // Workgroups are mapped XCD-contiguously, so neighbouring blocks (which read
 // each other's faces) share an L2.
-template <int NP>
+// RL: the update takes u from a second load in the epilogue instead of the
+// identity product (frees 32 AGPRs: four waves per SIMD instead of three for
+// NP = 64); measured faster only for 4^3 Jacobi (0.191 against 0.207 ms per
+// sweep on 64 patches of 64^3), slower for every smaller block and for the
+// in-place schemes, so the launcher takes it only there.
+template <int NP, bool RL>
 __global__ void __launch_bounds__(256) k_cube_small(CubeBatchArgs ba_)
 {
     __shared__ double Bs[NP][NP + 1];
@@ -154,13 +159,34 @@ __global__ void __launch_bounds__(256) k_cube_small(CubeBatchArgs ba_)
 #pragma unroll
             for (int j = 0; j < NP / 16; ++j) {
                 acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(r, Bs[c][j * 16 + l16], acc[j], 0, 0, 0);
-                accu[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(uc, c == j * 16 + l16 ? 1.0 : 0.0, accu[j], 0, 0, 0);
+                if constexpr (!RL)
+                    accu[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(uc, c == j * 16 + l16 ? 1.0 : 0.0, accu[j], 0, 0,
+                                                                   0);
             }
         }
     }
 
     // result register r of a lane: block 4r + l/16 of the wavefront, whose
     // base the operand lane 4r + l/16 holds
+    if constexpr (RL) {
+        // every old value of the chunk is read before any new one is stored
+        double uo[4][NP / 16];
+        int64_t bases[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            bases[r] = __shfl(ub, 4 * r + lk);
+#pragma unroll
+            for (int j = 0; j < NP / 16; ++j) uo[r][j] = a.u[bases[r] + So[0][j * 16 + l16]];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool ok = b0 + w * 16 + 4 * r + lk < bend;
+#pragma unroll
+            for (int j = 0; j < NP / 16; ++j)
+                if (ok && j * 16 + l16 < nb) a.dst[bases[r] + So[0][j * 16 + l16]] = fma(a.omega, acc[j][r], uo[r][j]);
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int m = 4 * r + lk;
@@ -326,9 +352,10 @@ hipError_t launch_cube_small(const CubeBatchArgs &a, int nchunks, int np, hipStr
 {
     if (nchunks <= 0) return hipSuccess;
     const dim3 grid(nchunks);
-    if (np == 16) hipLaunchKernelGGL(k_cube_small<16>, grid, dim3(256), 0, s, a);
-    else if (np == 32) hipLaunchKernelGGL(k_cube_small<32>, grid, dim3(256), 0, s, a);
-    else if (np == 64) hipLaunchKernelGGL(k_cube_small<64>, grid, dim3(256), 0, s, a);
+    if (np == 16) hipLaunchKernelGGL((k_cube_small<16, false>), grid, dim3(256), 0, s, a);
+    else if (np == 32) hipLaunchKernelGGL((k_cube_small<32, false>), grid, dim3(256), 0, s, a);
+    else if (np == 64 && a.list == 1) hipLaunchKernelGGL((k_cube_small<64, true>), grid, dim3(256), 0, s, a);   // Jacobi
+    else if (np == 64) hipLaunchKernelGGL((k_cube_small<64, false>), grid, dim3(256), 0, s, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
