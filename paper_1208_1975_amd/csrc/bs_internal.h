@@ -232,13 +232,17 @@ struct BLineArgs {
     const double *f;
     const PatchDesc *pd;
     const BLineItem *items;
-    double *scratch;          // 2 * maxlen * nlines doubles: [t][line] pivots and eliminated rhs
+    double *scratch;          // 2 * maxlen * nlines doubles: [2t + 1][line] residual, then eliminated rhs
+    double *fac;              // 2 * maxlen * nlines doubles: [2t][line] multiplier eps_a / m_{t-1}, [2t + 1][line] 1 / m_t
     int32_t axis, nitems, nlines, first;   // items [first, first + nitems) of nlines
     double omega;
 };
 // Two launches: the lines' residuals one cell per thread, then the solves one
 // line per thread (maxlen: the longest line of the set along the axis).
 hipError_t launch_bline(const BLineArgs &a, int maxlen, hipStream_t s);
+// The lines' LU factors (they depend on eps and the faces only), once per
+// patch set and axis: one line per thread, every item of a.items.
+hipError_t launch_bline_factors(const BLineArgs &a, hipStream_t s);
 
 // Multigrid transfers (k_mg.hip), per patch: pf / pc the fine / coarse
 // descriptors, max_cells the largest coarse (restriction) or fine

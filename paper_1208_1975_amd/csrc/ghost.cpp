@@ -157,7 +157,21 @@ bs_status bline_prepare(bs_patchset *ps, int axis)
         clear_graphs(ps);   // captured sequences may hold the old scratch
         if ((st = dev_alloc(ps->bline_scratch, need, "boundary line scratch")) != BS_OK) return st;
     }
+    // the lines' LU factors depend on eps and the faces only: formed once here
+    DevBuf fac;
+    if ((st = dev_alloc(fac, std::max<size_t>(need, 8), "boundary line factors")) != BS_OK) return st;
+    BLineArgs a{};
+    a.pd = static_cast<const PatchDesc *>(ps->desc_d.p);
+    a.items = static_cast<const BLineItem *>(d.p);
+    a.fac = static_cast<double *>(fac.p);
+    a.axis = axis;
+    a.nlines = a.nitems = static_cast<int32_t>(all.size());
+    hipError_t e = launch_bline_factors(a, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return hip_fail(e, "boundary line factors");
+    clear_graphs(ps);   // captured sequences may hold the old buffers
     ps->bline_d[axis].swap(d);
+    ps->bline_fac[axis].swap(fac);
     ps->bline_count[axis][0] = static_cast<int>(col[0].size());
     ps->bline_count[axis][1] = static_cast<int>(col[1].size());
     ps->bline_maxlen[axis] = maxlen;
@@ -177,6 +191,7 @@ bs_status bline_pass(bs_patchset *ps, int axis, int colour, const double *src, d
     a.pd = static_cast<const PatchDesc *>(ps->desc_d.p);
     a.items = static_cast<const BLineItem *>(ps->bline_d[axis].p);
     a.scratch = static_cast<double *>(ps->bline_scratch.p);
+    a.fac = static_cast<double *>(ps->bline_fac[axis].p);
     a.axis = axis;
     a.nlines = n0 + n1;
     a.first = colour == 1 ? n0 : 0;

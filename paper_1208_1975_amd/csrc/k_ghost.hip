@@ -98,14 +98,41 @@ __global__ void __launch_bounds__(256) k_bline_resid(BLineArgs a, int maxlen)
     a.scratch[(int64_t)(2 * t + 1) * a.nlines + line] = fma(-d, uc, fma(pd->h2, a.f[g.f0 + (int64_t)t * g.fa], nb));
 }
 
-// One thread per line: the Thomas algorithm on the line block
-// tridiag(-eps_a, d_t, -eps_a), d_t = 2(eps_x + eps_y + eps_z) plus eps_b for
-// every extrapolated face next to the line (its whole length) and eps_a at an
-// extrapolated end, with pivots formed on the fly.  The forward elimination
-// overwrites the residual (row 2t + 1) with the eliminated right-hand side
-// and stores the reciprocal pivot in row 2t; the back substitution writes
-// dst = src + omega du.  In place (src == dst) every cell of the line is read
-// before it is written.
+// The LU factors of each boundary line's block tridiag(-eps_a, d_t, -eps_a),
+// d_t = 2(eps_x + eps_y + eps_z) plus eps_b for every extrapolated face next
+// to the line (its whole length) and eps_a at an extrapolated end: pivots
+// m_0 = d_0, m_t = d_t - eps_a (eps_a / m_{t-1}); stored as the multiplier
+// eps_a / m_{t-1} (0 for t = 0) and 1 / m_t, [t][line] like the scratch.
+__global__ void __launch_bounds__(256) k_bline_factors(BLineArgs a)
+{
+    const int line = blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= a.nitems) return;
+    const BLineItem it = a.items[line];
+    const PatchDesc *pd = a.pd + it.patch;
+    const int ax = a.axis;
+    const BLineGeo g = bline_geo(pd, it, ax);
+    const double ea = pd->eps[ax];
+    const double dd = 2.0 * (pd->eps[0] + pd->eps[1] + pd->eps[2]) + g.shift;
+    const int64_t L = a.nlines;
+    double mprev = 1.0;
+    for (int t = 0; t < g.na; ++t) {
+        const double dt = dd + (t == 0 && g.lo_a ? ea : 0.0) + (t == g.na - 1 && g.hi_a ? ea : 0.0);
+        const double gm = t == 0 ? 0.0 : ea / mprev;
+        const double m = fma(-ea, gm, dt);
+        a.fac[(int64_t)(2 * t) * L + line] = gm;
+        a.fac[(int64_t)(2 * t + 1) * L + line] = 1.0 / m;
+        mprev = m;
+    }
+}
+
+// One thread per line: the Thomas algorithm on the line block with the
+// factors of k_bline_factors.  The forward elimination z_t = r_t + g_t z_{t-1}
+// overwrites the residual with the eliminated right-hand side; the back
+// substitution du_t = (z_t + eps_a du_{t+1}) / m_t writes dst = src + omega du.
+// The loads of B cells are issued together before the recurrences consume
+// them, so the chains are FMAs and a memory round trip is paid once per B
+// cells.  In place (src == dst) every cell of the line is read before it is
+// written.
 __global__ void __launch_bounds__(256) k_bline(BLineArgs a)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -116,47 +143,39 @@ __global__ void __launch_bounds__(256) k_bline(BLineArgs a)
     const int ax = a.axis;
     const BLineGeo g = bline_geo(pd, it, ax);
     const double ea = pd->eps[ax];
-    const double dd = 2.0 * (pd->eps[0] + pd->eps[1] + pd->eps[2]) + g.shift;
     const int na = g.na;
     double *sc = a.scratch + line;
+    const double *fc = a.fac + line;
     const int64_t L = a.nlines;
-    // The loads of B cells are issued together before the recurrence consumes
-    // them: the recurrence's own chain is arithmetic, and a memory round trip
-    // is paid once per B cells instead of once per cell (a 256-cell line:
-    // 189 us -> far less; the order of the arithmetic is unchanged).
     constexpr int B = 16;
-    double mprev = 1.0, zprev = 0.0;
+    double zprev = 0.0;
     for (int t0 = 0; t0 < na; t0 += B) {
-        double rb[B];
+        double rb[B], gb[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int t = t0 + k < na ? t0 + k : na - 1;
             rb[k] = sc[(int64_t)(2 * t + 1) * L];
+            gb[k] = fc[(int64_t)(2 * t) * L];
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int t = t0 + k;
             if (t < na) {
-                const double dt = dd + (t == 0 && g.lo_a ? ea : 0.0) + (t == na - 1 && g.hi_a ? ea : 0.0);
-                const double gm = t == 0 ? 0.0 : ea / mprev;
-                const double m = fma(-ea, gm, dt);
-                const double z = fma(gm, zprev, rb[k]);
-                sc[(int64_t)(2 * t) * L] = 1.0 / m;
+                const double z = fma(gb[k], zprev, rb[k]);
                 sc[(int64_t)(2 * t + 1) * L] = z;
-                mprev = m;
                 zprev = z;
             }
         }
     }
     double du = 0.0;
     for (int t1 = na - 1; t1 >= 0; t1 -= B) {
-        // this batch's factors, forward results and old values (each cell's
-        // old value is read before its new value is stored: in place for GS)
+        // this batch's factors, eliminated right-hand sides and old values
+        // (each cell's old value is read before its new value is stored)
         double qb[B], zb[B], ub[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int t = t1 - k >= 0 ? t1 - k : 0;
-            qb[k] = sc[(int64_t)(2 * t) * L];
+            qb[k] = fc[(int64_t)(2 * t + 1) * L];
             zb[k] = sc[(int64_t)(2 * t + 1) * L];
             ub[k] = a.src[g.u0 + (int64_t)t * g.sa];
         }
@@ -169,6 +188,13 @@ __global__ void __launch_bounds__(256) k_bline(BLineArgs a)
             }
         }
     }
+}
+
+hipError_t launch_bline_factors(const BLineArgs &a, hipStream_t s)
+{
+    if (a.nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bline_factors, dim3((a.nitems + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_bline(const BLineArgs &a, int maxlen, hipStream_t s)

@@ -148,6 +148,7 @@ struct bs_patchset {
     int bline_count[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // colour 0 items, then colour 1
     int bline_maxlen[3] = {0, 0, 0};                     // longest such line per axis
     bs::DevBuf bline_scratch;
+    bs::DevBuf bline_fac[3];                             // their LU factors per axis ([t][line])
     hipStream_t capture_stream = nullptr;
     uint64_t gen = 0;   // bumped whenever device tables or captured graphs are replaced
     bool use_graphs = true;
