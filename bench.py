@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--profile-cubes", action="store_true",
                     help="fixed cube-block sequence for rocprofv3 (64 patches of 64^3: 1 GiB copy, then one "
                          "Jacobi sweep each with 8^3 and 4^3 blocks)")
+    ap.add_argument("--profile-mg", action="store_true",
+                    help="fixed multigrid sequence for rocprofv3 (three V-cycles of the multigrid form)")
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3 counter runs: a 1 GiB device copy (reference for FETCH_SIZE / "
                          "WRITE_SIZE scaling), then 10 z-line Jacobi and 10 chaotic GS sweep launches; no JSON")
@@ -154,6 +156,28 @@ def profile_cubes_run():
         ps.cube_relax(blk, "jacobi", 0.8, 1, u, f, w)
         torch.cuda.synchronize()
         print("profile cubes %s done" % (blk,), flush=True)
+
+
+def profile_mg_run():
+    """Fixed V-cycle sequence for kernel traces: the multigrid form's cycle
+    (256^3, z-line two-colour GS with extrapolated faces), three cycles, the
+    last two replayed from the captured graph."""
+    import torch
+
+    import paper_1208_1975_amd as bs
+    from workloads import make_patch
+
+    p = make_patch(256, 256, 256, (1.0, 1.0, 100.0), 1.0 / 256, seed=2, f="zero", u0="uniform")
+    ps = bs.PatchSet([p.dims], [p.eps], [p.h])
+    ps.set_bc([63])
+    mg = bs.Multigrid(ps, "line", 2, "colored", 1.0, 1, 1, 20, 0, 63)
+    u, f = ps.pack_u([p.u0]), ps.pack_f([p.f])
+    for c in range(3):
+        mg.vcycle(u, f)
+        torch.cuda.synchronize()
+        print("profile mg cycle %d done" % c, flush=True)
+    mg.close()
+    ps.close()
 
 
 def measured_traffic():
@@ -595,6 +619,9 @@ def main():
         return
     if args.profile_cubes:
         profile_cubes_run()
+        return
+    if args.profile_mg:
+        profile_mg_run()
         return
     if args.cubes:
         import torch
