@@ -98,11 +98,17 @@ __global__ void __launch_bounds__(256) k_bline_resid(BLineArgs a, int maxlen)
     a.scratch[(int64_t)(2 * t + 1) * a.nlines + line] = fma(-d, uc, fma(pd->h2, a.f[g.f0 + (int64_t)t * g.fa], nb));
 }
 
-// The LU factors of each boundary line's block tridiag(-eps_a, d_t, -eps_a),
-// d_t = 2(eps_x + eps_y + eps_z) plus eps_b for every extrapolated face next
-// to the line (its whole length) and eps_a at an extrapolated end: pivots
-// m_0 = d_0, m_t = d_t - eps_a (eps_a / m_{t-1}); stored as the multiplier
-// eps_a / m_{t-1} (0 for t = 0) and 1 / m_t, [t][line] like the scratch.
+// Two-ended (twisted) factorisation of each boundary line's block
+// tridiag(-eps_a, d_t, -eps_a), d_t = 2(eps_x + eps_y + eps_z) plus eps_b for
+// every extrapolated face next to the line (its whole length) and eps_a at an
+// extrapolated end.  With the middle cell k = (na - 1) / 2, pivots are formed
+// from the top for t < k (m_0 = d_0, m_t = d_t - eps_a^2 / m_{t-1}) and from
+// the bottom for t > k (p_{na-1} = d_{na-1}, p_t = d_t - eps_a^2 / p_{t+1});
+// the middle row then has gamma_k = d_k - eps_a^2 / m_{k-1} - eps_a^2 / p_{k+1}.
+// Stored [t][line] like the scratch: row 2t the multiplier (eps_a / m_{t-1}
+// above the middle, eps_a / p_{t+1} below it, 0 at the two ends and the
+// middle), row 2t + 1 the reciprocal pivot (1 / m_t, 1 / p_t, 1 / gamma_k).
+// They depend on eps and the faces only: formed once per patch set and axis.
 __global__ void __launch_bounds__(256) k_bline_factors(BLineArgs a)
 {
     const int line = blockIdx.x * blockDim.x + threadIdx.x;
@@ -114,77 +120,115 @@ __global__ void __launch_bounds__(256) k_bline_factors(BLineArgs a)
     const double ea = pd->eps[ax];
     const double dd = 2.0 * (pd->eps[0] + pd->eps[1] + pd->eps[2]) + g.shift;
     const int64_t L = a.nlines;
-    double mprev = 1.0;
-    for (int t = 0; t < g.na; ++t) {
-        const double dt = dd + (t == 0 && g.lo_a ? ea : 0.0) + (t == g.na - 1 && g.hi_a ? ea : 0.0);
-        const double gm = t == 0 ? 0.0 : ea / mprev;
-        const double m = fma(-ea, gm, dt);
+    const int na = g.na, k = (na - 1) / 2;
+    auto diag = [&](int t) { return dd + (t == 0 && g.lo_a ? ea : 0.0) + (t == na - 1 && g.hi_a ? ea : 0.0); };
+    double m = 0.0, p = 0.0;
+    for (int t = 0; t < k; ++t) {
+        const double gm = t == 0 ? 0.0 : ea / m;
+        m = fma(-ea, gm, diag(t));
         a.fac[(int64_t)(2 * t) * L + line] = gm;
         a.fac[(int64_t)(2 * t + 1) * L + line] = 1.0 / m;
-        mprev = m;
     }
+    for (int t = na - 1; t > k; --t) {
+        const double hp = t == na - 1 ? 0.0 : ea / p;
+        p = fma(-ea, hp, diag(t));
+        a.fac[(int64_t)(2 * t) * L + line] = hp;
+        a.fac[(int64_t)(2 * t + 1) * L + line] = 1.0 / p;
+    }
+    double gam = diag(k);
+    if (k > 0) gam = fma(-ea, ea / m, gam);
+    if (k < na - 1) gam = fma(-ea, ea / p, gam);
+    a.fac[(int64_t)(2 * k) * L + line] = 0.0;
+    a.fac[(int64_t)(2 * k + 1) * L + line] = 1.0 / gam;
 }
 
-// One thread per line: the Thomas algorithm on the line block with the
-// factors of k_bline_factors.  The forward elimination z_t = r_t + g_t z_{t-1}
-// overwrites the residual with the eliminated right-hand side; the back
-// substitution du_t = (z_t + eps_a du_{t+1}) / m_t writes dst = src + omega du.
-// The loads of B cells are issued together before the recurrences consume
-// them, so the chains are FMAs and a memory round trip is paid once per B
-// cells.  In place (src == dst) every cell of the line is read before it is
-// written.
+// Two lanes per line (lanes 2l and 2l + 1 of a wavefront): lane 0 eliminates
+// from the top towards the middle cell k, z_t = r_t + g_t z_{t-1} (t < k), lane
+// 1 from the bottom, y_t = r_t + h_t y_{t+1} (t > k), in the same instruction
+// stream (each walks max(k, na - 1 - k) steps of its own direction); the lanes
+// exchange z_{k-1} / m_{k-1} and y_{k+1} / p_{k+1}, both form the middle value
+// x_k = (r_k + eps_a z_{k-1} / m_{k-1} + eps_a y_{k+1} / p_{k+1}) / gamma_k, and
+// each substitutes back along its half, x_t = (z_t + eps_a x_{t+1}) / m_t or
+// (y_t + eps_a x_{t-1}) / p_t, writing dst = src + omega x.  The chains are
+// half a line long and FMAs only; the loads of B cells are issued together
+// before they are consumed.  In place (src == dst) every cell is read before
+// it is written (each lane reads the old values of its own cells only; lane 0
+// owns the middle cell).
 __global__ void __launch_bounds__(256) k_bline(BLineArgs a)
 {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= a.nitems) return;
-    const int line = a.first + l;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = gid >> 1, side = gid & 1;
+    const bool live = l < a.nitems;
+    const int line = a.first + (live ? l : a.nitems - 1);   // both lanes of a pair run the exchange
     const BLineItem it = a.items[line];
     const PatchDesc *pd = a.pd + it.patch;
     const int ax = a.axis;
     const BLineGeo g = bline_geo(pd, it, ax);
     const double ea = pd->eps[ax];
-    const int na = g.na;
+    const int na = g.na, k = (na - 1) / 2;
     double *sc = a.scratch + line;
     const double *fc = a.fac + line;
     const int64_t L = a.nlines;
+    // side 0: cells 0 .. k-1 (step +1); side 1: cells na-1 .. k+1 (step -1);
+    // a pair past the last line (padding of the grid) steps nowhere and stores nothing
+    const int nst = !live ? 0 : (side == 0 ? k : na - 1 - k);
+    const int dir = side == 0 ? 1 : -1, tstart = side == 0 ? 0 : na - 1;
+    const int nmax = na - 1 - k;   // >= k: the longer half
     constexpr int B = 16;
     double zprev = 0.0;
-    for (int t0 = 0; t0 < na; t0 += B) {
+    for (int s0 = 0; s0 < nmax; s0 += B) {
         double rb[B], gb[B];
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const int t = t0 + k < na ? t0 + k : na - 1;
-            rb[k] = sc[(int64_t)(2 * t + 1) * L];
-            gb[k] = fc[(int64_t)(2 * t) * L];
+        for (int j = 0; j < B; ++j) {
+            const int s = s0 + j < nst ? s0 + j : (nst > 0 ? nst - 1 : 0);
+            const int t = tstart + dir * s;
+            rb[j] = sc[(int64_t)(2 * t + 1) * L];
+            gb[j] = fc[(int64_t)(2 * t) * L];
         }
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const int t = t0 + k;
-            if (t < na) {
-                const double z = fma(gb[k], zprev, rb[k]);
+        for (int j = 0; j < B; ++j) {
+            const int s = s0 + j;
+            if (s < nst) {
+                const int t = tstart + dir * s;
+                const double z = fma(gb[j], zprev, rb[j]);
                 sc[(int64_t)(2 * t + 1) * L] = z;
                 zprev = z;
             }
         }
     }
-    double du = 0.0;
-    for (int t1 = na - 1; t1 >= 0; t1 -= B) {
+    // this lane's contribution to the middle row: eps_a z_{k-1} / m_{k-1}
+    // (side 0) or eps_a y_{k+1} / p_{k+1} (side 1); 0 for an empty half
+    const int tn = side == 0 ? k - 1 : k + 1;
+    const double qn = nst > 0 ? fc[(int64_t)(2 * (nst > 0 ? tn : k) + 1) * L] : 0.0;
+    const double mine = nst > 0 ? ea * zprev * qn : 0.0;
+    const double other = __shfl_xor(mine, 1);
+    const double rk = sc[(int64_t)(2 * k + 1) * L];
+    const double gk = fc[(int64_t)(2 * k + 1) * L];
+    const double x_mid = (rk + (side == 0 ? mine + other : other + mine)) * gk;
+    if (!live) return;
+    if (side == 0) {
+        const int64_t cu = g.u0 + (int64_t)k * g.sa;
+        a.dst[cu] = fma(a.omega, x_mid, a.src[cu]);
+    }
+    double x = x_mid;
+    for (int s1 = nst - 1; s1 >= 0; s1 -= B) {
         // this batch's factors, eliminated right-hand sides and old values
-        // (each cell's old value is read before its new value is stored)
         double qb[B], zb[B], ub[B];
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const int t = t1 - k >= 0 ? t1 - k : 0;
-            qb[k] = fc[(int64_t)(2 * t + 1) * L];
-            zb[k] = sc[(int64_t)(2 * t + 1) * L];
-            ub[k] = a.src[g.u0 + (int64_t)t * g.sa];
+        for (int j = 0; j < B; ++j) {
+            const int s = s1 - j >= 0 ? s1 - j : 0;
+            const int t = tstart + dir * s;
+            qb[j] = fc[(int64_t)(2 * t + 1) * L];
+            zb[j] = sc[(int64_t)(2 * t + 1) * L];
+            ub[j] = a.src[g.u0 + (int64_t)t * g.sa];
         }
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const int t = t1 - k;
-            if (t >= 0) {
-                du = (t == na - 1 ? zb[k] : fma(ea, du, zb[k])) * qb[k];
-                a.dst[g.u0 + (int64_t)t * g.sa] = fma(a.omega, du, ub[k]);
+        for (int j = 0; j < B; ++j) {
+            const int s = s1 - j;
+            if (s >= 0) {
+                const int t = tstart + dir * s;
+                x = fma(ea, x, zb[j]) * qb[j];
+                a.dst[g.u0 + (int64_t)t * g.sa] = fma(a.omega, x, ub[j]);
             }
         }
     }
@@ -202,7 +246,7 @@ hipError_t launch_bline(const BLineArgs &a, int maxlen, hipStream_t s)
     if (a.nitems <= 0) return hipSuccess;
     const int64_t cells = (int64_t)a.nitems * maxlen;
     hipLaunchKernelGGL(k_bline_resid, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, a, maxlen);
-    hipLaunchKernelGGL(k_bline, dim3((a.nitems + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bline, dim3((2 * a.nitems + 255) / 256), dim3(256), 0, s, a);   // two lanes per line
     return hipGetLastError();
 }
 
